@@ -1,0 +1,203 @@
+"""phi_k(tau A) v by Newton interpolation at Leja points, and the exponential
+Euler step.
+
+Test infrastructure only (see the package docstring).
+
+Sec. II-C: with an a-priori bound [a, b] of the field of values of A,
+polynomial interpolation reduces phi_k(tau A) v to repeated products
+(alpha A + beta I) x (eq. (3)).  Sec. III-C names interpolation at Leja
+points.  The steps, in the order this module performs them:
+
+1. Interval: [a, b] from Gershgorin (``operators.gershgorin_interval``) unless
+   the caller supplies one.  Centre ``c = (a + b)/2``, quarter-width
+   ``gamma = (b - a)/4``, so that ``(A - cI)/gamma`` has its spectrum in
+   [-2, 2].
+2. Substeps: ``s = max(1, ceil(tau (b - a) / l_max))`` and ``delta = tau/s``.
+3. Divided differences ``d_j`` of ``x -> phi_k(delta (c + gamma x))`` at the
+   Leja points ``xi_0..xi_{m_max}`` of [-2, 2] (``leja.divided_differences``).
+4. Newton form applied to a vector r: ``w_0 = r``, ``p = d_0 w_0`` and for
+   ``j = 0, 1, ...``::
+
+       w_{j+1} = (alpha A + beta_j I) w_j,  alpha = 1/gamma,
+                                            beta_j = -(c/gamma + xi_j)
+       p      += d_{j+1} w_{j+1}
+
+   i.e. ``w_{j+1} = ((A - cI)/gamma - xi_j I) w_j``; every step is one
+   product of the form of eq. (3).
+5. Stop test (the paper fixes only that a tolerance controls the number of
+   products, Tables IV and V): with ``t_j = |d_j| ||w_j||_2``, stop after the
+   first step ``m = j + 1 >= 2`` with ``t_{m-1} + t_m <= tol ||p||_2``.
+   If ``m_max`` steps pass without stopping, the substep count doubles and the
+   whole evaluation restarts (at most ``max_retries`` times).
+6. Substeps of phi_1: ``y(t) = t phi_1(tA) v`` solves ``y' = A y + v``,
+   ``y(0) = 0``, and ``e^{dA} = I + dA phi_1(dA)``, hence
+   ``y_{l+1} = y_l + delta phi_1(delta A)(A y_l + v)`` and
+   ``phi_1(tau A) v = y_s / tau``.  For phi_0, ``y_{l+1} = e^{delta A} y_l``.
+   For k >= 2 only ``s = 1`` is supported.
+7. Exponential Euler, eq. (2), for ``u' = A u + g(u)`` (the paper writes
+   ``u' + A u = g`` with A having large negative eigenvalues; with A the
+   discrete Laplacian itself, whose eigenvalues are negative, the sign of A
+   flips and eq. (2) reads ``u_{n+1} = e^{tau A} u_n + tau phi_1(tau A) g(u_n)``).
+   Using ``e^{tau A} = I + tau A phi_1(tau A)`` this equals
+   ``u_n + tau phi_1(tau A)(A u_n + g(u_n))``; with substeps,
+   ``y_0 = u_n``, ``y_{l+1} = y_l + delta phi_1(delta A)(A y_l + g(u_n))``,
+   ``u_{n+1} = y_s``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import leja
+from .operators import gershgorin_interval
+
+
+@dataclass(frozen=True)
+class LejaParams:
+    l_max: float = 100.0     # largest delta*(b-a) per substep
+    m_max: int = 100         # largest number of Newton steps per substep
+    max_retries: int = 4     # substep doublings after a non-converged substep
+
+
+@dataclass
+class Stats:
+    substeps: int = 0
+    newton_steps: int = 0    # products inside the Newton loops
+    matvecs: int = 0         # all products with A (Newton + start vectors)
+    degrees: list = field(default_factory=list)
+    err_est: float = 0.0     # largest (t_{m-1} + t_m)/||p|| over the substeps
+    converged: bool = True
+    retries: int = 0
+    interval: tuple = (0.0, 0.0)
+
+
+def substep_count(tau: float, a: float, b: float, l_max: float) -> int:
+    """Step 2: ``s = max(1, ceil(tau (b - a) / l_max))``."""
+    return max(1, int(math.ceil(tau * (b - a) / l_max)))
+
+
+def newton_leja(A, r: np.ndarray, d: np.ndarray, xi: np.ndarray, c: float,
+                gamma: float, tol: float, m_max: int):
+    """Steps 4-5 on one vector.  Returns ``(p, m, err, converged)`` where
+    ``m`` is the number of products and ``err = (t_{m-1} + t_m)/||p||``."""
+    alpha = 1.0 / gamma
+    w = np.array(r, dtype=np.float64, copy=True)
+    p = d[0] * w
+    t_prev = abs(d[0]) * np.linalg.norm(w)
+    err = math.inf
+    for j in range(m_max):
+        beta = -(c / gamma + xi[j])
+        w = alpha * (A @ w) + beta * w
+        p = p + d[j + 1] * w
+        t = abs(d[j + 1]) * np.linalg.norm(w)
+        pn = np.linalg.norm(p)
+        m = j + 1
+        err = (t_prev + t) / pn if pn > 0 else (0.0 if t_prev + t == 0 else math.inf)
+        if m >= 2 and t_prev + t <= tol * pn:
+            return p, m, err, True
+        t_prev = t
+    return p, m_max, err, False
+
+
+def _interval(A, interval):
+    if interval is not None:
+        a, b = float(interval[0]), float(interval[1])
+    else:
+        a, b = gershgorin_interval(A)
+    if not a < b:
+        raise ValueError("degenerate interval: need a < b")
+    return a, b
+
+
+def phi_action(A, k: int, tau: float, v: np.ndarray, tol: float,
+               interval=None, params: LejaParams = LejaParams()):
+    """``phi_k(tau A) v`` (steps 1-6).  Returns ``(y, Stats)``."""
+    if k < 0:
+        raise ValueError("k must be non-negative")
+    v = np.asarray(v, dtype=np.float64)
+    a, b = _interval(A, interval)
+    c, gamma = 0.5 * (a + b), 0.25 * (b - a)
+    s = substep_count(tau, a, b, params.l_max)
+    xi = leja.leja_points(params.m_max + 1)
+    st = Stats(interval=(a, b))
+    for attempt in range(params.max_retries + 1):
+        if k >= 2 and s > 1:
+            raise NotImplementedError("phi_k with k >= 2 needs a single substep")
+        delta = tau / s
+        d = leja.divided_differences(k, delta, c, gamma, xi)
+        st = Stats(interval=(a, b), substeps=s, retries=attempt)
+        ok = True
+        if k == 0:
+            y = v.copy()
+            for _ in range(s):
+                y, m, err, conv = newton_leja(A, y, d, xi, c, gamma, tol, params.m_max)
+                st.newton_steps += m
+                st.degrees.append(m)
+                st.err_est = max(st.err_est, err)
+                ok &= conv
+            out = y
+        elif k == 1:
+            y = np.zeros_like(v)
+            for l in range(s):
+                r = v if l == 0 else (A @ y) + v
+                if l > 0:
+                    st.matvecs += 1
+                p, m, err, conv = newton_leja(A, r, d, xi, c, gamma, tol, params.m_max)
+                st.newton_steps += m
+                st.degrees.append(m)
+                st.err_est = max(st.err_est, err)
+                ok &= conv
+                y = y + delta * p
+            out = y / tau
+        else:
+            out, m, err, conv = newton_leja(A, v, d, xi, c, gamma, tol, params.m_max)
+            st.newton_steps += m
+            st.degrees.append(m)
+            st.err_est = err
+            ok = conv
+        st.matvecs += st.newton_steps
+        st.converged = ok
+        if ok:
+            return out, st
+        s *= 2
+    return out, st
+
+
+def cubic(u: np.ndarray) -> np.ndarray:
+    """The reaction term ``g(u) = u - u^3``."""
+    return u - u * u * u
+
+
+def expeuler_step(A, tau: float, u: np.ndarray, tol: float, g=cubic,
+                  interval=None, params: LejaParams = LejaParams()):
+    """One exponential Euler step (step 7).  Returns ``(u_next, Stats)``."""
+    u = np.asarray(u, dtype=np.float64)
+    a, b = _interval(A, interval)
+    c, gamma = 0.5 * (a + b), 0.25 * (b - a)
+    s = substep_count(tau, a, b, params.l_max)
+    xi = leja.leja_points(params.m_max + 1)
+    gn = g(u)
+    st = Stats(interval=(a, b))
+    for attempt in range(params.max_retries + 1):
+        delta = tau / s
+        d = leja.divided_differences(1, delta, c, gamma, xi)
+        st = Stats(interval=(a, b), substeps=s, retries=attempt)
+        ok = True
+        y = u.copy()
+        for _ in range(s):
+            r = (A @ y) + gn
+            st.matvecs += 1
+            p, m, err, conv = newton_leja(A, r, d, xi, c, gamma, tol, params.m_max)
+            st.newton_steps += m
+            st.degrees.append(m)
+            st.err_est = max(st.err_est, err)
+            ok &= conv
+            y = y + delta * p
+        st.matvecs += st.newton_steps
+        st.converged = ok
+        if ok:
+            return y, st
+        s *= 2
+    return y, st
