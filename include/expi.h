@@ -1,0 +1,200 @@
+/*
+ * expi.h - C ABI of the MI355X exponential-integrator hot path.
+ *
+ * Einkemmer & Ostermann, "Exponential Integrators on Graphic Processing
+ * Units" (HPCS 2013).  The library evaluates the action phi_k(tau A) v of the
+ * phi functions of a sparse operator A by Newton interpolation at real Leja
+ * points (Sec. III-C), which reduces the work to repeated products
+ * (alpha A + beta I) x (Sec. II-C, eq. (3)), and builds the exponential Euler
+ * step of eq. (2) on it.  A is a matrix-free 2D/3D stencil with the boundary
+ * conditions folded into it (Sec. III-A, III-B) or a CSR matrix (Sec. III-D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Device memory.  Every vector, matrix array, coefficient array and
+ *   workspace is device memory owned by the caller (the Python binding
+ *   allocates it with PyTorch).  The library allocates no device memory on
+ *   any call.  An operator handle BORROWS the device pointers given at
+ *   creation; they must stay valid until the handle is destroyed.
+ * - Streams.  `stream` is a hipStream_t passed as `void *` (NULL = the null
+ *   stream).  All device work of a call is enqueued on it.  phi_action and
+ *   expeuler_step read a 64-byte status record back to pinned host memory a
+ *   few times per Newton loop to decide how many further products to
+ *   enqueue, so they return only after their device work has completed.
+ *   apply_op and expi_op_interval(cached) return without synchronising.
+ * - Grid vectors are contiguous, x fastest: 2D index i + nx*j, 3D index
+ *   i + nx*(j + ny*k).  CSR uses int32 row pointers and column indices,
+ *   float64 values, columns sorted within a row.
+ * - Errors.  Every int-returning function returns EXPI_OK (0) or a negative
+ *   EXPI_E* code; expi_last_error() gives a message for the calling thread.
+ *   Argument validation happens before any HIP call, so it needs no GPU.
+ * - Concurrency.  Calls on different streams must use different workspaces.
+ *   An operator handle may be shared between threads and streams.
+ */
+#ifndef EXPI_H
+#define EXPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define EXPI_OK            0
+#define EXPI_EINVAL       -1  /* bad argument (null pointer, size, enum)         */
+#define EXPI_EALIAS       -2  /* output aliases an input that is read after it   */
+#define EXPI_EWORKSPACE   -3  /* workspace missing or smaller than required      */
+#define EXPI_ENOTCONV     -4  /* no convergence within m_max after all retries   */
+#define EXPI_ENONFINITE   -5  /* a norm became inf/NaN (input not finite)        */
+#define EXPI_EHIP         -6  /* a HIP runtime call failed                       */
+#define EXPI_EUNSUPPORTED -7  /* combination not implemented (e.g. k>=2, s>1)    */
+
+/* ---- enums -------------------------------------------------------------- */
+/* Storage of the Newton vectors w_j and the running sum p.  Solution vectors
+ * (v, y of phi_action; u of expeuler_step) are always float64; divided
+ * differences, norms and the stop test are always float64. */
+#define EXPI_F64 0
+#define EXPI_F32 1
+
+/* Boundary handling folded into the stencil (Sec. II-C: "incorporated into
+ * the matrix A"; Sec. III-A's two options). */
+#define EXPI_DIRICHLET0    0  /* u = 0 beyond the array; the face towards the
+                                 missing neighbour carries the cell's own a  */
+#define EXPI_NEUMANN0      1  /* zero flux through the boundary faces        */
+#define EXPI_INTERIOR_ONLY 2  /* rows of the outermost layer are zero: only
+                                 points whose stencil lies inside are updated */
+
+/* Diffusion coefficient a of div(a grad u); face value = mean of the two
+ * adjacent grid values (Sec. III-B uses a position-dependent coefficient). */
+#define EXPI_COEF_CONST     0 /* a = c0                                        */
+#define EXPI_COEF_SEPARABLE 1 /* a = c0 + c1 * tx[i] * ty[j] (* tz[k])          */
+#define EXPI_COEF_FIELD     2 /* a = field[index], float64, same layout as u    */
+
+/* Pointwise nonlinearity g of u' = A u + g(u). */
+#define EXPI_G_CUBIC 0        /* g(u) = u - u^3                                */
+
+/* ---- types -------------------------------------------------------------- */
+typedef struct expi_op expi_op;   /* opaque operator handle */
+
+/* Per-call statistics (any field may be left 0 by an early error). */
+typedef struct {
+    int32_t substeps;       /* s: number of substeps of the last attempt        */
+    int32_t newton_steps;   /* products inside the Newton loops                 */
+    int32_t matvecs;        /* all products with A (Newton + start vectors)     */
+    int32_t retries;        /* substep doublings after a non-converged substep  */
+    int32_t converged;      /* 1 if every substep met the stop test             */
+    int32_t degree_max;     /* largest Newton degree m over the substeps        */
+    int32_t degree_last;    /* Newton degree of the last substep                */
+    int32_t timed_products; /* fused Newton products timed (params.profile)     */
+    double  err_est;        /* largest (t_{m-1} + t_m)/||p|| over the substeps  */
+    double  interval_a;     /* spectral interval [a, b] used                    */
+    double  interval_b;
+    double  newton_ms;      /* summed device time of those products (HIP events
+                               recorded on `stream` around each launch); only
+                               products that did work (index < m) are counted */
+} expi_stats;
+
+/* Interpolation parameters; pass NULL for the defaults
+ * (l_max = 100, m_max = 100, max_retries = 4, Gershgorin interval,
+ * no profiling). */
+typedef struct {
+    double  l_max;          /* largest delta*(b-a) per substep                   */
+    int32_t m_max;          /* largest number of Newton products per substep    */
+    int32_t max_retries;    /* substep doublings after a non-converged substep  */
+    int32_t have_interval;  /* 1: use [interval_a, interval_b] below            */
+    int32_t profile;        /* 1: time each fused Newton product (stats)        */
+    double  interval_a;
+    double  interval_b;
+} expi_params;
+
+/* ---- operators ---------------------------------------------------------- */
+
+/* Matrix-free stencil A = div(a grad .) discretised with the 5-point (dim 2)
+ * or 7-point (dim 3) formula of Sec. III-A, boundary handling `bc` folded in,
+ * coefficient per Sec. III-B:
+ *   (A u)_c = sum over the 2*dim faces f of c:  a_f (u_nb - u_c) / h_d^2,
+ * a_f = (a_c + a_nb)/2.  For a = 1 and EXPI_DIRICHLET0 this is exactly the
+ * paper's seven-point formula divided by (dx)^2.
+ *   n[dim], h[dim]: host arrays, x first.  n[d] >= 1, product < 2^30.
+ *   tab_x/tab_y/tab_z: device float64 tables of length n[0], n[1], n[2]
+ *   (SEPARABLE only; tab_z ignored in 2D).  field: device float64 array of
+ *   the grid's size (FIELD only).  Borrowed.
+ * Returns EXPI_EINVAL on a bad dim/size/spacing/enum or a missing table. */
+int expi_op_create_stencil(expi_op **op, int dim, const int64_t *n, const double *h,
+                           int bc, int coef_kind, double c0, double c1,
+                           const double *tab_x, const double *tab_y, const double *tab_z,
+                           const double *field);
+
+/* CSR matrix (Sec. III-D): n rows, nnz entries; rowptr int32[n+1],
+ * colind int32[nnz] (sorted per row), val float64[nnz]; device, borrowed. */
+int expi_op_create_csr(expi_op **op, int64_t n, int64_t nnz, const int32_t *rowptr,
+                       const int32_t *colind, const double *val);
+
+int expi_op_destroy(expi_op *op);
+
+/* Number of unknowns of the operator. */
+int64_t expi_op_size(const expi_op *op);
+
+/* Bytes of device workspace phi_action / expeuler_step / expi_op_interval
+ * need for this operator and storage dtype (EXPI_F64 or EXPI_F32). */
+size_t expi_workspace_bytes(const expi_op *op, int dtype);
+
+/* Gershgorin interval [a, b] of A (Sec. II-C needs an a-priori bound of the
+ * field of values): a = min_i (A_ii - R_i), b = max_i (A_ii + R_i),
+ * R_i = sum_{j != i} |A_ij|.  Computed on the device once per handle (one
+ * sweep over the operator, then a 64-byte read-back on `stream`) and cached. */
+int expi_op_interval(expi_op *op, double *a, double *b, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* ---- the three calls of the hot path ------------------------------------ */
+
+/* y = (alpha A + beta I) x   (eq. (3)).  x, y: device arrays of the
+ * operator's size, float64 (dtype EXPI_F64) or float32 (EXPI_F32); y must not
+ * alias x (EXPI_EALIAS).  One kernel launch on `stream`, no synchronisation. */
+int apply_op(const expi_op *op, double alpha, double beta, const void *x, void *y,
+             int dtype, void *stream);
+
+/* y = phi_k(tau A) v by Newton interpolation at Leja points (Sec. III-C,
+ * Sec. II-C), k = 0 (exponential) or 1 (any substep count) or k >= 2 (one
+ * substep only, else EXPI_EUNSUPPORTED).  v, y: float64 device arrays; y must
+ * not alias v.  tol: relative 2-norm tolerance of the two-term stop test per
+ * substep.  dtype: storage of the Newton vectors (EXPI_F64 / EXPI_F32).
+ * ws: device workspace of at least expi_workspace_bytes(op, dtype) bytes,
+ * 256-byte aligned.  st may be NULL.  On EXPI_ENOTCONV y holds the last
+ * attempt's result; on EXPI_ENONFINITE its contents are unspecified. */
+int phi_action(expi_op *op, int k, double tau, const double *v, double *y, double tol,
+               int dtype, const expi_params *params, void *ws, size_t ws_bytes,
+               expi_stats *st, void *stream);
+
+/* One exponential Euler step (eq. (2)) for u' = A u + g(u), written as
+ * u <- u + tau phi_1(tau A) (A u + g(u)), which equals eq. (2) in exact
+ * arithmetic and needs one phi_1 action.  u: float64 device array, updated in
+ * place only when the step converged (left unchanged on any error).
+ * nonlin: EXPI_G_CUBIC.  Other arguments as for phi_action. */
+int expeuler_step(expi_op *op, int nonlin, double tau, double *u, double tol, int dtype,
+                  const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
+                  void *stream);
+
+/* ---- host-side interpolation data (no GPU needed) ----------------------- */
+
+/* The first `count` (1..256) real Leja points of [-2, 2]: xi_0 = 2 and xi_k
+ * maximises prod_{j<k} |x - xi_j| over [-2, 2], ties to the larger point. */
+int expi_leja_points(double *out, int count);
+
+/* Divided differences f[xi_0..xi_j], j < count, of
+ * f(x) = phi_k(delta (c + gamma x)) at the Leja points (the coefficients of
+ * the Newton form that approximates phi_k(delta A) for (A - cI)/gamma with
+ * spectrum in [-2, 2]).  count <= 256. */
+int expi_divided_differences(int k, double delta, double c, double gamma, int count,
+                             double *out);
+
+/* Thread-local message of the last error (never NULL). */
+const char *expi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXPI_H */

@@ -136,3 +136,44 @@ def gershgorin_interval(A) -> tuple[float, float]:
     absA = abs(A)
     r = np.asarray(absA.sum(axis=1)).reshape(-1) - np.abs(d)
     return float(np.min(d - r)), float(np.max(d + r))
+
+
+def apply_at(shape, h, bc: str, u: np.ndarray, points, coef=None) -> np.ndarray:
+    """``(A u)`` at the flat indices ``points``, evaluated one point at a time
+    from the definition in the module docstring, without assembling A (for
+    grids too large to assemble).  ``coef`` as in ``stencil_matrix``."""
+    if bc not in BCS:
+        raise ValueError(f"unknown boundary condition {bc!r}")
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    n = int(np.prod(shape))
+    u = np.asarray(u, dtype=np.float64).reshape(-1)
+    if coef is None:
+        a = lambda idx: 1.0
+    elif np.isscalar(coef):
+        a = lambda idx: float(coef)
+    else:
+        arr = np.asarray(coef, dtype=np.float64).reshape(-1)
+        if arr.size != n:
+            raise ValueError("coefficient has the wrong size")
+        a = lambda idx: float(arr[idx])
+    strides = [int(np.prod(shape[:d])) for d in range(dim)]
+    out = np.empty(len(points))
+    for q, flat in enumerate(points):
+        flat = int(flat)
+        pos = [(flat // strides[d]) % shape[d] for d in range(dim)]
+        if bc == "interior_only" and any(p == 0 or p == s - 1 for p, s in zip(pos, shape)):
+            out[q] = 0.0
+            continue
+        ac = a(flat)
+        total = 0.0
+        for d in range(dim):
+            for s in (-1, +1):
+                p = pos[d] + s
+                if 0 <= p < shape[d]:
+                    nb = flat + s * strides[d]
+                    total += 0.5 * (ac + a(nb)) * (u[nb] - u[flat]) / (h[d] * h[d])
+                elif bc == "dirichlet0":
+                    total += ac * (0.0 - u[flat]) / (h[d] * h[d])
+        out[q] = total
+    return out

@@ -1,0 +1,217 @@
+"""MI355X-native phi_k(tau A) v by real Leja-point Newton interpolation.
+
+Python face of libexpi.so (Einkemmer & Ostermann, "Exponential Integrators on
+Graphic Processing Units", HPCS 2013): operators (matrix-free stencils with
+folded boundary conditions, CSR), the product (alpha A + beta I) x of
+eq. (3), phi_k(tau A) v (Sec. II-C, III-C) and the exponential Euler step of
+eq. (2).  Device memory and streams come from PyTorch; every computation runs
+in the HIP library, and a missing library raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from ._binding import (COEF_CONST, COEF_FIELD, COEF_SEPARABLE, F32, F64, G_CUBIC, BCS, EXPORTS,
+                       ExpiError, LejaParams, Stats, check, divided_differences, leja_points, lib)
+
+__all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "expeuler_step", "leja_points",
+           "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype) -> int:
+    torch = _torch()
+    if dtype in ("f64", F64, torch.float64):
+        return F64
+    if dtype in ("f32", F32, torch.float32):
+        return F32
+    raise ValueError(f"dtype must be f64 or f32, got {dtype!r}")
+
+
+def _stream_ptr(stream, device):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t, device, n=None, name="array"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t, dtype=torch.float64)
+    t = t.to(device=device, dtype=torch.float64).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return t
+
+
+class _Op:
+    """Owns an expi_op handle and the device tensors it borrows."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+        self._keep = []
+        self._ws = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def size(self) -> int:
+        return int(lib().expi_op_size(self._h))
+
+    def workspace_bytes(self, dtype="f64") -> int:
+        return int(lib().expi_workspace_bytes(self._h, _dtype_code(dtype)))
+
+    def workspace(self, dtype="f64"):
+        """A cached device workspace of the required size for this operator."""
+        code = _dtype_code(dtype)
+        ws = self._ws.get(code)
+        if ws is None:
+            ws = workspace(self.workspace_bytes(code), self.device)
+            self._ws[code] = ws
+        return ws
+
+    def interval(self, stream=None):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        ws = self.workspace("f64")
+        check(lib().expi_op_interval(self._h, ctypes.byref(a), ctypes.byref(b),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream_ptr(stream, self.device)))
+        return a.value, b.value
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().expi_op_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+class StencilOp(_Op):
+    """Matrix-free 2D/3D stencil A = div(a grad .) with folded boundary handling.
+
+    shape: (nx, ny) or (nx, ny, nz), x fastest; h: spacing per axis.
+    bc: 'dirichlet0', 'neumann0' or 'interior_only'.
+    coef: None (a = 1), a float (a = c0), a tuple ('separable', c0, c1, tx, ty[, tz])
+    giving a = c0 + c1 tx[i] ty[j] tz[k], or an array of the grid's size.
+    """
+
+    def __init__(self, shape, h, bc="dirichlet0", coef=None, device="cuda:0"):
+        super().__init__()
+        torch = _torch()
+        self.device = torch.device(device)
+        self.shape = tuple(int(s) for s in shape)
+        self.h = tuple(float(x) for x in h)
+        dim = len(self.shape)
+        if dim not in (2, 3) or len(self.h) != dim:
+            raise ValueError("shape and h must both have length 2 or 3")
+        if bc not in BCS:
+            raise ValueError(f"unknown bc {bc!r}")
+        self.bc = bc
+        n = (ctypes.c_int64 * 3)(*(list(self.shape) + [1] * (3 - dim)))
+        hh = (ctypes.c_double * 3)(*(list(self.h) + [1.0] * (3 - dim)))
+        kind, c0, c1 = COEF_CONST, 1.0, 0.0
+        tabs = [None, None, None]
+        field = None
+        if coef is None:
+            pass
+        elif isinstance(coef, (int, float)):
+            c0 = float(coef)
+        elif isinstance(coef, tuple) and coef and coef[0] == "separable":
+            kind = COEF_SEPARABLE
+            c0, c1 = float(coef[1]), float(coef[2])
+            for d in range(dim):
+                t = _dev_f64(coef[3 + d], self.device, self.shape[d], f"table {d}")
+                self._keep.append(t)
+                tabs[d] = t
+        else:
+            kind = COEF_FIELD
+            field = _dev_f64(coef, self.device, int(torch.tensor(self.shape).prod()), "field")
+            self._keep.append(field)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        with torch.cuda.device(self.device):
+            check(lib().expi_op_create_stencil(ctypes.byref(self._h), dim, n, hh, BCS[bc], kind,
+                                               c0, c1, ptr(tabs[0]), ptr(tabs[1]), ptr(tabs[2]),
+                                               ptr(field)))
+
+
+class CsrOp(_Op):
+    """CSR matrix, int32 row pointers/column indices and float64 values."""
+
+    def __init__(self, n, rowptr, colind, val, device="cuda:0"):
+        super().__init__()
+        torch = _torch()
+        self.device = torch.device(device)
+        rp = torch.as_tensor(rowptr).to(device=self.device, dtype=torch.int32).contiguous()
+        ci = torch.as_tensor(colind).to(device=self.device, dtype=torch.int32).contiguous()
+        va = _dev_f64(val, self.device)
+        if rp.numel() != n + 1 or ci.numel() != va.numel():
+            raise ValueError("inconsistent CSR array sizes")
+        self._keep += [rp, ci, va]
+        self.nnz = int(va.numel())
+        check(lib().expi_op_create_csr(ctypes.byref(self._h), int(n), self.nnz,
+                                       ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()),
+                                       ctypes.c_void_p(va.data_ptr())))
+
+
+def workspace(nbytes: int, device="cuda:0"):
+    """Device byte buffer, 256-byte aligned, for phi_action/expeuler_step."""
+    torch = _torch()
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return ws
+
+
+def apply_op(op: _Op, alpha: float, beta: float, x, y=None, stream=None):
+    """y = (alpha A + beta I) x (eq. (3)); x float64 or float32 on the op's device."""
+    torch = _torch()
+    code = F32 if x.dtype == torch.float32 else F64
+    if y is None:
+        y = torch.empty_like(x)
+    check(lib().apply_op(op.handle, float(alpha), float(beta), ctypes.c_void_p(x.data_ptr()),
+                         ctypes.c_void_p(y.data_ptr()), code, _stream_ptr(stream, op.device)))
+    return y
+
+
+def phi_action(op: _Op, k: int, tau: float, v, y=None, tol: float = 1e-10, dtype="f64",
+               params: LejaParams | None = None, ws=None, stream=None):
+    """y = phi_k(tau A) v; returns (y, stats dict)."""
+    torch = _torch()
+    if y is None:
+        y = torch.empty_like(v)
+    code = _dtype_code(dtype)
+    if ws is None:
+        ws = op.workspace(code)
+    st = Stats()
+    cp = params.to_c() if params is not None else None
+    rc = lib().phi_action(op.handle, int(k), float(tau), ctypes.c_void_p(v.data_ptr()),
+                          ctypes.c_void_p(y.data_ptr()), float(tol), code,
+                          ctypes.byref(cp) if cp is not None else None,
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(st),
+                          _stream_ptr(stream, op.device))
+    check(rc)
+    return y, st.as_dict()
+
+
+def expeuler_step(op: _Op, tau: float, u, tol: float = 1e-10, dtype="f64",
+                  params: LejaParams | None = None, ws=None, stream=None):
+    """One exponential Euler step for u' = A u + u - u^3, in place on u; returns stats."""
+    code = _dtype_code(dtype)
+    if ws is None:
+        ws = op.workspace(code)
+    st = Stats()
+    cp = params.to_c() if params is not None else None
+    rc = lib().expeuler_step(op.handle, G_CUBIC, float(tau), ctypes.c_void_p(u.data_ptr()),
+                             float(tol), code, ctypes.byref(cp) if cp is not None else None,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(st),
+                             _stream_ptr(stream, op.device))
+    check(rc)
+    return st.as_dict()

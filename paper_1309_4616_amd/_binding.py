@@ -1,0 +1,141 @@
+"""ctypes binding of libexpi.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts Python and
+PyTorch arguments to the C ABI declared in include/expi.h and turns error
+codes into exceptions.  PyTorch provides device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexpi.so")
+
+EXPI_OK = 0
+ERRORS = {-1: "EINVAL", -2: "EALIAS", -3: "EWORKSPACE", -4: "ENOTCONV",
+          -5: "ENONFINITE", -6: "EHIP", -7: "EUNSUPPORTED"}
+F64, F32 = 0, 1
+BCS = {"dirichlet0": 0, "neumann0": 1, "interior_only": 2}
+COEF_CONST, COEF_SEPARABLE, COEF_FIELD = 0, 1, 2
+G_CUBIC = 0
+
+# every symbol include/expi.h declares
+EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "expi_op_size",
+           "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
+           "expeuler_step", "expi_leja_points", "expi_divided_differences", "expi_last_error")
+
+
+class ExpiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("substeps", ctypes.c_int32), ("newton_steps", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("retries", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("degree_max", ctypes.c_int32),
+                ("degree_last", ctypes.c_int32), ("timed_products", ctypes.c_int32),
+                ("err_est", ctypes.c_double), ("interval_a", ctypes.c_double),
+                ("interval_b", ctypes.c_double), ("newton_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("l_max", ctypes.c_double), ("m_max", ctypes.c_int32),
+                ("max_retries", ctypes.c_int32), ("have_interval", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("interval_a", ctypes.c_double),
+                ("interval_b", ctypes.c_double)]
+
+
+@dataclass
+class LejaParams:
+    l_max: float = 100.0
+    m_max: int = 100
+    max_retries: int = 4
+    interval: tuple | None = None
+    profile: bool = False
+
+    def to_c(self) -> Params:
+        p = Params()
+        p.l_max = float(self.l_max)
+        p.m_max = int(self.m_max)
+        p.max_retries = int(self.max_retries)
+        p.profile = 1 if self.profile else 0
+        if self.interval is not None:
+            p.have_interval = 1
+            p.interval_a, p.interval_b = (float(v) for v in self.interval)
+        return p
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libexpi.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1309_4616_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dblp = ctypes.POINTER(ctypes.c_double)
+    L.expi_op_create_stencil.argtypes = [ctypes.POINTER(c_void_p), c_int, i64p, dblp, c_int, c_int,
+                                         c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.expi_op_create_stencil.restype = c_int
+    L.expi_op_create_csr.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_int64, ctypes.c_int64,
+                                     c_void_p, c_void_p, c_void_p]
+    L.expi_op_create_csr.restype = c_int
+    L.expi_op_destroy.argtypes = [c_void_p]
+    L.expi_op_destroy.restype = c_int
+    L.expi_op_size.argtypes = [c_void_p]
+    L.expi_op_size.restype = ctypes.c_int64
+    L.expi_workspace_bytes.argtypes = [c_void_p, c_int]
+    L.expi_workspace_bytes.restype = c_size_t
+    L.expi_op_interval.argtypes = [c_void_p, dblp, dblp, c_void_p, c_size_t, c_void_p]
+    L.expi_op_interval.restype = c_int
+    L.apply_op.argtypes = [c_void_p, c_double, c_double, c_void_p, c_void_p, c_int, c_void_p]
+    L.apply_op.restype = c_int
+    L.phi_action.argtypes = [c_void_p, c_int, c_double, c_void_p, c_void_p, c_double, c_int,
+                             ctypes.POINTER(Params), c_void_p, c_size_t, ctypes.POINTER(Stats),
+                             c_void_p]
+    L.phi_action.restype = c_int
+    L.expeuler_step.argtypes = [c_void_p, c_int, c_double, c_void_p, c_double, c_int,
+                                ctypes.POINTER(Params), c_void_p, c_size_t, ctypes.POINTER(Stats),
+                                c_void_p]
+    L.expeuler_step.restype = c_int
+    L.expi_leja_points.argtypes = [dblp, c_int]
+    L.expi_leja_points.restype = c_int
+    L.expi_divided_differences.argtypes = [c_int, c_double, c_double, c_double, c_int, dblp]
+    L.expi_divided_differences.restype = c_int
+    L.expi_last_error.argtypes = []
+    L.expi_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != EXPI_OK:
+        raise ExpiError(rc, lib().expi_last_error().decode())
+
+
+def leja_points(count: int):
+    import numpy as np
+    out = np.empty(count, dtype=np.float64)
+    check(lib().expi_leja_points(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(count)))
+    return out
+
+
+def divided_differences(k: int, delta: float, c: float, gamma: float, count: int):
+    import numpy as np
+    out = np.empty(count, dtype=np.float64)
+    check(lib().expi_divided_differences(int(k), float(delta), float(c), float(gamma), int(count),
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out

@@ -1,0 +1,740 @@
+// C ABI and host driver of the hot path.
+//
+// phi_action / expeuler_step follow the interpolation scheme of Sec. II-C and
+// Sec. III-C of the paper: map the spectral interval [a, b] of A to [-2, 2]
+// (c = (a+b)/2, gamma = (b-a)/4), take s substeps of length delta = tau/s
+// with delta (b - a) <= l_max, and on each substep apply the Newton form of
+// the Leja interpolant of phi_k(delta A) to a start vector r:
+//
+//   w_0 = r,  p = d_0 w_0,
+//   w_{j+1} = ((A - cI)/gamma - xi_j I) w_j,  p += d_{j+1} w_{j+1},
+//
+// stopping after the first m >= 2 with t_{m-1} + t_m <= tol ||p||, where
+// t_j = |d_j| ||w_j||.  Substeps of phi_1 use y' = A y + v, y(0) = 0, so
+// y(t) = t phi_1(tA) v and y_{l+1} = y_l + delta phi_1(delta A)(A y_l + v).
+// The exponential Euler step of eq. (2), for u' = A u + g(u), equals
+// u + tau phi_1(tau A)(A u + g(u)); with substeps y_0 = u,
+// y_{l+1} = y_l + delta phi_1(delta A)(A y_l + g(u)), u_new = y_s.
+// A substep that has not met the stop test after m_max products doubles s
+// and restarts the call (up to max_retries times).
+//
+// Each product is one fused sweep (sweep.hip).  The stop test runs on the
+// device, so the host enqueues products ahead and reads a 64-byte status
+// record back to pinned memory only to decide when to stop enqueueing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <string>
+
+#include "expi_internal.h"
+#include "leja.h"
+
+namespace expi {
+
+namespace {
+
+thread_local std::string tl_error = "no error";
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));               \
+            return EXPI_EHIP;                                                           \
+        }                                                                               \
+    } while (0)
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t state, partials, w0, w1, p, y, total;
+};
+
+WsLayout layout(const Op& op, int dtype) {
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t n = (size_t)op.size;
+    const size_t tw = (dtype == EXPI_F32) ? 4 : 8;
+    L.state = take(256);
+    L.partials = take(partials_bytes(op));
+    L.w0 = take(n * tw);
+    L.w1 = take(n * tw);
+    L.p = take(n * tw);
+    L.y = take(n * 8);
+    L.total = off;
+    return L;
+}
+
+// ---- pinned read-back slots (per host thread) -----------------------------
+constexpr int kSlots = 64;
+
+struct HostCtx {
+    int device = -1;
+    NewtonState* pinned = nullptr;
+    hipEvent_t ev[kSlots];
+    bool inflight[kSlots];
+    int next = 0;
+    hipEvent_t tev[2 * kMaxLeja];   // timing events around Newton products
+    bool have_tev = false;
+};
+thread_local HostCtx tl_ctx;
+
+int ctx_init() {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (tl_ctx.device == dev && tl_ctx.pinned) return EXPI_OK;
+    HIP_TRY(hipHostMalloc((void**)&tl_ctx.pinned, kSlots * sizeof(NewtonState), hipHostMallocDefault));
+    for (int i = 0; i < kSlots; ++i) {
+        HIP_TRY(hipEventCreateWithFlags(&tl_ctx.ev[i], hipEventDisableTiming));
+        tl_ctx.inflight[i] = false;
+    }
+    tl_ctx.device = dev;
+    tl_ctx.next = 0;
+    tl_ctx.have_tev = false;
+    return EXPI_OK;
+}
+
+int timing_events() {
+    if (tl_ctx.have_tev) return EXPI_OK;
+    for (int i = 0; i < 2 * kMaxLeja; ++i) HIP_TRY(hipEventCreate(&tl_ctx.tev[i]));
+    tl_ctx.have_tev = true;
+    return EXPI_OK;
+}
+
+int readback(const NewtonState* st, hipStream_t s, int* slot_out) {
+    const int slot = tl_ctx.next;
+    tl_ctx.next = (tl_ctx.next + 1) % kSlots;
+    if (tl_ctx.inflight[slot]) {
+        HIP_TRY(hipEventSynchronize(tl_ctx.ev[slot]));
+        tl_ctx.inflight[slot] = false;
+    }
+    HIP_TRY(hipMemcpyAsync(&tl_ctx.pinned[slot], st, sizeof(NewtonState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(tl_ctx.ev[slot], s));
+    tl_ctx.inflight[slot] = true;
+    *slot_out = slot;
+    return EXPI_OK;
+}
+
+int wait_slot(int slot, NewtonState* out) {
+    HIP_TRY(hipEventSynchronize(tl_ctx.ev[slot]));
+    tl_ctx.inflight[slot] = false;
+    std::memcpy(out, &tl_ctx.pinned[slot], sizeof(NewtonState));
+    return EXPI_OK;
+}
+
+// ---- parameters ------------------------------------------------------------
+struct Params {
+    double l_max = 100.0;
+    int m_max = 100;
+    int max_retries = 4;
+    bool have_interval = false;
+    bool profile = false;
+    double ia = 0, ib = 0;
+};
+
+int read_params(const expi_params* p, Params* out) {
+    Params q;
+    if (p) {
+        q.l_max = p->l_max;
+        q.m_max = p->m_max;
+        q.max_retries = p->max_retries;
+        q.have_interval = p->have_interval != 0;
+        q.profile = p->profile != 0;
+        q.ia = p->interval_a;
+        q.ib = p->interval_b;
+    }
+    if (!(q.l_max > 0) || !std::isfinite(q.l_max)) return fail(EXPI_EINVAL, "params.l_max must be positive and finite");
+    if (q.m_max < 2 || q.m_max >= kMaxLeja) return fail(EXPI_EINVAL, "params.m_max must be in [2, 255]");
+    if (q.max_retries < 0 || q.max_retries > 30) return fail(EXPI_EINVAL, "params.max_retries must be in [0, 30]");
+    if (q.have_interval && !(std::isfinite(q.ia) && std::isfinite(q.ib) && q.ia < q.ib))
+        return fail(EXPI_EINVAL, "params interval must satisfy a < b, both finite");
+    *out = q;
+    return EXPI_OK;
+}
+
+bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+// ---- interval ----------------------------------------------------------------
+int op_interval(Op& op, double* a, double* b, char* ws, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> lock(op.mu);
+        if (op.have_interval) {
+            *a = op.ia;
+            *b = op.ib;
+            return EXPI_OK;
+        }
+    }
+    int rc = ctx_init();
+    if (rc) return rc;
+    const WsLayout L = layout(op, EXPI_F64);
+    NewtonState* st = reinterpret_cast<NewtonState*>(ws + L.state);
+    HIP_TRY(launch_reset(st, s));
+    SweepArgs args{};
+    args.st = st;
+    args.partials = reinterpret_cast<double*>(ws + L.partials);
+    HIP_TRY(launch_sweep(op, EPI_GERSH, 0, 0, args, s));
+    int slot;
+    rc = readback(st, s, &slot);
+    if (rc) return rc;
+    NewtonState h;
+    rc = wait_slot(slot, &h);
+    if (rc) return rc;
+    if (!std::isfinite(h.gmin) || !std::isfinite(h.gmax))
+        return fail(EXPI_ENONFINITE, "Gershgorin interval is not finite (operator entries inf/NaN?)");
+    std::lock_guard<std::mutex> lock(op.mu);
+    op.ia = h.gmin;
+    op.ib = h.gmax;
+    op.have_interval = true;
+    *a = op.ia;
+    *b = op.ib;
+    return EXPI_OK;
+}
+
+// ---- divided differences (cached per key) --------------------------------------
+typedef std::tuple<int, double, double, double, int> DdKey;
+
+std::vector<double> get_dd(Op& op, const DdKey& key) {
+    {
+        std::lock_guard<std::mutex> lock(op.mu);
+        auto it = op.dd_cache.find(key);
+        if (it != op.dd_cache.end()) return it->second;
+    }
+    std::vector<double> d(std::get<4>(key));
+    divided_differences(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key),
+                        (int)d.size(), d.data());
+    std::lock_guard<std::mutex> lock(op.mu);
+    if (op.dd_cache.size() > 64) op.dd_cache.clear();
+    op.dd_cache.emplace(key, d);
+    return d;
+}
+
+int get_hint(Op& op, const DdKey& key) {
+    std::lock_guard<std::mutex> lock(op.mu);
+    auto it = op.degree_hint.find(key);
+    return it == op.degree_hint.end() ? 0 : it->second;
+}
+
+void set_hint(Op& op, const DdKey& key, int m) {
+    std::lock_guard<std::mutex> lock(op.mu);
+    if (op.degree_hint.size() > 256) op.degree_hint.clear();
+    op.degree_hint[key] = m;
+}
+
+// ---- one Newton loop -----------------------------------------------------------
+struct LoopOut {
+    int m = 0;
+    int done = 0;
+    double err = 0;
+    int timed = 0;        // products timed (profile mode)
+    double ms = 0;        // their summed device time
+};
+
+struct Ctx {
+    Op* op;
+    int tw;                 // storage code of w, p: 0 double, 1 float
+    char* ws;
+    WsLayout L;
+    NewtonState* st;
+    double* partials;
+    hipStream_t s;
+    const double* xi;
+    std::vector<double> d;
+    double c, gamma, tol;
+    int m_max;
+    DdKey key;
+    bool profile;
+};
+
+// First product reads `src` (storage code tin) and writes w_1 to w0 and p to
+// `p`; products j >= 1 alternate between w0 and w1.
+int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
+    const std::vector<double>& d = C.d;
+    void* w[2] = {C.ws + C.L.w0, C.ws + C.L.w1};
+    SweepArgs a{};
+    a.st = C.st;
+    a.partials = C.partials;
+    a.tol = C.tol;
+    a.alpha = 1.0 / C.gamma;
+    a.p = p;
+    a.x = src;
+    a.out = w[0];
+    a.j = 0;
+    a.beta = -(C.c / C.gamma + C.xi[0]);
+    a.d0 = d[0];
+    a.d1 = d[1];
+    a.guard = 0;
+    HIP_TRY(launch_sweep(*C.op, EPI_FIRST, tin, C.tw, a, C.s));
+
+    const int hint = get_hint(*C.op, C.key);
+    int j = 1;
+    // With a degree hint the first batch ends exactly at the expected stop and
+    // later products go one by one; without one, batches of 4 then 2 run one
+    // batch ahead of the status read-back.
+    int chunk = hint >= 2 ? hint - 1 : 4;
+    const bool ahead = hint < 2;
+    std::deque<int> pending;
+    NewtonState last{};
+    bool finished = false;
+    while (!finished) {
+        if (j < C.m_max) {
+            const int cnt = std::min(chunk, C.m_max - j);
+            for (int q = 0; q < cnt; ++q, ++j) {
+                a.x = w[(j - 1) & 1];
+                a.out = w[j & 1];
+                a.j = j;
+                a.beta = -(C.c / C.gamma + C.xi[j]);
+                a.d1 = d[j + 1];
+                a.guard = 1;
+                if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
+                HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s));
+                if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j + 1], C.s));
+            }
+            int slot;
+            int rc = readback(C.st, C.s, &slot);
+            if (rc) return rc;
+            pending.push_back(slot);
+            chunk = ahead ? 2 : 1;
+        }
+        const size_t keep = ahead ? 1 : 0;
+        while (!pending.empty() && (pending.size() > keep || j >= C.m_max)) {
+            int rc = wait_slot(pending.front(), &last);
+            if (rc) return rc;
+            pending.pop_front();
+            if (last.done) {
+                finished = true;
+                break;
+            }
+        }
+        if (!finished && pending.empty() && j >= C.m_max) finished = true;
+    }
+    out->m = last.m;
+    out->done = last.done;
+    out->err = last.err;
+    if (last.done == 1) set_hint(*C.op, C.key, last.m);
+    if (C.profile && last.done != 2) {
+        // products 1..m-1 did work and precede the read-back that ended the loop
+        for (int q = 1; q < last.m; ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, tl_ctx.tev[2 * q], tl_ctx.tev[2 * q + 1]));
+            out->ms += ms;
+            out->timed += 1;
+        }
+    }
+    return EXPI_OK;
+}
+
+void stats_add(expi_stats* st, const LoopOut& lo) {
+    st->newton_steps += lo.m;
+    st->matvecs += lo.m;
+    st->degree_max = std::max(st->degree_max, lo.m);
+    st->degree_last = lo.m;
+    st->err_est = std::max(st->err_est, lo.err);
+    st->timed_products += lo.timed;
+    st->newton_ms += lo.ms;
+}
+
+int common_setup(Op& op, double tau, double tol, int dtype, const Params& P, char* ws,
+                 hipStream_t s, double* ia, double* ib) {
+    (void)tau;
+    (void)tol;
+    (void)dtype;
+    int rc = ctx_init();
+    if (rc) return rc;
+    if (P.profile) {
+        rc = timing_events();
+        if (rc) return rc;
+    }
+    if (P.have_interval) {
+        *ia = P.ia;
+        *ib = P.ib;
+    } else {
+        rc = op_interval(op, ia, ib, ws, s);
+        if (rc) return rc;
+    }
+    if (!(*ia < *ib))
+        return fail(EXPI_EINVAL, "degenerate spectral interval (a >= b); pass one in params");
+    return EXPI_OK;
+}
+
+int substep_count(double tau, double a, double b, double l_max) {
+    const double q = std::ceil(tau * (b - a) / l_max);
+    if (!(q >= 1.0)) return 1;
+    if (q > 1e8) return 100000000;
+    return (int)q;
+}
+
+int validate_call(const expi_op* op, double tau, double tol, int dtype, void* ws, size_t ws_bytes) {
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    if (!(tau >= 0) || !std::isfinite(tau)) return fail(EXPI_EINVAL, "tau must be finite and >= 0");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(EXPI_EINVAL, "tol must be finite and > 0");
+    if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
+    if (!ws) return fail(EXPI_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(EXPI_EWORKSPACE, "workspace must be 256-byte aligned");
+    const size_t need = layout(*reinterpret_cast<const Op*>(op), dtype).total;
+    if (ws_bytes < need)
+        return fail(EXPI_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    return EXPI_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { tl_error = msg; }
+
+// ---- phi_action -------------------------------------------------------------------
+static int run_phi(Op& op, int k, double tau, const double* v, double* y, double tol, int dtype,
+                   const Params& P, char* ws, expi_stats* st, hipStream_t s) {
+    double ia, ib;
+    int rc = common_setup(op, tau, tol, dtype, P, ws, s, &ia, &ib);
+    if (rc) return rc;
+    const double c = 0.5 * (ia + ib), gamma = 0.25 * (ib - ia);
+    const int count = P.m_max + 1;
+    const double* xi = leja_points(count);
+    const int tw = (dtype == EXPI_F32) ? 1 : 0;
+    const WsLayout L = layout(op, dtype);
+    const int64_t n = op.size;
+    int sub = substep_count(tau, ia, ib, P.l_max);
+    if (k >= 2 && sub > 1)
+        return fail(EXPI_EUNSUPPORTED, "phi_k with k >= 2 needs a single substep (tau (b-a) <= l_max)");
+    Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
+          reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
+          P.profile};
+    expi_stats acc{};
+    for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
+        if (k >= 2 && sub > 1)
+            return fail(EXPI_EUNSUPPORTED, "phi_k with k >= 2 needs a single substep");
+        const double delta = tau / sub;
+        C.key = DdKey(k, delta, c, gamma, count);
+        C.d = get_dd(op, C.key);
+        acc = expi_stats{};
+        acc.substeps = sub;
+        acc.retries = attempt;
+        acc.interval_a = ia;
+        acc.interval_b = ib;
+        HIP_TRY(launch_reset(C.st, s));
+        bool ok = true;
+        for (int l = 0; l < sub && ok; ++l) {
+            // p goes straight into y when y is the result and has p's type
+            const bool p_in_y = (sub == 1 && tw == 0);
+            void* p = p_in_y ? (void*)y : (void*)(ws + L.p);
+            const void* src;
+            int tin;
+            if (k == 1 && l > 0) {
+                // r = A y_l + v with y_l = tau * y' (y' = y_l / tau is kept in y)
+                SweepArgs a{};
+                a.x = y;
+                a.out = ws + L.w1;
+                a.g = v;
+                a.gmode = G_VEC;
+                a.sigma = tau;
+                HIP_TRY(launch_sweep(op, EPI_START, 0, tw, a, s));
+                acc.matvecs += 1;
+                src = ws + L.w1;
+                tin = tw;
+            } else if (k != 1 && l > 0) {
+                src = y;   // previous substep's result, copied into y below
+                tin = 0;
+            } else {
+                src = v;
+                tin = 0;
+            }
+            LoopOut lo;
+            rc = newton_loop(C, src, tin, p, &lo);
+            if (rc) return rc;
+            stats_add(&acc, lo);
+            if (lo.done == 2) return fail(EXPI_ENONFINITE, "a norm became inf/NaN (non-finite input?)");
+            if (lo.done != 1) {
+                ok = false;
+                break;
+            }
+            if (!p_in_y) {
+                if (k == 1) {
+                    // y' <- y' + p / s   (y' = 0 before the first substep)
+                    HIP_TRY(launch_update(n, y, l == 0 ? nullptr : y, p, tw, 1.0 / sub, C.st, 1, s));
+                } else {
+                    // e^{delta A} (or phi_k, single substep) applied: y <- p
+                    HIP_TRY(launch_update(n, y, nullptr, p, tw, 1.0, C.st, 1, s));
+                }
+            }
+        }
+        acc.converged = ok ? 1 : 0;
+        if (ok) {
+            if (st) *st = acc;
+            return EXPI_OK;
+        }
+        sub *= 2;
+        if (k >= 2) break;
+    }
+    if (st) *st = acc;
+    return fail(EXPI_ENOTCONV, "no convergence within m_max products after all substep doublings");
+}
+
+static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, int dtype,
+                        const Params& P, char* ws, expi_stats* st, hipStream_t s) {
+    (void)nonlin;
+    double ia, ib;
+    int rc = common_setup(op, tau, tol, dtype, P, ws, s, &ia, &ib);
+    if (rc) return rc;
+    const double c = 0.5 * (ia + ib), gamma = 0.25 * (ib - ia);
+    const int count = P.m_max + 1;
+    const double* xi = leja_points(count);
+    const int tw = (dtype == EXPI_F32) ? 1 : 0;
+    const WsLayout L = layout(op, dtype);
+    const int64_t n = op.size;
+    int sub = substep_count(tau, ia, ib, P.l_max);
+    Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
+          reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
+          P.profile};
+    double* yb = reinterpret_cast<double*>(ws + L.y);
+    void* p = ws + L.p;
+    expi_stats acc{};
+    for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
+        const double delta = tau / sub;
+        C.key = DdKey(1, delta, c, gamma, count);
+        C.d = get_dd(op, C.key);
+        acc = expi_stats{};
+        acc.substeps = sub;
+        acc.retries = attempt;
+        acc.interval_a = ia;
+        acc.interval_b = ib;
+        HIP_TRY(launch_reset(C.st, s));
+        bool ok = true;
+        for (int l = 0; l < sub && ok; ++l) {
+            // r = A y_l + g(u), y_0 = u
+            SweepArgs a{};
+            a.x = (l == 0) ? (const void*)u : (const void*)yb;
+            a.out = ws + L.w1;
+            a.g = u;
+            a.gmode = (l == 0) ? G_CUBIC_SELF : G_CUBIC_OF;
+            a.sigma = 1.0;
+            HIP_TRY(launch_sweep(op, EPI_START, 0, tw, a, s));
+            acc.matvecs += 1;
+            LoopOut lo;
+            rc = newton_loop(C, ws + L.w1, tw, p, &lo);
+            if (rc) return rc;
+            stats_add(&acc, lo);
+            if (lo.done == 2) return fail(EXPI_ENONFINITE, "a norm became inf/NaN (non-finite input?)");
+            if (lo.done != 1) {
+                ok = false;
+                break;
+            }
+            // y_{l+1} = y_l + delta p; the last substep writes u
+            const double* yin = (l == 0) ? u : yb;
+            double* yout = (l == sub - 1) ? u : yb;
+            HIP_TRY(launch_update(n, yout, yin, p, tw, delta, C.st, 1, s));
+        }
+        acc.converged = ok ? 1 : 0;
+        if (ok) {
+            if (st) *st = acc;
+            return EXPI_OK;
+        }
+        sub *= 2;
+    }
+    if (st) *st = acc;
+    return fail(EXPI_ENOTCONV, "no convergence within m_max products after all substep doublings");
+}
+
+}  // namespace expi
+
+using namespace expi;
+
+extern "C" {
+
+const char* expi_last_error(void) { return tl_error.c_str(); }
+
+int expi_op_create_stencil(expi_op** op, int dim, const int64_t* n, const double* h, int bc,
+                           int coef_kind, double c0, double c1, const double* tab_x,
+                           const double* tab_y, const double* tab_z, const double* field) {
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    *op = nullptr;
+    if (dim != 2 && dim != 3) return fail(EXPI_EINVAL, "dim must be 2 or 3");
+    if (!n || !h) return fail(EXPI_EINVAL, "n and h must be non-NULL");
+    int64_t total = 1;
+    for (int d = 0; d < dim; ++d) {
+        if (n[d] < 1) return fail(EXPI_EINVAL, "grid sizes must be >= 1");
+        if (!(h[d] > 0) || !std::isfinite(h[d])) return fail(EXPI_EINVAL, "grid spacings must be finite and > 0");
+        total *= n[d];
+        // marched indices run one plane past the grid, so stay well inside int32
+        if (total >= ((int64_t)1 << 30)) return fail(EXPI_EINVAL, "grid has 2^30 points or more");
+    }
+    if (bc != EXPI_DIRICHLET0 && bc != EXPI_NEUMANN0 && bc != EXPI_INTERIOR_ONLY)
+        return fail(EXPI_EINVAL, "unknown boundary condition");
+    if (!std::isfinite(c0) || !std::isfinite(c1)) return fail(EXPI_EINVAL, "c0, c1 must be finite");
+    if (coef_kind == EXPI_COEF_SEPARABLE) {
+        if (!tab_x || !tab_y || (dim == 3 && !tab_z))
+            return fail(EXPI_EINVAL, "separable coefficient needs tab_x, tab_y (and tab_z in 3D)");
+    } else if (coef_kind == EXPI_COEF_FIELD) {
+        if (!field) return fail(EXPI_EINVAL, "field coefficient needs a field pointer");
+    } else if (coef_kind != EXPI_COEF_CONST) {
+        return fail(EXPI_EINVAL, "unknown coefficient kind");
+    }
+    Op* o = new Op();
+    o->kind = 0;
+    o->dim = dim;
+    for (int d = 0; d < 3; ++d) {
+        o->n[d] = d < dim ? (int)n[d] : 1;
+        o->h[d] = d < dim ? h[d] : 1.0;
+    }
+    o->bc = bc;
+    o->coef = coef_kind;
+    o->c0 = c0;
+    o->c1 = (coef_kind == EXPI_COEF_SEPARABLE) ? c1 : 0.0;
+    o->tx = tab_x;
+    o->ty = tab_y;
+    o->tz = tab_z;
+    o->field = field;
+    o->nrows = o->nnz = 0;
+    o->rowptr = o->colind = nullptr;
+    o->val = nullptr;
+    o->size = total;
+    o->plan = make_plan(*o);
+    *op = reinterpret_cast<expi_op*>(o);
+    return EXPI_OK;
+}
+
+int expi_op_create_csr(expi_op** op, int64_t n, int64_t nnz, const int32_t* rowptr,
+                       const int32_t* colind, const double* val) {
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    *op = nullptr;
+    if (n < 1 || n >= ((int64_t)1 << 31) - 1) return fail(EXPI_EINVAL, "n must be in [1, 2^31-2]");
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return fail(EXPI_EINVAL, "nnz must be in [0, 2^31)");
+    if (!rowptr || (nnz > 0 && (!colind || !val))) return fail(EXPI_EINVAL, "CSR arrays must be non-NULL");
+    Op* o = new Op();
+    o->kind = 1;
+    o->dim = 0;
+    for (int d = 0; d < 3; ++d) {
+        o->n[d] = 1;
+        o->h[d] = 1.0;
+    }
+    o->bc = 0;
+    o->coef = 0;
+    o->c0 = o->c1 = 0;
+    o->tx = o->ty = o->tz = o->field = nullptr;
+    o->nrows = n;
+    o->nnz = nnz;
+    o->rowptr = rowptr;
+    o->colind = colind;
+    o->val = val;
+    o->size = n;
+    o->plan = make_plan(*o);
+    *op = reinterpret_cast<expi_op*>(o);
+    return EXPI_OK;
+}
+
+int expi_op_destroy(expi_op* op) {
+    delete reinterpret_cast<Op*>(op);
+    return EXPI_OK;
+}
+
+int64_t expi_op_size(const expi_op* op) {
+    return op ? reinterpret_cast<const Op*>(op)->size : -1;
+}
+
+size_t expi_workspace_bytes(const expi_op* op, int dtype) {
+    if (!op || (dtype != EXPI_F64 && dtype != EXPI_F32)) return 0;
+    return layout(*reinterpret_cast<const Op*>(op), dtype).total;
+}
+
+int expi_op_interval(expi_op* op, double* a, double* b, void* ws, size_t ws_bytes, void* stream) {
+    if (!op || !a || !b) return fail(EXPI_EINVAL, "op, a, b must be non-NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    {
+        std::lock_guard<std::mutex> lock(o.mu);
+        if (o.have_interval) {
+            *a = o.ia;
+            *b = o.ib;
+            return EXPI_OK;
+        }
+    }
+    if (!ws) return fail(EXPI_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(EXPI_EWORKSPACE, "workspace must be 256-byte aligned");
+    const WsLayout L = layout(o, EXPI_F64);
+    if (ws_bytes < L.partials + partials_bytes(o)) return fail(EXPI_EWORKSPACE, "workspace too small");
+    return op_interval(o, a, b, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+int apply_op(const expi_op* op, double alpha, double beta, const void* x, void* y, int dtype,
+             void* stream) {
+    if (!op || !x || !y) return fail(EXPI_EINVAL, "op, x, y must be non-NULL");
+    if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(EXPI_EINVAL, "alpha, beta must be finite");
+    const Op& o = *reinterpret_cast<const Op*>(op);
+    const size_t bytes = (size_t)o.size * (dtype == EXPI_F32 ? 4 : 8);
+    if (overlap(x, bytes, y, bytes)) return fail(EXPI_EALIAS, "y overlaps x");
+    SweepArgs a{};
+    a.x = x;
+    a.out = y;
+    a.alpha = alpha;
+    a.beta = beta;
+    const int t = dtype == EXPI_F32 ? 1 : 0;
+    HIP_TRY(launch_sweep(o, EPI_APPLY, t, t, a, static_cast<hipStream_t>(stream)));
+    return EXPI_OK;
+}
+
+int phi_action(expi_op* op, int k, double tau, const double* v, double* y, double tol, int dtype,
+               const expi_params* params, void* ws, size_t ws_bytes, expi_stats* st, void* stream) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    int rc = validate_call(op, tau, tol, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (k < 0 || k > 20) return fail(EXPI_EINVAL, "k must be in [0, 20]");
+    if (!v || !y) return fail(EXPI_EINVAL, "v, y must be non-NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    const size_t bytes = (size_t)o.size * 8;
+    if (overlap(v, bytes, y, bytes)) return fail(EXPI_EALIAS, "y overlaps v");
+    if (overlap(ws, ws_bytes, v, bytes) || overlap(ws, ws_bytes, y, bytes))
+        return fail(EXPI_EALIAS, "workspace overlaps v or y");
+    Params P;
+    rc = read_params(params, &P);
+    if (rc) return rc;
+    return run_phi(o, k, tau, v, y, tol, dtype, P, static_cast<char*>(ws), st,
+                   static_cast<hipStream_t>(stream));
+}
+
+int expeuler_step(expi_op* op, int nonlin, double tau, double* u, double tol, int dtype,
+                  const expi_params* params, void* ws, size_t ws_bytes, expi_stats* st,
+                  void* stream) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    int rc = validate_call(op, tau, tol, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (nonlin != EXPI_G_CUBIC) return fail(EXPI_EINVAL, "nonlin must be EXPI_G_CUBIC");
+    if (!u) return fail(EXPI_EINVAL, "u must be non-NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    if (overlap(ws, ws_bytes, u, (size_t)o.size * 8)) return fail(EXPI_EALIAS, "workspace overlaps u");
+    Params P;
+    rc = read_params(params, &P);
+    if (rc) return rc;
+    return run_expeuler(o, nonlin, tau, u, tol, dtype, P, static_cast<char*>(ws), st,
+                        static_cast<hipStream_t>(stream));
+}
+
+int expi_leja_points(double* out, int count) {
+    if (!out || count < 1 || count > kMaxLeja) return fail(EXPI_EINVAL, "count must be in [1, 256]");
+    const double* xi = leja_points(count);
+    std::memcpy(out, xi, sizeof(double) * count);
+    return EXPI_OK;
+}
+
+int expi_divided_differences(int k, double delta, double c, double gamma, int count, double* out) {
+    if (!out || count < 1 || count > kMaxLeja) return fail(EXPI_EINVAL, "count must be in [1, 256]");
+    if (k < 0 || k > 20) return fail(EXPI_EINVAL, "k must be in [0, 20]");
+    if (!std::isfinite(delta) || !std::isfinite(c) || !std::isfinite(gamma))
+        return fail(EXPI_EINVAL, "delta, c, gamma must be finite");
+    divided_differences(k, delta, c, gamma, count, out);
+    return EXPI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/expi.h"
+
+namespace expi {
+
+// ---------------------------------------------------------------------------
+// Device-side status of one Newton loop (lives at the start of the workspace).
+// Written by the last workgroup of each fused sweep; read back by the host.
+// ---------------------------------------------------------------------------
+struct alignas(64) NewtonState {
+    unsigned int arrive;  // workgroups of the running sweep that have finished
+    int done;             // 0 running, 1 stop test met, 2 non-finite norm
+    int m;                // products taken in this loop
+    int pad;
+    double t_prev;        // |d_m| ||w_m|| of the latest product
+    double err;           // (t_{m-1} + t_m) / ||p|| at the latest test
+    double pnorm;         // ||p||
+    double wnorm;         // ||w_m||
+    double gmin, gmax;    // Gershgorin reduction result
+};
+static_assert(sizeof(NewtonState) == 64, "status record is 64 bytes");
+
+// Epilogues of the fused sweep.
+enum Epilogue : int {
+    EPI_APPLY = 0,   // y = alpha A x + beta x
+    EPI_NEWTON = 1,  // w' = alpha A w + beta w; p += d1 w'; norms; stop test
+    EPI_FIRST = 2,   // w' = alpha A w + beta w; p = d0 w + d1 w'; norms
+    EPI_START = 3,   // r = sigma A x + g
+    EPI_GERSH = 4,   // per-row Gershgorin bounds, min/max over rows
+};
+
+// Source of g in EPI_START.
+enum GMode : int { G_VEC = 0, G_CUBIC_OF = 1, G_CUBIC_SELF = 2 };
+
+struct SweepArgs {
+    const void* x;        // input vector (stencil source)
+    void* out;            // w_{j+1}, y or r
+    void* p;              // running Newton sum
+    const double* g;      // EPI_START: v (G_VEC) or u_n (G_CUBIC_OF)
+    const double* tx;     // separable coefficient tables
+    const double* ty;
+    const double* tz;
+    const double* field;  // coefficient field
+    double* partials;     // [gridDim.x][4]
+    NewtonState* st;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* val;
+    double c0, c1;
+    double ih2[3];        // 1/h_d^2
+    double alpha, beta, d0, d1, sigma, tol;
+    int n[3];             // grid sizes (x, y, z); CSR: n[0] = rows
+    int nnz;              // CSR stored entries
+    int bc;
+    int j;                // Newton index of this product
+    int guard;            // 1: the sweep does nothing once st->done != 0
+    int gmode;
+    int tiles[3];
+    int ntiles;
+    int per_xcd;          // tiles per XCD slot
+};
+
+// Launch geometry of an operator's sweeps.
+struct Plan {
+    int grid;             // workgroups launched (multiple of 8)
+    int tiles[3];
+    int ntiles;
+    int per_xcd;
+};
+
+struct Op {
+    int kind;             // 0 stencil, 1 CSR
+    int dim;
+    int n[3];
+    double h[3];
+    int bc;
+    int coef;
+    double c0, c1;
+    const double *tx, *ty, *tz, *field;
+    int64_t nrows, nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* val;
+    int64_t size;
+    Plan plan;
+    std::mutex mu;
+    bool have_interval = false;
+    double ia = 0, ib = 0;
+    // divided differences keyed by (k, delta, c, gamma, count)
+    std::map<std::tuple<int, double, double, double, int>, std::vector<double>> dd_cache;
+    // Newton degree last seen for a key, used to size the first chunk
+    std::map<std::tuple<int, double, double, double, int>, int> degree_hint;
+};
+
+constexpr int kXcd = 8;          // XCDs of gfx950; workgroup b runs on XCD b % 8
+constexpr int kBlock = 256;      // threads per workgroup (4 waves of 64)
+constexpr int kMarchZ = 16;      // planes marched per 3D thread column
+constexpr int kMarchY = 8;       // rows marched per 2D thread column
+constexpr int kCsrGroup = 8;     // lanes per CSR row
+
+Plan make_plan(const Op& op);
+size_t partials_bytes(const Op& op);
+
+// Launchers (sweep.hip).  TIN/TOUT codes: 0 = double, 1 = float.
+hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a,
+                        hipStream_t s);
+hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
+                         double scale, NewtonState* st, int guard, hipStream_t s);
+hipError_t launch_reset(NewtonState* st, hipStream_t s);
+
+// Error reporting (api.hip).
+void set_error(const std::string& msg);
+
+}  // namespace expi

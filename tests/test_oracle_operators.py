@@ -188,3 +188,19 @@ def test_rgg_laplacian_brute_force():
     assert np.array_equal(np.diag(A), -adj.sum(axis=1).astype(float))
     lo, hi = O.gershgorin_interval(O.csr_matrix(g.n, g.rowptr, g.colind, g.val))
     assert lo == -2 * adj.sum(axis=1).max() and hi == 0.0
+
+
+@pytest.mark.parametrize("bc", ["dirichlet0", "neumann0", "interior_only"])
+@pytest.mark.parametrize("shape", [(9, 7), (6, 5, 8)])
+def test_apply_at_matches_assembled_matrix(bc, shape):
+    rng = np.random.default_rng(17)
+    n = int(np.prod(shape))
+    h = tuple(0.1 * (d + 1) for d in range(len(shape)))
+    coef = 1 + 0.5 * rng.uniform(size=n)
+    u = rng.standard_normal(n)
+    pts = rng.choice(n, size=40, replace=False)
+    for c in (None, 2.0, coef):
+        A = O.stencil_matrix(shape, h, bc, coef=c)
+        want = (A @ u)[pts]
+        got = O.apply_at(shape, h, bc, u, pts, coef=c)
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
