@@ -50,6 +50,32 @@ def step_bytes_per_pt(m: int, dt: str) -> int:
     return start + first + (m - 1) * newton + update
 
 
+def counter_traffic(kernel_sub: str):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 summary
+    under profiles/ (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of
+    known size), or None if no summary covers it or its source files have
+    changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*.md"))):
+        text = open(path).read()
+        if "```json" not in text:
+            continue
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if kernel_sub not in blob.get("kernel", ""):
+            continue
+        h = hashlib.sha256()
+        try:
+            for f in blob["source_files"]:
+                h.update(open(os.path.join(HERE, f), "rb").read())
+        except OSError:
+            return None
+        if h.hexdigest() != blob.get("source_sha256"):
+            return None
+        return {"bytes": blob["traffic_bytes_per_launch"], "profile": os.path.relpath(path, HERE)}
+    return None
+
+
 def run_gpu(args, dtype: str):
     import torch
     import paper_1309_4616_amd as E
@@ -148,6 +174,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy a 512 MiB float64 tensor 3 times (a kernel of known "
+                         "traffic, 512 MiB read + 512 MiB written per launch) to calibrate "
+                         "hardware byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -161,6 +191,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] f64: {args.warmup} warmup + {args.steps} timed steps at {args.n}^3", file=sys.stderr, flush=True)
     r64 = run_gpu(args, "f64")
     print(f"[bench] f64 done: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -174,6 +211,7 @@ def main():
         cpu = cpu_baseline(args)
 
     n = args.n
+    traffic = counter_traffic("stencil_sweep<3, 1, 1, double, double, 2>") if n == 256 else None
     out = {
         "metric": METRIC,
         "value": r64["value"],
@@ -207,7 +245,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r64["newton_gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_unit": "HBM bytes per launch",
+            "traffic_source": traffic["profile"] if traffic else None,
+            "algorithmic_bytes_per_launch": NEWTON_BYTES_PER_PT["f64"] * n ** 3,
             "bytes_per_point": NEWTON_BYTES_PER_PT["f64"],
             "avg_launch_us": r64["newton_avg_us"],
             "launches_timed": r64["newton_timed"],

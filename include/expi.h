@@ -91,9 +91,10 @@ typedef struct {
     double  err_est;        /* largest (t_{m-1} + t_m)/||p|| over the substeps  */
     double  interval_a;     /* spectral interval [a, b] used                    */
     double  interval_b;
-    double  newton_ms;      /* summed device time of those products (HIP events
-                               recorded on `stream` around each launch); only
-                               products that did work (index < m) are counted */
+    double  newton_ms;      /* summed device time of those products' sweep
+                               kernels (HIP events recorded on `stream` around
+                               each sweep launch); only products that did work
+                               (index < m) are counted */
 } expi_stats;
 
 /* Interpolation parameters; pass NULL for the defaults
@@ -136,6 +137,17 @@ int expi_op_destroy(expi_op *op);
 
 /* Number of unknowns of the operator. */
 int64_t expi_op_size(const expi_op *op);
+
+/* Tile setting of the operator's sweeps (the autotuner's knob; results do
+ * not depend on it beyond rounding order).  Stencils: vec = x points per
+ * thread (1 or 2; 2 needs an even x size and 16-byte aligned arrays, else 1
+ * is used), waves = 64-thread waves per workgroup (1..8, rows of a 3D tile),
+ * march = points each thread marches along the slowest axis (4..256, a
+ * multiple of 4).
+ * CSR: vec = lanes per row (4, 8 or 16), waves (1..8), march = 1.
+ * EXPI_EINVAL for anything else.  The workspace size does not depend on it. */
+int expi_op_set_tiles(expi_op *op, int vec, int waves, int march);
+int expi_op_get_tiles(const expi_op *op, int *vec, int *waves, int *march);
 
 /* Bytes of device workspace phi_action / expeuler_step / expi_op_interval
  * need for this operator and storage dtype (EXPI_F64 or EXPI_F32). */

@@ -77,6 +77,15 @@ class _Op:
             self._ws[code] = ws
         return ws
 
+    def set_tiles(self, vec: int, waves: int, march: int) -> None:
+        """Tile setting of the operator's sweeps (see expi_op_set_tiles)."""
+        check(lib().expi_op_set_tiles(self._h, int(vec), int(waves), int(march)))
+
+    def tiles(self) -> tuple:
+        v, w, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().expi_op_get_tiles(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(m)))
+        return v.value, w.value, m.value
+
     def interval(self, stream=None):
         a, b = ctypes.c_double(), ctypes.c_double()
         ws = self.workspace("f64")

@@ -23,7 +23,7 @@ G_CUBIC = 0
 
 # every symbol include/expi.h declares
 EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "expi_op_size",
-           "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
+           "expi_op_set_tiles", "expi_op_get_tiles", "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
            "expeuler_step", "expi_leja_points", "expi_divided_differences", "expi_last_error")
 
 
@@ -97,6 +97,11 @@ def lib() -> ctypes.CDLL:
     L.expi_op_destroy.restype = c_int
     L.expi_op_size.argtypes = [c_void_p]
     L.expi_op_size.restype = ctypes.c_int64
+    L.expi_op_set_tiles.argtypes = [c_void_p, c_int, c_int, c_int]
+    L.expi_op_set_tiles.restype = c_int
+    ip = ctypes.POINTER(c_int)
+    L.expi_op_get_tiles.argtypes = [c_void_p, ip, ip, ip]
+    L.expi_op_get_tiles.restype = c_int
     L.expi_workspace_bytes.argtypes = [c_void_p, c_int]
     L.expi_workspace_bytes.restype = c_size_t
     L.expi_op_interval.argtypes = [c_void_p, dblp, dblp, c_void_p, c_size_t, c_void_p]

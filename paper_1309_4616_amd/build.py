@@ -28,7 +28,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
-HIP_SOURCES = ["sweep.hip", "api.hip"]
+HIP_SOURCES = ["stencil.hip", "csr.hip", "sweep.hip", "api.hip"]
 CXX_SOURCES = ["leja.cpp"]
 
 
@@ -52,7 +52,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         jobs.append(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    with ThreadPoolExecutor(max_workers=min(len(jobs), 4)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(jobs), 8)) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:

@@ -301,8 +301,8 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
                 a.d1 = d[j + 1];
                 a.guard = 1;
                 if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
-                HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s));
-                if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j + 1], C.s));
+                HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s,
+                                     C.profile ? tl_ctx.tev[2 * j + 1] : nullptr));
             }
             int slot;
             int rc = readback(C.st, C.s, &slot);
@@ -601,7 +601,7 @@ int expi_op_create_stencil(expi_op** op, int dim, const int64_t* n, const double
     o->rowptr = o->colind = nullptr;
     o->val = nullptr;
     o->size = total;
-    o->plan = make_plan(*o);
+    o->tiles = default_tiles(*o);
     *op = reinterpret_cast<expi_op*>(o);
     return EXPI_OK;
 }
@@ -630,7 +630,7 @@ int expi_op_create_csr(expi_op** op, int64_t n, int64_t nnz, const int32_t* rowp
     o->colind = colind;
     o->val = val;
     o->size = n;
-    o->plan = make_plan(*o);
+    o->tiles = default_tiles(*o);
     *op = reinterpret_cast<expi_op*>(o);
     return EXPI_OK;
 }
@@ -642,6 +642,28 @@ int expi_op_destroy(expi_op* op) {
 
 int64_t expi_op_size(const expi_op* op) {
     return op ? reinterpret_cast<const Op*>(op)->size : -1;
+}
+
+int expi_op_set_tiles(expi_op* op, int vec, int waves, int march) {
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    Tiles t;
+    t.vec = vec;
+    t.waves = waves;
+    t.march = march;
+    if (!tiles_valid(o, t)) return fail(EXPI_EINVAL, "tile setting out of range for this operator");
+    std::lock_guard<std::mutex> lock(o.mu);
+    o.tiles = t;
+    return EXPI_OK;
+}
+
+int expi_op_get_tiles(const expi_op* op, int* vec, int* waves, int* march) {
+    if (!op || !vec || !waves || !march) return fail(EXPI_EINVAL, "NULL argument");
+    const Op& o = *reinterpret_cast<const Op*>(op);
+    *vec = o.tiles.vec;
+    *waves = o.tiles.waves;
+    *march = o.tiles.march;
+    return EXPI_OK;
 }
 
 size_t expi_workspace_bytes(const expi_op* op, int dtype) {

@@ -1,0 +1,134 @@
+// CSR sweeps (Sec. III-D: unstructured matrices) for gfx950.
+//
+// `group` lanes share a row (8 for ~27 stored entries per row); each lane
+// walks the row with stride `group`, the partial dot products meet by
+// cross-lane butterflies, and the group's first lane applies the epilogue
+// (sweep.hip lists them).  Rows are assigned to XCDs in contiguous runs, so
+// with a locality-preserving row order (e.g. Morton order of graph vertices)
+// the gathered vector entries are mostly hits in that XCD's L2.
+#include "sweep_common.h"
+
+namespace expi {
+namespace {
+
+template <int EPI, class TIN, class TOUT, int G>
+__global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
+    using TC = compute_t<TIN, TOUT>;
+    if (a.guard && a.st->done != 0) return;
+    const TIN* __restrict__ x = static_cast<const TIN*>(a.x);
+    TOUT* __restrict__ out = static_cast<TOUT*>(a.out);
+    TOUT* __restrict__ p = static_cast<TOUT*>(a.p);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (EPI == EPI_GERSH) {
+        s0 = INFINITY;
+        s1 = -INFINITY;
+    }
+    const int L = xcd_tile(a.per_xcd);
+    const int g = threadIdx.x / G, sub = threadIdx.x % G;
+    const int rows_per = blockDim.x / G;
+    const int row = L * rows_per + g;
+    if (L < a.ntiles && row < a.n[0]) {
+        // row range clamped to [0, nnz) and column indices checked against
+        // n, so a malformed matrix cannot send a load out of bounds
+        const int e0 = max(a.rowptr[row], 0), e1 = min(a.rowptr[row + 1], a.nnz);
+        const unsigned nrows = (unsigned)a.n[0];
+        if (EPI == EPI_GERSH) {
+            double dg = 0.0, off = 0.0;
+            for (int e = e0 + sub; e < e1; e += G) {
+                const double v = a.val[e];
+                if (a.colind[e] == row) dg += v; else off += fabs(v);
+            }
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                dg += __shfl_xor(dg, o, G);
+                off += __shfl_xor(off, o, G);
+            }
+            if (sub == 0) {
+                s0 = dg - off;
+                s1 = dg + off;
+            }
+        } else {
+            TC acc = 0;
+            for (int e = e0 + sub; e < e1; e += G) {
+                const int col = a.colind[e];
+                if ((unsigned)col < nrows) acc += (TC)a.val[e] * (TC)x[col];
+            }
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+            if (sub == 0) {
+                const TC wc = (TC)x[row];
+                const TC alpha = (TC)a.alpha, beta = (TC)a.beta;
+                if (EPI == EPI_APPLY) {
+                    out[row] = (TOUT)(alpha * acc + beta * wc);
+                } else if (EPI == EPI_NEWTON) {
+                    const TOUT wn = (TOUT)(alpha * acc + beta * wc);
+                    const TOUT pn = (TOUT)((TC)p[row] + (TC)a.d1 * (TC)wn);
+                    out[row] = wn;
+                    p[row] = pn;
+                    s1 = (double)wn * (double)wn;
+                    s2 = (double)pn * (double)pn;
+                } else if (EPI == EPI_FIRST) {
+                    const TOUT wn = (TOUT)(alpha * acc + beta * wc);
+                    const TOUT pn = (TOUT)((TC)a.d0 * wc + (TC)a.d1 * (TC)wn);
+                    out[row] = wn;
+                    p[row] = pn;
+                    s0 = (double)wc * (double)wc;
+                    s1 = (double)wn * (double)wn;
+                    s2 = (double)pn * (double)pn;
+                } else if (EPI == EPI_START) {
+                    TC gv;
+                    if (a.gmode == G_VEC) {
+                        gv = (TC)a.g[row];
+                    } else if (a.gmode == G_CUBIC_OF) {
+                        const TC u = (TC)a.g[row];
+                        gv = u - u * u * u;
+                    } else {
+                        gv = wc - wc * wc * wc;
+                    }
+                    out[row] = (TOUT)((TC)a.sigma * acc + gv);
+                }
+            }
+        }
+    }
+    if (EPI == EPI_NEWTON || EPI == EPI_FIRST || EPI == EPI_GERSH) finish_sweep<EPI>(a, s0, s1, s2);
+}
+
+template <int EPI, class TIN, class TOUT>
+hipError_t go(const Geom& g, const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(g.grid), block(64 * g.waves);
+    switch (g.vec) {  // lanes per row
+        case 4: hipLaunchKernelGGL((csr_sweep<EPI, TIN, TOUT, 4>), grid, block, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((csr_sweep<EPI, TIN, TOUT, 16>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((csr_sweep<EPI, TIN, TOUT, 8>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs& a, hipStream_t s) {
+    switch (epi) {
+        case EPI_APPLY:
+            if (tin == 0 && tout == 0) return go<EPI_APPLY, double, double>(g, a, s);
+            if (tin == 1 && tout == 1) return go<EPI_APPLY, float, float>(g, a, s);
+            break;
+        case EPI_NEWTON:
+            if (tin == 0 && tout == 0) return go<EPI_NEWTON, double, double>(g, a, s);
+            if (tin == 1 && tout == 1) return go<EPI_NEWTON, float, float>(g, a, s);
+            break;
+        case EPI_FIRST:
+            if (tin == 0 && tout == 0) return go<EPI_FIRST, double, double>(g, a, s);
+            if (tin == 0 && tout == 1) return go<EPI_FIRST, double, float>(g, a, s);
+            if (tin == 1 && tout == 1) return go<EPI_FIRST, float, float>(g, a, s);
+            break;
+        case EPI_START:
+            if (tin == 0 && tout == 0) return go<EPI_START, double, double>(g, a, s);
+            if (tin == 0 && tout == 1) return go<EPI_START, double, float>(g, a, s);
+            break;
+        case EPI_GERSH:
+            return go<EPI_GERSH, double, double>(g, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace expi

@@ -17,10 +17,10 @@ namespace expi {
 
 // ---------------------------------------------------------------------------
 // Device-side status of one Newton loop (lives at the start of the workspace).
-// Written by the last workgroup of each fused sweep; read back by the host.
+// Written by the finalize kernel after each reducing sweep; read back by the host.
 // ---------------------------------------------------------------------------
 struct alignas(64) NewtonState {
-    unsigned int arrive;  // workgroups of the running sweep that have finished
+    unsigned int arrive;  // reserved
     int done;             // 0 running, 1 stop test met, 2 non-finite norm
     int m;                // products taken in this loop
     int pad;
@@ -70,14 +70,36 @@ struct SweepArgs {
     int tiles[3];
     int ntiles;
     int per_xcd;          // tiles per XCD slot
+    int march;            // points marched per thread (stencils)
 };
 
-// Launch geometry of an operator's sweeps.
-struct Plan {
-    int grid;             // workgroups launched (multiple of 8)
+// Arguments of the one-workgroup finalize kernel that follows a reducing sweep.
+struct FinalArgs {
+    const double* partials;
+    NewtonState* st;
+    int nparts;
+    int j;
+    int guard;
+    double d0, d1, tol;
+};
+
+// Tile setting of an operator's sweeps (chosen by default or by the tuner).
+//   stencil: vec = x points per thread (1 or 2), waves per workgroup,
+//            march = points marched per thread along the slowest axis;
+//   CSR:     vec = lanes per row (4, 8, 16), waves per workgroup, march = 1.
+struct Tiles {
+    int vec = 2;
+    int waves = 4;
+    int march = 16;
+};
+
+// Launch geometry derived from a tile setting.
+struct Geom {
+    int vec, waves, march;
     int tiles[3];
     int ntiles;
     int per_xcd;
+    int grid;             // workgroups launched (multiple of 8)
 };
 
 struct Op {
@@ -94,7 +116,7 @@ struct Op {
     const int32_t* colind;
     const double* val;
     int64_t size;
-    Plan plan;
+    Tiles tiles;
     std::mutex mu;
     bool have_interval = false;
     double ia = 0, ib = 0;
@@ -105,17 +127,25 @@ struct Op {
 };
 
 constexpr int kXcd = 8;          // XCDs of gfx950; workgroup b runs on XCD b % 8
-constexpr int kBlock = 256;      // threads per workgroup (4 waves of 64)
-constexpr int kMarchZ = 16;      // planes marched per 3D thread column
-constexpr int kMarchY = 8;       // rows marched per 2D thread column
-constexpr int kCsrGroup = 8;     // lanes per CSR row
+constexpr int kMaxWaves = 8;     // waves per workgroup at most (512 threads)
+constexpr int kMinMarch = 4;     // accepted march lengths of a stencil sweep (multiples of 4)
+constexpr int kMaxMarch = 256;
 
-Plan make_plan(const Op& op);
+Geom make_geom(const Op& op, const Tiles& t);
+Tiles default_tiles(const Op& op);
+bool tiles_valid(const Op& op, const Tiles& t);
 size_t partials_bytes(const Op& op);
 
-// Launchers (sweep.hip).  TIN/TOUT codes: 0 = double, 1 = float.
+// Launchers.  TIN/TOUT codes: 0 = double, 1 = float.  launch_sweep picks the
+// geometry from op.tiles and adds the finalize kernel after reducing sweeps.
+// `after_sweep`, if given, is recorded on `s` between the sweep and its
+// finalize kernel (profiling of the sweep alone).
 hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t after_sweep = nullptr);
+hipError_t launch_stencil(const Op& op, const Geom& g, int epi, int tin, int tout,
+                          const SweepArgs& a, hipStream_t s);
+hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs& a,
+                      hipStream_t s);
 hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
                          double scale, NewtonState* st, int guard, hipStream_t s);
 hipError_t launch_reset(NewtonState* st, hipStream_t s);
