@@ -149,6 +149,19 @@ int64_t expi_op_size(const expi_op *op);
 int expi_op_set_tiles(expi_op *op, int vec, int waves, int march);
 int expi_op_get_tiles(const expi_op *op, int *vec, int *waves, int *march);
 
+/* Autotuner: times the fused Newton product (the hot loop's sweep, each
+ * product doing full work) under every candidate tile setting on this
+ * operator and storage dtype, `reps` launches each after one warm-up, with
+ * HIP events on `stream`, and keeps the fastest as the operator's setting.
+ * Candidates: stencils vec {2,1} x waves {1,2,4,8} x march {8,16,32,64}
+ * (3D) or {4,8,16,32} (2D); CSR lanes {4,8,16} x waves {1,2,4,8}.  The
+ * workspace (expi_workspace_bytes(op, dtype)) supplies the vectors and is
+ * overwritten.  If cand/us are given, the first max_cand tried settings
+ * (vec, waves, march triples) and their mean microseconds per launch are
+ * written there; *n_cand receives the number tried.  Synchronises `stream`. */
+int expi_op_autotune(expi_op *op, int dtype, int reps, void *ws, size_t ws_bytes, void *stream,
+                     int *cand, float *us, int max_cand, int *n_cand);
+
 /* Bytes of device workspace phi_action / expeuler_step / expi_op_interval
  * need for this operator and storage dtype (EXPI_F64 or EXPI_F32). */
 size_t expi_workspace_bytes(const expi_op *op, int dtype);

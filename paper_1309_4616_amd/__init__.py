@@ -11,11 +11,13 @@ from __future__ import annotations
 
 import ctypes
 
+from . import autotune
 from ._binding import (COEF_CONST, COEF_FIELD, COEF_SEPARABLE, F32, F64, G_CUBIC, BCS, EXPORTS,
                        ExpiError, LejaParams, Stats, check, divided_differences, leja_points, lib)
 
 __all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "expeuler_step", "leja_points",
-           "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32"]
+           "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32",
+           "autotune"]
 
 
 def _torch():
@@ -144,6 +146,7 @@ class StencilOp(_Op):
             kind = COEF_FIELD
             field = _dev_f64(coef, self.device, int(torch.tensor(self.shape).prod()), "field")
             self._keep.append(field)
+        self.coef_kind = kind
         ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
         with torch.cuda.device(self.device):
             check(lib().expi_op_create_stencil(ctypes.byref(self._h), dim, n, hh, BCS[bc], kind,

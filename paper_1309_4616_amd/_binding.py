@@ -23,7 +23,7 @@ G_CUBIC = 0
 
 # every symbol include/expi.h declares
 EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "expi_op_size",
-           "expi_op_set_tiles", "expi_op_get_tiles", "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
+           "expi_op_set_tiles", "expi_op_get_tiles", "expi_op_autotune", "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
            "expeuler_step", "expi_leja_points", "expi_divided_differences", "expi_last_error")
 
 
@@ -102,6 +102,9 @@ def lib() -> ctypes.CDLL:
     ip = ctypes.POINTER(c_int)
     L.expi_op_get_tiles.argtypes = [c_void_p, ip, ip, ip]
     L.expi_op_get_tiles.restype = c_int
+    L.expi_op_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p,
+                                   ip, ctypes.POINTER(ctypes.c_float), c_int, ip]
+    L.expi_op_autotune.restype = c_int
     L.expi_workspace_bytes.argtypes = [c_void_p, c_int]
     L.expi_workspace_bytes.restype = c_size_t
     L.expi_op_interval.argtypes = [c_void_p, dblp, dblp, c_void_p, c_size_t, c_void_p]

@@ -666,6 +666,91 @@ int expi_op_get_tiles(const expi_op* op, int* vec, int* waves, int* march) {
     return EXPI_OK;
 }
 
+int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes, void* stream,
+                     int* cand, float* us, int max_cand, int* n_cand) {
+    if (!op || !ws || !n_cand) return fail(EXPI_EINVAL, "op, ws, n_cand must be non-NULL");
+    if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
+    if (reps < 1 || reps > 1000) return fail(EXPI_EINVAL, "reps must be in [1, 1000]");
+    if (((uintptr_t)ws & 255) != 0) return fail(EXPI_EWORKSPACE, "workspace must be 256-byte aligned");
+    Op& o = *reinterpret_cast<Op*>(op);
+    const WsLayout L = layout(o, dtype);
+    if (ws_bytes < L.total) return fail(EXPI_EWORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int tw = dtype == EXPI_F32 ? 1 : 0;
+    char* w = static_cast<char*>(ws);
+    // candidate tile settings
+    std::vector<Tiles> C;
+    if (o.kind == 1) {
+        for (int v : {4, 8, 16})
+            for (int wv : {1, 2, 4, 8}) C.push_back(Tiles{v, wv, 1});
+    } else {
+        const int marches3[] = {8, 16, 32, 64};
+        const int marches2[] = {4, 8, 16, 32};
+        for (int v : {2, 1})
+            for (int wv : {1, 2, 4, 8})
+                for (int q = 0; q < 4; ++q) C.push_back(Tiles{v, wv, o.dim == 3 ? marches3[q] : marches2[q]});
+    }
+    // deterministic data in w0 and p; w1 is written by the sweep
+    HIP_TRY(launch_fill(w + L.w0, o.size, tw, 1.0, s));
+    HIP_TRY(launch_fill(w + L.p, o.size, tw, 0.5, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    SweepArgs a{};
+    a.x = w + L.w0;
+    a.out = w + L.w1;
+    a.p = w + L.p;
+    a.st = reinterpret_cast<NewtonState*>(w + L.state);
+    a.partials = reinterpret_cast<double*>(w + L.partials);
+    a.alpha = 1e-6;
+    a.beta = -0.5;
+    a.d1 = 1e-3;
+    a.tol = 1e-300;   // never met: every timed product does its work
+    a.j = 1;
+    a.guard = 0;
+    const Tiles keep = o.tiles;
+    Tiles best = keep;
+    float best_us = 1e30f;
+    int nc = 0;
+    hipError_t err = hipSuccess;
+    for (const Tiles& t : C) {
+        if (!tiles_valid(o, t)) continue;
+        o.tiles = t;
+        err = launch_sweep(o, EPI_NEWTON, tw, tw, a, s);   // warm up
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_sweep(o, EPI_NEWTON, tw, tw, a, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) break;
+        const float per = 1e3f * ms / reps;
+        if (nc < max_cand && cand && us) {
+            cand[3 * nc] = t.vec;
+            cand[3 * nc + 1] = t.waves;
+            cand[3 * nc + 2] = t.march;
+            us[nc] = per;
+        }
+        ++nc;
+        if (per < best_us) {
+            best_us = per;
+            best = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lock(o.mu);
+        o.tiles = (err == hipSuccess) ? best : keep;
+    }
+    *n_cand = nc;
+    if (err != hipSuccess) {
+        set_error(std::string("autotune: ") + hipGetErrorString(err));
+        return EXPI_EHIP;
+    }
+    return EXPI_OK;
+}
+
 size_t expi_workspace_bytes(const expi_op* op, int dtype) {
     if (!op || (dtype != EXPI_F64 && dtype != EXPI_F32)) return 0;
     return layout(*reinterpret_cast<const Op*>(op), dtype).total;

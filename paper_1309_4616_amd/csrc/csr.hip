@@ -48,10 +48,33 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
                 s1 = dg + off;
             }
         } else {
+            // first kBatch entries of the lane: all index and value loads,
+            // then all gathers, then the sums (three independent waves of
+            // memory traffic instead of a load -> gather chain per entry);
+            // indices are clamped so the loads need no branches
             TC acc = 0;
-            for (int e = e0 + sub; e < e1; e += G) {
-                const int col = a.colind[e];
-                if ((unsigned)col < nrows) acc += (TC)a.val[e] * (TC)x[col];
+            constexpr int kBatch = 4;
+            int col[kBatch];
+            TC vv[kBatch], xv[kBatch];
+            const int last = max(e1 - 1, 0);
+            const bool any = a.nnz > 0;   // an empty matrix may come without arrays
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int e = min(e0 + sub + q * G, last);
+                col[q] = any ? a.colind[e] : row;
+                vv[q] = any ? (TC)a.val[e] : (TC)0;
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const bool ok = (e0 + sub + q * G < e1) && ((unsigned)col[q] < nrows);
+                xv[q] = (TC)x[ok ? col[q] : row];
+                if (!ok) vv[q] = 0;
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) acc += vv[q] * xv[q];
+            for (int e = e0 + sub + kBatch * G; e < e1; e += G) {
+                const int c = a.colind[e];
+                if ((unsigned)c < nrows) acc += (TC)a.val[e] * (TC)x[c];
             }
 #pragma unroll
             for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);

@@ -149,6 +149,7 @@ hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs
 hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
                          double scale, NewtonState* st, int guard, hipStream_t s);
 hipError_t launch_reset(NewtonState* st, hipStream_t s);
+hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s);
 
 // Error reporting (api.hip).
 void set_error(const std::string& msg);

@@ -99,6 +99,14 @@ __global__ void reset_kernel(NewtonState* st) {
     }
 }
 
+// Smooth deterministic fill (for timing sweeps on meaningful data).
+template <class T>
+__global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ out, int64_t n, double scale) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (T)(scale * sin(1e-3 * (double)(i % 1000003)));
+}
+
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 }  // namespace
@@ -240,6 +248,19 @@ hipError_t launch_update(int64_t n, double* out, const double* yin, const void* 
 
 hipError_t launch_reset(NewtonState* st, hipStream_t s) {
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    if (t == 0)
+        hipLaunchKernelGGL(fill_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<double*>(out), n, scale);
+    else
+        hipLaunchKernelGGL(fill_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<float*>(out), n, scale);
     return hipGetLastError();
 }
 

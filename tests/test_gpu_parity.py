@@ -380,3 +380,35 @@ def test_full_size_256_apply_samples_and_step_invariants(E):
     assert relerr(N(u), u0 + 1e-5 * N(pf)) <= 1e-12
     del F, pf
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# autotuner: candidate timings, cached choice, unchanged results
+# ---------------------------------------------------------------------------
+
+def test_autotune_stencil_and_csr(E, tmp_path):
+    cache = str(tmp_path / "tiles.json")
+    shape = (96, 64, 48)
+    h = tuple(1.0 / s for s in shape)
+    op, A = stencil_pair(E, shape, h, "neumann0", "separable")
+    v = synth.uniform_vector(A.shape[0], 3)
+    y0, _ = E.phi_action(op, 1, 2e-3, T(v), tol=1e-10)
+    entry = E.autotune.tune(op, "f64", reps=3, path=cache)
+    assert len(entry["candidates"]) == 32
+    assert tuple(entry["tiles"]) == op.tiles()
+    assert entry["us"] == min(t for _, t in entry["candidates"])
+    y1, _ = E.phi_action(op, 1, 2e-3, T(v), tol=1e-10)
+    assert relerr(N(y1), N(y0)) <= 1e-13
+    yo, _ = I.phi_action(A, 1, 2e-3, v, 1e-10)
+    assert relerr(N(y1), yo) <= TOL_F64
+    # a fresh operator picks the cached setting without timing
+    op2, _ = stencil_pair(E, shape, h, "neumann0", "separable")
+    assert E.autotune.load(op2, "f64", path=cache)
+    assert op2.tiles() == op.tiles()
+    # CSR lanes per row
+    cop, CA, g = csr_pair(E, 20011, seed=3)
+    centry = E.autotune.tune(cop, "f64", reps=3, path=cache)
+    assert len(centry["candidates"]) == 12
+    x = synth.uniform_vector(g.n, 4)
+    y = E.apply_op(cop, -0.5, 2.0, T(x))
+    assert np.max(np.abs(N(y) - O.apply_op(CA, -0.5, 2.0, x))) <= 1e-13 * np.abs(N(y)).max()

@@ -134,4 +134,14 @@ def test_call_validation_before_any_hip_call(L):
     assert L.apply_op(op, 1.0, 0.0, x, x, 0, None) == -2
     assert L.apply_op(op, float("inf"), 0.0, x, yp, 0, None) == -1
     assert L.expeuler_step(op, 1, 1e-3, yp, 1e-10, 0, None, ws, need, ctypes.byref(st), None) == -1
+    nc = ctypes.c_int()
+    assert L.expi_op_autotune(op, 0, 0, ws, need, None, None, None, 0, ctypes.byref(nc)) == -1
+    assert L.expi_op_autotune(op, 0, 5, ws, need - 1, None, None, None, 0, ctypes.byref(nc)) == -3
+    assert L.expi_op_set_tiles(op, 3, 4, 8) == -1
+    assert L.expi_op_set_tiles(op, 2, 9, 8) == -1
+    assert L.expi_op_set_tiles(op, 2, 4, 6) == -1
+    assert L.expi_op_set_tiles(op, 1, 2, 16) == 0
+    v_, w_, m_ = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.expi_op_get_tiles(op, ctypes.byref(v_), ctypes.byref(w_), ctypes.byref(m_)) == 0
+    assert (v_.value, w_.value, m_.value) == (1, 2, 16)
     L.expi_op_destroy(op)
