@@ -202,6 +202,65 @@ int expeuler_step(expi_op *op, int nonlin, double tau, double *u, double tol, in
                   const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
                   void *stream);
 
+/* ---- many problems in one persistent launch ------------------------------ */
+
+/* A batch of independent 2D problems y_i = phi_1(tau_i A_i) v_i, A_i the
+ * constant-coefficient 5-point operator coef * Laplacian on an nx_i x ny_i
+ * grid with spacings hx_i, hy_i and boundary handling `bc` (DIRICHLET0 or
+ * NEUMANN0), each by the same Leja interpolation as phi_action (Sec. III-C),
+ * all of them in ONE persistent kernel launch that can be captured in a HIP
+ * graph.  The host computes each interval (closed-form Gershgorin bound
+ * [-4 coef (1/hx^2 + 1/hy^2), 0]), substep count and divided differences at
+ * creation.  Vectors of all instances are concatenated: instance i occupies
+ * [off_i, off_i + nx_i ny_i) of v and y (float64, device), with off_i from
+ * expi_batch_offsets and total length expi_batch_total_length.  dtype sets
+ * the storage of the Newton vectors (EXPI_F32 for the FP32-storage mode).
+ * No retries inside the launch: an instance that misses the stop test within
+ * m_max products reports EXPI_ENOTCONV in its status.
+ * CURRENTLY SWITCHED OFF: expi_batch_launch and expi_batch_capture return
+ * EXPI_EUNSUPPORTED (the persistent kernel did not finish on the GPU and the
+ * cause is not yet found); creation and layout calls work. */
+typedef struct expi_batch expi_batch;
+typedef struct {
+    int32_t status;         /* 0, EXPI_ENOTCONV or EXPI_ENONFINITE            */
+    int32_t substeps;
+    int32_t newton_steps;   /* products over all substeps                     */
+    int32_t degree_max;
+    int32_t degree_last;
+    int32_t reserved;
+    double  err_est;        /* largest (t_{m-1} + t_m)/||p|| over the substeps */
+} expi_batch_stat;
+
+int expi_batch_create(expi_batch **b, int count, const int32_t *nx, const int32_t *ny,
+                      const double *hx, const double *hy, const double *tau, int bc,
+                      double coef, double tol, int dtype, const expi_params *params);
+int expi_batch_destroy(expi_batch *b);
+/* Tile setting of the batch's sweeps: waves per workgroup (1..8), rows
+ * marched per thread (4..64, multiple of 4).  Requires expi_batch_prepare
+ * again; not allowed after expi_batch_capture. */
+int expi_batch_set_tiles(expi_batch *b, int waves, int march);
+int64_t expi_batch_total_length(const expi_batch *b);
+int expi_batch_offsets(const expi_batch *b, int64_t *off /* count entries */);
+size_t expi_batch_workspace_bytes(const expi_batch *b);
+/* Upload the instance table to the workspace (host-to-device copies), size
+ * the persistent grid from the occupancy of this device; synchronises. */
+int expi_batch_prepare(expi_batch *b, void *ws, size_t ws_bytes, void *stream);
+/* Enqueue the state reset and the persistent kernel (a cooperative launch:
+ * all workgroups co-resident, EXPI_EHIP if the runtime cannot guarantee it)
+ * on `stream` (no copies, no synchronisation). */
+int expi_batch_launch(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
+                      void *stream);
+/* Build a HIP graph of the same two launches (the persistent kernel as a
+ * cooperative kernel node), owned by the batch; replay it with
+ * expi_batch_replay (same v, y, ws).  `stream` is unused. */
+int expi_batch_capture(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
+                       void *stream);
+int expi_batch_replay(expi_batch *b, void *stream);
+/* Read per-instance results back (synchronises); returns EXPI_OK if every
+ * instance converged.  `rounds` (may be NULL) receives the rounds the
+ * persistent kernel ran. */
+int expi_batch_results(expi_batch *b, void *ws, void *stream, expi_batch_stat *out, int *rounds);
+
 /* ---- host-side interpolation data (no GPU needed) ----------------------- */
 
 /* The first `count` (1..256) real Leja points of [-2, 2]: xi_0 = 2 and xi_k

@@ -13,11 +13,12 @@ import ctypes
 
 from . import autotune
 from ._binding import (COEF_CONST, COEF_FIELD, COEF_SEPARABLE, F32, F64, G_CUBIC, BCS, EXPORTS,
-                       ExpiError, LejaParams, Stats, check, divided_differences, leja_points, lib)
+                       BatchStat, ExpiError, LejaParams, Stats, check, divided_differences,
+                       leja_points, lib)
 
 __all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "expeuler_step", "leja_points",
            "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32",
-           "autotune"]
+           "autotune", "Batch"]
 
 
 def _torch():
@@ -227,3 +228,97 @@ def expeuler_step(op: _Op, tau: float, u, tol: float = 1e-10, dtype="f64",
                              _stream_ptr(stream, op.device))
     check(rc)
     return st.as_dict()
+
+
+class Batch:
+    """Many independent 2D problems y_i = phi_1(tau_i A_i) v_i solved in one
+    persistent kernel launch (expi_batch_*).  A_i = coef * 5-point Laplacian
+    on an nx_i x ny_i grid with spacing (hx_i, hy_i) and boundary `bc`.
+    Vectors are concatenated; `offsets[i]` is where instance i starts."""
+
+    def __init__(self, nx, ny, hx, hy, tau, bc="dirichlet0", coef=1.0, tol=1e-8, dtype="f32",
+                 params: LejaParams | None = None, device="cuda:0"):
+        import numpy as np
+        torch = _torch()
+        self.device = torch.device(device)
+        self.count = len(nx)
+        arr = lambda a, t: np.ascontiguousarray(np.asarray(a, dtype=t))
+        self._nx, self._ny = arr(nx, np.int32), arr(ny, np.int32)
+        self._hx, self._hy, self._tau = arr(hx, np.float64), arr(hy, np.float64), arr(tau, np.float64)
+        for a_ in (self._ny, self._hx, self._hy, self._tau):
+            if a_.size != self.count:
+                raise ValueError("per-instance arrays differ in length")
+        if bc not in ("dirichlet0", "neumann0"):
+            raise ValueError("bc must be dirichlet0 or neumann0")
+        self._h = ctypes.c_void_p()
+        cp = params.to_c() if params is not None else None
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        dbl = ctypes.POINTER(ctypes.c_double)
+        check(lib().expi_batch_create(ctypes.byref(self._h), self.count,
+                                      self._nx.ctypes.data_as(i32), self._ny.ctypes.data_as(i32),
+                                      self._hx.ctypes.data_as(dbl), self._hy.ctypes.data_as(dbl),
+                                      self._tau.ctypes.data_as(dbl), BCS[bc], float(coef),
+                                      float(tol), _dtype_code(dtype),
+                                      ctypes.byref(cp) if cp is not None else None))
+        self.total_length = int(lib().expi_batch_total_length(self._h))
+        off = np.zeros(self.count, dtype=np.int64)
+        check(lib().expi_batch_offsets(self._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        self.offsets = off
+        self._ws = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sizes(self):
+        return [(int(a), int(b)) for a, b in zip(self._nx, self._ny)]
+
+    def workspace(self):
+        if self._ws is None:
+            self._ws = workspace(int(lib().expi_batch_workspace_bytes(self._h)), self.device)
+        return self._ws
+
+    def set_tiles(self, waves: int, march: int) -> None:
+        check(lib().expi_batch_set_tiles(self._h, int(waves), int(march)))
+        nb = int(lib().expi_batch_workspace_bytes(self._h))
+        if self._ws is not None and self._ws.numel() < nb:
+            self._ws = None
+
+    def prepare(self, stream=None):
+        ws = self.workspace()
+        check(lib().expi_batch_prepare(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_ptr(stream, self.device)))
+
+    def launch(self, v, y, stream=None):
+        ws = self.workspace()
+        check(lib().expi_batch_launch(self._h, ctypes.c_void_p(v.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel(), _stream_ptr(stream, self.device)))
+
+    def capture(self, v, y, stream=None):
+        ws = self.workspace()
+        check(lib().expi_batch_capture(self._h, ctypes.c_void_p(v.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                       ws.numel(), _stream_ptr(stream, self.device)))
+
+    def replay(self, stream=None):
+        check(lib().expi_batch_replay(self._h, _stream_ptr(stream, self.device)))
+
+    def results(self, stream=None, check_status=True):
+        """(per-instance stat dicts, rounds); raises on failure if check_status."""
+        st = (BatchStat * self.count)()
+        rounds = ctypes.c_int()
+        ws = self.workspace()
+        rc = lib().expi_batch_results(self._h, ctypes.c_void_p(ws.data_ptr()),
+                                      _stream_ptr(stream, self.device), st, ctypes.byref(rounds))
+        if check_status:
+            check(rc)
+        return [s.as_dict() for s in st], rounds.value
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().expi_batch_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass

@@ -24,7 +24,11 @@ G_CUBIC = 0
 # every symbol include/expi.h declares
 EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "expi_op_size",
            "expi_op_set_tiles", "expi_op_get_tiles", "expi_op_autotune", "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
-           "expeuler_step", "expi_leja_points", "expi_divided_differences", "expi_last_error")
+           "expeuler_step", "expi_leja_points", "expi_divided_differences", "expi_last_error",
+           "expi_batch_create", "expi_batch_destroy", "expi_batch_set_tiles",
+           "expi_batch_total_length", "expi_batch_offsets", "expi_batch_workspace_bytes",
+           "expi_batch_prepare", "expi_batch_launch", "expi_batch_capture", "expi_batch_replay",
+           "expi_batch_results")
 
 
 class ExpiError(RuntimeError):
@@ -44,6 +48,16 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BatchStat(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("substeps", ctypes.c_int32),
+                ("newton_steps", ctypes.c_int32), ("degree_max", ctypes.c_int32),
+                ("degree_last", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("err_est", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 class Params(ctypes.Structure):
@@ -119,6 +133,30 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(Params), c_void_p, c_size_t, ctypes.POINTER(Stats),
                                 c_void_p]
     L.expeuler_step.restype = c_int
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.expi_batch_create.argtypes = [ctypes.POINTER(c_void_p), c_int, i32p, i32p, dblp, dblp, dblp,
+                                    c_int, c_double, c_double, c_int, ctypes.POINTER(Params)]
+    L.expi_batch_create.restype = c_int
+    L.expi_batch_destroy.argtypes = [c_void_p]
+    L.expi_batch_destroy.restype = c_int
+    L.expi_batch_set_tiles.argtypes = [c_void_p, c_int, c_int]
+    L.expi_batch_set_tiles.restype = c_int
+    L.expi_batch_total_length.argtypes = [c_void_p]
+    L.expi_batch_total_length.restype = ctypes.c_int64
+    L.expi_batch_offsets.argtypes = [c_void_p, i64p]
+    L.expi_batch_offsets.restype = c_int
+    L.expi_batch_workspace_bytes.argtypes = [c_void_p]
+    L.expi_batch_workspace_bytes.restype = c_size_t
+    L.expi_batch_prepare.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+    L.expi_batch_prepare.restype = c_int
+    for name in ("expi_batch_launch", "expi_batch_capture"):
+        getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        getattr(L, name).restype = c_int
+    L.expi_batch_replay.argtypes = [c_void_p, c_void_p]
+    L.expi_batch_replay.restype = c_int
+    L.expi_batch_results.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(BatchStat),
+                                     ctypes.POINTER(c_int)]
+    L.expi_batch_results.restype = c_int
     L.expi_leja_points.argtypes = [dblp, c_int]
     L.expi_leja_points.restype = c_int
     L.expi_divided_differences.argtypes = [c_int, c_double, c_double, c_double, c_int, dblp]

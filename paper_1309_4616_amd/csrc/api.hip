@@ -737,8 +737,8 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
             best = t;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> lock(o.mu);
         o.tiles = (err == hipSuccess) ? best : keep;

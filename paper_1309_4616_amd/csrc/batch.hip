@@ -1,0 +1,759 @@
+// Batched phi_1(tau_i A_i) v_i for many independent 2D constant-coefficient
+// stencil problems of uneven sizes, in ONE persistent kernel launch.
+//
+// Each instance runs the same Leja interpolation as phi_action (Sec. III-C;
+// substeps as in api.hip): per substep an optional start vector
+// r = tau A y' + v, the first product, fused Newton products until the
+// two-term stop test holds, and the update y' += p / s.  The host computes
+// every instance's interval (the Gershgorin bound of a constant-coefficient
+// 5-point operator has a closed form), substep count and divided
+// differences ahead of time; they do not depend on the data.
+//
+// The kernel runs rounds.  In each round every unfinished instance takes one
+// step of its own sequence; the tiles of all of them form one list that the
+// workgroups share through an atomic counter (load balance across uneven
+// sizes).  A grid barrier ends the round's tile work; then one workgroup per
+// instance combines that instance's tile partials in a fixed order, applies
+// the stop test and advances the instance's state; a second barrier
+// publishes the states.  Instances drop out as they finish.
+//
+// The kernel is launched cooperatively (directly or as a cooperative graph
+// node), so all of its workgroups are resident together.  Every wait in the
+// barrier is bounded in time: a workgroup that waits too long sets an abort
+// flag that every other waiter also sees, so all waves exit and the host
+// reports the failure.  The launch has no host interaction and no memory
+// copies or fills, so it can be put in a HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "leja.h"
+#include "stencil_tile.h"
+
+namespace expi {
+
+namespace {
+
+enum Phase : int { PH_START = 0, PH_FIRST = 1, PH_NEWTON = 2, PH_UPDATE = 3, PH_DONE = 4, PH_FAILED = 5 };
+
+constexpr int kMaxBatch = 4096;
+constexpr int kBatchLaunchEnabled = 0;   // see expi_batch_launch
+
+struct alignas(16) BatchInfo {   // static per instance
+    long long off;               // offset of the instance's vectors, in elements
+    int nx, ny;
+    int tiles0, ntiles, vec, s;
+    int dd_off, part_off;
+    double ihx, ihy;             // 1/h^2 per axis
+    double alpha, cg;            // 1/gamma and c/gamma of the interval map
+    double tau, inv_s;
+};
+
+struct alignas(16) BatchState {  // advanced by the finalize step
+    int phase, l, j, newton;
+    int degree_max, degree_last, status, pad;
+    double t_prev, err_max;
+};
+
+struct alignas(64) BatchCtrl {
+    unsigned bar_count, bar_gen, abort, rounds;
+    unsigned tile_ctr[2];
+    unsigned pad[10];
+};
+
+struct BatchArgs {
+    const BatchInfo* info;
+    BatchState* state;
+    BatchCtrl* ctrl;
+    const double* dd;
+    const double* xi;
+    double* partials;
+    const double* v;
+    double* y;
+    void* w0;
+    void* w1;
+    void* p;
+    int count, m_max, march, max_rounds, bc;
+    double c0, tol;
+    long long deadline_ticks;   // longest wait at a barrier, GPU wall-clock ticks
+};
+
+// Grid barrier with a time limit; returns false once any workgroup has
+// aborted.  Arrival releases the workgroup's writes; waiting polls the
+// generation counter with relaxed loads (an acquire per poll would
+// invalidate caches for every waiter on every poll) and one acquire fence
+// follows.  A waiter past the deadline (GPU wall clock) sets the abort flag,
+// which every other waiter sees, so no wave can wait forever.
+__device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BatchCtrl* c = B.ctrl;
+        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long t_end = wall_clock64() + B.deadline_ticks;
+            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() > t_end) {
+                    __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+template <class TW, int V>
+__device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchState& S, int phase,
+                         int lt, double* red_partial) {
+    const int waves = blockDim.x >> 6;
+    const int t0 = lt % I.tiles0, t1 = lt / I.tiles0;
+    SweepArgs a{};
+    a.n[0] = I.nx;
+    a.n[1] = I.ny;
+    a.n[2] = 1;
+    a.ih2[0] = I.ihx;
+    a.ih2[1] = I.ihy;
+    a.ih2[2] = 0.0;
+    a.bc = B.bc;
+    a.c0 = B.c0;
+    a.march = B.march;
+    TW* w0 = static_cast<TW*>(B.w0) + I.off;
+    TW* w1 = static_cast<TW*>(B.w1) + I.off;
+    TW* pp = static_cast<TW*>(B.p) + I.off;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (phase == PH_START) {
+        a.x = B.y + I.off;
+        a.out = w1;
+        a.g = B.v + I.off;
+        a.gmode = G_VEC;
+        a.sigma = I.tau;
+        tile::stencil_tile<2, EXPI_COEF_CONST, EPI_START, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
+        return;
+    }
+    if (phase == PH_UPDATE) {
+        // y' <- (l == 0 ? 0 : y') + p / s over the tile's points
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int rows = waves * B.march;
+        double* y = B.y + I.off;
+        for (int r = 0; r < B.march; ++r) {
+            const int j = t1 * rows + wv * B.march + r;
+            if (j >= I.ny) break;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int i = t0 * 64 * V + lane * V + v;
+                if (i < I.nx) {
+                    const int idx = i + I.nx * j;
+                    y[idx] = (S.l == 0 ? 0.0 : y[idx]) + I.inv_s * (double)pp[idx];
+                }
+            }
+        }
+        return;
+    }
+    const int j = (phase == PH_FIRST) ? 0 : S.j;
+    a.alpha = I.alpha;
+    a.beta = -(I.cg + B.xi[j]);
+    a.d0 = B.dd[I.dd_off];
+    a.d1 = B.dd[I.dd_off + j + 1];
+    a.p = pp;
+    if (phase == PH_FIRST) {
+        a.out = w0;
+        if (S.l == 0) {
+            a.x = B.v + I.off;
+            tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
+        } else {
+            a.x = w1;
+            tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+        }
+    } else {
+        a.x = (j & 1) ? w0 : w1;     // w_j lives in w[(j-1) & 1]
+        a.out = (j & 1) ? w1 : w0;
+        tile::stencil_tile<2, EXPI_COEF_CONST, EPI_NEWTON, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+    }
+    __shared__ double red[kMaxWaves][3];
+    block_combine<EPI_NEWTON>(s0, s1, s2, red);
+    if (threadIdx.x == 0) {
+        red_partial[0] = s0;
+        red_partial[1] = s1;
+        red_partial[2] = s2;
+    }
+}
+
+// Combine an instance's tile partials in index order and advance its state.
+__device__ void finalize_instance(const BatchArgs& B, int inst) {
+    __shared__ double red[kMaxWaves][3];
+    const BatchInfo& I = B.info[inst];
+    BatchState* S = &B.state[inst];
+    const int phase = S->phase;
+    if (phase == PH_FIRST || phase == PH_NEWTON) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
+            const double* q = B.partials + 4 * (size_t)(I.part_off + t);
+            s0 += q[0];
+            s1 += q[1];
+            s2 += q[2];
+        }
+        block_combine<EPI_NEWTON>(s0, s1, s2, red);
+        if (threadIdx.x == 0) {
+            const int j = (phase == PH_FIRST) ? 0 : S->j;
+            const double wn = sqrt(s1), pn = sqrt(s2);
+            const double t = fabs(B.dd[I.dd_off + j + 1]) * wn;
+            const double tprev = (phase == PH_FIRST) ? fabs(B.dd[I.dd_off]) * sqrt(s0) : S->t_prev;
+            const int m = j + 1;
+            const double num = tprev + t;
+            const double err = (pn > 0.0) ? num / pn : (num == 0.0 ? 0.0 : INFINITY);
+            S->newton += 1;
+            S->t_prev = t;
+            if (!isfinite(wn) || !isfinite(pn) || !isfinite(tprev)) {
+                S->phase = PH_FAILED;
+                S->status = 2;
+            } else if (m >= 2 && num <= B.tol * pn) {
+                S->degree_last = m;
+                S->degree_max = max(S->degree_max, m);
+                S->err_max = fmax(S->err_max, err);
+                S->phase = PH_UPDATE;
+            } else if (m >= B.m_max) {
+                S->phase = PH_FAILED;
+                S->status = 1;
+                S->err_max = fmax(S->err_max, err);
+            } else {
+                S->phase = PH_NEWTON;
+                S->j = m;
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        if (phase == PH_START) {
+            S->phase = PH_FIRST;
+        } else if (phase == PH_UPDATE) {
+            S->l += 1;
+            S->j = 0;
+            S->phase = (S->l < I.s) ? PH_START : PH_DONE;
+        }
+    }
+    __syncthreads();
+}
+
+template <class TW>
+__global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
+    __shared__ int s_pref[kMaxBatch + 1];
+    __shared__ int s_ids[kMaxBatch];
+    __shared__ int s_chunk[kMaxWaves * 64];
+    __shared__ int s_nact, s_tile, s_ok;
+    const int nt = blockDim.x;
+    for (int round = 0; round < B.max_rounds; ++round) {
+        // (A) active instances and the prefix sums of their tile counts, in
+        // instance order; every workgroup computes the same list
+        const int per = (B.count + nt - 1) / nt;
+        const int lo = threadIdx.x * per, hi = min(lo + per, B.count);
+        int cnt = 0, tiles = 0;
+        for (int i = lo; i < hi; ++i) {
+            const int ph = B.state[i].phase;
+            if (ph != PH_DONE && ph != PH_FAILED) {
+                ++cnt;
+                tiles += B.info[i].ntiles;
+            }
+        }
+        s_chunk[threadIdx.x] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int t = 0; t < nt; ++t) {
+                const int c = s_chunk[t];
+                s_chunk[t] = acc;
+                acc += c;
+            }
+            s_nact = acc;
+        }
+        __syncthreads();
+        int k = s_chunk[threadIdx.x];
+        __syncthreads();
+        s_chunk[threadIdx.x] = tiles;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int t = 0; t < nt; ++t) {
+                const int c = s_chunk[t];
+                s_chunk[t] = acc;
+                acc += c;
+            }
+            s_pref[s_nact] = acc;
+        }
+        __syncthreads();
+        int tp = s_chunk[threadIdx.x];
+        for (int i = lo; i < hi; ++i) {
+            const int ph = B.state[i].phase;
+            if (ph != PH_DONE && ph != PH_FAILED) {
+                s_ids[k] = i;
+                s_pref[k] = tp;
+                tp += B.info[i].ntiles;
+                ++k;
+            }
+        }
+        __syncthreads();
+        const int nact = s_nact;
+        const int total = s_pref[nact];
+        if (nact == 0) break;
+        // (B) the round's tiles
+        unsigned* ctr = &B.ctrl->tile_ctr[round & 1];
+        while (true) {
+            if (threadIdx.x == 0) s_tile = (int)atomicAdd(ctr, 1u);
+            __syncthreads();
+            const int t = s_tile;
+            __syncthreads();
+            if (t >= total) break;
+            int l = 0, h = nact - 1;   // last k with s_pref[k] <= t
+            while (l < h) {
+                const int mid = (l + h + 1) >> 1;
+                if (s_pref[mid] <= t) l = mid; else h = mid - 1;
+            }
+            const int inst = s_ids[l];
+            const int lt = t - s_pref[l];
+            const BatchInfo& I = B.info[inst];
+            const BatchState S = B.state[inst];
+            double* part = B.partials + 4 * (size_t)(I.part_off + lt);
+            if (I.vec == 2) run_tile<TW, 2>(B, I, S, S.phase, lt, part);
+            else run_tile<TW, 1>(B, I, S, S.phase, lt, part);
+        }
+        // (C) all tiles of the round are done
+        if (!grid_barrier(B, &s_ok)) return;
+        // (D) finalize: active instance k belongs to workgroup k mod grid
+        for (int q = blockIdx.x; q < nact; q += gridDim.x) finalize_instance(B, s_ids[q]);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            __hip_atomic_store(&B.ctrl->tile_ctr[(round + 1) & 1], 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            B.ctrl->rounds = round + 1;
+        }
+        // (E) publish the new states
+        if (!grid_barrier(B, &s_ok)) return;
+    }
+}
+
+__global__ void batch_reset_kernel(BatchState* st, BatchCtrl* ctrl, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        BatchState s{};
+        s.phase = PH_FIRST;
+        st[i] = s;
+    }
+    if (i == 0) {
+        ctrl->bar_count = 0;
+        ctrl->bar_gen = 0;
+        ctrl->abort = 0;
+        ctrl->rounds = 0;
+        ctrl->tile_ctr[0] = 0;
+        ctrl->tile_ctr[1] = 0;
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct Batch {
+    int count, dtype, bc, m_max, waves, march;
+    double c0, tol;
+    std::vector<BatchInfo> info;
+    std::vector<double> dd;       // count x (m_max + 1)
+    std::vector<double> xi;       // m_max + 1
+    long long total_len = 0;
+    int total_tiles = 0, max_rounds = 0;
+    size_t off_ctrl, off_info, off_state, off_dd, off_xi, off_part, off_w0, off_w1, off_p, ws_total;
+    void* prepared_ws = nullptr;
+    int grid = 0;
+    long long deadline_ticks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+int bfail(int code, const std::string& m) {
+    set_error(m);
+    return code;
+}
+
+#define BHIP(expr)                                                                   \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));            \
+            return EXPI_EHIP;                                                        \
+        }                                                                            \
+    } while (0)
+
+void layout_tiles(Batch& b) {
+    int part = 0;
+    b.total_tiles = 0;
+    for (auto& I : b.info) {
+        I.tiles0 = (I.nx + 64 * I.vec - 1) / (64 * I.vec);
+        const int rows = b.waves * b.march;
+        const int tiles1 = (I.ny + rows - 1) / rows;
+        I.ntiles = I.tiles0 * tiles1;
+        I.part_off = part;
+        part += I.ntiles;
+    }
+    b.total_tiles = part;
+    const size_t tw = b.dtype == EXPI_F32 ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    b.off_ctrl = take(sizeof(BatchCtrl));
+    b.off_info = take(sizeof(BatchInfo) * b.count);
+    b.off_state = take(sizeof(BatchState) * b.count);
+    b.off_dd = take(sizeof(double) * b.dd.size());
+    b.off_xi = take(sizeof(double) * b.xi.size());
+    // partial slots sized for the smallest accepted tiles (waves 1, march 4)
+    size_t maxpart = 0;
+    for (const auto& I : b.info) {
+        const int t0 = (I.nx + 63) / 64;
+        maxpart += (size_t)t0 * ((I.ny + 3) / 4);
+    }
+    b.off_part = take(4 * sizeof(double) * maxpart);
+    b.off_w0 = take(tw * b.total_len);
+    b.off_w1 = take(tw * b.total_len);
+    b.off_p = take(tw * b.total_len);
+    b.ws_total = off;
+}
+
+BatchArgs make_args(const Batch& b, char* ws, const double* v, double* y) {
+    BatchArgs a{};
+    a.info = reinterpret_cast<const BatchInfo*>(ws + b.off_info);
+    a.state = reinterpret_cast<BatchState*>(ws + b.off_state);
+    a.ctrl = reinterpret_cast<BatchCtrl*>(ws + b.off_ctrl);
+    a.dd = reinterpret_cast<const double*>(ws + b.off_dd);
+    a.xi = reinterpret_cast<const double*>(ws + b.off_xi);
+    a.partials = reinterpret_cast<double*>(ws + b.off_part);
+    a.v = v;
+    a.y = y;
+    a.w0 = ws + b.off_w0;
+    a.w1 = ws + b.off_w1;
+    a.p = ws + b.off_p;
+    a.count = b.count;
+    a.m_max = b.m_max;
+    a.march = b.march;
+    a.max_rounds = b.max_rounds;
+    a.bc = b.bc;
+    a.c0 = b.c0;
+    a.tol = b.tol;
+    a.deadline_ticks = b.deadline_ticks;
+    return a;
+}
+
+// The persistent kernel needs every workgroup resident at once.  The grid
+// is two workgroups per CU (the occupancy limit is higher) and every launch
+// is cooperative, so the runtime refuses a grid that cannot be co-resident
+// instead of letting the barrier wait.
+int occupancy_grid(Batch& b) {
+    int dev = 0, cus = 0, per = 0, khz = 0;
+    BHIP(hipGetDevice(&dev));
+    BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (b.dtype == EXPI_F32)
+        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<float>, 64 * b.waves, 0));
+    else
+        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<double>, 64 * b.waves, 0));
+    if (per < 1) return bfail(EXPI_EHIP, "batched kernel cannot be resident");
+    b.grid = std::min(per, 2) * cus;
+    // a barrier wait longer than two seconds means something is wrong
+    b.deadline_ticks = 2ll * 1000ll * (long long)(khz > 0 ? khz : 100000);
+    return EXPI_OK;
+}
+
+const void* kernel_ptr(const Batch& b) {
+    return b.dtype == EXPI_F32 ? reinterpret_cast<const void*>(batch_kernel<float>)
+                               : reinterpret_cast<const void*>(batch_kernel<double>);
+}
+
+int enqueue(Batch& b, char* ws, const double* v, double* y, hipStream_t s) {
+    BatchArgs a = make_args(b, ws, v, y);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((b.count + 255) / 256), dim3(256), 0, s,
+                       a.state, a.ctrl, b.count);
+    BHIP(hipGetLastError());
+    void* params[] = {&a};
+    BHIP(hipLaunchCooperativeKernel(kernel_ptr(b), dim3(b.grid), dim3(64 * b.waves), params, 0, s));
+    return EXPI_OK;
+}
+
+// The same two launches as a graph built node by node, with the persistent
+// kernel's node marked cooperative.
+int build_graph(Batch& b, char* ws, const double* v, double* y) {
+    BatchArgs a = make_args(b, ws, v, y);
+    BatchState* st = a.state;
+    BatchCtrl* ctrl = a.ctrl;
+    int count = b.count;
+    hipGraph_t g = nullptr;
+    BHIP(hipGraphCreate(&g, 0));
+    hipGraphNode_t n0 = nullptr, n1 = nullptr;
+    void* p0[] = {&st, &ctrl, &count};
+    hipKernelNodeParams k0{};
+    k0.func = reinterpret_cast<void*>(batch_reset_kernel);
+    k0.gridDim = dim3((b.count + 255) / 256);
+    k0.blockDim = dim3(256);
+    k0.kernelParams = p0;
+    void* p1[] = {&a};
+    hipKernelNodeParams k1{};
+    k1.func = const_cast<void*>(kernel_ptr(b));
+    k1.gridDim = dim3(b.grid);
+    k1.blockDim = dim3(64 * b.waves);
+    k1.kernelParams = p1;
+    hipKernelNodeAttrValue coop{};
+    coop.cooperative = 1;
+    hipError_t e = hipGraphAddKernelNode(&n0, g, nullptr, 0, &k0);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&n1, g, &n0, 1, &k1);
+    if (e == hipSuccess) e = hipGraphKernelNodeSetAttribute(n1, hipKernelNodeAttributeCooperative, &coop);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b.graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return bfail(EXPI_EHIP, std::string("batched graph: ") + hipGetErrorString(e));
+    }
+    b.graph = g;
+    return EXPI_OK;
+}
+
+}  // namespace
+
+}  // namespace expi
+
+using namespace expi;
+
+extern "C" {
+
+int expi_batch_create(expi_batch** out, int count, const int32_t* nx, const int32_t* ny,
+                      const double* hx, const double* hy, const double* tau, int bc, double coef,
+                      double tol, int dtype, const expi_params* params) {
+    if (!out) return bfail(EXPI_EINVAL, "batch is NULL");
+    *out = nullptr;
+    if (count < 1 || count > kMaxBatch) return bfail(EXPI_EINVAL, "count must be in [1, 4096]");
+    if (!nx || !ny || !hx || !hy || !tau) return bfail(EXPI_EINVAL, "per-instance arrays must be non-NULL");
+    if (bc != EXPI_DIRICHLET0 && bc != EXPI_NEUMANN0) return bfail(EXPI_EINVAL, "bc must be DIRICHLET0 or NEUMANN0");
+    if (!(coef > 0) || !std::isfinite(coef)) return bfail(EXPI_EINVAL, "coef must be finite and > 0");
+    if (!(tol > 0) || !std::isfinite(tol)) return bfail(EXPI_EINVAL, "tol must be finite and > 0");
+    if (dtype != EXPI_F64 && dtype != EXPI_F32) return bfail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
+    double l_max = 100.0;
+    int m_max = 100;
+    if (params) {
+        l_max = params->l_max;
+        m_max = params->m_max;
+        if (params->have_interval) return bfail(EXPI_EINVAL, "batched intervals are computed per instance");
+    }
+    if (!(l_max > 0) || !std::isfinite(l_max)) return bfail(EXPI_EINVAL, "l_max must be finite and > 0");
+    if (m_max < 2 || m_max >= kMaxLeja) return bfail(EXPI_EINVAL, "m_max must be in [2, 255]");
+    Batch* b = new Batch();
+    b->count = count;
+    b->dtype = dtype;
+    b->bc = bc;
+    b->m_max = m_max;
+    b->waves = 4;
+    b->march = 8;
+    b->c0 = coef;
+    b->tol = tol;
+    const int nd = m_max + 1;
+    const double* xi = leja_points(nd);
+    b->xi.assign(xi, xi + nd);
+    b->dd.resize((size_t)count * nd);
+    b->info.resize(count);
+    long long off = 0;
+    int max_sub = 1;
+    for (int i = 0; i < count; ++i) {
+        if (nx[i] < 1 || ny[i] < 1 || (long long)nx[i] * ny[i] >= (1ll << 28) ||
+            !(hx[i] > 0) || !(hy[i] > 0) || !std::isfinite(hx[i]) || !std::isfinite(hy[i]) ||
+            !(tau[i] >= 0) || !std::isfinite(tau[i])) {
+            delete b;
+            return bfail(EXPI_EINVAL, "instance " + std::to_string(i) + ": bad size, spacing or tau");
+        }
+        BatchInfo& I = b->info[i];
+        I.off = off;
+        off += ((long long)nx[i] * ny[i] + 31) / 32 * 32;   // 256-byte aligned starts
+        I.nx = nx[i];
+        I.ny = ny[i];
+        I.vec = (nx[i] % 2 == 0) ? 2 : 1;
+        I.ihx = 1.0 / (hx[i] * hx[i]);
+        I.ihy = 1.0 / (hy[i] * hy[i]);
+        // Gershgorin bound of the constant-coefficient 5-point operator with the
+        // boundary folded in: every row lies in [-4 coef (1/hx^2 + 1/hy^2), 0]
+        const double a = -4.0 * coef * (I.ihx + I.ihy), bb = 0.0;
+        const double c = 0.5 * (a + bb), gamma = 0.25 * (bb - a);
+        double q = std::ceil(tau[i] * (bb - a) / l_max);
+        const int s = q < 1.0 ? 1 : (int)q;
+        I.s = s;
+        max_sub = std::max(max_sub, s);
+        I.alpha = 1.0 / gamma;
+        I.cg = c / gamma;
+        I.tau = tau[i];
+        I.inv_s = 1.0 / s;
+        I.dd_off = i * nd;
+        divided_differences(1, tau[i] / s, c, gamma, nd, &b->dd[(size_t)i * nd]);
+    }
+    b->total_len = off;
+    // each substep: start, first, at most m_max - 1 products, update
+    b->max_rounds = max_sub * (m_max + 2) + 2;
+    layout_tiles(*b);
+    *out = reinterpret_cast<expi_batch*>(b);
+    return EXPI_OK;
+}
+
+int expi_batch_destroy(expi_batch* bp) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (b) {
+        if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        delete b;
+    }
+    return EXPI_OK;
+}
+
+int expi_batch_set_tiles(expi_batch* bp, int waves, int march) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b) return bfail(EXPI_EINVAL, "batch is NULL");
+    if (waves < 1 || waves > kMaxWaves || march < 4 || march > 64 || march % 4)
+        return bfail(EXPI_EINVAL, "waves in [1, 8], march in {4, 8, ..., 64}");
+    if (b->graph_exec) return bfail(EXPI_EINVAL, "tiles cannot change after a graph was captured");
+    b->waves = waves;
+    b->march = march;
+    const size_t keep = b->ws_total;
+    layout_tiles(*b);
+    b->ws_total = keep > b->ws_total ? keep : b->ws_total;
+    b->prepared_ws = nullptr;
+    return EXPI_OK;
+}
+
+int64_t expi_batch_total_length(const expi_batch* bp) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    return b ? b->total_len : -1;
+}
+
+int expi_batch_offsets(const expi_batch* bp, int64_t* off) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    if (!b || !off) return bfail(EXPI_EINVAL, "NULL argument");
+    for (int i = 0; i < b->count; ++i) off[i] = b->info[i].off;
+    return EXPI_OK;
+}
+
+size_t expi_batch_workspace_bytes(const expi_batch* bp) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    return b ? b->ws_total : 0;
+}
+
+int expi_batch_prepare(expi_batch* bp, void* ws, size_t ws_bytes, void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !ws) return bfail(EXPI_EINVAL, "batch and ws must be non-NULL");
+    if (((uintptr_t)ws & 255) != 0) return bfail(EXPI_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < b->ws_total) return bfail(EXPI_EWORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    BHIP(hipMemcpyAsync(w + b->off_info, b->info.data(), sizeof(BatchInfo) * b->count,
+                        hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync(w + b->off_dd, b->dd.data(), sizeof(double) * b->dd.size(),
+                        hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync(w + b->off_xi, b->xi.data(), sizeof(double) * b->xi.size(),
+                        hipMemcpyHostToDevice, s));
+    BHIP(hipStreamSynchronize(s));
+    int rc = occupancy_grid(*b);
+    if (rc) return rc;
+    b->prepared_ws = ws;
+    return EXPI_OK;
+}
+
+// The persistent launch is switched off: on the GPU it did not finish (the
+// host waited past its test's time limit on both runs, the second with
+// cooperative launches and time-bounded barrier waits), and the cause has
+// not been shown yet.  Creation, layout and the host-side tables still work.
+static int batch_disabled() {
+    return bfail(EXPI_EUNSUPPORTED,
+                 "the persistent batched kernel is switched off until the cause of its "
+                 "unfinished GPU runs is found");
+}
+
+int expi_batch_launch(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
+                      void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
+    if (kBatchLaunchEnabled == 0) return batch_disabled();
+    if (ws != b->prepared_ws) return bfail(EXPI_EINVAL, "call expi_batch_prepare with this workspace first");
+    if (ws_bytes < b->ws_total) return bfail(EXPI_EWORKSPACE, "workspace too small");
+    const size_t vb = (size_t)b->total_len * 8;
+    const char* pv = reinterpret_cast<const char*>(v);
+    const char* py = reinterpret_cast<const char*>(y);
+    if (pv < py + vb && py < pv + vb) return bfail(EXPI_EALIAS, "y overlaps v");
+    return enqueue(*b, static_cast<char*>(ws), v, y, static_cast<hipStream_t>(stream));
+}
+
+int expi_batch_capture(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
+                       void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
+    if (kBatchLaunchEnabled == 0) return batch_disabled();
+    if (ws != b->prepared_ws) return bfail(EXPI_EINVAL, "call expi_batch_prepare with this workspace first");
+    if (ws_bytes < b->ws_total) return bfail(EXPI_EWORKSPACE, "workspace too small");
+    if (b->graph_exec) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        b->graph_exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    (void)stream;
+    return build_graph(*b, static_cast<char*>(ws), v, y);
+}
+
+int expi_batch_replay(expi_batch* bp, void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !b->graph_exec) return bfail(EXPI_EINVAL, "no captured graph");
+    BHIP(hipGraphLaunch(b->graph_exec, static_cast<hipStream_t>(stream)));
+    return EXPI_OK;
+}
+
+int expi_batch_results(expi_batch* bp, void* ws, void* stream, expi_batch_stat* out,
+                       int* rounds) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !ws) return bfail(EXPI_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<BatchState> st(b->count);
+    BatchCtrl ctrl;
+    char* w = static_cast<char*>(ws);
+    BHIP(hipMemcpyAsync(st.data(), w + b->off_state, sizeof(BatchState) * b->count,
+                        hipMemcpyDeviceToHost, s));
+    BHIP(hipMemcpyAsync(&ctrl, w + b->off_ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+    if (rounds) *rounds = (int)ctrl.rounds;
+    int worst = EXPI_OK;
+    for (int i = 0; i < b->count; ++i) {
+        if (out) {
+            out[i].status = st[i].phase == PH_DONE ? 0 : (st[i].status == 2 ? EXPI_ENONFINITE : EXPI_ENOTCONV);
+            out[i].substeps = b->info[i].s;
+            out[i].newton_steps = st[i].newton;
+            out[i].degree_max = st[i].degree_max;
+            out[i].degree_last = st[i].degree_last;
+            out[i].reserved = 0;
+            out[i].err_est = st[i].err_max;
+        }
+        if (st[i].phase != PH_DONE) worst = (st[i].status == 2) ? EXPI_ENONFINITE : EXPI_ENOTCONV;
+    }
+    if (ctrl.abort) return bfail(EXPI_EHIP, "batched kernel aborted: workgroups were not all resident");
+    if (worst == EXPI_ENOTCONV) return bfail(worst, "some instances did not converge within m_max");
+    if (worst == EXPI_ENONFINITE) return bfail(worst, "some instances became non-finite");
+    return EXPI_OK;
+}
+
+}  // extern "C"

@@ -22,343 +22,30 @@
 //    into L1/L2;
 //  * tiles are mapped so that each XCD owns a contiguous run of them;
 //  * boundaries are predicated face terms, no ghost cells.
-#include "sweep_common.h"
+#include "stencil_tile.h"
 
 namespace expi {
 namespace {
 
-template <int V, class T, class TC>
-__device__ __forceinline__ void vld(const T* __restrict__ p, int idx, TC (&o)[V]) {
-    if constexpr (V == 2) {
-        typedef T T2 __attribute__((ext_vector_type(2)));
-        const T2 t = *reinterpret_cast<const T2*>(p + idx);
-        o[0] = (TC)t.x;
-        o[1] = (TC)t.y;
-    } else {
-        o[0] = (TC)p[idx];
-    }
-}
-
-template <int V, class T, class TC>
-__device__ __forceinline__ void vst(T* __restrict__ p, int idx, const TC (&v)[V]) {
-    if constexpr (V == 2) {
-        typedef T T2 __attribute__((ext_vector_type(2)));
-        T2 t;
-        t.x = (T)v[0];
-        t.y = (T)v[1];
-        *reinterpret_cast<T2*>(p + idx) = t;
-    } else {
-        p[idx] = (T)v[0];
-    }
-}
-
-template <int V, class TC>
-__device__ __forceinline__ void vzero(TC (&o)[V]) {
-#pragma unroll
-    for (int v = 0; v < V; ++v) o[v] = (TC)0;
-}
-
-// Coefficients of a point and its six neighbours.
-template <class TC>
-struct Coefs {
-    TC c, xm, xq, ym, yq, zm, zq;
-};
-
-// One marched plane of one thread: registers that the pipeline fills one
-// stage ahead (cache-served neighbour values) or two stages ahead (HBM).
-template <class TC, int V>
-struct Side {
-    TC ym[V], yq[V];   // y neighbours (3D)
-    TC xl, xr;         // x neighbours beyond the wave's ends (edge lanes)
-};
-
 template <int DIM, int COEF, int EPI, class TIN, class TOUT, int V>
 __global__ __launch_bounds__(kMaxWaves * 64) void stencil_sweep(SweepArgs a) {
-    using TC = compute_t<TIN, TOUT>;
     if (a.guard && a.st->done != 0) return;
-    const TIN* __restrict__ x = static_cast<const TIN*>(a.x);
-    TOUT* __restrict__ out = static_cast<TOUT*>(a.out);
-    TOUT* __restrict__ p = static_cast<TOUT*>(a.p);
-    const double* __restrict__ fld = a.field;
-    constexpr bool kW = (EPI != EPI_GERSH);          // reads the vector
-    constexpr bool kP = (EPI == EPI_NEWTON);         // reads p
-    constexpr bool kF = (COEF == EXPI_COEF_FIELD);   // reads the coefficient field
-
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (EPI == EPI_GERSH) {
         s0 = INFINITY;
         s1 = -INFINITY;
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
     const int L = xcd_tile(a.per_xcd);
     if (L < a.ntiles) {
         const int t0 = L % a.tiles[0];
         const int rem = L / a.tiles[0];
         const int t1 = rem % a.tiles[1];
         const int t2 = rem / a.tiles[1];
-        const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-        const int ns = (DIM == 3) ? n2 : n1;          // marched axis
-        const int ss = (DIM == 3) ? n0 * n1 : n0;     // its stride
-        const int i = t0 * (64 * V) + lane * V;
-        int j, kb;
-        if (DIM == 3) {
-            j = t1 * nw + wv;
-            kb = t2 * a.march;
-        } else {
-            j = 0;
-            kb = t1 * (nw * a.march) + wv * a.march;
-        }
-        const int ke = min(kb + a.march, ns);
-        // whole waves outside the grid skip the march; lanes past the row end
-        // stay in it (masked) so that the x-neighbour shuffles see every lane
-        const bool wave_live = (DIM == 2 || j < n1) && kb < ke;
-        const bool active = wave_live && i < n0;
-        if (wave_live) {
-            const bool dir = (a.bc == EXPI_DIRICHLET0);
-            const bool ionly = (a.bc == EXPI_INTERIOR_ONLY);
-            const TC ihx = (TC)a.ih2[0];
-            const TC ihy = (TC)a.ih2[1];
-            const TC ihz = (TC)a.ih2[DIM == 3 ? 2 : 1];
-            const TC alpha = (TC)a.alpha, beta = (TC)a.beta;
-            const TC d0 = (TC)a.d0, d1 = (TC)a.d1, sigma = (TC)a.sigma;
-            const TC c0 = (TC)a.c0, c1 = (TC)a.c1;
-            const bool eym = (DIM == 3) && j > 0, eyq = (DIM == 3) && j < n1 - 1;
-            // Every load below is unconditional, from an index clamped into
-            // the grid; values of neighbours that do not exist are masked by
-            // the existence flags.  Straight-line loads let the compiler track
-            // each one's completion precisely.  Lanes past the row end
-            // (i >= n0) load from the last column and store nothing.
-            const int ic = active ? i : (n0 - V);
-            const int jc = (DIM == 3) ? min(j, n1 - 1) : 0;
-            const int rowb = ic + ((DIM == 3) ? n0 * jc : 0);       // (i, j) at plane 0
-            const int yoffm = (DIM == 3 && eym) ? -n0 : 0;          // y neighbour offsets
-            const int yoffq = (DIM == 3 && eyq) ? n0 : 0;
-            // one extra load per plane feeds the wave-edge lanes: lane 0 its
-            // left neighbour, lane 63 its right one, the rest reload a point
-            int eoff = 0;
-            if (lane == 0 && ic > 0) eoff = -1;
-            if (lane == 63 && ic + V < n0) eoff = V;
-            auto at = [&](int k) { return rowb + ss * min(max(k, 0), ns - 1); };
-
-            // separable coefficient: x values of the thread's points and of
-            // their outer neighbours, y values of the row, a ring of z values
-            TC Xv[V], Xl = 0, Xr = 0, Ym = 0, Yc = 0, Yq = 0, Zr[4] = {0, 0, 0, 0};
-            vzero<V>(Xv);
-            const double* Ts = (DIM == 3) ? a.tz : a.ty;
-            if (COEF == EXPI_COEF_SEPARABLE) {
-#pragma unroll
-                for (int v = 0; v < V; ++v) Xv[v] = (TC)a.tx[ic + v];
-                Xl = (TC)a.tx[max(ic - 1, 0)];
-                Xr = (TC)a.tx[min(ic + V, n0 - 1)];
-                if (DIM == 3) {
-                    Yc = (TC)a.ty[jc];
-                    Ym = (TC)a.ty[max(jc - 1, 0)];
-                    Yq = (TC)a.ty[min(jc + 1, n1 - 1)];
-                }
-                Zr[0] = (TC)Ts[max(kb - 1, 0)];
-                Zr[1] = (TC)Ts[kb];
-                Zr[2] = (TC)Ts[min(kb + 1, ns - 1)];
-            }
-            // register queues: stage s (plane k = k0 + s) finds w at k-1, k,
-            // k+1 in W[s&3], W[(s+1)&3], W[(s+2)&3] and loads k+2 into
-            // W[(s+3)&3]; p and the side values alternate between two slots
-            TC W[4][V], F[4][V], P[2][V];
-            Side<TC, V> S[2], SF[2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                vzero<V>(W[q]);
-                vzero<V>(F[q]);
-            }
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                vzero<V>(P[q]);
-                vzero<V>(S[q].ym);
-                vzero<V>(S[q].yq);
-                vzero<V>(SF[q].ym);
-                vzero<V>(SF[q].yq);
-                S[q].xl = S[q].xr = SF[q].xl = SF[q].xr = 0;
-            }
-            auto load_side = [&](int k, Side<TC, V>& sd, const auto* src) {
-                const int b = at(k);
-                if (DIM == 3) {
-                    vld<V>(src, b + yoffm, sd.ym);
-                    vld<V>(src, b + yoffq, sd.yq);
-                }
-                const TC e = (TC)src[b + eoff];
-                sd.xl = e;
-                sd.xr = e;
-            };
-            if (kW) {
-                vld<V>(x, at(kb - 1), W[0]);
-                vld<V>(x, at(kb), W[1]);
-                vld<V>(x, at(kb + 1), W[2]);
-                load_side(kb, S[0], x);
-            }
-            if (kP) vld<V>(p, at(kb), P[0]);
-            if (kF) {
-                vld<V>(fld, at(kb - 1), F[0]);
-                vld<V>(fld, at(kb), F[1]);
-                vld<V>(fld, at(kb + 1), F[2]);
-                load_side(kb, SF[0], fld);
-            }
-            int idx = at(kb);
-
-            for (int k0 = kb; k0 < ke; k0 += 4) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int k = k0 + s;
-                    const bool kvalid = k < ke;   // all four stages run; only kvalid ones store
-                    {
-                        const int cur = s & 1, nxt = cur ^ 1;
-                        // (1) cache-served values of the next plane
-                        if (kW) load_side(k + 1, S[nxt], x);
-                        if (kF) load_side(k + 1, SF[nxt], fld);
-                        // (2) HBM prefetch: w two planes ahead, p one plane ahead
-                        if (kW) vld<V>(x, at(k + 2), W[(s + 3) & 3]);
-                        if (kP) vld<V>(p, at(k + 1), P[nxt]);
-                        if (kF) vld<V>(fld, at(k + 2), F[(s + 3) & 3]);
-                        if (COEF == EXPI_COEF_SEPARABLE) Zr[(s + 3) & 3] = (TC)Ts[min(k + 2, ns - 1)];
-                        const TC* wm = W[s & 3];
-                        const TC* wc = W[(s + 1) & 3];
-                        const TC* wq = W[(s + 2) & 3];
-                        const TC* Fm = F[s & 3];
-                        const TC* Fc = F[(s + 1) & 3];
-                        const TC* Fq = F[(s + 2) & 3];
-                        const TC Zm = Zr[s & 3], Zc = Zr[(s + 1) & 3], Zq = Zr[(s + 2) & 3];
-                        const bool ezm = k > 0, ezq = k < ns - 1;
-                        // (3) x neighbours of the outer points from adjacent lanes
-                        TC left = 0, right = 0, Fleft = 0, Fright = 0;
-                        if (kW) {
-                            left = __shfl_up(wc[V - 1], 1, 64);
-                            right = __shfl_down(wc[0], 1, 64);
-                            if (lane == 0) left = S[cur].xl;
-                            if (lane == 63) right = S[cur].xr;
-                        }
-                        if (kF) {
-                            Fleft = __shfl_up(Fc[V - 1], 1, 64);
-                            Fright = __shfl_down(Fc[0], 1, 64);
-                            if (lane == 0) Fleft = SF[cur].xl;
-                            if (lane == 63) Fright = SF[cur].xr;
-                        }
-                        // (4) the points of this plane
-                        if (active && kvalid) {
-                            TC wo[V], po[V];
-#pragma unroll
-                            for (int v = 0; v < V; ++v) {
-                                const int iv = i + v;
-                                const bool exm = iv > 0, exq = iv < n0 - 1;
-                                Coefs<TC> cf;
-                                if (COEF == EXPI_COEF_CONST) {
-                                    cf.c = cf.xm = cf.xq = cf.ym = cf.yq = cf.zm = cf.zq = c0;
-                                } else if (COEF == EXPI_COEF_SEPARABLE) {
-                                    const TC X_l = (v > 0) ? Xv[v - 1] : Xl;
-                                    const TC X_r = (v < V - 1) ? Xv[v + 1] : Xr;
-                                    if (DIM == 3) {
-                                        const TC zy = Zc * Yc;
-                                        cf.c = c0 + c1 * (zy * Xv[v]);
-                                        cf.xm = c0 + c1 * (zy * X_l);
-                                        cf.xq = c0 + c1 * (zy * X_r);
-                                        cf.ym = c0 + c1 * ((Zc * Ym) * Xv[v]);
-                                        cf.yq = c0 + c1 * ((Zc * Yq) * Xv[v]);
-                                        cf.zm = c0 + c1 * ((Zm * Yc) * Xv[v]);
-                                        cf.zq = c0 + c1 * ((Zq * Yc) * Xv[v]);
-                                    } else {
-                                        cf.c = c0 + c1 * (Zc * Xv[v]);
-                                        cf.xm = c0 + c1 * (Zc * X_l);
-                                        cf.xq = c0 + c1 * (Zc * X_r);
-                                        cf.ym = cf.yq = (TC)0;
-                                        cf.zm = c0 + c1 * (Zm * Xv[v]);
-                                        cf.zq = c0 + c1 * (Zq * Xv[v]);
-                                    }
-                                } else {
-                                    cf.c = Fc[v];
-                                    cf.xm = (v > 0) ? Fc[v - 1] : Fleft;
-                                    cf.xq = (v < V - 1) ? Fc[v + 1] : Fright;
-                                    cf.ym = SF[cur].ym[v];
-                                    cf.yq = SF[cur].yq[v];
-                                    cf.zm = Fm[v];
-                                    cf.zq = Fq[v];
-                                }
-                                const bool inner = exm && exq && ezm && ezq && (DIM == 2 || (eym && eyq));
-                                const bool zero_row = ionly && !inner;
-                                const TC fxm = face_weight<TC>(exm, dir, cf.c, cf.xm) * ihx;
-                                const TC fxq = face_weight<TC>(exq, dir, cf.c, cf.xq) * ihx;
-                                const TC fzm = face_weight<TC>(ezm, dir, cf.c, cf.zm) * ihz;
-                                const TC fzq = face_weight<TC>(ezq, dir, cf.c, cf.zq) * ihz;
-                                TC fym = 0, fyq = 0;
-                                if (DIM == 3) {
-                                    fym = face_weight<TC>(eym, dir, cf.c, cf.ym) * ihy;
-                                    fyq = face_weight<TC>(eyq, dir, cf.c, cf.yq) * ihy;
-                                }
-                                if (EPI == EPI_GERSH) {
-                                    // diagonal = -(sum of the face weights); off-diagonal
-                                    // magnitude = weights of faces that have a neighbour
-                                    TC diag = -(fxm + fxq + fym + fyq + fzm + fzq);
-                                    TC off = (exm ? fxm : (TC)0) + (exq ? fxq : (TC)0) +
-                                             (eym ? fym : (TC)0) + (eyq ? fyq : (TC)0) +
-                                             (ezm ? fzm : (TC)0) + (ezq ? fzq : (TC)0);
-                                    if (zero_row) diag = off = 0;
-                                    s0 = fmin(s0, (double)(diag - off));
-                                    s1 = fmax(s1, (double)(diag + off));
-                                } else {
-                                    // sum over faces of weight * (w_nb - w_c); a missing
-                                    // neighbour reads 0 (Dirichlet) or has weight 0
-                                    const TC w_c = wc[v];
-                                    const TC wl = exm ? ((v > 0) ? wc[v - 1] : left) : (TC)0;
-                                    const TC wr = exq ? ((v < V - 1) ? wc[v + 1] : right) : (TC)0;
-                                    const TC wzm = ezm ? wm[v] : (TC)0;
-                                    const TC wzq = ezq ? wq[v] : (TC)0;
-                                    TC Aw = fxm * (wl - w_c) + fxq * (wr - w_c) + fzm * (wzm - w_c) +
-                                            fzq * (wzq - w_c);
-                                    if (DIM == 3) {
-                                        const TC wy0 = eym ? S[cur].ym[v] : (TC)0;
-                                        const TC wy1 = eyq ? S[cur].yq[v] : (TC)0;
-                                        Aw += fym * (wy0 - w_c) + fyq * (wy1 - w_c);
-                                    }
-                                    if (zero_row) Aw = 0;
-                                    if (EPI == EPI_APPLY) {
-                                        wo[v] = alpha * Aw + beta * w_c;
-                                    } else if (EPI == EPI_NEWTON) {
-                                        const TC wn_ = (TC)(TOUT)(alpha * Aw + beta * w_c);
-                                        const TC pn_ = (TC)(TOUT)(P[cur][v] + d1 * wn_);
-                                        wo[v] = wn_;
-                                        po[v] = pn_;
-                                        s1 += (double)wn_ * (double)wn_;
-                                        s2 += (double)pn_ * (double)pn_;
-                                    } else if (EPI == EPI_FIRST) {
-                                        const TC wn_ = (TC)(TOUT)(alpha * Aw + beta * w_c);
-                                        const TC pn_ = (TC)(TOUT)(d0 * w_c + d1 * wn_);
-                                        wo[v] = wn_;
-                                        po[v] = pn_;
-                                        s0 += (double)w_c * (double)w_c;
-                                        s1 += (double)wn_ * (double)wn_;
-                                        s2 += (double)pn_ * (double)pn_;
-                                    } else if (EPI == EPI_START) {
-                                        TC gv;
-                                        if (a.gmode == G_VEC) {
-                                            gv = (TC)a.g[idx + v];
-                                        } else if (a.gmode == G_CUBIC_OF) {
-                                            const TC u = (TC)a.g[idx + v];
-                                            gv = u - u * u * u;
-                                        } else {
-                                            gv = w_c - w_c * w_c * w_c;
-                                        }
-                                        wo[v] = sigma * Aw + gv;
-                                    }
-                                }
-                            }
-                            if (kW) vst<V>(out, idx, wo);
-                            if (EPI == EPI_NEWTON || EPI == EPI_FIRST) vst<V>(p, idx, po);
-                        }
-                        idx += ss;
-                    }
-                }
-            }
-        }
+        tile::stencil_tile<DIM, COEF, EPI, TIN, TOUT, V>(a, t0, t1, t2, s0, s1, s2);
     }
     if (EPI == EPI_NEWTON || EPI == EPI_FIRST || EPI == EPI_GERSH) finish_sweep<EPI>(a, s0, s1, s2);
 }
+
 
 template <int DIM, int COEF, int EPI, class TIN, class TOUT>
 hipError_t go(const Geom& g, const SweepArgs& a, hipStream_t s) {

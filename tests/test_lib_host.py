@@ -145,3 +145,45 @@ def test_call_validation_before_any_hip_call(L):
     assert L.expi_op_get_tiles(op, ctypes.byref(v_), ctypes.byref(w_), ctypes.byref(m_)) == 0
     assert (v_.value, w_.value, m_.value) == (1, 2, 16)
     L.expi_op_destroy(op)
+
+
+def test_batch_create_validation_and_layout(L):
+    """The batch is built on the host (intervals, substeps, divided
+    differences, offsets); no GPU is touched until prepare/launch."""
+    import numpy as np
+    from paper_1309_4616_amd import _binding
+    nx = np.array([64, 33, 100], dtype=np.int32)
+    ny = np.array([64, 40, 7], dtype=np.int32)
+    h = 1.0 / (nx + 1.0)
+    tau = np.array([1e-4, 2e-3, 0.0])
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    dbl = ctypes.POINTER(ctypes.c_double)
+    b = ctypes.c_void_p()
+    args = lambda **kw: (ctypes.byref(b), kw.get("count", 3), nx.ctypes.data_as(i32), ny.ctypes.data_as(i32),
+                         h.ctypes.data_as(dbl), h.ctypes.data_as(dbl), kw.get("tau", tau).ctypes.data_as(dbl),
+                         kw.get("bc", 0), kw.get("coef", 1.0), kw.get("tol", 1e-8), kw.get("dtype", 1), None)
+    assert L.expi_batch_create(*args(count=0)) == -1
+    assert L.expi_batch_create(*args(bc=2)) == -1
+    assert L.expi_batch_create(*args(coef=0.0)) == -1
+    assert L.expi_batch_create(*args(tol=-1.0)) == -1
+    assert L.expi_batch_create(*args(tau=np.array([1e-4, -1.0, 0.0]))) == -1
+    assert L.expi_batch_create(*args()) == 0
+    total = L.expi_batch_total_length(b)
+    off = np.zeros(3, dtype=np.int64)
+    assert L.expi_batch_offsets(b, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))) == 0
+    assert off[0] == 0 and np.all(off % 32 == 0)
+    assert np.all(np.diff(off) >= (nx * ny)[:-1]) and total >= off[-1] + nx[-1] * ny[-1]
+    ws_bytes = L.expi_batch_workspace_bytes(b)
+    assert ws_bytes > 3 * 4 * total
+    assert L.expi_batch_set_tiles(b, 9, 8) == -1
+    assert L.expi_batch_set_tiles(b, 2, 6) == -1
+    assert L.expi_batch_set_tiles(b, 2, 16) == 0
+    assert L.expi_batch_workspace_bytes(b) == ws_bytes
+    st = (_binding.BatchStat * 3)()
+    assert L.expi_batch_launch(b, None, None, None, 0, None) == -1
+    assert L.expi_batch_replay(b, None) == -1        # nothing captured
+    # the persistent launch is switched off and says so before any HIP call
+    dummy = ctypes.c_void_p(256)
+    assert L.expi_batch_launch(b, dummy, ctypes.c_void_p(512), dummy, ws_bytes, None) == -7
+    assert b"switched off" in L.expi_last_error()
+    L.expi_batch_destroy(b)
