@@ -95,6 +95,13 @@ typedef struct {
                                kernels (HIP events recorded on `stream` around
                                each sweep launch); only products that did work
                                (index < m) are counted */
+    double  rnorm;          /* ||r|| of the first substep's start vector        */
+    double  t_first[5];     /* |d_j| ||w_j||, j = 0..4, of the first substep
+                               (features of the step selector)                 */
+    int32_t pred_degree;    /* step selector: predicted degree (0 if unused)    */
+    int32_t pred_substeps;  /* step selector: predicted substep count           */
+    int32_t fallback;       /* step selector: products beyond the prediction     */
+    int32_t finalized;      /* products whose norms were reduced (stop tests)   */
 } expi_stats;
 
 /* Interpolation parameters; pass NULL for the defaults
@@ -108,6 +115,17 @@ typedef struct {
     int32_t profile;        /* 1: time each fused Newton product (stats)        */
     double  interval_a;
     double  interval_b;
+    /* Learned step selector (optional): device float buffer laid out as
+     * x_mean[8], x_std[8], y_mean[2], y_std[2], then the network parameters
+     * (expi_mlp_param_count(selector_hidden) values).  When set, each Newton
+     * loop takes its first four products with stop tests, the network
+     * predicts the degree m from the features (interval, tau, ||r||,
+     * t_0..t_4), the products up to m run without norm reductions, and the
+     * two-term stop test judges the result at m; if it is not met the plain
+     * error-controlled loop continues (fallback). */
+    const void *selector;
+    int32_t selector_hidden;
+    int32_t reserved2;
 } expi_params;
 
 /* ---- operators ---------------------------------------------------------- */
@@ -260,6 +278,29 @@ int expi_batch_replay(expi_batch *b, void *stream);
  * instance converged.  `rounds` (may be NULL) receives the rounds the
  * persistent kernel ran. */
 int expi_batch_results(expi_batch *b, void *ws, void *stream, expi_batch_stat *out, int *rounds);
+
+/* ---- step-selector network (float32, device buffers) --------------------- */
+
+/* Network 8 -> H -> H -> 2 (ReLU); parameters packed as W1 (H x 8, row-major),
+ * b1 (H), W2 (H x H), b2 (H), W3 (2 x H), b3 (2).  Returns 0 for H outside
+ * [1, 256]. */
+size_t expi_mlp_param_count(int hidden);
+/* Floats of scratch memory expi_mlp_backward needs for n samples. */
+size_t expi_mlp_scratch_floats(int hidden, int n);
+/* out[n x 2] = network(x[n x 8]); act (n x 2H, may be NULL) keeps the
+ * pre-activations for the backward pass. */
+int expi_mlp_forward(int hidden, const float *params, const float *x, int n, float *out,
+                     float *act, void *stream);
+/* Gradient of the asymmetric loss L = 1/(2n) sum w (out - target)^2,
+ * w = kappa where out < target, else 1, into grad (param_count floats);
+ * *loss (device float, may be NULL) receives L.  Sample sums run in index
+ * order (deterministic). */
+int expi_mlp_backward(int hidden, const float *params, const float *x, const float *act,
+                      const float *out, const float *target, int n, float kappa, float *grad,
+                      float *loss, float *scratch, void *stream);
+/* One Adam step (bias-corrected moments), step counts from 1. */
+int expi_mlp_adam(int count, float *params, const float *grad, float *m, float *v, int step,
+                  float lr, float beta1, float beta2, float eps, void *stream);
 
 /* ---- host-side interpolation data (no GPU needed) ----------------------- */
 

@@ -11,14 +11,14 @@ from __future__ import annotations
 
 import ctypes
 
-from . import autotune
+from . import autotune, selector
 from ._binding import (COEF_CONST, COEF_FIELD, COEF_SEPARABLE, F32, F64, G_CUBIC, BCS, EXPORTS,
                        BatchStat, ExpiError, LejaParams, Stats, check, divided_differences,
                        leja_points, lib)
 
 __all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "expeuler_step", "leja_points",
            "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32",
-           "autotune", "Batch"]
+           "autotune", "selector", "Batch"]
 
 
 def _torch():

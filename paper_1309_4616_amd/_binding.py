@@ -28,7 +28,8 @@ EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "e
            "expi_batch_create", "expi_batch_destroy", "expi_batch_set_tiles",
            "expi_batch_total_length", "expi_batch_offsets", "expi_batch_workspace_bytes",
            "expi_batch_prepare", "expi_batch_launch", "expi_batch_capture", "expi_batch_replay",
-           "expi_batch_results")
+           "expi_batch_results", "expi_mlp_param_count", "expi_mlp_scratch_floats",
+           "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam")
 
 
 class ExpiError(RuntimeError):
@@ -44,10 +45,15 @@ class Stats(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("degree_max", ctypes.c_int32),
                 ("degree_last", ctypes.c_int32), ("timed_products", ctypes.c_int32),
                 ("err_est", ctypes.c_double), ("interval_a", ctypes.c_double),
-                ("interval_b", ctypes.c_double), ("newton_ms", ctypes.c_double)]
+                ("interval_b", ctypes.c_double), ("newton_ms", ctypes.c_double),
+                ("rnorm", ctypes.c_double), ("t_first", ctypes.c_double * 5),
+                ("pred_degree", ctypes.c_int32), ("pred_substeps", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("finalized", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["t_first"] = list(self.t_first)
+        return d
 
 
 class BatchStat(ctypes.Structure):
@@ -64,7 +70,8 @@ class Params(ctypes.Structure):
     _fields_ = [("l_max", ctypes.c_double), ("m_max", ctypes.c_int32),
                 ("max_retries", ctypes.c_int32), ("have_interval", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("interval_a", ctypes.c_double),
-                ("interval_b", ctypes.c_double)]
+                ("interval_b", ctypes.c_double), ("selector", ctypes.c_void_p),
+                ("selector_hidden", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 @dataclass
@@ -74,6 +81,8 @@ class LejaParams:
     max_retries: int = 4
     interval: tuple | None = None
     profile: bool = False
+    selector: object = None          # device float tensor (see selector.pack)
+    selector_hidden: int = 64
 
     def to_c(self) -> Params:
         p = Params()
@@ -81,6 +90,9 @@ class LejaParams:
         p.m_max = int(self.m_max)
         p.max_retries = int(self.max_retries)
         p.profile = 1 if self.profile else 0
+        if self.selector is not None:
+            p.selector = ctypes.c_void_p(self.selector.data_ptr())
+            p.selector_hidden = int(self.selector_hidden)
         if self.interval is not None:
             p.have_interval = 1
             p.interval_a, p.interval_b = (float(v) for v in self.interval)
@@ -157,6 +169,18 @@ def lib() -> ctypes.CDLL:
     L.expi_batch_results.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(BatchStat),
                                      ctypes.POINTER(c_int)]
     L.expi_batch_results.restype = c_int
+    L.expi_mlp_param_count.argtypes = [c_int]
+    L.expi_mlp_param_count.restype = c_size_t
+    L.expi_mlp_scratch_floats.argtypes = [c_int, c_int]
+    L.expi_mlp_scratch_floats.restype = c_size_t
+    L.expi_mlp_forward.argtypes = [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]
+    L.expi_mlp_forward.restype = c_int
+    L.expi_mlp_backward.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                    ctypes.c_float, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.expi_mlp_backward.restype = c_int
+    L.expi_mlp_adam.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]
+    L.expi_mlp_adam.restype = c_int
     L.expi_leja_points.argtypes = [dblp, c_int]
     L.expi_leja_points.restype = c_int
     L.expi_divided_differences.argtypes = [c_int, c_double, c_double, c_double, c_int, dblp]

@@ -141,6 +141,8 @@ struct Params {
     bool have_interval = false;
     bool profile = false;
     double ia = 0, ib = 0;
+    const float* selector = nullptr;
+    int hidden = 0;
 };
 
 int read_params(const expi_params* p, Params* out) {
@@ -153,7 +155,11 @@ int read_params(const expi_params* p, Params* out) {
         q.profile = p->profile != 0;
         q.ia = p->interval_a;
         q.ib = p->interval_b;
+        q.selector = static_cast<const float*>(p->selector);
+        q.hidden = p->selector_hidden;
     }
+    if (q.selector && (q.hidden < 1 || q.hidden > 256))
+        return fail(EXPI_EINVAL, "params.selector_hidden must be in [1, 256]");
     if (!(q.l_max > 0) || !std::isfinite(q.l_max)) return fail(EXPI_EINVAL, "params.l_max must be positive and finite");
     if (q.m_max < 2 || q.m_max >= kMaxLeja) return fail(EXPI_EINVAL, "params.m_max must be in [2, 255]");
     if (q.max_retries < 0 || q.max_retries > 30) return fail(EXPI_EINVAL, "params.max_retries must be in [0, 30]");
@@ -242,6 +248,11 @@ struct LoopOut {
     double err = 0;
     int timed = 0;        // products timed (profile mode)
     double ms = 0;        // their summed device time
+    double rnorm = 0;     // ||r||
+    double hist[kHist] = {0, 0, 0, 0, 0};
+    int pred_m = 0, pred_s = 0;
+    int fallback = 0;     // learned mode: the prediction fell short
+    int finalized = 0;    // products followed by a norm reduction and stop test
 };
 
 struct Ctx {
@@ -258,6 +269,9 @@ struct Ctx {
     int m_max;
     DdKey key;
     bool profile;
+    const float* selector;
+    int hidden;
+    double ia, ib, tau;
 };
 
 // First product reads `src` (storage code tin) and writes w_1 to w0 and p to
@@ -279,52 +293,103 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     a.d1 = d[1];
     a.guard = 0;
     HIP_TRY(launch_sweep(*C.op, EPI_FIRST, tin, C.tw, a, C.s));
+    int finalized = 1;
 
-    const int hint = get_hint(*C.op, C.key);
+    // product j of the loop (j >= 1); `fin` adds the norm reduction and stop test
+    auto product = [&](int j, bool fin) -> int {
+        a.x = w[(j - 1) & 1];
+        a.out = w[j & 1];
+        a.j = j;
+        a.beta = -(C.c / C.gamma + C.xi[j]);
+        a.d1 = d[j + 1];
+        a.guard = 1;
+        if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
+        HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s,
+                             C.profile ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
+        if (fin) ++finalized;
+        return EXPI_OK;
+    };
+    auto sync_state = [&](NewtonState* st) -> int {
+        int slot;
+        int rc = readback(C.st, C.s, &slot);
+        if (rc) return rc;
+        return wait_slot(slot, st);
+    };
+
     int j = 1;
-    // With a degree hint the first batch ends exactly at the expected stop and
-    // later products go one by one; without one, batches of 4 then 2 run one
-    // batch ahead of the status read-back.
-    int chunk = hint >= 2 ? hint - 1 : 4;
-    const bool ahead = hint < 2;
-    std::deque<int> pending;
     NewtonState last{};
     bool finished = false;
-    while (!finished) {
-        if (j < C.m_max) {
-            const int cnt = std::min(chunk, C.m_max - j);
-            for (int q = 0; q < cnt; ++q, ++j) {
-                a.x = w[(j - 1) & 1];
-                a.out = w[j & 1];
-                a.j = j;
-                a.beta = -(C.c / C.gamma + C.xi[j]);
-                a.d1 = d[j + 1];
-                a.guard = 1;
-                if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
-                HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s,
-                                     C.profile ? tl_ctx.tev[2 * j + 1] : nullptr));
-            }
-            int slot;
-            int rc = readback(C.st, C.s, &slot);
+    bool learned_tail = false;
+    if (C.selector && C.m_max >= 6) {
+        // Learned mode: four products with stop tests give the features; the
+        // network predicts the degree m; products up to m skip the norm
+        // reductions except the last two, whose two-term stop test judges the
+        // prediction.  If it is not met the plain loop below continues.
+        for (; j < 4; ++j) {
+            int rc = product(j, true);
             if (rc) return rc;
-            pending.push_back(slot);
-            chunk = ahead ? 2 : 1;
         }
-        const size_t keep = ahead ? 1 : 0;
-        while (!pending.empty() && (pending.size() > keep || j >= C.m_max)) {
-            int rc = wait_slot(pending.front(), &last);
-            if (rc) return rc;
-            pending.pop_front();
-            if (last.done) {
-                finished = true;
-                break;
+        HIP_TRY(launch_selector(C.selector, C.hidden, C.st, C.ia, C.ib, C.tau, C.m_max, C.s));
+        int rc = sync_state(&last);
+        if (rc) return rc;
+        out->pred_m = last.pred_m;
+        out->pred_s = last.pred_s;
+        if (last.done) {
+            finished = true;
+        } else {
+            const int mh = std::min(std::max(last.pred_m, j + 1), C.m_max);
+            for (; j < mh; ++j) {
+                rc = product(j, j >= mh - 2);
+                if (rc) return rc;
             }
+            rc = sync_state(&last);
+            if (rc) return rc;
+            if (last.done) finished = true;
+            else out->fallback = 1;
         }
-        if (!finished && pending.empty() && j >= C.m_max) finished = true;
+        learned_tail = true;
+    }
+
+    if (!finished) {
+        const int hint = learned_tail ? 0 : get_hint(*C.op, C.key);
+        // With a degree hint (or after a prediction) the first batch ends at
+        // the expected stop and later products go one by one; without one,
+        // batches of 4 then 2 run one batch ahead of the status read-back.
+        int chunk = learned_tail ? 1 : (hint >= 2 ? hint - 1 : 4);
+        const bool ahead = !learned_tail && hint < 2;
+        std::deque<int> pending;
+        while (!finished) {
+            if (j < C.m_max) {
+                const int cnt = std::min(chunk, C.m_max - j);
+                for (int q = 0; q < cnt; ++q, ++j) {
+                    int rc = product(j, true);
+                    if (rc) return rc;
+                }
+                int slot;
+                int rc = readback(C.st, C.s, &slot);
+                if (rc) return rc;
+                pending.push_back(slot);
+                chunk = ahead ? 2 : 1;
+            }
+            const size_t keep = ahead ? 1 : 0;
+            while (!pending.empty() && (pending.size() > keep || j >= C.m_max)) {
+                int rc = wait_slot(pending.front(), &last);
+                if (rc) return rc;
+                pending.pop_front();
+                if (last.done) {
+                    finished = true;
+                    break;
+                }
+            }
+            if (!finished && pending.empty() && j >= C.m_max) finished = true;
+        }
     }
     out->m = last.m;
     out->done = last.done;
     out->err = last.err;
+    out->rnorm = last.rnorm;
+    for (int q = 0; q < kHist; ++q) out->hist[q] = last.hist[q];
+    out->finalized = finalized;
     if (last.done == 1) set_hint(*C.op, C.key, last.m);
     if (C.profile && last.done != 2) {
         // products 1..m-1 did work and precede the read-back that ended the loop
@@ -339,6 +404,15 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
 }
 
 void stats_add(expi_stats* st, const LoopOut& lo) {
+    if (st->newton_steps == 0 && st->matvecs <= 1) {
+        // features of the first substep's loop
+        st->rnorm = lo.rnorm;
+        for (int q = 0; q < kHist; ++q) st->t_first[q] = lo.hist[q];
+        st->pred_degree = lo.pred_m;
+        st->pred_substeps = lo.pred_s;
+    }
+    st->fallback += lo.fallback;
+    st->finalized += lo.finalized;
     st->newton_steps += lo.m;
     st->matvecs += lo.m;
     st->degree_max = std::max(st->degree_max, lo.m);
@@ -412,7 +486,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
         return fail(EXPI_EUNSUPPORTED, "phi_k with k >= 2 needs a single substep (tau (b-a) <= l_max)");
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile};
+          P.profile, P.selector, P.hidden, ia, ib, tau};
     expi_stats acc{};
     for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
         if (k >= 2 && sub > 1)
@@ -498,7 +572,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     int sub = substep_count(tau, ia, ib, P.l_max);
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile};
+          P.profile, P.selector, P.hidden, ia, ib, tau};
     double* yb = reinterpret_cast<double*>(ws + L.y);
     void* p = ws + L.p;
     expi_stats acc{};

@@ -15,6 +15,8 @@
 
 namespace expi {
 
+constexpr int kHist = 5;         // Newton-term norms t_0..t_4 kept per loop
+
 // ---------------------------------------------------------------------------
 // Device-side status of one Newton loop (lives at the start of the workspace).
 // Written by the finalize kernel after each reducing sweep; read back by the host.
@@ -29,8 +31,12 @@ struct alignas(64) NewtonState {
     double pnorm;         // ||p||
     double wnorm;         // ||w_m||
     double gmin, gmax;    // Gershgorin reduction result
+    double hist[kHist];   // t_0 .. t_4 of this loop (features of the step selector)
+    double rnorm;         // ||r|| of the loop's start vector
+    int pred_m;           // step selector's predicted Newton degree
+    int pred_s;           // step selector's predicted substep count
 };
-static_assert(sizeof(NewtonState) == 64, "status record is 64 bytes");
+static_assert(sizeof(NewtonState) == 128, "status record is 128 bytes");
 
 // Epilogues of the fused sweep.
 enum Epilogue : int {
@@ -82,6 +88,11 @@ struct FinalArgs {
     int guard;
     double d0, d1, tol;
 };
+
+// Step-selector network (mlp.hip): predicted (substeps, degree) from the
+// interval, tau, ||r|| and t_0..t_4 in `st`; written to st->pred_s/pred_m.
+hipError_t launch_selector(const float* sel, int hidden, NewtonState* st, double a, double b,
+                           double tau, int m_max, hipStream_t s);
 
 // Tile setting of an operator's sweeps (chosen by default or by the tuner).
 //   stencil: vec = x points per thread (1 or 2), waves per workgroup,
@@ -141,7 +152,8 @@ size_t partials_bytes(const Op& op);
 // `after_sweep`, if given, is recorded on `s` between the sweep and its
 // finalize kernel (profiling of the sweep alone).
 hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a,
-                        hipStream_t s, hipEvent_t after_sweep = nullptr);
+                        hipStream_t s, hipEvent_t after_sweep = nullptr,
+                        bool finalize = true);
 hipError_t launch_stencil(const Op& op, const Geom& g, int epi, int tin, int tout,
                           const SweepArgs& a, hipStream_t s);
 hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs& a,

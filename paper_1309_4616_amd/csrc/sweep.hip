@@ -71,6 +71,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs f) {
     st->wnorm = wn;
     st->m = m;
     st->done = done;
+    if (EPI == EPI_FIRST) {
+        st->rnorm = sqrt(s0);
+        st->hist[0] = tprev;
+    }
+    if (m < kHist) st->hist[m] = t;
 }
 
 template <class TP>
@@ -96,6 +101,10 @@ __global__ void reset_kernel(NewtonState* st) {
         st->wnorm = 0.0;
         st->gmin = 0.0;
         st->gmax = 0.0;
+        for (int q = 0; q < kHist; ++q) st->hist[q] = 0.0;
+        st->rnorm = 0.0;
+        st->pred_m = 0;
+        st->pred_s = 0;
     }
 }
 
@@ -176,7 +185,7 @@ size_t partials_bytes(const Op& op) {
 }
 
 hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, hipStream_t s,
-                        hipEvent_t after_sweep) {
+                        hipEvent_t after_sweep, bool finalize) {
     Tiles t = op.tiles;
     if (op.kind == 0 && t.vec == 2) {
         // 16-byte vector accesses need an even row length and aligned arrays
@@ -217,6 +226,7 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
         if (e != hipSuccess) return e;
     }
     if (epi != EPI_NEWTON && epi != EPI_FIRST && epi != EPI_GERSH) return hipSuccess;
+    if (!finalize) return hipSuccess;
     FinalArgs f;
     f.partials = a.partials;
     f.st = a.st;

@@ -1,0 +1,155 @@
+"""GPU tests of the step-selector network and the learned mode.
+
+* forward, backward and Adam kernels against the float64 oracle (oracle.mlp);
+* the learned mode on held-out exponential Euler steps of the 3D
+  reaction-diffusion problem: same accuracy as the plain method, with the
+  network's degree prediction replacing most stop tests.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrators as I
+from oracle import mlp as omlp
+from oracle import operators as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E(device):
+    import paper_1309_4616_amd as E
+    E.lib()
+    return E
+
+
+def unpack(vec, H):
+    """Packed W1 b1 W2 b2 W3 b3 -> the oracle's dict."""
+    o = 0
+    out = {}
+    for name, shape in (("W1", (H, 8)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)),
+                        ("W3", (2, H)), ("b3", (2,))):
+        n = int(np.prod(shape))
+        out[name] = np.asarray(vec[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
+
+
+def pack(p):
+    return np.concatenate([p[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+@pytest.mark.parametrize("H", [16, 64])
+def test_mlp_kernels_match_oracle(E, H):
+    import torch
+    rng = np.random.default_rng(H)
+    net = E.selector.Net(H, seed=3)
+    p64 = unpack(net.params.double().cpu().numpy(), H)
+    for k in ("b1", "b2", "b3"):
+        p64[k] = rng.uniform(-0.3, 0.3, size=p64[k].shape)
+    net.params.copy_(torch.as_tensor(pack(p64), dtype=torch.float32))
+    p64 = unpack(net.params.double().cpu().numpy(), H)   # what the device holds
+    n = 37
+    x = rng.standard_normal((n, 8))
+    t = rng.standard_normal((n, 2))
+    xt = torch.as_tensor(x, dtype=torch.float32, device="cuda:0")
+    tt = torch.as_tensor(t, dtype=torch.float32, device="cuda:0")
+    x32 = xt.double().cpu().numpy()
+    t32 = tt.double().cpu().numpy()
+    o_ref, cache = omlp.forward(p64, x32)
+    g, loss, out = net.grad(xt, tt, kappa=3.0)
+    assert np.allclose(out.double().cpu().numpy(), o_ref, rtol=1e-5, atol=1e-5)
+    assert loss.item() == pytest.approx(omlp.loss(o_ref, t32, 3.0), rel=1e-5)
+    g_ref = pack(omlp.backward(p64, cache, o_ref, t32, kappa=3.0))
+    gg = g.double().cpu().numpy()
+    scale = np.abs(g_ref).max()
+    assert np.max(np.abs(gg - g_ref)) <= 1e-4 * scale
+    # Adam: three steps with the same gradient against the oracle's update
+    m = {k: np.zeros_like(v) for k, v in p64.items()}
+    v = {k: np.zeros_like(w) for k, w in p64.items()}
+    gd = unpack(gg, H)
+    pr = {k: w.copy() for k, w in p64.items()}
+    for step in range(1, 4):
+        net.adam(g, lr=1e-2)
+        omlp.adam_step(pr, gd, m, v, step, lr=1e-2)
+    assert np.allclose(net.params.double().cpu().numpy(), pack(pr), rtol=1e-5, atol=1e-6)
+
+
+def rd_op(E, n, amp):
+    coef = synth.sine_coefficient(n, amp)
+    h = 1.0 / n
+    return E.StencilOp((n, n, n), (h, h, h), "neumann0",
+                       coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
+
+
+def log_plain(E, n, amps, steps, tau, tol, seed0):
+    """Run plain exponential Euler trajectories; return features, targets, stats."""
+    import torch
+    X, Y, runs = [], [], []
+    for k, amp in enumerate(amps):
+        op = rd_op(E, n, amp)
+        u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=seed0 + k), device="cuda:0")
+        for _ in range(steps):
+            st = E.expeuler_step(op, tau, u, tol=tol)
+            X.append(E.selector.features(st, tau))
+            Y.append(E.selector.targets(st))
+            runs.append(st)
+    return np.array(X), np.array(Y), runs
+
+
+def test_learned_selector_on_held_out_steps(E):
+    import torch
+    n = 40
+    tau = 1e-5 * (256 / n) ** 2     # same stiffness tau*(b-a) as the 256^3 grid at 1e-5
+    tol = 1e-8
+    amps = synth.diffusivity_amplitudes(8, seed=7)
+    X, Y, _ = log_plain(E, n, amps[:6], 12, tau, tol, seed0=100)
+    net, norms, hist = E.selector.train(X, Y, hidden=64, epochs=1500, lr=3e-3, seed=0)
+    assert hist[-1] < 0.5 * hist[0]
+    sel = E.selector.pack(net, norms)
+    pred = E.selector.predict(net, norms, X)
+    assert np.mean(np.abs(pred[:, 1] - Y[:, 1])) < 1.5      # fits the degrees it saw
+    # held-out trajectories: plain vs learned from the same states
+    plain_mv = learned_mv = plain_fin = learned_fin = 0
+    for k, amp in enumerate(amps[6:]):
+        op = rd_op(E, n, amp)
+        u0 = torch.as_tensor(synth.gaussian_bump_3d(n, seed=500 + k), device="cuda:0")
+        up, ul = u0.clone(), u0.clone()
+        params = E.LejaParams(selector=sel, selector_hidden=64)
+        for step in range(10):
+            sp = E.expeuler_step(op, tau, up, tol=tol)
+            sl = E.expeuler_step(op, tau, ul, tol=tol, params=params)
+            plain_mv += sp["matvecs"]
+            learned_mv += sl["matvecs"]
+            plain_fin += sp["finalized"]
+            learned_fin += sl["finalized"]
+            assert sl["pred_degree"] > 0
+            # both met the same two-term test at 1e-8: states agree to that level
+            d = (ul - up).norm().item() / up.norm().item()
+            assert d <= 5e-8, (step, d)
+    # the prediction replaces most stop tests; products stay within ~10%
+    assert learned_fin < 0.6 * plain_fin
+    assert learned_mv <= 1.1 * plain_mv + 2
+    print(f"matvecs plain {plain_mv} learned {learned_mv}; stop tests plain {plain_fin} learned {learned_fin}")
+
+
+def test_learned_mode_matches_oracle(E):
+    """The learned mode's result is judged by the same stop test: at tol 1e-10
+    it agrees with the oracle like the plain method does."""
+    import torch
+    n = 24
+    tau = 1e-5 * (256 / n) ** 2
+    X, Y, _ = log_plain(E, n, [0.3, 0.6, 0.8], 6, tau, 1e-10, seed0=1)
+    net, norms, _ = E.selector.train(X, Y, hidden=32, epochs=800, lr=3e-3, seed=1)
+    sel = E.selector.pack(net, norms)
+    op = rd_op(E, n, 0.5)
+    u0 = synth.gaussian_bump_3d(n, seed=9)
+    u = torch.as_tensor(u0, device="cuda:0")
+    st = E.expeuler_step(op, tau, u, tol=1e-10, params=E.LejaParams(selector=sel, selector_hidden=32))
+    A = O.stencil_matrix((n, n, n), (1 / n,) * 3, "neumann0", coef=synth.sine_coefficient(n, 0.5).field())
+    uo, _ = I.expeuler_step(A, tau, u0, 1e-10)
+    got = u.cpu().numpy()
+    assert np.linalg.norm(got - uo) / np.linalg.norm(uo) <= 1e-10
+    assert st["pred_degree"] > 0
