@@ -127,6 +127,86 @@ def run_gpu(args, dtype: str):
     }
 
 
+def run_learned(args):
+    """Learned vs plain on held-out steps (the step-selector workload):
+    log `train_steps` plain exponential Euler steps of the same 256^3 problem
+    over trajectories whose diffusivity amplitude is drawn from [0.1, 0.9]
+    (seeded), train the selector network on the GPU with the library's
+    kernels, then run `eval_steps` held-out steps both ways from the same
+    states, at the same tolerance."""
+    import numpy as np
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+
+    n = args.n
+    h = 1.0 / n
+    per = 100
+    n_train = max(1, args.train_steps // per)
+    n_eval = max(1, args.eval_steps // per)
+    amps = synth.diffusivity_amplitudes(n_train + n_eval, seed=2024)
+
+    def make_op(amp):
+        coef = synth.sine_coefficient(n, float(amp))
+        return E.StencilOp((n, n, n), (h, h, h), "neumann0",
+                           coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
+
+    X, Y = [], []
+    t0 = time.perf_counter()
+    for k in range(n_train):
+        op = make_op(amps[k])
+        u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=1000 + k), device="cuda:0")
+        for _ in range(min(per, args.train_steps)):
+            st = E.expeuler_step(op, args.tau, u, tol=args.tol)
+            X.append(E.selector.features(st, args.tau))
+            Y.append(E.selector.targets(st))
+        del op
+    log_s = time.perf_counter() - t0
+    X, Y = np.array(X), np.array(Y)
+    t0 = time.perf_counter()
+    net, norms, hist = E.selector.train(X, Y, hidden=64, epochs=2000, lr=3e-3, kappa=1.5, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    sel = E.selector.pack(net, norms)
+    lp = E.LejaParams(selector=sel, selector_hidden=64)
+    res = {"plain": {"mv": 0, "tests": 0, "t": 0.0}, "learned": {"mv": 0, "tests": 0, "t": 0.0}}
+    fallbacks = 0
+    max_diff = 0.0
+    steps = 0
+    for k in range(n_eval):
+        op = make_op(amps[n_train + k])
+        ws = op.workspace("f64")
+        u0 = torch.as_tensor(synth.gaussian_bump_3d(n, seed=5000 + k), device="cuda:0")
+        up, ul = u0.clone(), u0.clone()
+        E.expeuler_step(op, args.tau, u0.clone(), tol=args.tol, ws=ws)   # interval, hints
+        for _ in range(min(per, args.eval_steps)):
+            for key, u, params in (("plain", up, None), ("learned", ul, lp)):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = E.expeuler_step(op, args.tau, u, tol=args.tol, params=params, ws=ws)
+                torch.cuda.synchronize()
+                res[key]["t"] += time.perf_counter() - t1
+                res[key]["mv"] += st["matvecs"]
+                res[key]["tests"] += st["finalized"]
+                if key == "learned":
+                    fallbacks += 1 if st["fallback"] else 0
+            max_diff = max(max_diff, ((ul - up).norm() / up.norm()).item())
+            steps += 1
+        del op
+    out = {
+        "train_steps": len(X), "eval_steps": steps, "hidden": 64,
+        "log_s": log_s, "train_s": train_s, "loss_first_last": [hist[0], hist[-1]],
+        "tol": args.tol,
+        "max_rel_state_diff": max_diff,
+        "fallback_rate": fallbacks / max(steps, 1),
+    }
+    for key in ("plain", "learned"):
+        out[key] = {"matvecs_per_step": res[key]["mv"] / steps,
+                    "stop_tests_per_step": res[key]["tests"] / steps,
+                    "ms_per_step": 1e3 * res[key]["t"] / steps}
+    return out
+
+
 def cpu_baseline(args):
     """The oracle on a bounded sample: the same problem on the 128^3 grid with
     tau scaled by (256/128)^2, which keeps tau*(b-a) and hence the number of
@@ -174,6 +254,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--eval-steps", type=int, default=200)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 512 MiB float64 tensor 3 times (a kernel of known "
                          "traffic, 512 MiB read + 512 MiB written per launch) to calibrate "
@@ -205,6 +288,12 @@ def main():
     if not args.no_fp32:
         r32 = run_gpu(args, "f32")
         print(f"[bench] f32 done: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    learned = None
+    if not args.no_learned:
+        print(f"[bench] learned selector: log {args.train_steps} plain steps, train, "
+              f"evaluate {args.eval_steps} held-out steps", file=sys.stderr, flush=True)
+        learned = run_learned(args)
+        print(f"[bench] learned done", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -267,6 +356,8 @@ def main():
             "step_hbm_gbs": r32["step_gbs"],
             "note": "w, p stored in float32; divided differences, norms, stop test and u in float64",
         }
+    if learned:
+        out["learned_vs_plain"] = learned
     print(json.dumps(out), flush=True)
 
 
