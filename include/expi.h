@@ -220,24 +220,27 @@ int expeuler_step(expi_op *op, int nonlin, double tau, double *u, double tol, in
                   const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
                   void *stream);
 
-/* ---- many problems in one persistent launch ------------------------------ */
+/* ---- many problems in one batch ------------------------------------------ */
 
 /* A batch of independent 2D problems y_i = phi_1(tau_i A_i) v_i, A_i the
  * constant-coefficient 5-point operator coef * Laplacian on an nx_i x ny_i
  * grid with spacings hx_i, hy_i and boundary handling `bc` (DIRICHLET0 or
  * NEUMANN0), each by the same Leja interpolation as phi_action (Sec. III-C),
- * all of them in ONE persistent kernel launch that can be captured in a HIP
- * graph.  The host computes each interval (closed-form Gershgorin bound
- * [-4 coef (1/hx^2 + 1/hy^2), 0]), substep count and divided differences at
- * creation.  Vectors of all instances are concatenated: instance i occupies
- * [off_i, off_i + nx_i ny_i) of v and y (float64, device), with off_i from
- * expi_batch_offsets and total length expi_batch_total_length.  dtype sets
- * the storage of the Newton vectors (EXPI_F32 for the FP32-storage mode).
- * No retries inside the launch: an instance that misses the stop test within
- * m_max products reports EXPI_ENOTCONV in its status.
- * CURRENTLY SWITCHED OFF: expi_batch_launch and expi_batch_capture return
- * EXPI_EUNSUPPORTED (the persistent kernel did not finish on the GPU and the
- * cause is not yet found); creation and layout calls work. */
+ * all of them together.  The host computes each interval (closed-form
+ * Gershgorin bound [-4 coef (1/hx^2 + 1/hy^2), 0]), substep count and
+ * divided differences at creation.  Vectors of all instances are
+ * concatenated: instance i occupies [off_i, off_i + nx_i ny_i) of v and y
+ * (float64, device), with off_i from expi_batch_offsets and total length
+ * expi_batch_total_length.  dtype sets the storage of the Newton vectors
+ * (EXPI_F32 for the FP32-storage mode); divided differences, norms, the stop
+ * test and y stay float64.
+ *
+ * The work runs in rounds; in each round every unfinished instance takes one
+ * step (start vector, one Newton product, or the substep update).  A round
+ * is two kernels (the tiles of all unfinished instances, then one stop test
+ * per instance); nothing inside waits on memory.  At most
+ * expi_batch_max_rounds rounds are needed.  No retries: an instance that
+ * misses the stop test within m_max products reports EXPI_ENOTCONV. */
 typedef struct expi_batch expi_batch;
 typedef struct {
     int32_t status;         /* 0, EXPI_ENOTCONV or EXPI_ENONFINITE            */
@@ -260,24 +263,44 @@ int expi_batch_set_tiles(expi_batch *b, int waves, int march);
 int64_t expi_batch_total_length(const expi_batch *b);
 int expi_batch_offsets(const expi_batch *b, int64_t *off /* count entries */);
 size_t expi_batch_workspace_bytes(const expi_batch *b);
+/* Upper bound on the rounds any instance needs: the largest substep count
+ * times (m_max + 2), plus 2. */
+int expi_batch_max_rounds(const expi_batch *b);
 /* Upload the instance table to the workspace (host-to-device copies), size
- * the persistent grid from the occupancy of this device; synchronises. */
+ * the grids from the occupancy of this device; synchronises. */
 int expi_batch_prepare(expi_batch *b, void *ws, size_t ws_bytes, void *stream);
-/* Enqueue the state reset and the persistent kernel (a cooperative launch:
- * all workgroups co-resident, EXPI_EHIP if the runtime cannot guarantee it)
- * on `stream` (no copies, no synchronisation). */
+/* Solve the batch: enqueue the state reset and rounds on `stream` until
+ * every instance has finished, reading a 64-byte status block back to
+ * pinned host memory after every 8 rounds (one chunk of rounds stays
+ * enqueued ahead of the check).  Returns after the device is done (the
+ * call synchronises `stream`); results via expi_batch_results.  y must not
+ * overlap v (EXPI_EALIAS). */
 int expi_batch_launch(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
                       void *stream);
-/* Build a HIP graph of the same two launches (the persistent kernel as a
- * cooperative kernel node), owned by the batch; replay it with
- * expi_batch_replay (same v, y, ws).  `stream` is unused. */
+/* Build a HIP graph (owned by the batch) of the state reset and `rounds`
+ * rounds as kernel nodes, for v, y and ws as given; rounds = 0 (or more
+ * than expi_batch_max_rounds) takes expi_batch_max_rounds, enough for every
+ * instance; rounds after the last instance finished return at once.  With
+ * fewer rounds, unfinished instances report EXPI_ENOTCONV.  Replay with
+ * expi_batch_replay (asynchronous, one graph launch on `stream`).  The
+ * graph holds no copies or fills.  `stream` of capture is unused. */
 int expi_batch_capture(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
-                       void *stream);
+                       int rounds, void *stream);
 int expi_batch_replay(expi_batch *b, void *stream);
+/* Rounds of the captured graph (0 if none). */
+int expi_batch_graph_rounds(const expi_batch *b);
 /* Read per-instance results back (synchronises); returns EXPI_OK if every
- * instance converged.  `rounds` (may be NULL) receives the rounds the
- * persistent kernel ran. */
+ * instance converged.  `rounds` (may be NULL) receives the rounds in which
+ * some instance was still unfinished. */
 int expi_batch_results(expi_batch *b, void *ws, void *stream, expi_batch_stat *out, int *rounds);
+/* All rounds in ONE persistent kernel with grid barriers (cooperative
+ * launch), directly or as a cooperative graph node.  SWITCHED OFF: both
+ * return EXPI_EUNSUPPORTED (the kernel did not finish on the GPU and the
+ * cause is not yet found). */
+int expi_batch_launch_persistent(expi_batch *b, const double *v, double *y, void *ws,
+                                 size_t ws_bytes, void *stream);
+int expi_batch_capture_persistent(expi_batch *b, const double *v, double *y, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* ---- step-selector network (float32, device buffers) --------------------- */
 

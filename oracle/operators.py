@@ -177,3 +177,56 @@ def apply_at(shape, h, bc: str, u: np.ndarray, points, coef=None) -> np.ndarray:
                     total += ac * (0.0 - u[flat]) / (h[d] * h[d])
         out[q] = total
     return out
+
+
+def phi_values(k: int, z) -> np.ndarray:
+    """phi_k(z) elementwise in float64 (phi_0 = exp, phi_{j+1}(z) =
+    (phi_j(z) - 1/j!) / z, phi_j(0) = 1/j!).  Near zero (|z| < 1) the Taylor
+    series sum_i z^i / (i + k)! to 30 terms avoids the cancellation of the
+    recurrence; elsewhere phi_1 = expm1(z)/z starts the recurrence."""
+    import math
+    z = np.asarray(z, dtype=np.float64)
+    if k == 0:
+        return np.exp(z)
+    out = np.empty_like(z)
+    small = np.abs(z) < 1.0
+    zs = z[small]
+    ser = np.zeros_like(zs)
+    term = np.full_like(zs, 1.0 / math.factorial(k))
+    for i in range(30):
+        ser += term
+        term = term * zs / (i + k + 1)
+    out[small] = ser
+    zb = z[~small]
+    val = np.expm1(zb) / zb
+    for j in range(1, k):
+        val = (val - 1.0 / math.factorial(j)) / zb
+    out[~small] = val
+    return out
+
+
+def dirichlet_box_phi(k: int, shape, h, tau: float, v: np.ndarray, coef: float = 1.0) -> np.ndarray:
+    """Closed form of phi_k(tau A) v for A = coef times the constant-coefficient
+    Laplacian (five- or seven-point formula, Sec. III-A) with homogeneous
+    Dirichlet boundaries, ``h_d = 1/(n_d + 1)`` on every axis.
+
+    The sine modes diagonalise A: the orthonormal DST-I along each axis maps
+    v to mode coefficients, mode (j_1, j_2, ...) has the eigenvalue
+    ``-coef * sum_d (4/h_d^2) sin^2(j_d pi / (2 (n_d + 1)))``, and phi_k of
+    tau times it scales the coefficient.  Exact up to rounding; no Leja
+    interpolation involved, so it checks the interpolation's result
+    independently of its algorithm.  ``shape`` is (n_x, n_y[, n_z]) with x
+    fastest in ``v``."""
+    import scipy.fft as F
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    lam = 0.0
+    for d in range(dim):
+        j = np.arange(1, shape[d] + 1)
+        l1 = -coef * (4.0 / (h[d] * h[d])) * np.sin(j * np.pi / (2.0 * (shape[d] + 1))) ** 2
+        sh = [1] * dim
+        sh[dim - 1 - d] = shape[d]
+        lam = lam + l1.reshape(sh)
+    V = np.asarray(v, dtype=np.float64).reshape(shape[::-1])
+    modes = F.dstn(V, type=1, norm="ortho")
+    return F.dstn(phi_values(k, tau * lam) * modes, type=1, norm="ortho").reshape(-1)

@@ -231,10 +231,11 @@ def expeuler_step(op: _Op, tau: float, u, tol: float = 1e-10, dtype="f64",
 
 
 class Batch:
-    """Many independent 2D problems y_i = phi_1(tau_i A_i) v_i solved in one
-    persistent kernel launch (expi_batch_*).  A_i = coef * 5-point Laplacian
-    on an nx_i x ny_i grid with spacing (hx_i, hy_i) and boundary `bc`.
-    Vectors are concatenated; `offsets[i]` is where instance i starts."""
+    """Many independent 2D problems y_i = phi_1(tau_i A_i) v_i solved together
+    in rounds of two kernels each (expi_batch_*), eagerly or as a replayed
+    HIP graph.  A_i = coef * 5-point Laplacian on an nx_i x ny_i grid with
+    spacing (hx_i, hy_i) and boundary `bc`.  Vectors are concatenated;
+    `offsets[i]` is where instance i starts."""
 
     def __init__(self, nx, ny, hx, hy, tau, bc="dirichlet0", coef=1.0, tol=1e-8, dtype="f32",
                  params: LejaParams | None = None, device="cuda:0"):
@@ -289,20 +290,39 @@ class Batch:
         check(lib().expi_batch_prepare(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream_ptr(stream, self.device)))
 
-    def launch(self, v, y, stream=None):
+    def _run_args(self, v, y):
         ws = self.workspace()
-        check(lib().expi_batch_launch(self._h, ctypes.c_void_p(v.data_ptr()),
-                                      ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
-                                      ws.numel(), _stream_ptr(stream, self.device)))
+        return (self._h, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                ctypes.c_void_p(ws.data_ptr()), ws.numel())
 
-    def capture(self, v, y, stream=None):
-        ws = self.workspace()
-        check(lib().expi_batch_capture(self._h, ctypes.c_void_p(v.data_ptr()),
-                                       ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
-                                       ws.numel(), _stream_ptr(stream, self.device)))
+    def launch(self, v, y, stream=None):
+        """Solve every instance (returns once the device is done)."""
+        check(lib().expi_batch_launch(*self._run_args(v, y), _stream_ptr(stream, self.device)))
+
+    def capture(self, v, y, rounds: int = 0, stream=None):
+        """Record reset + `rounds` rounds (0: enough for every instance) as a graph."""
+        check(lib().expi_batch_capture(*self._run_args(v, y), int(rounds),
+                                       _stream_ptr(stream, self.device)))
 
     def replay(self, stream=None):
         check(lib().expi_batch_replay(self._h, _stream_ptr(stream, self.device)))
+
+    @property
+    def max_rounds(self) -> int:
+        return int(lib().expi_batch_max_rounds(self._h))
+
+    @property
+    def graph_rounds(self) -> int:
+        return int(lib().expi_batch_graph_rounds(self._h))
+
+    def launch_persistent(self, v, y, stream=None):
+        """The single persistent-kernel launch (switched off: raises)."""
+        check(lib().expi_batch_launch_persistent(*self._run_args(v, y),
+                                                 _stream_ptr(stream, self.device)))
+
+    def capture_persistent(self, v, y, stream=None):
+        check(lib().expi_batch_capture_persistent(*self._run_args(v, y),
+                                                  _stream_ptr(stream, self.device)))
 
     def results(self, stream=None, check_status=True):
         """(per-instance stat dicts, rounds); raises on failure if check_status."""

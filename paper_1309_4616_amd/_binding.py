@@ -28,7 +28,8 @@ EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "e
            "expi_batch_create", "expi_batch_destroy", "expi_batch_set_tiles",
            "expi_batch_total_length", "expi_batch_offsets", "expi_batch_workspace_bytes",
            "expi_batch_prepare", "expi_batch_launch", "expi_batch_capture", "expi_batch_replay",
-           "expi_batch_results", "expi_mlp_param_count", "expi_mlp_scratch_floats",
+           "expi_batch_results", "expi_batch_max_rounds", "expi_batch_graph_rounds",
+           "expi_batch_launch_persistent", "expi_batch_capture_persistent", "expi_mlp_param_count", "expi_mlp_scratch_floats",
            "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam")
 
 
@@ -161,8 +162,14 @@ def lib() -> ctypes.CDLL:
     L.expi_batch_workspace_bytes.restype = c_size_t
     L.expi_batch_prepare.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     L.expi_batch_prepare.restype = c_int
-    for name in ("expi_batch_launch", "expi_batch_capture"):
+    for name in ("expi_batch_launch", "expi_batch_launch_persistent",
+                 "expi_batch_capture_persistent"):
         getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        getattr(L, name).restype = c_int
+    L.expi_batch_capture.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p]
+    L.expi_batch_capture.restype = c_int
+    for name in ("expi_batch_max_rounds", "expi_batch_graph_rounds"):
+        getattr(L, name).argtypes = [c_void_p]
         getattr(L, name).restype = c_int
     L.expi_batch_replay.argtypes = [c_void_p, c_void_p]
     L.expi_batch_replay.restype = c_int

@@ -1,5 +1,5 @@
 // Batched phi_1(tau_i A_i) v_i for many independent 2D constant-coefficient
-// stencil problems of uneven sizes, in ONE persistent kernel launch.
+// stencil problems of uneven sizes.
 //
 // Each instance runs the same Leja interpolation as phi_action (Sec. III-C;
 // substeps as in api.hip): per substep an optional start vector
@@ -9,23 +9,28 @@
 // 5-point operator has a closed form), substep count and divided
 // differences ahead of time; they do not depend on the data.
 //
-// The kernel runs rounds.  In each round every unfinished instance takes one
-// step of its own sequence; the tiles of all of them form one list that the
-// workgroups share through an atomic counter (load balance across uneven
-// sizes).  A grid barrier ends the round's tile work; then one workgroup per
-// instance combines that instance's tile partials in a fixed order, applies
-// the stop test and advances the instance's state; a second barrier
-// publishes the states.  Instances drop out as they finish.
+// The work runs in rounds.  In each round every unfinished instance takes
+// one step of its own sequence (start vector, a product, or the update).  A
+// round is two ordinary kernels:
+//  * the tiles kernel: every workgroup builds the same list of unfinished
+//    instances and the prefix sums of their tile counts from the states in
+//    memory, then works through a contiguous share of the round's tiles
+//    (load balance across uneven sizes; shares are contiguous per XCD so a
+//    tile's neighbours mostly sit in the same L2);
+//  * the finalize kernel: one workgroup per instance combines that
+//    instance's tile partials in a fixed order, applies the stop test and
+//    advances its state.
+// The kernel boundaries order the rounds; nothing waits on memory, so the
+// rounds can be enqueued eagerly or recorded as kernel nodes of a HIP graph
+// (no copies or fills inside) and replayed.  A round in which no instance is
+// left returns at once.
 //
-// The kernel is launched cooperatively (directly or as a cooperative graph
-// node), so all of its workgroups are resident together.  Every wait in the
-// barrier is bounded in time: a workgroup that waits too long sets an abort
-// flag that every other waiter also sees, so all waves exit and the host
-// reports the failure.  The launch has no host interaction and no memory
-// copies or fills, so it can be put in a HIP graph and replayed.
+// A single persistent kernel that runs all rounds with grid barriers is kept
+// below but switched off (see expi_batch_launch_persistent).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -60,7 +65,8 @@ struct alignas(16) BatchState {  // advanced by the finalize step
 struct alignas(64) BatchCtrl {
     unsigned bar_count, bar_gen, abort, rounds;
     unsigned tile_ctr[2];
-    unsigned pad[10];
+    unsigned finished;           // instances done or failed (round kernels)
+    unsigned pad[9];
 };
 
 struct BatchArgs {
@@ -250,65 +256,128 @@ __device__ void finalize_instance(const BatchArgs& B, int inst) {
     __syncthreads();
 }
 
+// Exclusive prefix sum over the workgroup (blockDim a multiple of 64);
+// `total` receives the sum of all values.
+__device__ int block_scan(int v, int* s_wave, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int c = s_wave[w];
+            s_wave[w] = acc;
+            acc += c;
+        }
+        s_wave[nw] = acc;
+    }
+    __syncthreads();
+    const int r = s_wave[wv] + x - v;
+    *total = s_wave[nw];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ bool active_phase(int ph) { return ph != PH_DONE && ph != PH_FAILED; }
+
+// Unfinished instances in index order (s_ids) and the prefix sums of their
+// tile counts (s_pref, with s_pref[nact] = total), built by the whole
+// workgroup from the states in memory; every workgroup builds the same list.
+__device__ void active_list(const BatchArgs& B, int* s_pref, int* s_ids, int* s_wave, int& nact,
+                            int& total) {
+    const int nt = blockDim.x;
+    const int per = (B.count + nt - 1) / nt;
+    const int lo = min((int)threadIdx.x * per, B.count), hi = min(lo + per, B.count);
+    int cnt = 0, tiles = 0;
+    for (int i = lo; i < hi; ++i) {
+        if (active_phase(B.state[i].phase)) {
+            ++cnt;
+            tiles += B.info[i].ntiles;
+        }
+    }
+    int n_all, t_all;
+    int k = block_scan(cnt, s_wave, &n_all);
+    int tp = block_scan(tiles, s_wave, &t_all);
+    for (int i = lo; i < hi; ++i) {
+        if (active_phase(B.state[i].phase)) {
+            s_ids[k] = i;
+            s_pref[k] = tp;
+            tp += B.info[i].ntiles;
+            ++k;
+        }
+    }
+    if (threadIdx.x == 0) s_pref[n_all] = t_all;
+    __syncthreads();
+    nact = n_all;
+    total = t_all;
+}
+
+// Position of global tile t in the list: the last k with s_pref[k] <= t.
+__device__ __forceinline__ int find_instance(const int* s_pref, int nact, int t) {
+    int l = 0, h = nact - 1;
+    while (l < h) {
+        const int mid = (l + h + 1) >> 1;
+        if (s_pref[mid] <= t) l = mid; else h = mid - 1;
+    }
+    return l;
+}
+
+// ---- round kernels -----------------------------------------------------------
+
+// The tiles of one round.  The grid is a multiple of the XCD count; logical
+// workgroup L (XCD-major numbering) takes the L-th contiguous share.
+template <class TW>
+__global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B) {
+    __shared__ int s_pref[kMaxBatch + 1];
+    __shared__ int s_ids[kMaxBatch];
+    __shared__ int s_wave[kMaxWaves + 1];
+    if (B.ctrl->finished >= (unsigned)B.count) return;
+    int nact, total;
+    active_list(B, s_pref, s_ids, s_wave, nact, total);
+    if (nact == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->rounds += 1;
+    const int L = xcd_tile(gridDim.x / kXcd);
+    const int share = (total + gridDim.x - 1) / gridDim.x;
+    const int t_lo = L * share, t_hi = min(t_lo + share, total);
+    for (int t = t_lo; t < t_hi; ++t) {
+        const int q = find_instance(s_pref, nact, t);
+        const int inst = s_ids[q];
+        const int lt = t - s_pref[q];
+        const BatchInfo& I = B.info[inst];
+        const BatchState S = B.state[inst];
+        double* part = B.partials + 4 * (size_t)(I.part_off + lt);
+        if (I.vec == 2) run_tile<TW, 2>(B, I, S, S.phase, lt, part);
+        else run_tile<TW, 1>(B, I, S, S.phase, lt, part);
+    }
+}
+
+// Stop test and state update of one instance per workgroup.
+__global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
+    const int inst = blockIdx.x;
+    if (inst >= B.count || !active_phase(B.state[inst].phase)) return;
+    finalize_instance(B, inst);
+    if (threadIdx.x == 0 && !active_phase(B.state[inst].phase)) atomicAdd(&B.ctrl->finished, 1u);
+}
+
+// ---- persistent kernel (switched off) -----------------------------------------
+
 template <class TW>
 __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
     __shared__ int s_pref[kMaxBatch + 1];
     __shared__ int s_ids[kMaxBatch];
-    __shared__ int s_chunk[kMaxWaves * 64];
-    __shared__ int s_nact, s_tile, s_ok;
-    const int nt = blockDim.x;
+    __shared__ int s_wave[kMaxWaves + 1];
+    __shared__ int s_tile, s_ok;
     for (int round = 0; round < B.max_rounds; ++round) {
-        // (A) active instances and the prefix sums of their tile counts, in
-        // instance order; every workgroup computes the same list
-        const int per = (B.count + nt - 1) / nt;
-        const int lo = threadIdx.x * per, hi = min(lo + per, B.count);
-        int cnt = 0, tiles = 0;
-        for (int i = lo; i < hi; ++i) {
-            const int ph = B.state[i].phase;
-            if (ph != PH_DONE && ph != PH_FAILED) {
-                ++cnt;
-                tiles += B.info[i].ntiles;
-            }
-        }
-        s_chunk[threadIdx.x] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int t = 0; t < nt; ++t) {
-                const int c = s_chunk[t];
-                s_chunk[t] = acc;
-                acc += c;
-            }
-            s_nact = acc;
-        }
-        __syncthreads();
-        int k = s_chunk[threadIdx.x];
-        __syncthreads();
-        s_chunk[threadIdx.x] = tiles;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int t = 0; t < nt; ++t) {
-                const int c = s_chunk[t];
-                s_chunk[t] = acc;
-                acc += c;
-            }
-            s_pref[s_nact] = acc;
-        }
-        __syncthreads();
-        int tp = s_chunk[threadIdx.x];
-        for (int i = lo; i < hi; ++i) {
-            const int ph = B.state[i].phase;
-            if (ph != PH_DONE && ph != PH_FAILED) {
-                s_ids[k] = i;
-                s_pref[k] = tp;
-                tp += B.info[i].ntiles;
-                ++k;
-            }
-        }
-        __syncthreads();
-        const int nact = s_nact;
-        const int total = s_pref[nact];
+        // (A) active instances and the prefix sums of their tile counts
+        int nact, total;
+        active_list(B, s_pref, s_ids, s_wave, nact, total);
         if (nact == 0) break;
         // (B) the round's tiles
         unsigned* ctr = &B.ctrl->tile_ctr[round & 1];
@@ -318,11 +387,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
             const int t = s_tile;
             __syncthreads();
             if (t >= total) break;
-            int l = 0, h = nact - 1;   // last k with s_pref[k] <= t
-            while (l < h) {
-                const int mid = (l + h + 1) >> 1;
-                if (s_pref[mid] <= t) l = mid; else h = mid - 1;
-            }
+            const int l = find_instance(s_pref, nact, t);
             const int inst = s_ids[l];
             const int lt = t - s_pref[l];
             const BatchInfo& I = B.info[inst];
@@ -359,6 +424,7 @@ __global__ void batch_reset_kernel(BatchState* st, BatchCtrl* ctrl, int count) {
         ctrl->rounds = 0;
         ctrl->tile_ctr[0] = 0;
         ctrl->tile_ctr[1] = 0;
+        ctrl->finished = 0;
     }
 }
 
@@ -376,10 +442,14 @@ struct Batch {
     int total_tiles = 0, max_rounds = 0;
     size_t off_ctrl, off_info, off_state, off_dd, off_xi, off_part, off_w0, off_w1, off_p, ws_total;
     void* prepared_ws = nullptr;
-    int grid = 0;
+    int grid = 0;                 // persistent kernel
+    int round_grid = 0;           // tiles kernel of a round
     long long deadline_ticks = 0;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;   // captured rounds (or the persistent launch)
     hipGraphExec_t graph_exec = nullptr;
+    int graph_rounds = 0;
+    BatchCtrl* pinned = nullptr;  // host slots for status read-backs
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -474,6 +544,10 @@ int occupancy_grid(Batch& b) {
         BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<double>, 64 * b.waves, 0));
     if (per < 1) return bfail(EXPI_EHIP, "batched kernel cannot be resident");
     b.grid = std::min(per, 2) * cus;
+    // tiles kernel of a round: up to four workgroups per CU, a multiple of
+    // the XCD count, no more than the batch has tiles
+    const int want = std::min(4 * cus, ((b.total_tiles + kXcd - 1) / kXcd) * kXcd);
+    b.round_grid = std::max(kXcd, (want / kXcd) * kXcd);
     // a barrier wait longer than two seconds means something is wrong
     b.deadline_ticks = 2ll * 1000ll * (long long)(khz > 0 ? khz : 100000);
     return EXPI_OK;
@@ -491,6 +565,107 @@ int enqueue(Batch& b, char* ws, const double* v, double* y, hipStream_t s) {
     BHIP(hipGetLastError());
     void* params[] = {&a};
     BHIP(hipLaunchCooperativeKernel(kernel_ptr(b), dim3(b.grid), dim3(64 * b.waves), params, 0, s));
+    return EXPI_OK;
+}
+
+constexpr int kRoundChunk = 8;   // rounds enqueued between status read-backs
+
+hipError_t enqueue_round(const Batch& b, const BatchArgs& a, hipStream_t s) {
+    if (b.dtype == EXPI_F32)
+        hipLaunchKernelGGL(batch_tiles_kernel<float>, dim3(b.round_grid), dim3(64 * b.waves), 0, s, a);
+    else
+        hipLaunchKernelGGL(batch_tiles_kernel<double>, dim3(b.round_grid), dim3(64 * b.waves), 0, s, a);
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(b.count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int ensure_pinned(Batch& b) {
+    if (b.pinned) return EXPI_OK;
+    BHIP(hipHostMalloc(reinterpret_cast<void**>(&b.pinned), 4 * sizeof(BatchCtrl), hipHostMallocDefault));
+    for (auto& e : b.ev) BHIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return EXPI_OK;
+}
+
+// Reset, then rounds in chunks until every instance has finished (or the
+// round bound is reached).  The control block is read back after each
+// chunk while the next chunk is already enqueued, so the device does not
+// idle on the host's check.
+int run_rounds(Batch& b, char* ws, const double* v, double* y, hipStream_t s) {
+    int rc = ensure_pinned(b);
+    if (rc) return rc;
+    BatchArgs a = make_args(b, ws, v, y);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((b.count + 255) / 256), dim3(256), 0, s,
+                       a.state, a.ctrl, b.count);
+    BHIP(hipGetLastError());
+    int enq = 0, next = 0;
+    std::deque<int> pending;
+    bool done = false;
+    while (!done) {
+        if (enq < b.max_rounds) {
+            const int cnt = std::min(kRoundChunk, b.max_rounds - enq);
+            for (int q = 0; q < cnt; ++q) BHIP(enqueue_round(b, a, s));
+            enq += cnt;
+            const int slot = next++ & 3;
+            BHIP(hipMemcpyAsync(&b.pinned[slot], a.ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, s));
+            BHIP(hipEventRecord(b.ev[slot], s));
+            pending.push_back(slot);
+        }
+        while (!pending.empty() && (pending.size() > 1 || enq >= b.max_rounds)) {
+            const int slot = pending.front();
+            pending.pop_front();
+            BHIP(hipEventSynchronize(b.ev[slot]));
+            if (b.pinned[slot].finished >= (unsigned)b.count) {
+                done = true;
+                break;
+            }
+        }
+        if (pending.empty() && enq >= b.max_rounds) done = true;
+    }
+    BHIP(hipStreamSynchronize(s));
+    return EXPI_OK;
+}
+
+// Graph of the reset and `rounds` rounds, built node by node as one chain.
+int build_round_graph(Batch& b, char* ws, const double* v, double* y, int rounds) {
+    BatchArgs a = make_args(b, ws, v, y);
+    BatchState* st = a.state;
+    BatchCtrl* ctrl = a.ctrl;
+    int count = b.count;
+    hipGraph_t g = nullptr;
+    BHIP(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    void* p0[] = {&st, &ctrl, &count};
+    hipKernelNodeParams k0{};
+    k0.func = reinterpret_cast<void*>(batch_reset_kernel);
+    k0.gridDim = dim3((b.count + 255) / 256);
+    k0.blockDim = dim3(256);
+    k0.kernelParams = p0;
+    hipError_t e = hipGraphAddKernelNode(&prev, g, nullptr, 0, &k0);
+    void* pa[] = {&a};
+    hipKernelNodeParams kt{};
+    kt.func = b.dtype == EXPI_F32 ? reinterpret_cast<void*>(batch_tiles_kernel<float>)
+                                  : reinterpret_cast<void*>(batch_tiles_kernel<double>);
+    kt.gridDim = dim3(b.round_grid);
+    kt.blockDim = dim3(64 * b.waves);
+    kt.kernelParams = pa;
+    hipKernelNodeParams kf{};
+    kf.func = reinterpret_cast<void*>(batch_finalize_kernel);
+    kf.gridDim = dim3(b.count);
+    kf.blockDim = dim3(256);
+    kf.kernelParams = pa;
+    for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+        hipGraphNode_t nt = nullptr, nf = nullptr;
+        e = hipGraphAddKernelNode(&nt, g, &prev, 1, &kt);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&nf, g, &nt, 1, &kf);
+        prev = nf;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b.graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return bfail(EXPI_EHIP, std::string("batched round graph: ") + hipGetErrorString(e));
+    }
+    b.graph = g;
+    b.graph_rounds = rounds;
     return EXPI_OK;
 }
 
@@ -617,6 +792,9 @@ int expi_batch_destroy(expi_batch* bp) {
     if (b) {
         if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
+        for (auto& e : b->ev)
+            if (e) (void)hipEventDestroy(e);
+        if (b->pinned) (void)hipHostFree(b->pinned);
         delete b;
     }
     return EXPI_OK;
@@ -677,34 +855,27 @@ int expi_batch_prepare(expi_batch* bp, void* ws, size_t ws_bytes, void* stream) 
 // The persistent launch is switched off: on the GPU it did not finish (the
 // host waited past its test's time limit on both runs, the second with
 // cooperative launches and time-bounded barrier waits), and the cause has
-// not been shown yet.  Creation, layout and the host-side tables still work.
+// not been shown yet.  The round kernels replace it.
 static int batch_disabled() {
     return bfail(EXPI_EUNSUPPORTED,
                  "the persistent batched kernel is switched off until the cause of its "
-                 "unfinished GPU runs is found");
+                 "unfinished GPU runs is found; use expi_batch_launch");
 }
 
-int expi_batch_launch(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
-                      void* stream) {
-    Batch* b = reinterpret_cast<Batch*>(bp);
+static int check_run_args(Batch* b, const double* v, double* y, void* ws, size_t ws_bytes) {
     if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
-    if (kBatchLaunchEnabled == 0) return batch_disabled();
     if (ws != b->prepared_ws) return bfail(EXPI_EINVAL, "call expi_batch_prepare with this workspace first");
     if (ws_bytes < b->ws_total) return bfail(EXPI_EWORKSPACE, "workspace too small");
     const size_t vb = (size_t)b->total_len * 8;
     const char* pv = reinterpret_cast<const char*>(v);
     const char* py = reinterpret_cast<const char*>(y);
     if (pv < py + vb && py < pv + vb) return bfail(EXPI_EALIAS, "y overlaps v");
-    return enqueue(*b, static_cast<char*>(ws), v, y, static_cast<hipStream_t>(stream));
+    if (((uintptr_t)v & 15) != 0 || ((uintptr_t)y & 15) != 0)
+        return bfail(EXPI_EINVAL, "v and y must be 16-byte aligned");
+    return EXPI_OK;
 }
 
-int expi_batch_capture(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
-                       void* stream) {
-    Batch* b = reinterpret_cast<Batch*>(bp);
-    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
-    if (kBatchLaunchEnabled == 0) return batch_disabled();
-    if (ws != b->prepared_ws) return bfail(EXPI_EINVAL, "call expi_batch_prepare with this workspace first");
-    if (ws_bytes < b->ws_total) return bfail(EXPI_EWORKSPACE, "workspace too small");
+static void drop_graph(Batch* b) {
     if (b->graph_exec) {
         (void)hipGraphExecDestroy(b->graph_exec);
         b->graph_exec = nullptr;
@@ -713,8 +884,27 @@ int expi_batch_capture(expi_batch* bp, const double* v, double* y, void* ws, siz
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
+    b->graph_rounds = 0;
+}
+
+int expi_batch_launch(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
+                      void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    int rc = check_run_args(b, v, y, ws, ws_bytes);
+    if (rc) return rc;
+    return run_rounds(*b, static_cast<char*>(ws), v, y, static_cast<hipStream_t>(stream));
+}
+
+int expi_batch_capture(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
+                       int rounds, void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    int rc = check_run_args(b, v, y, ws, ws_bytes);
+    if (rc) return rc;
+    if (rounds < 0) return bfail(EXPI_EINVAL, "rounds must be >= 0");
+    if (rounds == 0 || rounds > b->max_rounds) rounds = b->max_rounds;
     (void)stream;
-    return build_graph(*b, static_cast<char*>(ws), v, y);
+    drop_graph(b);
+    return build_round_graph(*b, static_cast<char*>(ws), v, y, rounds);
 }
 
 int expi_batch_replay(expi_batch* bp, void* stream) {
@@ -722,6 +912,38 @@ int expi_batch_replay(expi_batch* bp, void* stream) {
     if (!b || !b->graph_exec) return bfail(EXPI_EINVAL, "no captured graph");
     BHIP(hipGraphLaunch(b->graph_exec, static_cast<hipStream_t>(stream)));
     return EXPI_OK;
+}
+
+int expi_batch_graph_rounds(const expi_batch* bp) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    return b ? b->graph_rounds : -1;
+}
+
+int expi_batch_max_rounds(const expi_batch* bp) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    return b ? b->max_rounds : -1;
+}
+
+int expi_batch_launch_persistent(expi_batch* bp, const double* v, double* y, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
+    if (kBatchLaunchEnabled == 0) return batch_disabled();
+    int rc = check_run_args(b, v, y, ws, ws_bytes);
+    if (rc) return rc;
+    return enqueue(*b, static_cast<char*>(ws), v, y, static_cast<hipStream_t>(stream));
+}
+
+int expi_batch_capture_persistent(expi_batch* bp, const double* v, double* y, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
+    if (kBatchLaunchEnabled == 0) return batch_disabled();
+    int rc = check_run_args(b, v, y, ws, ws_bytes);
+    if (rc) return rc;
+    (void)stream;
+    drop_graph(b);
+    return build_graph(*b, static_cast<char*>(ws), v, y);
 }
 
 int expi_batch_results(expi_batch* bp, void* ws, void* stream, expi_batch_stat* out,
@@ -751,7 +973,8 @@ int expi_batch_results(expi_batch* bp, void* ws, void* stream, expi_batch_stat* 
         if (st[i].phase != PH_DONE) worst = (st[i].status == 2) ? EXPI_ENONFINITE : EXPI_ENOTCONV;
     }
     if (ctrl.abort) return bfail(EXPI_EHIP, "batched kernel aborted: workgroups were not all resident");
-    if (worst == EXPI_ENOTCONV) return bfail(worst, "some instances did not converge within m_max");
+    if (worst == EXPI_ENOTCONV)
+        return bfail(worst, "some instances did not converge within m_max or did not finish in the rounds run");
     if (worst == EXPI_ENONFINITE) return bfail(worst, "some instances became non-finite");
     return EXPI_OK;
 }

@@ -1,0 +1,218 @@
+"""GPU parity of the batched solver (many uneven 2D problems, run in rounds).
+
+Each instance is compared with the oracle on its own: the Leja oracle
+(phi_action on the assembled matrix, same interval) at small sizes, the
+sine-mode closed form at larger ones.  The captured graph is replayed with
+eager work in between and every replay is compared with the eager run.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrators as I
+from oracle import operators as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-10
+TOL_F32 = 5e-6
+
+
+@pytest.fixture(scope="module")
+def E(device):
+    import paper_1309_4616_amd as E
+    E.lib()
+    return E
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def batch_case(seed=0, count=12):
+    """Uneven sizes with ragged tails, a one-column instance and a 64^2 one."""
+    rng = np.random.default_rng(seed)
+    nx = rng.integers(9, 90, size=count)
+    ny = rng.integers(9, 90, size=count)
+    nx[0], ny[0] = 64, 64
+    nx[1], ny[1] = 1, 30
+    hx, hy = 1.0 / (nx + 1.0), 1.0 / (ny + 1.0)
+    tau = 10 ** rng.uniform(-5, -2.3, size=count)
+    return nx, ny, hx, hy, tau
+
+
+def leja_oracle(nx, ny, hx, hy, tau, v_all, off, bc, tol, coef=1.0):
+    out = []
+    for i in range(len(nx)):
+        n = int(nx[i] * ny[i])
+        A = O.stencil_matrix((int(nx[i]), int(ny[i])), (hx[i], hy[i]), bc, coef=coef)
+        a = -4.0 * coef * (1 / hx[i] ** 2 + 1 / hy[i] ** 2)
+        y, st = I.phi_action(A, 1, tau[i], v_all[off[i]:off[i] + n], tol, interval=(a, 0.0))
+        out.append((y, st))
+    return out
+
+
+def run(E, nx, ny, hx, hy, tau, seed=11, **kw):
+    import torch
+    b = E.Batch(nx, ny, hx, hy, tau, **kw)
+    v_all = synth.uniform_vector(b.total_length, seed)
+    v = T(v_all)
+    y = torch.zeros_like(v)
+    b.prepare()
+    print(f"batch launch: count={b.count} kw={kw}", flush=True)
+    b.launch(v, y)
+    stats, rounds = b.results()
+    return b, v_all, N(y), stats, rounds
+
+
+@pytest.mark.parametrize("dtype,bc", [("f64", "dirichlet0"), ("f32", "dirichlet0"), ("f64", "neumann0"),
+                                      ("f32", "neumann0")])
+def test_batch_matches_leja_oracle_per_instance(E, dtype, bc):
+    nx, ny, hx, hy, tau = batch_case()
+    b, v_all, yy, stats, rounds = run(E, nx, ny, hx, hy, tau, bc=bc, tol=1e-10, dtype=dtype)
+    want = leja_oracle(nx, ny, hx, hy, tau, v_all, b.offsets, bc, 1e-10)
+    bar = TOL_F64 if dtype == "f64" else TOL_F32
+    for i, (yo, sto) in enumerate(want):
+        n = int(nx[i] * ny[i])
+        got = yy[b.offsets[i]:b.offsets[i] + n]
+        assert relerr(got, yo) <= bar, (i, relerr(got, yo))
+        assert stats[i]["status"] == 0 and stats[i]["substeps"] == sto.substeps
+        if dtype == "f64":
+            # the stop test sees the same norms up to summation order
+            assert abs(stats[i]["degree_last"] - sto.degrees[-1]) <= 1
+            assert abs(stats[i]["newton_steps"] - sum(sto.degrees)) <= sto.substeps
+    # each round advances every unfinished instance by one step
+    longest = max(s["newton_steps"] + 2 * s["substeps"] for s in stats)
+    assert max(s["newton_steps"] for s in stats) <= rounds <= min(longest, b.max_rounds)
+
+
+def test_batch_coef_and_tiles(E):
+    """A non-unit coefficient and several tile settings give the oracle's result."""
+    nx, ny, hx, hy, tau = batch_case(seed=5, count=7)
+    ref = None
+    for waves, march in ((4, 8), (2, 16), (1, 4), (8, 64)):
+        import torch
+        b = E.Batch(nx, ny, hx, hy, tau, coef=0.35, tol=1e-10, dtype="f64")
+        b.set_tiles(waves, march)
+        v_all = synth.uniform_vector(b.total_length, 2)
+        y = torch.zeros(b.total_length, dtype=torch.float64, device="cuda:0")
+        b.prepare()
+        print(f"batch tiles {waves}x{march}", flush=True)
+        b.launch(T(v_all), y)
+        stats, _ = b.results()
+        if ref is None:
+            ref = leja_oracle(nx, ny, hx, hy, tau, v_all, b.offsets, "dirichlet0", 1e-10, coef=0.35)
+        yy = N(y)
+        for i, (yo, _) in enumerate(ref):
+            n = int(nx[i] * ny[i])
+            assert relerr(yy[b.offsets[i]:b.offsets[i] + n], yo) <= TOL_F64, (waves, march, i)
+
+
+def test_batch_larger_grids_against_sine_modes(E):
+    """Sizes up to 300^2 and time steps from the cfg range (several substeps)
+    against the closed form, FP64 and FP32 storage."""
+    nx = np.array([300, 257, 128, 64, 191, 96])
+    ny = nx.copy()
+    h = 1.0 / (nx + 1.0)
+    tau = np.array([3e-4, 1e-5, 1e-3, 5e-4, 1e-4, 9e-4])
+    for dtype, bar in (("f64", 1e-9), ("f32", 2e-5)):
+        b, v_all, yy, stats, _ = run(E, nx, ny, h, h, tau, tol=1e-10 if dtype == "f64" else 1e-7,
+                                     dtype=dtype)
+        for i in range(len(nx)):
+            n = int(nx[i] * ny[i])
+            v = v_all[b.offsets[i]:b.offsets[i] + n]
+            want = O.dirichlet_box_phi(1, (int(nx[i]), int(ny[i])), (h[i], h[i]), tau[i], v)
+            got = yy[b.offsets[i]:b.offsets[i] + n]
+            assert relerr(got, want) <= bar, (dtype, i, relerr(got, want))
+        assert max(s["substeps"] for s in stats) > 1
+
+
+def test_batch_tau_zero_and_single_instance(E):
+    """phi_1(0) v = v exactly in FP64 (the divided differences beyond d_0 vanish)."""
+    nx, ny = np.array([50]), np.array([37])
+    h = 1.0 / (nx + 1.0)
+    b, v_all, yy, stats, rounds = run(E, nx, ny, h, h, np.array([0.0]), dtype="f64")
+    n = 50 * 37
+    assert np.array_equal(yy[:n], v_all[:n])
+    assert stats[0]["status"] == 0 and stats[0]["degree_last"] == 2
+    assert rounds == 3   # first product, second product (stop), update
+
+
+def test_batch_round_graph_replays_match_eager(E):
+    """Three replays of the captured graph, with eager work and syncs in
+    between, each equal to the eager run bit for bit."""
+    import torch
+    nx, ny, hx, hy, tau = batch_case(seed=3, count=20)
+    b = E.Batch(nx, ny, hx, hy, tau, tol=1e-8, dtype="f32")
+    v = T(synth.uniform_vector(b.total_length, 5))
+    y_eager = torch.zeros_like(v)
+    b.prepare()
+    b.launch(v, y_eager)
+    s_eager, r_eager = b.results()
+    y = torch.zeros_like(v)
+    b.capture(v, y)
+    assert b.graph_rounds == b.max_rounds
+    mask = torch.zeros(b.total_length, dtype=torch.bool, device=v.device)
+    for i in range(b.count):
+        mask[int(b.offsets[i]):int(b.offsets[i]) + int(nx[i] * ny[i])] = True
+    for rep in range(3):
+        y.fill_(float("nan"))
+        scratch = torch.randn(1 << 20, device=v.device).sum()   # eager work in between
+        torch.cuda.synchronize()
+        print(f"batch graph replay {rep}", flush=True)
+        b.replay()
+        torch.cuda.synchronize()
+        s_rep, r_rep = b.results()
+        assert r_rep == r_eager
+        assert torch.equal(y[mask], y_eager[mask]), rep
+        assert [s["newton_steps"] for s in s_rep] == [s["newton_steps"] for s in s_eager]
+        del scratch
+
+
+def test_batch_short_graph_leaves_instances_unfinished(E):
+    import torch
+    nx, ny, hx, hy, tau = batch_case(seed=4, count=5)
+    b = E.Batch(nx, ny, hx, hy, tau, tol=1e-8, dtype="f64")
+    v = T(synth.uniform_vector(b.total_length, 1))
+    y = torch.zeros_like(v)
+    b.prepare()
+    b.capture(v, y, rounds=3)
+    assert b.graph_rounds == 3
+    b.replay()
+    torch.cuda.synchronize()
+    stats, rounds = b.results(check_status=False)
+    assert rounds == 3
+    assert all(s["status"] != 0 for s in stats)
+    with pytest.raises(RuntimeError, match="did not finish"):
+        b.results()
+    # the eager launch afterwards still solves everything
+    b.launch(v, y)
+    stats, _ = b.results()
+    assert all(s["status"] == 0 for s in stats)
+
+
+def test_batch_rejects_bad_arguments(E):
+    import torch
+    nx, ny, hx, hy, tau = batch_case(seed=6, count=3)
+    b = E.Batch(nx, ny, hx, hy, tau, dtype="f64")
+    v = T(synth.uniform_vector(b.total_length + 1, 1))
+    y = torch.zeros_like(v)
+    with pytest.raises(RuntimeError, match="prepare"):
+        b.launch(v[:-1], y[:-1])
+    b.prepare()
+    with pytest.raises(RuntimeError, match="overlaps"):
+        b.launch(v[:-1], v[1:])
+    with pytest.raises(RuntimeError, match="aligned"):
+        b.launch(v[1:], y[:-1])
+    with pytest.raises(RuntimeError, match="switched off"):
+        b.launch_persistent(v[:-1], y[:-1])

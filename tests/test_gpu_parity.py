@@ -453,7 +453,7 @@ def test_batch_matches_oracle_per_instance(E, dtype, bc):
     v = T(v_all)
     y = torch.zeros_like(v)
     b.prepare()
-    b.launch(v, y)
+    b.launch_persistent(v, y)
     stats, rounds = b.results()
     want = batch_oracle(nx, ny, hx, hy, tau, v_all, b.offsets, bc, 1e-10)
     yy = N(y)
@@ -476,10 +476,10 @@ def test_batch_graph_replays_are_identical(E):
     v = T(synth.uniform_vector(b.total_length, 5))
     y_eager = torch.zeros_like(v)
     b.prepare()
-    b.launch(v, y_eager)
+    b.launch_persistent(v, y_eager)
     s_eager, r_eager = b.results()
     y = torch.zeros_like(v)
-    b.capture(v, y)
+    b.capture_persistent(v, y)
     mask = torch.zeros(b.total_length, dtype=torch.bool, device=v.device)
     for i in range(b.count):
         mask[int(b.offsets[i]):int(b.offsets[i]) + int(nx[i] * ny[i])] = True

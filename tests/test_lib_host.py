@@ -179,11 +179,19 @@ def test_batch_create_validation_and_layout(L):
     assert L.expi_batch_set_tiles(b, 2, 6) == -1
     assert L.expi_batch_set_tiles(b, 2, 16) == 0
     assert L.expi_batch_workspace_bytes(b) == ws_bytes
-    st = (_binding.BatchStat * 3)()
+    # substeps from the closed-form interval: s_i = ceil(tau_i 4 (2/h_i^2) / 100)
+    s_want = np.maximum(np.ceil(tau * 8.0 / h**2 / 100.0), 1).astype(int)
+    assert L.expi_batch_max_rounds(b) == int(s_want.max()) * (100 + 2) + 2
+    assert L.expi_batch_graph_rounds(b) == 0
     assert L.expi_batch_launch(b, None, None, None, 0, None) == -1
     assert L.expi_batch_replay(b, None) == -1        # nothing captured
-    # the persistent launch is switched off and says so before any HIP call
     dummy = ctypes.c_void_p(256)
-    assert L.expi_batch_launch(b, dummy, ctypes.c_void_p(512), dummy, ws_bytes, None) == -7
+    # launching or capturing needs a prepared workspace (checked before any HIP call)
+    assert L.expi_batch_launch(b, dummy, ctypes.c_void_p(1 << 40), dummy, ws_bytes, None) == -1
+    assert b"prepare" in L.expi_last_error()
+    assert L.expi_batch_capture(b, dummy, ctypes.c_void_p(1 << 40), dummy, ws_bytes, 0, None) == -1
+    # the persistent launch is switched off and says so before any HIP call
+    assert L.expi_batch_launch_persistent(b, dummy, ctypes.c_void_p(512), dummy, ws_bytes, None) == -7
     assert b"switched off" in L.expi_last_error()
+    assert L.expi_batch_capture_persistent(b, dummy, ctypes.c_void_p(512), dummy, ws_bytes, None) == -7
     L.expi_batch_destroy(b)

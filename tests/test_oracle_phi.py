@@ -324,3 +324,40 @@ def test_expeuler_substeps_match_single_step_form():
     Fu = A @ u0 + u0 - u0 ** 3
     want = u0 + tau * dst_apply((N, N), (h, h), phi_scalar(1, tau * dst_eigvals((N, N), (h, h))), Fu)
     assert relerr(u1, want) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the closed-form sine-mode phi_k of the oracle (used for large batched grids)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("shape,coef,tau", [((5, 4), 1.0, 3e-2), ((3, 4, 5), 0.7, 1e-2), ((7, 1), 2.0, 5e-2)])
+def test_dirichlet_box_phi_matches_dense_brute_force(k, shape, coef, tau):
+    """Against phi_k of the dense matrix: expm of tau A (k = 0), the augmented
+    matrix for k = 1, and the (k+1)-block augmented matrix for k = 2."""
+    h = tuple(1.0 / (s + 1.0) for s in shape)
+    A = O.stencil_matrix(shape, h, "dirichlet0", coef=coef).toarray()
+    n = A.shape[0]
+    v = synth.uniform_vector(n, 4)
+    got = O.dirichlet_box_phi(k, shape, h, tau, v, coef=coef)
+    # phi_k(tau A) v = top-right block of expm([[tau A, v e_1^T, 0], [0, J]]) with a
+    # Jordan shift block J of size k: the last column of the first block row
+    M = np.zeros((n + k, n + k))
+    M[:n, :n] = tau * A
+    if k >= 1:
+        M[:n, n] = v
+        for q in range(k - 1):
+            M[n + q, n + q + 1] = 1.0
+        want = sla.expm(M)[:n, n + k - 1]
+    else:
+        want = sla.expm(M) @ v
+    assert relerr(got, want) <= 1e-12
+
+
+def test_phi_values_series_and_recurrence_agree_with_mpmath_values():
+    from oracle import leja as L
+    z = np.array([-40.0, -3.0, -1.0, -0.999, -0.3, -1e-7, 0.0, 1e-9, 0.5, 0.9999, 1.0, 2.5])
+    for k in (1, 2, 3):
+        got = O.phi_values(k, z)
+        want = np.array([L.phi(k, float(t)) for t in z])
+        assert np.allclose(got, want, rtol=2e-14, atol=0), k
