@@ -207,6 +207,87 @@ def run_learned(args):
     return out
 
 
+def run_batched(args):
+    """The batched workload: `batch_count` independent 2D Dirichlet problems,
+    side lengths log-uniform in [64, 1024] and tau uniform in [1e-5, 1e-3]
+    (seeded), FP32 storage of the Newton vectors with float64 divided
+    differences, norms, stop test and y; solved eagerly (host-enqueued rounds)
+    and as one replay of the captured round graph.  Errors per instance are
+    against the float64 sine-mode closed form of phi_1(tau A) v."""
+    import numpy as np
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+    from oracle import operators as O
+
+    inst = synth.batched_instances(args.batch_count, seed=0)
+    ns = np.array([it.n for it in inst])
+    taus = np.array([it.tau for it in inst])
+    h = 1.0 / (ns + 1.0)
+    b = E.Batch(ns, ns, h, h, taus, bc="dirichlet0", tol=args.tol, dtype="f32")
+    v_host = np.zeros(b.total_length)
+    for i, it in enumerate(inst):
+        o = int(b.offsets[i])
+        v_host[o:o + it.n * it.n] = synth.uniform_vector(it.n * it.n, it.seed)
+    v = torch.as_tensor(v_host, device="cuda:0")
+    y = torch.zeros_like(v)
+    b.prepare()
+    b.launch(v, y)                      # warm-up (also the eager reference)
+    stats, rounds = b.results()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        b.launch(v, y)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / args.batch_reps
+    y_eager = y.clone()
+    t0 = time.perf_counter()
+    b.capture(v, y)                     # rounds = the bound every instance fits in
+    t_capture = time.perf_counter() - t0
+    b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        b.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / args.batch_reps
+    same = bool(torch.equal(y, y_eager))
+    s_graph, r_graph = b.results()
+    yy = y.cpu().numpy()
+    errs = []
+    for i, it in enumerate(inst):
+        o, n2 = int(b.offsets[i]), it.n * it.n
+        want = O.dirichlet_box_phi(1, (it.n, it.n), (h[i], h[i]), it.tau, v_host[o:o + n2])
+        errs.append(float(np.linalg.norm(yy[o:o + n2] - want) / np.linalg.norm(want)))
+    pts = int((ns * ns).sum())
+    prods = sum(int(st["newton_steps"]) * it.n * it.n for st, it in zip(stats, inst))
+    best = min(eager, graph)
+    return {
+        "workload": (f"{args.batch_count} independent 2D 5-point Dirichlet problems, sides "
+                     f"log-uniform in [64, 1024], tau uniform in [1e-5, 1e-3], seed 0"),
+        "value": pts / best,
+        "unit": "grid-pts/s",
+        "dtype": "f32 storage, f64 recurrences",
+        "tol": args.tol,
+        "total_points": pts,
+        "eager_ms": 1e3 * eager,
+        "graph_replay_ms": 1e3 * graph,
+        "graph_rounds": b.graph_rounds,
+        "graph_capture_s": t_capture,
+        "graph_equals_eager": same and r_graph == rounds,
+        "rounds": rounds,
+        "substeps_max": int(max(st["substeps"] for st in stats)),
+        "newton_products": int(sum(st["newton_steps"] for st in stats)),
+        "point_products_per_s": prods / best,
+        "newton_gbs": NEWTON_BYTES_PER_PT["f32"] * prods / best / 1e9,
+        "err_vs_closed_form": {"max": max(errs), "median": float(np.median(errs)),
+                               "worst_instance": int(np.argmax(errs))},
+        "note": ("newton_gbs counts 16 B per point per Newton product over the whole "
+                 "solve (start vectors, updates, stop tests and host gaps included in "
+                 "the time)"),
+    }
+
+
 def cpu_baseline(args):
     """The oracle on a bounded sample: the same problem on the 128^3 grid with
     tau scaled by (256/128)^2, which keeps tau*(b-a) and hence the number of
@@ -257,6 +338,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--eval-steps", type=int, default=200)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 512 MiB float64 tensor 3 times (a kernel of known "
                          "traffic, 512 MiB read + 512 MiB written per launch) to calibrate "
@@ -294,6 +378,12 @@ def main():
               f"evaluate {args.eval_steps} held-out steps", file=sys.stderr, flush=True)
         learned = run_learned(args)
         print(f"[bench] learned done", file=sys.stderr, flush=True)
+    batched = None
+    if not args.no_batched:
+        print(f"[bench] batched: {args.batch_count} problems, eager and graph", file=sys.stderr, flush=True)
+        batched = run_batched(args)
+        print(f"[bench] batched done: eager {batched['eager_ms']:.1f} ms, graph "
+              f"{batched['graph_replay_ms']:.1f} ms", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -358,6 +448,8 @@ def main():
         }
     if learned:
         out["learned_vs_plain"] = learned
+    if batched:
+        out["batched"] = batched
     print(json.dumps(out), flush=True)
 
 

@@ -66,7 +66,8 @@ struct alignas(64) BatchCtrl {
     unsigned bar_count, bar_gen, abort, rounds;
     unsigned tile_ctr[2];
     unsigned finished;           // instances done or failed (round kernels)
-    unsigned pad[9];
+    unsigned hot_rounds;         // rounds with Newton products on stored vectors
+    unsigned pad[8];
 };
 
 struct BatchArgs {
@@ -126,7 +127,21 @@ __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
     return *s_ok != 0;
 }
 
-template <class TW, int V>
+// Which steps a tiles kernel takes: all of them (persistent kernel), the
+// products on Newton vectors of the storage type (first product of a later
+// substep, Newton products), or the rest (start vector, update, first
+// product of the first substep, which reads the float64 input).  Keeping the
+// hot products in a kernel of their own keeps its register count, and so its
+// occupancy, that of the plain sweep.
+enum PhaseSet : int { SET_ALL = 0, SET_HOT = 1, SET_AUX = 2 };
+
+__device__ __forceinline__ bool in_set(int set, int phase, int l) {
+    if (phase == PH_DONE || phase == PH_FAILED) return false;
+    const bool hot = phase == PH_NEWTON || (phase == PH_FIRST && l > 0);
+    return set == SET_ALL || (set == SET_HOT) == hot;
+}
+
+template <class TW, int V, int SET>
 __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchState& S, int phase,
                          int lt, double* red_partial) {
     const int waves = blockDim.x >> 6;
@@ -145,7 +160,7 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
     TW* w1 = static_cast<TW*>(B.w1) + I.off;
     TW* pp = static_cast<TW*>(B.p) + I.off;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (phase == PH_START) {
+    if (SET != SET_HOT && phase == PH_START) {
         a.x = B.y + I.off;
         a.out = w1;
         a.g = B.v + I.off;
@@ -154,7 +169,7 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
         tile::stencil_tile<2, EXPI_COEF_CONST, EPI_START, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
         return;
     }
-    if (phase == PH_UPDATE) {
+    if (SET != SET_HOT && phase == PH_UPDATE) {
         // y' <- (l == 0 ? 0 : y') + p / s over the tile's points
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         const int rows = waves * B.march;
@@ -182,16 +197,22 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
     if (phase == PH_FIRST) {
         a.out = w0;
         if (S.l == 0) {
-            a.x = B.v + I.off;
-            tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
+            if constexpr (SET != SET_HOT) {
+                a.x = B.v + I.off;
+                tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
+            }
         } else {
-            a.x = w1;
-            tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+            if constexpr (SET != SET_AUX) {
+                a.x = w1;
+                tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+            }
         }
     } else {
-        a.x = (j & 1) ? w0 : w1;     // w_j lives in w[(j-1) & 1]
-        a.out = (j & 1) ? w1 : w0;
-        tile::stencil_tile<2, EXPI_COEF_CONST, EPI_NEWTON, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+        if constexpr (SET != SET_AUX) {
+            a.x = (j & 1) ? w0 : w1;     // w_j lives in w[(j-1) & 1]
+            a.out = (j & 1) ? w1 : w0;
+            tile::stencil_tile<2, EXPI_COEF_CONST, EPI_NEWTON, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+        }
     }
     __shared__ double red[kMaxWaves][3];
     block_combine<EPI_NEWTON>(s0, s1, s2, red);
@@ -287,17 +308,18 @@ __device__ int block_scan(int v, int* s_wave, int* total) {
 
 __device__ __forceinline__ bool active_phase(int ph) { return ph != PH_DONE && ph != PH_FAILED; }
 
-// Unfinished instances in index order (s_ids) and the prefix sums of their
-// tile counts (s_pref, with s_pref[nact] = total), built by the whole
-// workgroup from the states in memory; every workgroup builds the same list.
-__device__ void active_list(const BatchArgs& B, int* s_pref, int* s_ids, int* s_wave, int& nact,
-                            int& total) {
+// Unfinished instances whose step is in `set`, in index order (s_ids), and
+// the prefix sums of their tile counts (s_pref, with s_pref[nact] = total),
+// built by the whole workgroup from the states in memory; every workgroup
+// builds the same list.
+__device__ void active_list(const BatchArgs& B, int set, int* s_pref, int* s_ids, int* s_wave,
+                            int& nact, int& total) {
     const int nt = blockDim.x;
     const int per = (B.count + nt - 1) / nt;
     const int lo = min((int)threadIdx.x * per, B.count), hi = min(lo + per, B.count);
     int cnt = 0, tiles = 0;
     for (int i = lo; i < hi; ++i) {
-        if (active_phase(B.state[i].phase)) {
+        if (in_set(set, B.state[i].phase, B.state[i].l)) {
             ++cnt;
             tiles += B.info[i].ntiles;
         }
@@ -306,7 +328,7 @@ __device__ void active_list(const BatchArgs& B, int* s_pref, int* s_ids, int* s_
     int k = block_scan(cnt, s_wave, &n_all);
     int tp = block_scan(tiles, s_wave, &t_all);
     for (int i = lo; i < hi; ++i) {
-        if (active_phase(B.state[i].phase)) {
+        if (in_set(set, B.state[i].phase, B.state[i].l)) {
             s_ids[k] = i;
             s_pref[k] = tp;
             tp += B.info[i].ntiles;
@@ -331,32 +353,57 @@ __device__ __forceinline__ int find_instance(const int* s_pref, int nact, int t)
 
 // ---- round kernels -----------------------------------------------------------
 
-// The tiles of one round.  The grid is a multiple of the XCD count; logical
-// workgroup L (XCD-major numbering) takes the L-th contiguous share.
-template <class TW>
+// The tiles of one round whose steps are in SET.  The grid is a multiple of
+// the XCD count.  The instance list lives in dynamic LDS of
+// (2 count + kMaxWaves + 2) ints.
+template <class TW, int SET>
 __global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B) {
-    __shared__ int s_pref[kMaxBatch + 1];
-    __shared__ int s_ids[kMaxBatch];
-    __shared__ int s_wave[kMaxWaves + 1];
+    extern __shared__ int s_dyn[];
+    int* s_pref = s_dyn;                  // count + 1
+    int* s_ids = s_dyn + B.count + 1;     // count
+    int* s_wave = s_ids + B.count;        // kMaxWaves + 1
     if (B.ctrl->finished >= (unsigned)B.count) return;
+    // a round counts when some instance is unfinished at its start (the
+    // count changes only in the finalize kernel that ends the round)
+    if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->rounds += 1;
     int nact, total;
-    active_list(B, s_pref, s_ids, s_wave, nact, total);
+    active_list(B, SET, s_pref, s_ids, s_wave, nact, total);
+    // values read from LDS are the same in every lane; saying so keeps the
+    // instance data and everything derived from it in scalar registers
+    nact = __builtin_amdgcn_readfirstlane(nact);
+    total = __builtin_amdgcn_readfirstlane(total);
     if (nact == 0) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->rounds += 1;
-    const int L = xcd_tile(gridDim.x / kXcd);
-    const int share = (total + gridDim.x - 1) / gridDim.x;
-    const int t_lo = L * share, t_hi = min(t_lo + share, total);
-    for (int t = t_lo; t < t_hi; ++t) {
-        const int q = find_instance(s_pref, nact, t);
-        const int inst = s_ids[q];
-        const int lt = t - s_pref[q];
-        const BatchInfo& I = B.info[inst];
-        const BatchState S = B.state[inst];
+    if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->hot_rounds += 1;
+    // Grid-stride order over the XCD-major logical index: in each pass the
+    // workgroups together take G consecutive tiles and every XCD a
+    // contiguous block of them, so tiles that share halo rows and DRAM pages
+    // run at the same time on the same L2.
+    const int G = gridDim.x;
+    const int L = xcd_tile(G / kXcd);
+    if (L >= total) return;
+    int q = __builtin_amdgcn_readfirstlane(find_instance(s_pref, nact, L));
+    int inst = __builtin_amdgcn_readfirstlane(s_ids[q]);
+    int base = __builtin_amdgcn_readfirstlane(s_pref[q]);
+    int next = __builtin_amdgcn_readfirstlane(s_pref[q + 1]);
+    BatchInfo I = B.info[inst];
+    BatchState S = B.state[inst];
+    for (int t = L; t < total; t += G) {
+        if (t >= next) {
+            q = __builtin_amdgcn_readfirstlane(find_instance(s_pref, nact, t));
+            inst = __builtin_amdgcn_readfirstlane(s_ids[q]);
+            base = __builtin_amdgcn_readfirstlane(s_pref[q]);
+            next = __builtin_amdgcn_readfirstlane(s_pref[q + 1]);
+            I = B.info[inst];
+            S = B.state[inst];
+        }
+        const int lt = t - base;
         double* part = B.partials + 4 * (size_t)(I.part_off + lt);
-        if (I.vec == 2) run_tile<TW, 2>(B, I, S, S.phase, lt, part);
-        else run_tile<TW, 1>(B, I, S, S.phase, lt, part);
+        if (I.vec == 2) run_tile<TW, 2, SET>(B, I, S, S.phase, lt, part);
+        else run_tile<TW, 1, SET>(B, I, S, S.phase, lt, part);
     }
 }
+
+size_t tiles_lds_bytes(int count) { return sizeof(int) * (2 * (size_t)count + kMaxWaves + 2); }
 
 // Stop test and state update of one instance per workgroup.
 __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
@@ -377,7 +424,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
     for (int round = 0; round < B.max_rounds; ++round) {
         // (A) active instances and the prefix sums of their tile counts
         int nact, total;
-        active_list(B, s_pref, s_ids, s_wave, nact, total);
+        active_list(B, SET_ALL, s_pref, s_ids, s_wave, nact, total);
         if (nact == 0) break;
         // (B) the round's tiles
         unsigned* ctr = &B.ctrl->tile_ctr[round & 1];
@@ -393,8 +440,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
             const BatchInfo& I = B.info[inst];
             const BatchState S = B.state[inst];
             double* part = B.partials + 4 * (size_t)(I.part_off + lt);
-            if (I.vec == 2) run_tile<TW, 2>(B, I, S, S.phase, lt, part);
-            else run_tile<TW, 1>(B, I, S, S.phase, lt, part);
+            if (I.vec == 2) run_tile<TW, 2, SET_ALL>(B, I, S, S.phase, lt, part);
+            else run_tile<TW, 1, SET_ALL>(B, I, S, S.phase, lt, part);
         }
         // (C) all tiles of the round are done
         if (!grid_barrier(B, &s_ok)) return;
@@ -425,6 +472,7 @@ __global__ void batch_reset_kernel(BatchState* st, BatchCtrl* ctrl, int count) {
         ctrl->tile_ctr[0] = 0;
         ctrl->tile_ctr[1] = 0;
         ctrl->finished = 0;
+        ctrl->hot_rounds = 0;
     }
 }
 
@@ -529,6 +577,14 @@ BatchArgs make_args(const Batch& b, char* ws, const double* v, double* y) {
     return a;
 }
 
+const void* tiles_kernel(const Batch& b, int set) {
+    if (b.dtype == EXPI_F32)
+        return set == SET_HOT ? reinterpret_cast<const void*>(batch_tiles_kernel<float, SET_HOT>)
+                              : reinterpret_cast<const void*>(batch_tiles_kernel<float, SET_AUX>);
+    return set == SET_HOT ? reinterpret_cast<const void*>(batch_tiles_kernel<double, SET_HOT>)
+                          : reinterpret_cast<const void*>(batch_tiles_kernel<double, SET_AUX>);
+}
+
 // The persistent kernel needs every workgroup resident at once.  The grid
 // is two workgroups per CU (the occupancy limit is higher) and every launch
 // is cooperative, so the runtime refuses a grid that cannot be co-resident
@@ -544,9 +600,14 @@ int occupancy_grid(Batch& b) {
         BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<double>, 64 * b.waves, 0));
     if (per < 1) return bfail(EXPI_EHIP, "batched kernel cannot be resident");
     b.grid = std::min(per, 2) * cus;
-    // tiles kernel of a round: up to four workgroups per CU, a multiple of
-    // the XCD count, no more than the batch has tiles
-    const int want = std::min(4 * cus, ((b.total_tiles + kXcd - 1) / kXcd) * kXcd);
+    // tiles kernels of a round: as many workgroups as fit on the device at
+    // once (occupancy of the hot kernel), a multiple of the XCD count, no
+    // more than the batch has tiles
+    int per_hot = 0;
+    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_hot, tiles_kernel(b, SET_HOT), 64 * b.waves,
+                                                      tiles_lds_bytes(b.count)));
+    if (per_hot < 1) return bfail(EXPI_EHIP, "batched tiles kernel cannot be resident");
+    const int want = std::min(per_hot * cus, ((b.total_tiles + kXcd - 1) / kXcd) * kXcd);
     b.round_grid = std::max(kXcd, (want / kXcd) * kXcd);
     // a barrier wait longer than two seconds means something is wrong
     b.deadline_ticks = 2ll * 1000ll * (long long)(khz > 0 ? khz : 100000);
@@ -570,11 +631,16 @@ int enqueue(Batch& b, char* ws, const double* v, double* y, hipStream_t s) {
 
 constexpr int kRoundChunk = 8;   // rounds enqueued between status read-backs
 
+// One round: the auxiliary steps, the hot products, then the stop tests.
 hipError_t enqueue_round(const Batch& b, const BatchArgs& a, hipStream_t s) {
-    if (b.dtype == EXPI_F32)
-        hipLaunchKernelGGL(batch_tiles_kernel<float>, dim3(b.round_grid), dim3(64 * b.waves), 0, s, a);
-    else
-        hipLaunchKernelGGL(batch_tiles_kernel<double>, dim3(b.round_grid), dim3(64 * b.waves), 0, s, a);
+    const size_t lds = tiles_lds_bytes(b.count);
+    if (b.dtype == EXPI_F32) {
+        hipLaunchKernelGGL((batch_tiles_kernel<float, SET_AUX>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
+        hipLaunchKernelGGL((batch_tiles_kernel<float, SET_HOT>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
+    } else {
+        hipLaunchKernelGGL((batch_tiles_kernel<double, SET_AUX>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
+        hipLaunchKernelGGL((batch_tiles_kernel<double, SET_HOT>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
+    }
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(b.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -642,20 +708,23 @@ int build_round_graph(Batch& b, char* ws, const double* v, double* y, int rounds
     k0.kernelParams = p0;
     hipError_t e = hipGraphAddKernelNode(&prev, g, nullptr, 0, &k0);
     void* pa[] = {&a};
-    hipKernelNodeParams kt{};
-    kt.func = b.dtype == EXPI_F32 ? reinterpret_cast<void*>(batch_tiles_kernel<float>)
-                                  : reinterpret_cast<void*>(batch_tiles_kernel<double>);
-    kt.gridDim = dim3(b.round_grid);
-    kt.blockDim = dim3(64 * b.waves);
-    kt.kernelParams = pa;
+    hipKernelNodeParams kx{};
+    kx.func = const_cast<void*>(tiles_kernel(b, SET_AUX));
+    kx.gridDim = dim3(b.round_grid);
+    kx.blockDim = dim3(64 * b.waves);
+    kx.sharedMemBytes = (unsigned)tiles_lds_bytes(b.count);
+    kx.kernelParams = pa;
+    hipKernelNodeParams kt = kx;
+    kt.func = const_cast<void*>(tiles_kernel(b, SET_HOT));
     hipKernelNodeParams kf{};
     kf.func = reinterpret_cast<void*>(batch_finalize_kernel);
     kf.gridDim = dim3(b.count);
     kf.blockDim = dim3(256);
     kf.kernelParams = pa;
     for (int r = 0; r < rounds && e == hipSuccess; ++r) {
-        hipGraphNode_t nt = nullptr, nf = nullptr;
-        e = hipGraphAddKernelNode(&nt, g, &prev, 1, &kt);
+        hipGraphNode_t nx = nullptr, nt = nullptr, nf = nullptr;
+        e = hipGraphAddKernelNode(&nx, g, &prev, 1, &kx);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&nt, g, &nx, 1, &kt);
         if (e == hipSuccess) e = hipGraphAddKernelNode(&nf, g, &nt, 1, &kf);
         prev = nf;
     }
