@@ -219,6 +219,7 @@ def run_batched(args):
     import paper_1309_4616_amd as E
     import synth
     from oracle import operators as O
+    from paper_1309_4616_amd import autotune
 
     inst = synth.batched_instances(args.batch_count, seed=0)
     ns = np.array([it.n for it in inst])
@@ -231,7 +232,8 @@ def run_batched(args):
         v_host[o:o + it.n * it.n] = synth.uniform_vector(it.n * it.n, it.seed)
     v = torch.as_tensor(v_host, device="cuda:0")
     y = torch.zeros_like(v)
-    b.prepare()
+    # tile shape chosen by the library's autotuner (one timed solve per candidate)
+    tuned = autotune.tune_batch(b, v, y, reps=1, use_cache=False)
     b.launch(v, y)                      # warm-up (also the eager reference)
     stats, rounds = b.results()
     torch.cuda.synchronize()
@@ -273,6 +275,8 @@ def run_batched(args):
         "eager_ms": 1e3 * eager,
         "graph_replay_ms": 1e3 * graph,
         "graph_rounds": b.graph_rounds,
+        "tiles": {"waves_march": tuned["tiles"], "chosen_by": "expi_batch_autotune",
+                  "candidates_ms": tuned["candidates"]},
         "graph_capture_s": t_capture,
         "graph_equals_eager": same and r_graph == rounds,
         "rounds": rounds,

@@ -287,6 +287,16 @@ int expi_batch_launch(expi_batch *b, const double *v, double *y, void *ws, size_
 int expi_batch_capture(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
                        int rounds, void *stream);
 int expi_batch_replay(expi_batch *b, void *stream);
+/* Autotuner: solves the batch (v, y, ws as for expi_batch_launch; y is
+ * overwritten) under every candidate tile setting, waves {2,4,8} x march
+ * {4,8,16,32}, one warm-up and `reps` timed solves each (host wall clock
+ * around the synchronising solve), and keeps the fastest, prepared for
+ * `ws`.  A captured graph is dropped.  If cand/ms are given, the first
+ * max_cand (waves, march) pairs tried and their milliseconds per solve are
+ * written there; *n_cand receives the number tried. */
+int expi_batch_autotune(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
+                        int reps, void *stream, int *cand, float *ms, int max_cand, int *n_cand);
+int expi_batch_get_tiles(const expi_batch *b, int *waves, int *march);
 /* Rounds of the captured graph (0 if none). */
 int expi_batch_graph_rounds(const expi_batch *b);
 /* Read per-instance results back (synchronises); returns EXPI_OK if every

@@ -251,6 +251,7 @@ class Batch:
                 raise ValueError("per-instance arrays differ in length")
         if bc not in ("dirichlet0", "neumann0"):
             raise ValueError("bc must be dirichlet0 or neumann0")
+        self.bc, self.dtype = bc, dtype
         self._h = ctypes.c_void_p()
         cp = params.to_c() if params is not None else None
         i32 = ctypes.POINTER(ctypes.c_int32)
@@ -278,6 +279,11 @@ class Batch:
         if self._ws is None:
             self._ws = workspace(int(lib().expi_batch_workspace_bytes(self._h)), self.device)
         return self._ws
+
+    def tiles(self):
+        w, m = ctypes.c_int(), ctypes.c_int()
+        check(lib().expi_batch_get_tiles(self._h, ctypes.byref(w), ctypes.byref(m)))
+        return (w.value, m.value)
 
     def set_tiles(self, waves: int, march: int) -> None:
         check(lib().expi_batch_set_tiles(self._h, int(waves), int(march)))

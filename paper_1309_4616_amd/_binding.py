@@ -29,7 +29,8 @@ EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "e
            "expi_batch_total_length", "expi_batch_offsets", "expi_batch_workspace_bytes",
            "expi_batch_prepare", "expi_batch_launch", "expi_batch_capture", "expi_batch_replay",
            "expi_batch_results", "expi_batch_max_rounds", "expi_batch_graph_rounds",
-           "expi_batch_launch_persistent", "expi_batch_capture_persistent", "expi_mlp_param_count", "expi_mlp_scratch_floats",
+           "expi_batch_launch_persistent", "expi_batch_capture_persistent",
+           "expi_batch_autotune", "expi_batch_get_tiles", "expi_mlp_param_count", "expi_mlp_scratch_floats",
            "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam")
 
 
@@ -168,6 +169,12 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).restype = c_int
     L.expi_batch_capture.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p]
     L.expi_batch_capture.restype = c_int
+    L.expi_batch_autotune.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int, c_void_p,
+                                      ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_int,
+                                      ctypes.POINTER(c_int)]
+    L.expi_batch_autotune.restype = c_int
+    L.expi_batch_get_tiles.argtypes = [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    L.expi_batch_get_tiles.restype = c_int
     for name in ("expi_batch_max_rounds", "expi_batch_graph_rounds"):
         getattr(L, name).argtypes = [c_void_p]
         getattr(L, name).restype = c_int

@@ -100,3 +100,46 @@ def tune(op, dtype: str = "f64", reps: int = 10, path: str | None = None,
         _write(path, data)
     torch.cuda.synchronize(op.device)
     return entry
+
+
+def batch_key(batch) -> str:
+    """Cache key of a batch: sizes, time steps, boundary, dtype and GPU."""
+    import hashlib
+    import numpy as np
+    h = hashlib.sha1()
+    for a in (batch._nx, batch._ny, batch._tau):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return f"batch{batch.count}-{h.hexdigest()[:16]}-{batch.bc}-{batch.dtype}-{device_tag(batch.device)}"
+
+
+def tune_batch(batch, v, y, reps: int = 1, path: str | None = None, use_cache: bool = True,
+               stream=None) -> dict:
+    """Solve the batch under every candidate tile setting (expi_batch_autotune),
+    keep the fastest (prepared for the batch's workspace), record it; returns
+    {'tiles': (waves, march), 'ms': best time, 'candidates': [...]}.  y is
+    overwritten."""
+    from . import _stream_ptr
+    path = path or cache_path()
+    key = batch_key(batch)
+    data = _read(path) if use_cache else {}
+    if use_cache and key in data:
+        batch.set_tiles(*data[key]["tiles"])
+        batch.prepare(stream)
+        return data[key]
+    ws = batch.workspace()
+    maxc = 32
+    cand = (ctypes.c_int * (2 * maxc))()
+    ms = (ctypes.c_float * maxc)()
+    nc = ctypes.c_int()
+    check(lib().expi_batch_autotune(batch.handle, ctypes.c_void_p(v.data_ptr()),
+                                    ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                    ws.numel(), int(reps), _stream_ptr(stream, batch.device), cand, ms,
+                                    maxc, ctypes.byref(nc)))
+    rows = [((cand[2 * i], cand[2 * i + 1]), float(ms[i])) for i in range(min(nc.value, maxc))]
+    entry = {"tiles": list(batch.tiles()), "ms": min(t for _, t in rows) if rows else None,
+             "candidates": [[list(c), t] for c, t in rows]}
+    if use_cache:
+        data = _read(path)
+        data[key] = entry
+        _write(path, data)
+    return entry

@@ -28,6 +28,7 @@
 // A single persistent kernel that runs all rounds with grid barriers is kept
 // below but switched off (see expi_batch_launch_persistent).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -991,6 +992,57 @@ int expi_batch_graph_rounds(const expi_batch* bp) {
 int expi_batch_max_rounds(const expi_batch* bp) {
     const Batch* b = reinterpret_cast<const Batch*>(bp);
     return b ? b->max_rounds : -1;
+}
+
+int expi_batch_autotune(expi_batch* bp, const double* v, double* y, void* ws, size_t ws_bytes,
+                        int reps, void* stream, int* cand, float* ms, int max_cand, int* n_cand) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b || !v || !y || !ws || !n_cand) return bfail(EXPI_EINVAL, "NULL argument");
+    if (reps < 1 || reps > 100) return bfail(EXPI_EINVAL, "reps must be in [1, 100]");
+    if (ws_bytes < b->ws_total) return bfail(EXPI_EWORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    drop_graph(b);
+    const int waves_c[] = {2, 4, 8};
+    const int march_c[] = {4, 8, 16, 32};
+    int best_w = b->waves, best_m = b->march, n = 0;
+    double best = 1e300;
+    for (int wv : waves_c) {
+        for (int mc : march_c) {
+            int rc = expi_batch_set_tiles(bp, wv, mc);
+            if (rc == EXPI_OK) rc = expi_batch_prepare(bp, ws, ws_bytes, stream);
+            if (rc == EXPI_OK) rc = check_run_args(b, v, y, ws, ws_bytes);
+            if (rc == EXPI_OK) rc = run_rounds(*b, static_cast<char*>(ws), v, y, s);   // warm-up
+            if (rc) return rc;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < reps && rc == EXPI_OK; ++r) rc = run_rounds(*b, static_cast<char*>(ws), v, y, s);
+            if (rc) return rc;
+            const double t = std::chrono::duration<double, std::milli>(
+                                 std::chrono::steady_clock::now() - t0).count() / reps;
+            if (cand && ms && n < max_cand) {
+                cand[2 * n] = wv;
+                cand[2 * n + 1] = mc;
+                ms[n] = (float)t;
+            }
+            ++n;
+            if (t < best) {
+                best = t;
+                best_w = wv;
+                best_m = mc;
+            }
+        }
+    }
+    *n_cand = n;
+    int rc = expi_batch_set_tiles(bp, best_w, best_m);
+    if (rc == EXPI_OK) rc = expi_batch_prepare(bp, ws, ws_bytes, stream);
+    return rc;
+}
+
+int expi_batch_get_tiles(const expi_batch* bp, int* waves, int* march) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    if (!b || !waves || !march) return bfail(EXPI_EINVAL, "NULL argument");
+    *waves = b->waves;
+    *march = b->march;
+    return EXPI_OK;
 }
 
 int expi_batch_launch_persistent(expi_batch* bp, const double* v, double* y, void* ws,

@@ -216,3 +216,33 @@ def test_batch_rejects_bad_arguments(E):
         b.launch(v[1:], y[:-1])
     with pytest.raises(RuntimeError, match="switched off"):
         b.launch_persistent(v[:-1], y[:-1])
+
+
+def test_batch_autotune_picks_a_candidate_and_caches(E, tmp_path):
+    import torch
+    from paper_1309_4616_amd import autotune
+    nx, ny, hx, hy, tau = batch_case(seed=8, count=6)
+    b = E.Batch(nx, ny, hx, hy, tau, tol=1e-10, dtype="f64")
+    v_all = synth.uniform_vector(b.total_length, 3)
+    v = T(v_all)
+    y = torch.zeros_like(v)
+    path = str(tmp_path / "tiles.json")
+    print("batch autotune", flush=True)
+    entry = autotune.tune_batch(b, v, y, reps=1, path=path)
+    cands = [tuple(c) for c, _ in entry["candidates"]]
+    assert len(cands) == 12 and tuple(entry["tiles"]) in cands
+    assert b.tiles() == tuple(entry["tiles"])
+    assert entry["ms"] == min(t for _, t in entry["candidates"])
+    # the tuned batch is prepared and solves correctly
+    y.zero_()
+    b.launch(v, y)
+    b.results()
+    want = leja_oracle(nx, ny, hx, hy, tau, v_all, b.offsets, "dirichlet0", 1e-10)
+    yy = N(y)
+    for i, (yo, _) in enumerate(want):
+        n = int(nx[i] * ny[i])
+        assert relerr(yy[b.offsets[i]:b.offsets[i] + n], yo) <= TOL_F64
+    # a second batch with the same table takes the cached setting without timing
+    b2 = E.Batch(nx, ny, hx, hy, tau, tol=1e-10, dtype="f64")
+    assert autotune.tune_batch(b2, v, y, path=path) == entry
+    assert b2.tiles() == tuple(entry["tiles"])
