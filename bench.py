@@ -7,14 +7,17 @@ zero-flux (homogeneous Neumann) boundaries, a = 1 + 0.5 sin(2 pi x) sin(2 pi y)
 sin(2 pi z), u0 = Gaussian bump (sigma 0.1, centre (1/2,1/2,1/2)) + 0.01 N(0,1)
 noise (seed 0), tau = 1e-5, relative tolerance 1e-8.  Each step is one
 phi_1(tau A) action (Leja-point Newton interpolation) plus its start vector
-and update, all in the HIP library.
+and update, all in the HIP library; consecutive Newton products run as pair
+sweeps (two products per pass) unless --no-pairs.
 
 A step of the benchmark is one exponential Euler step on the whole grid.
 `value` is solved grid points per second (points x steps / wall time) in
 FP64; the same run is repeated with FP32 storage of the Newton vectors.
-`roofline` covers the fused Newton product, whose launches are timed with HIP
-events on the library's stream during the timed region.  `cpu_baseline` is
-the FP64 oracle on a bounded sample of the same workload.
+`roofline` covers the dominant kernel (the pair sweep), whose launches are
+timed with HIP events on the library's stream during the timed region.
+`cpu_baseline` is the FP64 oracle on a bounded sample of the same workload.
+Further legs: the learned step selector against the plain loop, and the
+batched solve of 256 uneven 2D problems.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -38,16 +41,17 @@ HBM_PEAK_GBS = 8000.0
 NEWTON_BYTES_PER_PT = {"f64": 32, "f32": 16}
 
 
-def step_bytes_per_pt(m: int, dt: str) -> int:
-    """Algorithmic bytes per point of one exponential Euler step with m
-    Newton products: start vector (read u, write r), first product (read r,
-    write w_1 and p), m-1 fused products, update (read u and p, write u)."""
+def step_bytes_per_pt(singles: int, pairs: int, dt: str) -> int:
+    """Algorithmic bytes per point of one exponential Euler step: start
+    vector (read u, write r), first product (read r, write w_1 and p), the
+    single Newton products and the pair sweeps (read w and p, write w and p
+    each), update (read u and p, write u)."""
     s = 8 if dt == "f64" else 4
     start = 8 + s
     first = 3 * s
     newton = 4 * s
     update = 8 + s + 8
-    return start + first + (m - 1) * newton + update
+    return start + first + (singles + pairs) * newton + update
 
 
 def counter_traffic(kernel_sub: str):
@@ -88,13 +92,13 @@ def run_gpu(args, dtype: str):
                      coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
     u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=0), device="cuda:0")
     ws = op.workspace(dtype)
-    params = E.LejaParams(profile=True)
+    params = E.LejaParams(profile=True, pairs=not args.no_pairs)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         E.expeuler_step(op, args.tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
     torch.cuda.synchronize()
-    matvecs = newton = timed = 0
-    newton_ms = 0.0
+    matvecs = newton = timed = pairs = 0
+    newton_ms = pair_ms = 0.0
     degrees = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -103,14 +107,21 @@ def run_gpu(args, dtype: str):
         newton += st["newton_steps"]
         timed += st["timed_products"]
         newton_ms += st["newton_ms"]
+        pairs += st["timed_pairs"]
+        pair_ms += st["pair_ms"]
         degrees.append(st["degree_last"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     del stream
     pts = n ** 3
-    bytes_total = sum(step_bytes_per_pt(m, dtype) for m in degrees) * pts
-    avg_ms = newton_ms / max(timed, 1)
-    achieved = NEWTON_BYTES_PER_PT[dtype] * pts / (avg_ms * 1e-3) / 1e9
+    singles = timed - 2 * pairs
+    # start vector, first product and update of every step, plus every launch
+    # of the Newton loops that did work
+    bytes_total = pts * (args.steps * step_bytes_per_pt(0, 0, dtype) +
+                         (singles + pairs) * NEWTON_BYTES_PER_PT[dtype])
+    per_launch = NEWTON_BYTES_PER_PT[dtype] * pts
+    single_us = 1e3 * (newton_ms - pair_ms) / max(singles, 1)
+    pair_us = 1e3 * pair_ms / max(pairs, 1)
     return {
         "wall_s": wall,
         "value": pts * args.steps / wall,
@@ -120,9 +131,12 @@ def run_gpu(args, dtype: str):
         "degrees": sorted(set(degrees)),
         "point_products_per_s": pts * matvecs / wall,
         "step_gbs": bytes_total / wall / 1e9,
-        "newton_avg_us": 1e3 * avg_ms,
-        "newton_timed": timed,
-        "newton_gbs": achieved,
+        "pairs_per_step": pairs / args.steps,
+        "singles_per_step": singles / args.steps,
+        "pair_avg_us": pair_us if pairs else None,
+        "pair_gbs": per_launch / (pair_us * 1e-6) / 1e9 if pairs else None,
+        "single_avg_us": single_us if singles else None,
+        "single_gbs": per_launch / (single_us * 1e-6) / 1e9 if singles else None,
         "u_checksum": float(u.double().sum().item()),
     }
 
@@ -343,6 +357,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--eval-steps", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-pairs", action="store_true",
+                    help="single Newton products only (no pair sweeps)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
@@ -394,7 +410,46 @@ def main():
         cpu = cpu_baseline(args)
 
     n = args.n
-    traffic = counter_traffic("stencil_sweep<3, 1, 1, double, double, 2>") if n == 256 else None
+    alg = NEWTON_BYTES_PER_PT["f64"] * n ** 3
+    if r64["pair_avg_us"]:
+        # the dominant kernel: the pair sweep (two Newton products per launch;
+        # algorithmic traffic read w_j and p, write w_{j+2} and p)
+        traffic = counter_traffic("pair_sweep<1, double>") if n == 256 else None
+        roofline = {
+            "bound": "hbm",
+            "kernel": "pair sweep: two fused Newton products per launch (3D separable stencil, f64)",
+            "achieved": r64["pair_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": r64["pair_gbs"] / HBM_PEAK_GBS,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_unit": "HBM bytes per launch",
+            "traffic_source": traffic["profile"] if traffic else None,
+            "algorithmic_bytes_per_launch": alg,
+            "bytes_per_point": NEWTON_BYTES_PER_PT["f64"],
+            "products_per_launch": 2,
+            "avg_launch_us": r64["pair_avg_us"],
+            "launches_per_step": r64["pairs_per_step"],
+            "single_product": {"avg_launch_us": r64["single_avg_us"], "achieved_gbs": r64["single_gbs"],
+                               "launches_per_step": r64["singles_per_step"]},
+        }
+    else:
+        traffic = counter_traffic("stencil_sweep<3, 1, 1, double, double, 2>") if n == 256 else None
+        roofline = {
+            "bound": "hbm",
+            "kernel": "fused Newton product (3D separable-coefficient stencil, f64)",
+            "achieved": r64["single_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": r64["single_gbs"] / HBM_PEAK_GBS,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_unit": "HBM bytes per launch",
+            "traffic_source": traffic["profile"] if traffic else None,
+            "algorithmic_bytes_per_launch": alg,
+            "bytes_per_point": NEWTON_BYTES_PER_PT["f64"],
+            "avg_launch_us": r64["single_avg_us"],
+            "launches_per_step": r64["singles_per_step"],
+        }
     out = {
         "metric": METRIC,
         "value": r64["value"],
@@ -421,21 +476,7 @@ def main():
             "point_products_per_s": r64["point_products_per_s"],
             "step_hbm_gbs": r64["step_gbs"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "fused Newton product (3D separable-coefficient stencil, f64)",
-            "achieved": r64["newton_gbs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": r64["newton_gbs"] / HBM_PEAK_GBS,
-            "traffic": traffic["bytes"] if traffic else None,
-            "traffic_unit": "HBM bytes per launch",
-            "traffic_source": traffic["profile"] if traffic else None,
-            "algorithmic_bytes_per_launch": NEWTON_BYTES_PER_PT["f64"] * n ** 3,
-            "bytes_per_point": NEWTON_BYTES_PER_PT["f64"],
-            "avg_launch_us": r64["newton_avg_us"],
-            "launches_timed": r64["newton_timed"],
-        },
+        "roofline": roofline,
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")}
                          if cpu else None),
     }
@@ -444,11 +485,13 @@ def main():
             "value": r32["value"],
             "ms_per_step": r32["ms_per_step"],
             "matvecs_per_step": r32["matvecs_per_step"],
-            "newton_gbs": r32["newton_gbs"],
-            "newton_frac": r32["newton_gbs"] / HBM_PEAK_GBS,
-            "newton_avg_us": r32["newton_avg_us"],
+            "single_avg_us": r32["single_avg_us"],
+            "single_gbs": r32["single_gbs"],
+            "single_frac": (r32["single_gbs"] / HBM_PEAK_GBS) if r32["single_gbs"] else None,
+            "pairs_per_step": r32["pairs_per_step"],
             "step_hbm_gbs": r32["step_gbs"],
-            "note": "w, p stored in float32; divided differences, norms, stop test and u in float64",
+            "note": ("w, p stored in float32; divided differences, norms, stop test and u in "
+                     "float64; with the separable coefficient every product is a single sweep"),
         }
     if learned:
         out["learned_vs_plain"] = learned

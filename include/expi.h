@@ -91,10 +91,10 @@ typedef struct {
     double  err_est;        /* largest (t_{m-1} + t_m)/||p|| over the substeps  */
     double  interval_a;     /* spectral interval [a, b] used                    */
     double  interval_b;
-    double  newton_ms;      /* summed device time of those products' sweep
-                               kernels (HIP events recorded on `stream` around
-                               each sweep launch); only products that did work
-                               (index < m) are counted */
+    double  newton_ms;      /* summed device time of the Newton sweep launches
+                               (single products and pair sweeps; HIP events
+                               recorded on `stream` around each launch) that
+                               did work: launches that began before the stop */
     double  rnorm;          /* ||r|| of the first substep's start vector        */
     double  t_first[5];     /* |d_j| ||w_j||, j = 0..4, of the first substep
                                (features of the step selector)                 */
@@ -102,6 +102,9 @@ typedef struct {
     int32_t pred_substeps;  /* step selector: predicted substep count           */
     int32_t fallback;       /* step selector: products beyond the prediction     */
     int32_t finalized;      /* products whose norms were reduced (stop tests)   */
+    int32_t timed_pairs;    /* pair sweeps among the timed launches (each covers
+                               two products; timed_products counts both)       */
+    double  pair_ms;        /* summed device time of those pair sweeps          */
 } expi_stats;
 
 /* Interpolation parameters; pass NULL for the defaults
@@ -125,7 +128,12 @@ typedef struct {
      * error-controlled loop continues (fallback). */
     const void *selector;
     int32_t selector_hidden;
-    int32_t reserved2;
+    /* 1: never fuse two Newton products into one sweep.  By default, on 3D
+     * stencils with a constant or separable coefficient and rows of at most
+     * 256 points, consecutive products run as pair sweeps that keep w_{j+1}
+     * on chip (same arithmetic, half the vector traffic) and test the stop
+     * rule after each of the two. */
+    int32_t no_pairs;
 } expi_params;
 
 /* ---- operators ---------------------------------------------------------- */

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("interval_b", ctypes.c_double), ("newton_ms", ctypes.c_double),
                 ("rnorm", ctypes.c_double), ("t_first", ctypes.c_double * 5),
                 ("pred_degree", ctypes.c_int32), ("pred_substeps", ctypes.c_int32),
-                ("fallback", ctypes.c_int32), ("finalized", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("finalized", ctypes.c_int32),
+                ("timed_pairs", ctypes.c_int32), ("pair_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -73,7 +74,7 @@ class Params(ctypes.Structure):
                 ("max_retries", ctypes.c_int32), ("have_interval", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("interval_a", ctypes.c_double),
                 ("interval_b", ctypes.c_double), ("selector", ctypes.c_void_p),
-                ("selector_hidden", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("selector_hidden", ctypes.c_int32), ("no_pairs", ctypes.c_int32)]
 
 
 @dataclass
@@ -85,6 +86,7 @@ class LejaParams:
     profile: bool = False
     selector: object = None          # device float tensor (see selector.pack)
     selector_hidden: int = 64
+    pairs: bool = True               # fuse consecutive Newton products where supported
 
     def to_c(self) -> Params:
         p = Params()
@@ -92,6 +94,7 @@ class LejaParams:
         p.m_max = int(self.m_max)
         p.max_retries = int(self.max_retries)
         p.profile = 1 if self.profile else 0
+        p.no_pairs = 0 if self.pairs else 1
         if self.selector is not None:
             p.selector = ctypes.c_void_p(self.selector.data_ptr())
             p.selector_hidden = int(self.selector_hidden)

@@ -143,6 +143,7 @@ struct Params {
     double ia = 0, ib = 0;
     const float* selector = nullptr;
     int hidden = 0;
+    bool pairs = true;
 };
 
 int read_params(const expi_params* p, Params* out) {
@@ -157,6 +158,7 @@ int read_params(const expi_params* p, Params* out) {
         q.ib = p->interval_b;
         q.selector = static_cast<const float*>(p->selector);
         q.hidden = p->selector_hidden;
+        q.pairs = p->no_pairs == 0;
     }
     if (q.selector && (q.hidden < 1 || q.hidden > 256))
         return fail(EXPI_EINVAL, "params.selector_hidden must be in [1, 256]");
@@ -246,13 +248,17 @@ struct LoopOut {
     int m = 0;
     int done = 0;
     double err = 0;
-    int timed = 0;        // products timed (profile mode)
+    int timed = 0;        // products covered by the timed launches (profile mode)
     double ms = 0;        // their summed device time
+    int pairs_timed = 0;  // pair sweeps among them
+    double pair_ms = 0;   // and their device time
     double rnorm = 0;     // ||r||
     double hist[kHist] = {0, 0, 0, 0, 0};
     int pred_m = 0, pred_s = 0;
     int fallback = 0;     // learned mode: the prediction fell short
     int finalized = 0;    // products followed by a norm reduction and stop test
+    double fix = 0;       // p holds d_{m+1} w_{m+1} too many (pair stopped at its first product)
+    const void* fix_w = nullptr;   // where w_{m+1} is
 };
 
 struct Ctx {
@@ -272,10 +278,13 @@ struct Ctx {
     const float* selector;
     int hidden;
     double ia, ib, tau;
+    bool pairs;             // fuse consecutive products into pair sweeps
 };
 
 // First product reads `src` (storage code tin) and writes w_1 to w0 and p to
-// `p`; products j >= 1 alternate between w0 and w1.
+// `p`.  Later products read the buffer holding the latest w and write the
+// other one: a single product j writes w_{j+1}, a pair sweep at j writes
+// w_{j+2} (w_{j+1} stays on chip).
 int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     const std::vector<double>& d = C.d;
     void* w[2] = {C.ws + C.L.w0, C.ws + C.L.w1};
@@ -294,11 +303,18 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     a.guard = 0;
     HIP_TRY(launch_sweep(*C.op, EPI_FIRST, tin, C.tw, a, C.s));
     int finalized = 1;
+    int cur = 0;   // w[cur] holds the latest w
 
-    // product j of the loop (j >= 1); `fin` adds the norm reduction and stop test
-    auto product = [&](int j, bool fin) -> int {
-        a.x = w[(j - 1) & 1];
-        a.out = w[j & 1];
+    struct Launch {
+        int j, n;        // first product index, products covered
+        const void* out;
+    };
+    std::vector<Launch> log;
+
+    // single product j (j >= 1); `fin` adds the norm reduction and stop test
+    auto single = [&](int j, bool fin) -> int {
+        a.x = w[cur];
+        a.out = w[cur ^ 1];
         a.j = j;
         a.beta = -(C.c / C.gamma + C.xi[j]);
         a.d1 = d[j + 1];
@@ -306,7 +322,48 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
         HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s,
                              C.profile ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
+        log.push_back({j, 1, w[cur ^ 1]});
+        cur ^= 1;
         if (fin) ++finalized;
+        return EXPI_OK;
+    };
+    // products j and j+1 in one pair sweep
+    auto pair = [&](int j, bool fin) -> int {
+        PairArgs b{};
+        b.x = w[cur];
+        b.out = w[cur ^ 1];
+        b.p = p;
+        b.partials = C.partials;
+        b.st = C.st;
+        b.alpha = 1.0 / C.gamma;
+        b.beta1 = -(C.c / C.gamma + C.xi[j]);
+        b.beta2 = -(C.c / C.gamma + C.xi[j + 1]);
+        b.d1 = d[j + 1];
+        b.d2 = d[j + 2];
+        b.tol = C.tol;
+        b.j = j;
+        b.guard = 1;
+        if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
+        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, C.profile ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
+        log.push_back({j, 2, w[cur ^ 1]});
+        cur ^= 1;
+        if (fin) finalized += 2;
+        return EXPI_OK;
+    };
+    // `count` products from j on (pairs where allowed), advancing j
+    auto advance = [&](int& j, int count, bool fin) -> int {
+        const int end = j + count;
+        while (j < end) {
+            int rc;
+            if (C.pairs && end - j >= 2) {
+                rc = pair(j, fin);
+                j += 2;
+            } else {
+                rc = single(j, fin);
+                j += 1;
+            }
+            if (rc) return rc;
+        }
         return EXPI_OK;
     };
     auto sync_state = [&](NewtonState* st) -> int {
@@ -326,7 +383,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         // reductions except the last two, whose two-term stop test judges the
         // prediction.  If it is not met the plain loop below continues.
         for (; j < 4; ++j) {
-            int rc = product(j, true);
+            int rc = single(j, true);
             if (rc) return rc;
         }
         HIP_TRY(launch_selector(C.selector, C.hidden, C.st, C.ia, C.ib, C.tau, C.m_max, C.s));
@@ -338,8 +395,13 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
             finished = true;
         } else {
             const int mh = std::min(std::max(last.pred_m, j + 1), C.m_max);
+            // unreduced products up to mh - 2, then the last two with tests
+            if (mh - 2 > j) {
+                rc = advance(j, mh - 2 - j, false);
+                if (rc) return rc;
+            }
             for (; j < mh; ++j) {
-                rc = product(j, j >= mh - 2);
+                rc = single(j, true);
                 if (rc) return rc;
             }
             rc = sync_state(&last);
@@ -353,23 +415,23 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     if (!finished) {
         const int hint = learned_tail ? 0 : get_hint(*C.op, C.key);
         // With a degree hint (or after a prediction) the first batch ends at
-        // the expected stop and later products go one by one; without one,
-        // batches of 4 then 2 run one batch ahead of the status read-back.
-        int chunk = learned_tail ? 1 : (hint >= 2 ? hint - 1 : 4);
+        // the expected stop and later batches are one launch; without one,
+        // batches of 4 then 2 products run one batch ahead of the status
+        // read-back.
+        const int step = C.pairs ? 2 : 1;
+        int chunk = learned_tail ? step : (hint >= 2 ? hint - 1 : 4);
         const bool ahead = !learned_tail && hint < 2;
         std::deque<int> pending;
         while (!finished) {
             if (j < C.m_max) {
                 const int cnt = std::min(chunk, C.m_max - j);
-                for (int q = 0; q < cnt; ++q, ++j) {
-                    int rc = product(j, true);
-                    if (rc) return rc;
-                }
+                int rc = advance(j, cnt, true);
+                if (rc) return rc;
                 int slot;
-                int rc = readback(C.st, C.s, &slot);
+                rc = readback(C.st, C.s, &slot);
                 if (rc) return rc;
                 pending.push_back(slot);
-                chunk = ahead ? 2 : 1;
+                chunk = ahead ? 2 : step;
             }
             const size_t keep = ahead ? 1 : 0;
             while (!pending.empty() && (pending.size() > keep || j >= C.m_max)) {
@@ -390,14 +452,26 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     out->rnorm = last.rnorm;
     for (int q = 0; q < kHist; ++q) out->hist[q] = last.hist[q];
     out->finalized = finalized;
+    if (last.done == 1 && last.fix != 0.0) {
+        // the pair sweep at m - 1 wrote w_{m+1}
+        for (const Launch& L : log)
+            if (L.n == 2 && L.j == last.m - 1) out->fix_w = L.out;
+        if (!out->fix_w) return fail(EXPI_EHIP, "internal: no pair sweep for the stop at m");
+        out->fix = last.fix;
+    }
     if (last.done == 1) set_hint(*C.op, C.key, last.m);
     if (C.profile && last.done != 2) {
-        // products 1..m-1 did work and precede the read-back that ended the loop
-        for (int q = 1; q < last.m; ++q) {
+        // launches that began before the stop did work and precede the read-back
+        for (const Launch& L : log) {
+            if (L.j >= last.m) continue;
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, tl_ctx.tev[2 * q], tl_ctx.tev[2 * q + 1]));
+            HIP_TRY(hipEventElapsedTime(&ms, tl_ctx.tev[2 * L.j], tl_ctx.tev[2 * L.j + 1]));
             out->ms += ms;
-            out->timed += 1;
+            out->timed += L.n;
+            if (L.n == 2) {
+                out->pair_ms += ms;
+                out->pairs_timed += 1;
+            }
         }
     }
     return EXPI_OK;
@@ -420,6 +494,8 @@ void stats_add(expi_stats* st, const LoopOut& lo) {
     st->err_est = std::max(st->err_est, lo.err);
     st->timed_products += lo.timed;
     st->newton_ms += lo.ms;
+    st->timed_pairs += lo.pairs_timed;
+    st->pair_ms += lo.pair_ms;
 }
 
 int common_setup(Op& op, double tau, double tol, int dtype, const Params& P, char* ws,
@@ -486,7 +562,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
         return fail(EXPI_EUNSUPPORTED, "phi_k with k >= 2 needs a single substep (tau (b-a) <= l_max)");
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile, P.selector, P.hidden, ia, ib, tau};
+          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pair_supported(op, tw)};
     expi_stats acc{};
     for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
         if (k >= 2 && sub > 1)
@@ -527,6 +603,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
                 tin = 0;
             }
             LoopOut lo;
+            C.pairs = P.pairs && pair_supported(op, tw) && (((uintptr_t)p & 15) == 0);
             rc = newton_loop(C, src, tin, p, &lo);
             if (rc) return rc;
             stats_add(&acc, lo);
@@ -538,11 +615,15 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
             if (!p_in_y) {
                 if (k == 1) {
                     // y' <- y' + p / s   (y' = 0 before the first substep)
-                    HIP_TRY(launch_update(n, y, l == 0 ? nullptr : y, p, tw, 1.0 / sub, C.st, 1, s));
+                    HIP_TRY(launch_update(n, y, l == 0 ? nullptr : y, p, tw, 1.0 / sub, C.st, 1, s,
+                                          lo.fix_w, lo.fix));
                 } else {
                     // e^{delta A} (or phi_k, single substep) applied: y <- p
-                    HIP_TRY(launch_update(n, y, nullptr, p, tw, 1.0, C.st, 1, s));
+                    HIP_TRY(launch_update(n, y, nullptr, p, tw, 1.0, C.st, 1, s, lo.fix_w, lo.fix));
                 }
+            } else if (lo.fix != 0.0) {
+                // y holds p: remove the one term too many in place
+                HIP_TRY(launch_update(n, y, nullptr, y, 0, 1.0, C.st, 1, s, lo.fix_w, lo.fix));
             }
         }
         acc.converged = ok ? 1 : 0;
@@ -572,7 +653,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     int sub = substep_count(tau, ia, ib, P.l_max);
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile, P.selector, P.hidden, ia, ib, tau};
+          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pair_supported(op, tw)};
     double* yb = reinterpret_cast<double*>(ws + L.y);
     void* p = ws + L.p;
     expi_stats acc{};
@@ -609,7 +690,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
             // y_{l+1} = y_l + delta p; the last substep writes u
             const double* yin = (l == 0) ? u : yb;
             double* yout = (l == sub - 1) ? u : yb;
-            HIP_TRY(launch_update(n, yout, yin, p, tw, delta, C.st, 1, s));
+            HIP_TRY(launch_update(n, yout, yin, p, tw, delta, C.st, 1, s, lo.fix_w, lo.fix));
         }
         acc.converged = ok ? 1 : 0;
         if (ok) {

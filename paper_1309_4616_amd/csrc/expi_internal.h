@@ -16,6 +16,7 @@
 namespace expi {
 
 constexpr int kHist = 5;         // Newton-term norms t_0..t_4 kept per loop
+constexpr int kMaxPairWaves = 16;   // waves of a pair-sweep workgroup
 
 // ---------------------------------------------------------------------------
 // Device-side status of one Newton loop (lives at the start of the workspace).
@@ -35,6 +36,8 @@ struct alignas(64) NewtonState {
     double rnorm;         // ||r|| of the loop's start vector
     int pred_m;           // step selector's predicted Newton degree
     int pred_s;           // step selector's predicted substep count
+    double fix;           // pair sweep met the test at its first product: d_{m+1},
+                          // whose term d_{m+1} w_{m+1} p holds one too many; else 0
 };
 static_assert(sizeof(NewtonState) == 128, "status record is 128 bytes");
 
@@ -79,6 +82,34 @@ struct SweepArgs {
     int march;            // points marched per thread (stencils)
 };
 
+// Arguments of the pair sweep (two Newton products in one pass, pair.hip).
+struct PairArgs {
+    const void* x;        // w_j
+    void* out;            // w_{j+2}
+    void* p;              // running Newton sum, p_j in, p_{j+2} out
+    const double* tx;     // separable coefficient tables
+    const double* ty;
+    const double* tz;
+    double* partials;     // [grid][4]: ||w_{j+1}||^2, ||p_{j+1}||^2, ||w_{j+2}||^2, ||p_{j+2}||^2
+    NewtonState* st;
+    double c0, c1;
+    double ih2[3];
+    double alpha, beta1, beta2, d1, d2, tol;   // beta_j, beta_{j+1}, d_{j+1}, d_{j+2}
+    int n[3];
+    int bc;
+    int guard;
+    int j;
+    int nxw;              // waves per grid row (1 or 2)
+    int rows;             // output rows per row tile
+    int nrt;              // row tiles
+    int chunk;            // (row tile, plane) units per workgroup
+    int per_xcd;
+};
+
+struct PairGeom {
+    int nxw, rows, nrt, chunk, grid, per_xcd;
+};
+
 // Arguments of the one-workgroup finalize kernel that follows a reducing sweep.
 struct FinalArgs {
     const double* partials;
@@ -87,6 +118,7 @@ struct FinalArgs {
     int j;
     int guard;
     double d0, d1, tol;
+    double d2;            // pair sweeps: d_{j+2}
 };
 
 // Step-selector network (mlp.hip): predicted (substeps, degree) from the
@@ -159,8 +191,18 @@ hipError_t launch_stencil(const Op& op, const Geom& g, int epi, int tin, int tou
 hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs& a,
                       hipStream_t s);
 hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
-                         double scale, NewtonState* st, int guard, hipStream_t s);
+                         double scale, const NewtonState* st, int guard, hipStream_t s,
+                         const void* wfix = nullptr, double fix = 0.0);
 hipError_t launch_reset(NewtonState* st, hipStream_t s);
+
+// Pair sweeps: two Newton products in one pass (pair.hip), then a finalize
+// kernel that applies the stop test after each of them.
+bool pair_supported(const Op& op, int tw);
+PairGeom pair_geom(const Op& op, int cus);
+hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s,
+                       hipEvent_t after_sweep = nullptr, bool finalize = true);
+hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
+                                int guard, double d1, double d2, double tol, hipStream_t s);
 hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s);
 
 // Error reporting (api.hip).

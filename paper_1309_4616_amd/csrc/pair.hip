@@ -1,0 +1,473 @@
+// Two consecutive Newton products of the Leja interpolation in one sweep
+// (Sec. III-C; the products are eq. (3)) for 3D stencils on gfx950:
+//
+//   w_{j+1} = alpha A w_j     + beta_j     w_j,     p_{j+1} = p_j     + d_{j+1} w_{j+1}
+//   w_{j+2} = alpha A w_{j+1} + beta_{j+1} w_{j+1}, p_{j+2} = p_{j+1} + d_{j+2} w_{j+2}
+//
+// with the partial sums of ||w_{j+1}||^2, ||p_{j+1}||^2, ||w_{j+2}||^2 and
+// ||p_{j+2}||^2 per workgroup, so that the finalize kernel can apply the
+// two-term stop test after each of the two products.  w_{j+1} never goes to
+// HBM: the sweep reads w_j and p once and writes w_{j+2} and p once, half
+// the traffic of two single products.  Every value is computed by the same
+// formula as in the single product, rounded to the storage type where the
+// single product stores it.
+//
+// Layout and traversal:
+//  * a workgroup is 16 waves; a wave owns 128 consecutive x points of one row
+//    (2 per lane), so a row of n0 <= 256 points takes NX = 1 or 2 waves and
+//    the workgroup holds 16/NX rows: R = 16/NX - 2 output rows and one halo
+//    row on each side;
+//  * every wave marches along z computing w_{j+1} of its row one plane ahead;
+//    the plane goes into a three-plane LDS ring, one barrier per plane, and
+//    the inner waves then compute w_{j+2} of the plane behind from their own
+//    registers (z neighbours) and the ring (y and wave-edge x neighbours);
+//  * w_j streams through a four-slot register queue as in the single sweep
+//    (y neighbours are cache-served loads of the neighbouring rows);
+//  * the grid has one workgroup per CU slot; the (row tile, plane) units are
+//    split into equal contiguous chunks numbered XCD-major, so that the
+//    chunks that share halo rows run on the same L2 at the same time.
+#include <algorithm>
+
+#include "sweep_common.h"
+
+namespace expi {
+namespace {
+
+constexpr int kPairWaves = 16;
+constexpr int kPairLds = kPairWaves * 128;   // points of one ring plane
+
+// Face weights.  With a(x, y, z) = c0 + c1 X(x) Y(y) Z(z) the weight of the
+// face between cells c and c' (the mean of a_c and a_c') is
+// c0 + c1 * (product of the other two tables) * (mean of the two values of
+// the table along the face's axis); a missing neighbour under homogeneous
+// Dirichlet counts with the cell's own coefficient (face value := own value)
+// and value 0, under zero-flux Neumann not at all.  So on a plane of a row
+// every y and z face weight is A + B X(x) with A, B the same in all lanes,
+// and so is the sum of the diagonal parts of those faces.  The x faces keep
+// per-lane face values.  The constant coefficient is the case c1 = 0.
+template <class TC>
+struct RowW {          // per (row, segment): y data of the row
+    TC y, gym, gyq;    // Y(y); c1 ihy e Yf for the two y faces
+    TC aym, ayq;       // c0 ihy e
+    TC ady, gdy;       // diagonal: c0 ihy (d_m + d_q), c1 ihy (d_m Yf_m + d_q Yf_q)
+    TC hz;             // c1 ihz Y(y)
+};
+
+template <class TC>
+struct PlaneW {        // per (row, plane): weights A + B X of the y, z faces
+    TC sx;             // x faces: c0 ihx + sx Xf
+    TC aym, bym, ayq, byq, azm, bzm, azq, bzq, ad, bd;
+};
+
+template <int COEF, class TC>
+__device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const double* __restrict__ tz,
+                                                    int q, int n2, bool dir, TC c0ihz, TC c1ihx) {
+    PlaneW<TC> w;
+    const bool ezm = q > 0, ezq = q < n2 - 1;
+    const TC em = ezm ? (TC)1 : (TC)0, eq = ezq ? (TC)1 : (TC)0;
+    const TC dm = (ezm || dir) ? (TC)1 : (TC)0, dq = (ezq || dir) ? (TC)1 : (TC)0;
+    w.aym = r.aym;
+    w.ayq = r.ayq;
+    w.azm = em * c0ihz;
+    w.azq = eq * c0ihz;
+    w.ad = r.ady + c0ihz * (dm + dq);
+    if (COEF == EXPI_COEF_SEPARABLE) {
+        const int qc = min(max(q, 0), n2 - 1);
+        const TC zc = (TC)tz[qc];
+        const TC zfm = ezm ? (TC)0.5 * ((TC)tz[qc - 1] + zc) : zc;
+        const TC zfq = ezq ? (TC)0.5 * ((TC)tz[qc + 1] + zc) : zc;
+        w.sx = c1ihx * (r.y * zc);
+        w.bym = r.gym * zc;
+        w.byq = r.gyq * zc;
+        w.bzm = em * (r.hz * zfm);
+        w.bzq = eq * (r.hz * zfq);
+        w.bd = r.gdy * zc + r.hz * (dm * zfm + dq * zfq);
+    } else {
+        w.sx = w.bym = w.byq = w.bzm = w.bzq = w.bd = (TC)0;
+    }
+    return w;
+}
+
+// (A w) at the lane's two points from the values of the points (wc), their
+// x neighbours outside the pair (wl, wr, already set for a missing
+// neighbour: 0 under Dirichlet, the point's own value otherwise), the y and
+// z neighbour values (anything finite where the neighbour is missing: its
+// weight is 0) and the weights.
+template <int COEF, class TC>
+__device__ __forceinline__ void aw_pair(const TC (&wc)[2], TC wl, TC wr, const TC (&ym)[2],
+                                        const TC (&yq)[2], const TC (&zm)[2], const TC (&zq)[2],
+                                        const PlaneW<TC>& w, TC c0ihx, const TC* xd, TC (&aw)[2]) {
+    // xd: X of the two points, face values left, between, right
+    TC wxl, wxc, wxr, X[2] = {1, 1};
+    if (COEF == EXPI_COEF_SEPARABLE) {
+        X[0] = xd[0];
+        X[1] = xd[1];
+        wxl = c0ihx + w.sx * xd[2];
+        wxc = c0ihx + w.sx * xd[3];
+        wxr = c0ihx + w.sx * xd[4];
+    } else {
+        wxl = wxc = wxr = c0ihx;
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        TC wym, wyq, wzm, wzq, d;
+        if (COEF == EXPI_COEF_SEPARABLE) {
+            wym = w.aym + w.bym * X[v];
+            wyq = w.ayq + w.byq * X[v];
+            wzm = w.azm + w.bzm * X[v];
+            wzq = w.azq + w.bzq * X[v];
+            d = w.ad + w.bd * X[v];
+        } else {
+            wym = w.aym;
+            wyq = w.ayq;
+            wzm = w.azm;
+            wzq = w.azq;
+            d = w.ad;
+        }
+        const TC left = v == 0 ? wl : wc[0];
+        const TC right = v == 1 ? wr : wc[1];
+        const TC fl = v == 0 ? wxl : wxc;
+        const TC fr = v == 1 ? wxr : wxc;
+        aw[v] = fl * (left - wc[v]) + fr * (right - wc[v]) + wym * ym[v] + wyq * yq[v] +
+                wzm * zm[v] + wzq * zq[v] - d * wc[v];
+    }
+}
+
+template <class T, class TC>
+__device__ __forceinline__ void ld2(const T* __restrict__ p, int idx, TC (&o)[2]) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    const T2 t = *reinterpret_cast<const T2*>(p + idx);
+    o[0] = (TC)t.x;
+    o[1] = (TC)t.y;
+}
+
+template <class T, class TC>
+__device__ __forceinline__ void st2(T* __restrict__ p, int idx, const TC (&v)[2]) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    T2 t;
+    t.x = (T)v[0];
+    t.y = (T)v[1];
+    *reinterpret_cast<T2*>(p + idx) = t;
+}
+
+// Whole-wave shifts by one lane through DPP: lane l receives `src` of lane
+// l-1 (from_left) or l+1 (from_right); the lane without a source (0, resp.
+// 63) keeps `edge`.
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float edge, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, src), CTRL,
+                                                                 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double edge, double src) {
+    const unsigned long long e = __builtin_bit_cast(unsigned long long, edge);
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, src);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)e, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(e >> 32), (int)(unsigned)(v >> 32), CTRL,
+                                               0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+constexpr int kDppWaveShr1 = 0x138;   // lane l <- lane l-1
+constexpr int kDppWaveShl1 = 0x130;   // lane l <- lane l+1
+
+template <int COEF, class TW>
+__global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
+    using TC = compute_t<TW, TW>;
+    typedef TC TC2 __attribute__((ext_vector_type(2)));
+    if (a.guard && a.st->done != 0) return;
+    __shared__ TC ring[3 * kPairLds];
+    __shared__ TC xdat[2 * 64][6];
+    __shared__ RowW<TC> rowdat[kPairWaves];
+    const TW* __restrict__ x = static_cast<const TW*>(a.x);
+    TW* __restrict__ out = static_cast<TW*>(a.out);
+    TW* __restrict__ pv = static_cast<TW*>(a.p);
+    // the wave index is the same in every lane; saying so keeps the row data
+    // (and everything derived from it) in scalar registers
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int NX = a.nxw, R = a.rows;
+    const int ry = wv / NX, xq = wv % NX;
+    const int RW = 128 * NX;                      // ring row width (>= n0)
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int plane = n0 * n1;
+    const int i = xq * 128 + lane * 2;            // first of the lane's two x points
+    const bool xin = i < n0;                      // n0 is even: both points in the row
+    const int ic = xin ? i : n0 - 2;
+    const bool dir = (a.bc == EXPI_DIRICHLET0), ionly = (a.bc == EXPI_INTERIOR_ONLY);
+    const TC ihx = (TC)a.ih2[0], ihy = (TC)a.ih2[1], ihz = (TC)a.ih2[2];
+    const TC alpha = (TC)a.alpha, beta1 = (TC)a.beta1, beta2 = (TC)a.beta2;
+    const TC d1 = (TC)a.d1, d2 = (TC)a.d2;
+    const TC c0 = (TC)a.c0, c1 = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1 : (TC)0;
+    const TC c0ihx = c0 * ihx, c0ihz = c0 * ihz, c1ihx = c1 * ihx;
+    // Row ends.  The x neighbour of a point at a row end is 0 under
+    // Dirichlet and the point's own value otherwise (no flux), so that one
+    // formula serves all points.  The first lane of a row has no left
+    // source lane (DPP keeps its edge value); where the row ends inside a
+    // wave, the lanes past the end offer the last point's value (or 0).
+    const bool lb = ic == 0, rb = ic + 2 >= n0;
+    const bool partial = (xq + 1) * 128 > n0;     // the row ends inside this wave
+    // x data of the lane in LDS: table values of its points, face values
+    // left of point 0, between the points and right of point 1 (own value
+    // where the row ends); reading them where they are used costs less than
+    // holding them in registers all along
+    if (COEF == EXPI_COEF_SEPARABLE) {
+        if (ry == 0) {
+            const TC X0 = (TC)a.tx[ic], X1 = (TC)a.tx[ic + 1];
+            TC* e = xdat[xq * 64 + lane];
+            e[0] = X0;
+            e[1] = X1;
+            e[2] = lb ? X0 : (TC)0.5 * ((TC)a.tx[ic - 1] + X0);
+            e[3] = (TC)0.5 * (X0 + X1);
+            e[4] = rb ? X1 : (TC)0.5 * (X1 + (TC)a.tx[ic + 2]);
+        }
+    }
+    const TC* xd = xdat[xq * 64 + lane];
+    // edge lanes: offset of the value they take in for a neighbour of w_j
+    int eoff = 0;
+    if (lane == 0) eoff = ic > 0 ? -1 : 0;
+    if (lane == 63) eoff = ic + 2 < n0 ? 2 : 1;
+    const TC efac = (dir && ((lane == 0 && lb) || (lane == 63 && rb))) ? (TC)0 : (TC)1;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+
+    // the neighbours of the lane's pair from the adjacent lanes; el, er are
+    // the values lanes 0 and 63 take in
+    auto neighbours = [&](const TC (&wc)[2], TC el, TC er, TC& left, TC& right) {
+        TC srcr = wc[0];
+        if (partial && !xin) srcr = dir ? (TC)0 : wc[1];   // past the row end: the last point
+        left = dpp_shift<kDppWaveShr1>(el, wc[1]);
+        right = dpp_shift<kDppWaveShl1>(er, srcr);
+        if (partial && xin && rb) right = dir ? (TC)0 : wc[1];
+    };
+
+    const long long units = (long long)a.nrt * n2;
+    const long long u_lo = (long long)xcd_tile(a.per_xcd) * a.chunk;
+    const long long u_hi = min(u_lo + (long long)a.chunk, units);
+    for (long long u = u_lo; u < u_hi;) {
+        const int rt = (int)(u / n2), kb = (int)(u % n2);
+        const int ke = (int)min((long long)n2, kb + (u_hi - u));
+        u += ke - kb;
+        // this wave's row: step 1 on rows rt*R-1 .. rt*R+R, step 2 on the inner R
+        const int y = rt * R - 1 + ry;
+        const bool yin = y >= 0 && y < n1;
+        const bool outw = yin && ry >= 1 && ry <= R;
+        const int yc = min(max(y, 0), n1 - 1);
+        const bool eym = y > 0, eyq = y < n1 - 1;
+        const int rowb = ic + n0 * yc;
+        const int yoffm = eym ? -n0 : 0, yoffq = eyq ? n0 : 0;
+        auto at = [&](int k) { return rowb + plane * min(max(k, 0), n2 - 1); };
+        // y data of the row, kept in LDS (read where used)
+        if (lane == 0) {
+            const TC c0ihy = c0 * ihy, c1ihy = c1 * ihy;
+            const TC em = eym ? (TC)1 : (TC)0, eq = eyq ? (TC)1 : (TC)0;
+            const TC dm = (eym || dir) ? (TC)1 : (TC)0, dq = (eyq || dir) ? (TC)1 : (TC)0;
+            TC Y = 1, yfm = 1, yfq = 1;
+            if (COEF == EXPI_COEF_SEPARABLE) {
+                Y = (TC)a.ty[yc];
+                yfm = eym ? (TC)0.5 * ((TC)a.ty[yc - 1] + Y) : Y;
+                yfq = eyq ? (TC)0.5 * ((TC)a.ty[yc + 1] + Y) : Y;
+            }
+            RowW<TC> rw;
+            rw.y = Y;
+            rw.gym = em * (c1ihy * yfm);
+            rw.gyq = eq * (c1ihy * yfq);
+            rw.aym = em * c0ihy;
+            rw.ayq = eq * c0ihy;
+            rw.ady = c0ihy * (dm + dq);
+            rw.gdy = c1ihy * (dm * yfm + dq * yfq);
+            rw.hz = (c1 * ihz) * Y;
+            rowdat[wv] = rw;
+        }
+        __syncthreads();   // the x and row data are in LDS
+        const RowW<TC>& rw = rowdat[wv];
+        // a point of the outer layer has a zero row under interior_only
+        const bool yedge = !(eym && eyq);
+
+        // Iteration k: start the loads of w_j on plane k+3, of the y and edge
+        // neighbours of w_j on plane k+1 and of p on plane k; compute w_{j+2}
+        // on plane k-1 (inner rows); then w_{j+1} on plane k+1; one barrier.
+        // w_j of planes k, k+1, k+2 is in W[s], W[s+1], W[s+2] (mod 4);
+        // w_{j+1} of planes k-2, k-1, k in W1[s+2], W1[s+3], W1[s] and plane
+        // k+1 goes to W1[s+1]; p of plane k-1 in P[(s+1)&1].
+        const int kst = kb - 2;
+        TC W[4][2], W1[4][2], P[2][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W[q][0] = W[q][1] = W1[q][0] = W1[q][1] = 0;
+        P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
+        if (yin) {
+            ld2(x, at(kst), W[0]);
+            ld2(x, at(kst + 1), W[1]);
+            ld2(x, at(kst + 2), W[2]);
+        }
+        for (int k0 = kst; k0 <= ke; k0 += 4) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + s;
+                // (1) loads
+                TC Sym[2] = {0, 0}, Syq[2] = {0, 0}, Se = 0;
+                if (yin) {
+                    const int b = at(k + 1);
+                    ld2(x, b + yoffm, Sym);
+                    ld2(x, b + yoffq, Syq);
+                    Se = efac * (TC)x[b + eoff];
+                    ld2(x, at(k + 3), W[(s + 3) & 3]);
+                    if (outw) ld2(pv, at(k), P[s & 1]);
+                }
+                // (2) w_{j+2} on plane k-1 (inner rows)
+                const int kp = k - 1;
+                if (outw && kp >= kb && kp < ke) {
+                    const int slot = (kp - kst) % 3;
+                    const TC* base = &ring[slot * kPairLds];
+                    const TC wc[2] = {W1[(s + 3) & 3][0], W1[(s + 3) & 3][1]};
+                    const TC2 ymv = *reinterpret_cast<const TC2*>(base + (ry - 1) * RW + i);
+                    const TC2 yqv = *reinterpret_cast<const TC2*>(base + (ry + 1) * RW + i);
+                    const TC el = base[ry * RW + (ic > 0 ? ic - 1 : ic)];
+                    const TC er = base[ry * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
+                    TC left, right;
+                    neighbours(wc, efac * el, efac * er, left, right);
+                    const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, a.tz, kp, n2, dir, c0ihz, c1ihx);
+                    const TC zm[2] = {W1[(s + 2) & 3][0], W1[(s + 2) & 3][1]};
+                    const TC zq[2] = {W1[s & 3][0], W1[s & 3][1]};
+                    const TC ym[2] = {ymv.x, ymv.y};
+                    const TC yq[2] = {yqv.x, yqv.y};
+                    TC aw[2];
+                    aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
+                    if (ionly) {
+                        const bool edge = yedge || kp == 0 || kp == n2 - 1;
+                        if (edge || lb) aw[0] = 0;
+                        if (edge || rb) aw[1] = 0;
+                    }
+                    TC wo[2], po[2];
+                    const TC* pp = P[(s + 1) & 1];
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        const TC p1 = (TC)(TW)(pp[v] + d1 * wc[v]);
+                        const TC w2 = (TC)(TW)(alpha * aw[v] + beta2 * wc[v]);
+                        const TC p2 = (TC)(TW)(p1 + d2 * w2);
+                        wo[v] = w2;
+                        po[v] = p2;
+                        if (xin) {
+                            s0 += (double)wc[v] * (double)wc[v];
+                            s1 += (double)p1 * (double)p1;
+                            s2 += (double)w2 * (double)w2;
+                            s3 += (double)p2 * (double)p2;
+                        }
+                    }
+                    if (xin) {
+                        const int idx = at(kp);
+                        st2(out, idx, wo);
+                        st2(pv, idx, po);
+                    }
+                }
+                // (3) w_{j+1} on plane k+1 (values of planes outside the grid
+                // or of rows outside it are never used with a nonzero weight)
+                {
+                    const int q = k + 1;
+                    const TC wc[2] = {W[(s + 1) & 3][0], W[(s + 1) & 3][1]};
+                    TC left, right;
+                    neighbours(wc, Se, Se, left, right);
+                    const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, a.tz, q, n2, dir, c0ihz, c1ihx);
+                    const TC zm[2] = {W[s & 3][0], W[s & 3][1]};
+                    const TC zq[2] = {W[(s + 2) & 3][0], W[(s + 2) & 3][1]};
+                    TC aw[2];
+                    aw_pair<COEF, TC>(wc, left, right, Sym, Syq, zm, zq, pw, c0ihx, xd, aw);
+                    if (ionly) {
+                        const bool edge = yedge || q == 0 || q == n2 - 1;
+                        if (edge || lb) aw[0] = 0;
+                        if (edge || rb) aw[1] = 0;
+                    }
+                    TC r[2];
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) r[v] = (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
+                    W1[(s + 1) & 3][0] = r[0];
+                    W1[(s + 1) & 3][1] = r[1];
+                    const int slot = (q - kst) % 3;
+                    TC2 t;
+                    t.x = r[0];
+                    t.y = r[1];
+                    *reinterpret_cast<TC2*>(&ring[slot * kPairLds + ry * RW + i]) = t;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    finish_sweep4(a.partials, s0, s1, s2, s3);
+}
+
+template <class TW>
+hipError_t go(const PairGeom& g, int coef, const PairArgs& a, hipStream_t s) {
+    if (coef == EXPI_COEF_SEPARABLE)
+        hipLaunchKernelGGL((pair_sweep<EXPI_COEF_SEPARABLE, TW>), dim3(g.grid), dim3(kPairWaves * 64), 0, s, a);
+    else
+        hipLaunchKernelGGL((pair_sweep<EXPI_COEF_CONST, TW>), dim3(g.grid), dim3(kPairWaves * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Pair sweeps need a 3D stencil with a constant or separable coefficient,
+// rows of at most 256 points (even, for the two-point vector accesses), and
+// 16-byte aligned vectors.  With float storage and the separable
+// coefficient the pair sweep is bound by its arithmetic and measured slower
+// than two single products, so it is used there only for the constant one.
+bool pair_supported(const Op& op, int tw) {
+    return op.kind == 0 && op.dim == 3 && op.n[0] % 2 == 0 && op.n[0] <= 256 &&
+           (op.coef == EXPI_COEF_CONST || (op.coef == EXPI_COEF_SEPARABLE && tw == 0));
+}
+
+PairGeom pair_geom(const Op& op, int cus) {
+    PairGeom g{};
+    g.nxw = (op.n[0] + 127) / 128;
+    g.rows = kPairWaves / g.nxw - 2;
+    g.nrt = (op.n[1] + g.rows - 1) / g.rows;
+    const long long units = (long long)g.nrt * op.n[2];
+    // one workgroup per CU, a multiple of the XCD count, every one busy
+    long long grid = std::min<long long>(cus > 0 ? cus : 256, units);
+    grid = std::max<long long>(kXcd, (grid / kXcd) * kXcd);
+    g.chunk = (int)((units + grid - 1) / grid);
+    g.grid = (int)grid;
+    g.per_xcd = g.grid / kXcd;
+    return g;
+}
+
+// Compute units of the current device (cached per host thread and device).
+int device_cus() {
+    static thread_local int dev_cached = -1, cus_cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev != dev_cached) {
+        if (hipDeviceGetAttribute(&cus_cached, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus_cached = 0;
+        dev_cached = dev;
+    }
+    return cus_cached;
+}
+
+hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep,
+                       bool finalize) {
+    const PairGeom g = pair_geom(op, device_cus());
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = op.n[d];
+        a.ih2[d] = 1.0 / (op.h[d] * op.h[d]);
+    }
+    a.bc = op.bc;
+    a.c0 = op.c0;
+    a.c1 = op.c1;
+    a.tx = op.tx;
+    a.ty = op.ty;
+    a.tz = op.tz;
+    a.nxw = g.nxw;
+    a.rows = g.rows;
+    a.nrt = g.nrt;
+    a.chunk = g.chunk;
+    a.per_xcd = g.per_xcd;
+    hipError_t e = tw == 1 ? go<float>(g, op.coef, a, s) : go<double>(g, op.coef, a, s);
+    if (e != hipSuccess) return e;
+    if (after_sweep) {
+        e = hipEventRecord(after_sweep, s);
+        if (e != hipSuccess) return e;
+    }
+    if (!finalize) return hipSuccess;
+    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d1, a.d2, a.tol, s);
+}
+
+}  // namespace expi

@@ -78,15 +78,80 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs f) {
     if (m < kHist) st->hist[m] = t;
 }
 
+// out = yin + scale * p (yin may be NULL for 0).  After a pair sweep that
+// met the stop test at its first product, p holds one term too many:
+// p - fix * wfix removes d_{m+1} w_{m+1} (wfix NULL otherwise).
 template <class TP>
-__global__ __launch_bounds__(256) void update_kernel(int64_t n, double* __restrict__ out,
-                                                     const double* __restrict__ yin,
-                                                     const TP* __restrict__ p, double scale,
-                                                     const NewtonState* st, int guard) {
+__global__ __launch_bounds__(256) void update_kernel(int64_t n, double* out, const double* yin,
+                                                     const TP* p, double scale,
+                                                     const NewtonState* st, int guard,
+                                                     const TP* __restrict__ wfix, double fix) {
     if (guard && st->done != 1) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        out[i] = (yin ? yin[i] : 0.0) + scale * (double)p[i];
+    if (wfix) {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            out[i] = (yin ? yin[i] : 0.0) + scale * ((double)p[i] - fix * (double)wfix[i]);
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            out[i] = (yin ? yin[i] : 0.0) + scale * (double)p[i];
+    }
+}
+
+// Stop tests after a pair sweep: the two-term test at m = j+1 with
+// ||w_{j+1}||, ||p_{j+1}||, and, if that one fails, at m = j+2 with
+// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel).
+__global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
+    __shared__ double red[kMaxWaves][4];
+    NewtonState* st = f.st;
+    if (f.guard && st->done != 0) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
+        const double* part = f.partials + 4 * (size_t)b;
+        for (int q = 0; q < 4; ++q) s[q] += part[q];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) red[wv][q] = s[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < 4; ++q) {
+        s[q] = red[0][q];
+        for (int w = 1; w < nw; ++w) s[q] += red[w][q];
+    }
+    const double wn1 = sqrt(s[0]), pn1 = sqrt(s[1]), wn2 = sqrt(s[2]), pn2 = sqrt(s[3]);
+    const double tprev = st->t_prev;
+    const double t1 = fabs(f.d1) * wn1;
+    const int m1 = f.j + 1;
+    const double num1 = tprev + t1;
+    if (m1 < kHist) st->hist[m1] = t1;
+    int done = 0;
+    if (!isfinite(wn1) || !isfinite(pn1) || !isfinite(tprev)) done = 2;
+    else if (m1 >= 2 && num1 <= f.tol * pn1) done = 1;
+    if (done) {
+        st->t_prev = t1;
+        st->err = (pn1 > 0.0) ? num1 / pn1 : (num1 == 0.0 ? 0.0 : INFINITY);
+        st->pnorm = pn1;
+        st->wnorm = wn1;
+        st->m = m1;
+        st->fix = (done == 1) ? f.d2 : 0.0;
+        st->done = done;
+        return;
+    }
+    const double t2 = fabs(f.d2) * wn2;
+    const int m2 = f.j + 2;
+    const double num2 = t1 + t2;
+    if (m2 < kHist) st->hist[m2] = t2;
+    if (!isfinite(wn2) || !isfinite(pn2)) done = 2;
+    else if (num2 <= f.tol * pn2) done = 1;
+    st->t_prev = t2;
+    st->err = (pn2 > 0.0) ? num2 / pn2 : (num2 == 0.0 ? 0.0 : INFINITY);
+    st->pnorm = pn2;
+    st->wnorm = wn2;
+    st->m = m2;
+    st->fix = 0.0;
+    st->done = done;
 }
 
 __global__ void reset_kernel(NewtonState* st) {
@@ -105,6 +170,7 @@ __global__ void reset_kernel(NewtonState* st) {
         st->rnorm = 0.0;
         st->pred_m = 0;
         st->pred_s = 0;
+        st->fix = 0.0;
     }
 }
 
@@ -181,7 +247,9 @@ size_t partials_bytes(const Op& op) {
         t.waves = 1;
         t.march = kMinMarch;
     }
-    return (size_t)make_geom(op, t).grid * 4 * sizeof(double);
+    // also covers the pair sweep, whose grid never exceeds max(CU count, 8)
+    const size_t grid = std::max<size_t>((size_t)make_geom(op, t).grid, 1024);
+    return grid * 4 * sizeof(double);
 }
 
 hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, hipStream_t s,
@@ -243,16 +311,35 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
 }
 
 hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
-                         double scale, NewtonState* st, int guard, hipStream_t s) {
+                         double scale, const NewtonState* st, int guard, hipStream_t s,
+                         const void* wfix, double fix) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
+    if (fix == 0.0) wfix = nullptr;
     if (tp == 0)
         hipLaunchKernelGGL(update_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, n, out,
-                           yin, static_cast<const double*>(p), scale, st, guard);
+                           yin, static_cast<const double*>(p), scale, st, guard,
+                           static_cast<const double*>(wfix), fix);
     else
         hipLaunchKernelGGL(update_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, n, out,
-                           yin, static_cast<const float*>(p), scale, st, guard);
+                           yin, static_cast<const float*>(p), scale, st, guard,
+                           static_cast<const float*>(wfix), fix);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
+                                int guard, double d1, double d2, double tol, hipStream_t s) {
+    FinalArgs f{};
+    f.partials = partials;
+    f.st = st;
+    f.nparts = nparts;
+    f.j = j;
+    f.guard = guard;
+    f.d1 = d1;
+    f.d2 = d2;
+    f.tol = tol;
+    hipLaunchKernelGGL(pair_finalize_kernel, dim3(1), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 

@@ -1,0 +1,170 @@
+"""GPU parity of the pair sweep (two Newton products per pass).
+
+phi_1(tau A) v on 3D stencils with the pair sweep on (the default where it
+applies) against the FP64 oracle, over shapes that exercise its tiling: one
+and two waves per row, rows ragged against the row tile, few planes,
+chunks that cross row tiles, every boundary handling, both coefficient kinds
+it covers, FP32 storage, and stops after either product of a pair (the
+second case removes the extra term).  The single-product path on the same
+inputs must agree.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrators as I
+from oracle import operators as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def E(device):
+    import paper_1309_4616_amd as E
+    E.lib()
+    return E
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make(E, shape, bc, kind):
+    h = tuple(1.0 / s for s in shape)
+    if kind == "const":
+        return E.StencilOp(shape, h, bc, coef=1.3), O.stencil_matrix(shape, h, bc, coef=1.3)
+    tabs = [np.cos(2 * math.pi * (np.arange(s) + 0.5) / s) for s in shape]
+    c0, c1 = 1.0, 0.45
+    fld = c0 + c1 * ((tabs[2][:, None, None] * tabs[1][None, :, None]) * tabs[0][None, None, :])
+    op = E.StencilOp(shape, h, bc, coef=("separable", c0, c1, *tabs))
+    return op, O.stencil_matrix(shape, h, bc, coef=fld.reshape(-1))
+
+
+def run_pair_and_single(E, op, v, tau, tol, dtype="f64", interval=None):
+    yp, sp = E.phi_action(op, 1, tau, T(v), tol=tol, dtype=dtype,
+                          params=E.LejaParams(profile=True, interval=interval))
+    ys, ss = E.phi_action(op, 1, tau, T(v), tol=tol, dtype=dtype,
+                          params=E.LejaParams(pairs=False, profile=True, interval=interval))
+    return N(yp), sp, N(ys), ss
+
+
+SHAPES = [
+    (256, 12, 9),     # two waves per row, rows ragged against the 6-row tile
+    (128, 20, 7),     # one wave per row, 14-row tiles
+    (130, 7, 5),      # two waves, second nearly empty
+    (64, 6, 33),      # many planes: chunks cross row tiles
+    (2, 3, 4),        # tiny
+    (200, 1, 3),      # a single row
+    (96, 15, 1),      # a single plane
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["dirichlet0", "neumann0", "interior_only"])
+def test_pair_sweep_phi1_matches_oracle(E, shape, bc):
+    for kind in ("const", "separable"):
+        op, A = make(E, shape, bc, kind)
+        n = int(np.prod(shape))
+        v = synth.uniform_vector(n, 7)
+        a, b = O.gershgorin_interval(A)
+        # interior_only with a side of at most 2 points has no interior: A = 0
+        # and a = b, so both sides get the interval [-1, 0] instead
+        iv = None if b > a else (-1.0, 0.0)
+        tau = 8.0 / (b - a) if iv is None else 1e-3     # tau (b - a) = 8: one substep
+        print(f"pair phi1 {shape} {bc} {kind}", flush=True)
+        yp, sp, ys, ss = run_pair_and_single(E, op, v, tau, 1e-10, interval=iv)
+        yo, so = I.phi_action(A, 1, tau, v, 1e-10, interval=iv)
+        assert relerr(yp, yo) <= TOL_F64, (kind, relerr(yp, yo))
+        assert relerr(ys, yo) <= TOL_F64
+        assert abs(sp["degree_last"] - so.degrees[-1]) <= 1
+        # the pair path took pair sweeps (it applies to every shape here)
+        assert sp["timed_pairs"] >= 1 and ss["timed_pairs"] == 0
+
+
+def test_pair_stops_after_either_product(E):
+    """Vary tau so the stop falls after the first and after the second
+    product of a pair; both match the oracle, the first with the extra term
+    removed."""
+    shape = (256, 10, 6)
+    op, A = make(E, shape, "neumann0", "separable")
+    n = int(np.prod(shape))
+    v = synth.uniform_vector(n, 3)
+    a, b = O.gershgorin_interval(A)
+    parities = set()
+    for q in np.linspace(2.0, 40.0, 12):
+        tau = q / (b - a)
+        yp, sp, ys, ss = run_pair_and_single(E, op, v, tau, 1e-10)
+        yo, so = I.phi_action(A, 1, tau, v, 1e-10)
+        assert relerr(yp, yo) <= TOL_F64, (q, relerr(yp, yo))
+        assert sp["degree_last"] == ss["degree_last"]
+        parities.add(sp["degree_last"] % 2)
+    assert parities == {0, 1}
+
+
+def test_pair_substeps_expeuler_and_fp32(E):
+    """Several substeps (start vectors between loops), the exponential Euler
+    step, and FP32 storage through the pair sweep."""
+    shape = (256, 14, 11)
+    op, A = make(E, shape, "neumann0", "separable")
+    n = int(np.prod(shape))
+    v = synth.uniform_vector(n, 5)
+    a, b = O.gershgorin_interval(A)
+    tau = 230.0 / (b - a)                      # three substeps
+    yp, sp, ys, ss = run_pair_and_single(E, op, v, tau, 1e-10)
+    yo, so = I.phi_action(A, 1, tau, v, 1e-10)
+    assert sp["substeps"] == so.substeps == 3
+    assert relerr(yp, yo) <= TOL_F64 and relerr(ys, yo) <= TOL_F64
+    y32, s32 = E.phi_action(op, 1, tau, T(v), tol=1e-10, dtype="f32")
+    assert relerr(N(y32), yo) <= 5e-6
+    u0 = 0.5 + 0.1 * synth.uniform_vector(n, 9)
+    tau_e = 20.0 / (b - a)
+    u = T(u0)
+    st = E.expeuler_step(op, tau_e, u, tol=1e-10)
+    uo, _ = I.expeuler_step(A, tau_e, u0, 1e-10)
+    assert relerr(N(u), uo) <= TOL_F64
+    assert st["converged"] == 1
+
+
+def test_pair_profile_accounting(E):
+    shape = (256, 30, 20)
+    op, A = make(E, shape, "dirichlet0", "const")
+    v = synth.uniform_vector(int(np.prod(shape)), 1)
+    a, b = O.gershgorin_interval(A)
+    yp, sp, ys, ss = run_pair_and_single(E, op, v, 30.0 / (b - a), 1e-10)
+    m = sp["degree_last"]
+    # first product single, then pairs (and maybe one single) up to the stop
+    assert sp["timed_products"] >= m - 1 - 1 and sp["timed_products"] <= m
+    assert sp["timed_pairs"] >= (m - 2) // 2 - 1
+    assert 0 < sp["pair_ms"] <= sp["newton_ms"]
+    assert ss["timed_products"] == m - 1 and ss["timed_pairs"] == 0
+
+
+def test_pair_fp32_constant_coefficient(E):
+    """FP32 storage takes pair sweeps for the constant coefficient (and single
+    products for the separable one)."""
+    shape = (256, 9, 13)
+    op, A = make(E, shape, "dirichlet0", "const")
+    v = synth.uniform_vector(int(np.prod(shape)), 2)
+    a, b = O.gershgorin_interval(A)
+    tau = 25.0 / (b - a)
+    y, st = E.phi_action(op, 1, tau, T(v), tol=1e-10, dtype="f32", params=E.LejaParams(profile=True))
+    yo, _ = I.phi_action(A, 1, tau, v, 1e-10)
+    assert relerr(N(y), yo) <= 5e-6
+    assert st["timed_pairs"] >= 1
+    op2, A2 = make(E, shape, "dirichlet0", "separable")
+    y2, st2 = E.phi_action(op2, 1, tau, T(v), tol=1e-10, dtype="f32", params=E.LejaParams(profile=True))
+    assert st2["timed_pairs"] == 0
