@@ -34,7 +34,9 @@ namespace expi {
 namespace {
 
 constexpr int kPairWaves = 16;
-constexpr int kPairLds = kPairWaves * 128;   // points of one ring plane
+constexpr int kPairLds = kPairWaves * 128;   // points of one plane of the w_{j+1} ring
+constexpr int kWRingLds = 2560;              // points of one plane of the w_j ring:
+                                             // (16/NX + 2) rows of 128 NX points
 
 // Face weights.  With a(x, y, z) = c0 + c1 X(x) Y(y) Z(z) the weight of the
 // face between cells c and c' (the mean of a_c and a_c') is
@@ -176,9 +178,13 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
     typedef TC TC2 __attribute__((ext_vector_type(2)));
     if (a.guard && a.st->done != 0) return;
-    __shared__ TC ring[3 * kPairLds];
+    __shared__ TC ring[3 * kPairLds];     // w_{j+1}: rows y0-1 .. y0+R of three planes
+    __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
     __shared__ TC xdat[2 * 64][6];
     __shared__ RowW<TC> rowdat[kPairWaves];
+    // every ring entry holds a finite value before it is read
+    for (int t = threadIdx.x; t < 3 * kPairLds; t += blockDim.x) ring[t] = 0;
+    for (int t = threadIdx.x; t < 3 * kWRingLds; t += blockDim.x) wring[t] = 0;
     const TW* __restrict__ x = static_cast<const TW*>(a.x);
     TW* __restrict__ out = static_cast<TW*>(a.out);
     TW* __restrict__ pv = static_cast<TW*>(a.p);
@@ -222,10 +228,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         }
     }
     const TC* xd = xdat[xq * 64 + lane];
-    // edge lanes: offset of the value they take in for a neighbour of w_j
-    int eoff = 0;
-    if (lane == 0) eoff = ic > 0 ? -1 : 0;
-    if (lane == 63) eoff = ic + 2 < n0 ? 2 : 1;
+    // Dirichlet row ends: the edge lanes take in 0
     const TC efac = (dir && ((lane == 0 && lb) || (lane == 63 && rb))) ? (TC)0 : (TC)1;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 
@@ -253,8 +256,14 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         const int yc = min(max(y, 0), n1 - 1);
         const bool eym = y > 0, eyq = y < n1 - 1;
         const int rowb = ic + n0 * yc;
-        const int yoffm = eym ? -n0 : 0, yoffq = eyq ? n0 : 0;
         auto at = [&](int k) { return rowb + plane * min(max(k, 0), n2 - 1); };
+        // the first and last wave rows also bring in the row beyond them
+        // (y0-2, y0+R+1) into the w_j ring; they compute no w_{j+2}, so they
+        // carry it in the registers that hold p in the inner rows
+        const int rr = ry + 1;                            // own row in the w_j ring
+        const bool hal = ry == 0 || ry == R + 1;
+        const int rh = ry == 0 ? 0 : R + 3;               // the extra row
+        const int hoff = ry == 0 ? (eym ? -n0 : 0) : (eyq ? n0 : 0);
         // y data of the row, kept in LDS (read where used)
         if (lane == 0) {
             const TC c0ihy = c0 * ihy, c1ihy = c1 * ihy;
@@ -293,25 +302,41 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) W[q][0] = W[q][1] = W1[q][0] = W1[q][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
-        if (yin) {
-            ld2(x, at(kst), W[0]);
-            ld2(x, at(kst + 1), W[1]);
-            ld2(x, at(kst + 2), W[2]);
+        auto wslot = [&](int q) { return &wring[((q - kst) % 3) * kWRingLds]; };
+        auto put = [&](TC* base, int row, const TC (&v)[2]) {
+            TC2 t;
+            t.x = v[0];
+            t.y = v[1];
+            *reinterpret_cast<TC2*>(base + row * RW + i) = t;
+        };
+        {
+            TC h[2] = {0, 0};
+            if (yin) {
+                ld2(x, at(kst), W[0]);
+                ld2(x, at(kst + 1), W[1]);
+                ld2(x, at(kst + 2), W[2]);
+                if (hal) {
+                    ld2(x, at(kst + 1) + hoff, h);
+                    ld2(x, at(kst + 2) + hoff, P[1]);
+                }
+            }
+            // plane kst+1 of w_j into the ring (iteration kst reads it)
+            put(wslot(kst + 1), rr, W[1]);
+            if (hal) put(wslot(kst + 1), rh, h);
         }
         for (int k0 = kst; k0 <= ke; k0 += 4) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int k = k0 + s;
-                // (1) loads
-                TC Sym[2] = {0, 0}, Syq[2] = {0, 0}, Se = 0;
+                // (1) loads: w_j on plane k+3 (and the extra row), p on plane k
                 if (yin) {
-                    const int b = at(k + 1);
-                    ld2(x, b + yoffm, Sym);
-                    ld2(x, b + yoffq, Syq);
-                    Se = efac * (TC)x[b + eoff];
                     ld2(x, at(k + 3), W[(s + 3) & 3]);
                     if (outw) ld2(pv, at(k), P[s & 1]);
+                    else if (hal) ld2(x, at(k + 3) + hoff, P[s & 1]);
                 }
+                // w_j on plane k+2 (loaded one iteration ago) into the ring
+                put(wslot(k + 2), rr, W[(s + 2) & 3]);
+                if (hal) put(wslot(k + 2), rh, P[(s + 1) & 1]);
                 // (2) w_{j+2} on plane k-1 (inner rows)
                 const int kp = k - 1;
                 if (outw && kp >= kb && kp < ke) {
@@ -362,9 +387,15 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 // or of rows outside it are never used with a nonzero weight)
                 {
                     const int q = k + 1;
+                    const TC* wb = wslot(q);
                     const TC wc[2] = {W[(s + 1) & 3][0], W[(s + 1) & 3][1]};
+                    const TC2 ymv = *reinterpret_cast<const TC2*>(wb + (rr - 1) * RW + i);
+                    const TC2 yqv = *reinterpret_cast<const TC2*>(wb + (rr + 1) * RW + i);
+                    const TC Sym[2] = {ymv.x, ymv.y}, Syq[2] = {yqv.x, yqv.y};
+                    const TC el = wb[rr * RW + (ic > 0 ? ic - 1 : ic)];
+                    const TC er = wb[rr * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                     TC left, right;
-                    neighbours(wc, Se, Se, left, right);
+                    neighbours(wc, efac * el, efac * er, left, right);
                     const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, a.tz, q, n2, dir, c0ihz, c1ihx);
                     const TC zm[2] = {W[s & 3][0], W[s & 3][1]};
                     const TC zq[2] = {W[(s + 2) & 3][0], W[(s + 2) & 3][1]};
