@@ -490,8 +490,9 @@ def main():
             "single_frac": (r32["single_gbs"] / HBM_PEAK_GBS) if r32["single_gbs"] else None,
             "pairs_per_step": r32["pairs_per_step"],
             "step_hbm_gbs": r32["step_gbs"],
-            "note": ("w, p stored in float32; divided differences, norms, stop test and u in "
-                     "float64; with the separable coefficient every product is a single sweep"),
+            "pair_avg_us": r32["pair_avg_us"],
+            "pair_gbs": r32["pair_gbs"],
+            "note": "w, p stored in float32; divided differences, norms, stop test and u in float64",
         }
     if learned:
         out["learned_vs_plain"] = learned
