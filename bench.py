@@ -414,7 +414,7 @@ def main():
     if r64["pair_avg_us"]:
         # the dominant kernel: the pair sweep (two Newton products per launch;
         # algorithmic traffic read w_j and p, write w_{j+2} and p)
-        traffic = counter_traffic("pair_sweep<1, double>") if n == 256 else None
+        traffic = counter_traffic("pair_sweep<1, 1, double>") if n == 256 else None
         roofline = {
             "bound": "hbm",
             "kernel": "pair sweep: two fused Newton products per launch (3D separable stencil, f64)",

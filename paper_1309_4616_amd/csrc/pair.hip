@@ -173,7 +173,7 @@ __device__ __forceinline__ double dpp_shift(double edge, double src) {
 constexpr int kDppWaveShr1 = 0x138;   // lane l <- lane l-1
 constexpr int kDppWaveShl1 = 0x130;   // lane l <- lane l+1
 
-template <int COEF, class TW>
+template <int COEF, int BC, class TW>
 __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
     typedef TC TC2 __attribute__((ext_vector_type(2)));
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     const int i = xq * 128 + lane * 2;            // first of the lane's two x points
     const bool xin = i < n0;                      // n0 is even: both points in the row
     const int ic = xin ? i : n0 - 2;
-    const bool dir = (a.bc == EXPI_DIRICHLET0), ionly = (a.bc == EXPI_INTERIOR_ONLY);
+    constexpr bool dir = BC == EXPI_DIRICHLET0, ionly = BC == EXPI_INTERIOR_ONLY;
     const TC ihx = (TC)a.ih2[0], ihy = (TC)a.ih2[1], ihz = (TC)a.ih2[2];
     const TC alpha = (TC)a.alpha, beta1 = (TC)a.beta1, beta2 = (TC)a.beta2;
     const TC d1 = (TC)a.d1, d2 = (TC)a.d2;
@@ -302,7 +302,15 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) W[q][0] = W[q][1] = W1[q][0] = W1[q][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
-        auto wslot = [&](int q) { return &wring[((q - kst) % 3) * kWRingLds]; };
+        // ring slot of a plane: (plane - kst) mod 3.  Within an unrolled
+        // block the plane is k0 + c for a constant c, and k0 - kst = 4 * it
+        // is 'it' mod 3; so the slot is (b + c) mod 3 with b = it mod 3.
+        int b3 = 0;
+        auto slot_of = [&](int c) {   // c >= 0, constant after unrolling
+            const int t = b3 + c % 3;
+            return t >= 3 ? t - 3 : t;
+        };
+        auto wslot_c = [&](int c) { return &wring[slot_of(c) * kWRingLds]; };
         auto put = [&](TC* base, int row, const TC (&v)[2]) {
             TC2 t;
             t.x = v[0];
@@ -321,8 +329,8 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 }
             }
             // plane kst+1 of w_j into the ring (iteration kst reads it)
-            put(wslot(kst + 1), rr, W[1]);
-            if (hal) put(wslot(kst + 1), rh, h);
+            put(wslot_c(1), rr, W[1]);
+            if (hal) put(wslot_c(1), rh, h);
         }
         for (int k0 = kst; k0 <= ke; k0 += 4) {
 #pragma unroll
@@ -335,13 +343,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     else if (hal) ld2(x, at(k + 3) + hoff, P[s & 1]);
                 }
                 // w_j on plane k+2 (loaded one iteration ago) into the ring
-                put(wslot(k + 2), rr, W[(s + 2) & 3]);
-                if (hal) put(wslot(k + 2), rh, P[(s + 1) & 1]);
+                put(wslot_c(s + 2), rr, W[(s + 2) & 3]);
+                if (hal) put(wslot_c(s + 2), rh, P[(s + 1) & 1]);
                 // (2) w_{j+2} on plane k-1 (inner rows)
                 const int kp = k - 1;
                 if (outw && kp >= kb && kp < ke) {
-                    const int slot = (kp - kst) % 3;
-                    const TC* base = &ring[slot * kPairLds];
+                    const TC* base = &ring[slot_of(s + 2) * kPairLds];   // plane k-1 = k0 + s - 1
                     const TC wc[2] = {W1[(s + 3) & 3][0], W1[(s + 3) & 3][1]};
                     const TC2 ymv = *reinterpret_cast<const TC2*>(base + (ry - 1) * RW + i);
                     const TC2 yqv = *reinterpret_cast<const TC2*>(base + (ry + 1) * RW + i);
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 // or of rows outside it are never used with a nonzero weight)
                 {
                     const int q = k + 1;
-                    const TC* wb = wslot(q);
+                    const TC* wb = wslot_c(s + 1);
                     const TC wc[2] = {W[(s + 1) & 3][0], W[(s + 1) & 3][1]};
                     const TC2 ymv = *reinterpret_cast<const TC2*>(wb + (rr - 1) * RW + i);
                     const TC2 yqv = *reinterpret_cast<const TC2*>(wb + (rr + 1) * RW + i);
@@ -411,25 +418,39 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     for (int v = 0; v < 2; ++v) r[v] = (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
                     W1[(s + 1) & 3][0] = r[0];
                     W1[(s + 1) & 3][1] = r[1];
-                    const int slot = (q - kst) % 3;
                     TC2 t;
                     t.x = r[0];
                     t.y = r[1];
-                    *reinterpret_cast<TC2*>(&ring[slot * kPairLds + ry * RW + i]) = t;
+                    *reinterpret_cast<TC2*>(&ring[slot_of(s + 1) * kPairLds + ry * RW + i]) = t;
                 }
                 __syncthreads();
             }
+            b3 = b3 == 2 ? 0 : b3 + 1;   // 4 = 1 mod 3
         }
     }
     finish_sweep4(a.partials, s0, s1, s2, s3);
 }
 
+template <int COEF, class TW>
+void go_bc(const PairGeom& g, int bc, const PairArgs& a, hipStream_t s) {
+    const dim3 grid(g.grid), block(kPairWaves * 64);
+    switch (bc) {
+        case EXPI_DIRICHLET0:
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW>), grid, block, 0, s, a);
+            break;
+        case EXPI_NEUMANN0:
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_NEUMANN0, TW>), grid, block, 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_INTERIOR_ONLY, TW>), grid, block, 0, s, a);
+            break;
+    }
+}
+
 template <class TW>
-hipError_t go(const PairGeom& g, int coef, const PairArgs& a, hipStream_t s) {
-    if (coef == EXPI_COEF_SEPARABLE)
-        hipLaunchKernelGGL((pair_sweep<EXPI_COEF_SEPARABLE, TW>), dim3(g.grid), dim3(kPairWaves * 64), 0, s, a);
-    else
-        hipLaunchKernelGGL((pair_sweep<EXPI_COEF_CONST, TW>), dim3(g.grid), dim3(kPairWaves * 64), 0, s, a);
+hipError_t go(const PairGeom& g, int coef, int bc, const PairArgs& a, hipStream_t s) {
+    if (coef == EXPI_COEF_SEPARABLE) go_bc<EXPI_COEF_SEPARABLE, TW>(g, bc, a, s);
+    else go_bc<EXPI_COEF_CONST, TW>(g, bc, a, s);
     return hipGetLastError();
 }
 
@@ -493,7 +514,7 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent
     a.nrt = g.nrt;
     a.chunk = g.chunk;
     a.per_xcd = g.per_xcd;
-    hipError_t e = tw == 1 ? go<float>(g, op.coef, a, s) : go<double>(g, op.coef, a, s);
+    hipError_t e = tw == 1 ? go<float>(g, op.coef, op.bc, a, s) : go<double>(g, op.coef, op.bc, a, s);
     if (e != hipSuccess) return e;
     if (after_sweep) {
         e = hipEventRecord(after_sweep, s);
