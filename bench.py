@@ -306,6 +306,59 @@ def run_batched(args):
     }
 
 
+def run_csr(args):
+    """The unstructured workload: phi_1(tau A) v for the negative graph
+    Laplacian of a seeded random geometric graph in the unit cube, n = 2^20
+    rows, about 27 stored entries per row (Morton-ordered points), int32
+    indices, float64 values, tau rho(A) = 50, tol 1e-10, FP64.  Per-product
+    algorithmic bytes: values and columns once (12 B per stored entry), row
+    pointers (4 B per row), w read once, p read and written, w written
+    (32 B per row)."""
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+
+    n = 1 << args.csr_log2n
+    g = synth.rgg_negative_laplacian(n, seed=0)
+    rho = synth.spectral_radius_symmetric(g)
+    tau = 50.0 / rho
+    op = E.CsrOp(g.n, g.rowptr, g.colind, g.val)
+    v = torch.as_tensor(synth.uniform_vector(g.n, 0), device="cuda:0")
+    y = torch.empty_like(v)
+    params = E.LejaParams(profile=True)
+    ws = op.workspace("f64")
+    E.phi_action(op, 1, tau, v, y=y, tol=1e-10, params=params, ws=ws)
+    torch.cuda.synchronize()
+    reps = args.csr_reps
+    timed = 0
+    ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = E.phi_action(op, 1, tau, v, y=y, tol=1e-10, params=params, ws=ws)
+        timed += st["timed_products"]
+        ms += st["newton_ms"]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    per_product = 12 * g.nnz + 4 * (g.n + 1) + 32 * g.n
+    avg_us = 1e3 * ms / max(timed, 1)
+    gbs = per_product / (avg_us * 1e-6) / 1e9
+    return {
+        "workload": (f"phi_1(tau A) v, A = negative graph Laplacian of a random geometric graph, "
+                     f"n = 2^{args.csr_log2n}, {g.nnz / g.n:.1f} stored entries per row, "
+                     f"tau rho(A) = 50, tol 1e-10, f64"),
+        "value": g.n / wall,
+        "unit": "rows/s (phi_1 results)",
+        "ms_per_phi": 1e3 * wall,
+        "substeps": st["substeps"],
+        "newton_products": st["newton_steps"],
+        "product_avg_us": avg_us,
+        "product_gbs": gbs,
+        "product_frac": gbs / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_product": per_product,
+        "nnz": int(g.nnz),
+    }
+
+
 def cpu_baseline(args):
     """The oracle on a bounded sample: the same problem on the 128^3 grid with
     tau scaled by (256/128)^2, which keeps tau*(b-a) and hence the number of
@@ -357,6 +410,11 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--eval-steps", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-csr", action="store_true")
+    ap.add_argument("--csr-only", action="store_true",
+                    help="run only the CSR leg and print its JSON (for profiling)")
+    ap.add_argument("--csr-log2n", type=int, default=20)
+    ap.add_argument("--csr-reps", type=int, default=5)
     ap.add_argument("--no-pairs", action="store_true",
                     help="single Newton products only (no pair sweeps)")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -385,6 +443,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.csr_only:
+        print("[bench] csr only", file=sys.stderr, flush=True)
+        print(json.dumps({"csr": run_csr(args)}), flush=True)
+        return
     print(f"[bench] f64: {args.warmup} warmup + {args.steps} timed steps at {args.n}^3", file=sys.stderr, flush=True)
     r64 = run_gpu(args, "f64")
     print(f"[bench] f64 done: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -404,6 +466,12 @@ def main():
         batched = run_batched(args)
         print(f"[bench] batched done: eager {batched['eager_ms']:.1f} ms, graph "
               f"{batched['graph_replay_ms']:.1f} ms", file=sys.stderr, flush=True)
+    csr = None
+    if not args.no_csr:
+        print("[bench] csr: random geometric graph Laplacian, n = 2^%d" % args.csr_log2n,
+              file=sys.stderr, flush=True)
+        csr = run_csr(args)
+        print(f"[bench] csr done: {csr['product_avg_us']:.1f} us per product", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -498,6 +566,8 @@ def main():
         out["learned_vs_plain"] = learned
     if batched:
         out["batched"] = batched
+    if csr:
+        out["csr"] = csr
     print(json.dumps(out), flush=True)
 
 

@@ -23,11 +23,15 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
         s0 = INFINITY;
         s1 = -INFINITY;
     }
-    const int L = xcd_tile(a.per_xcd);
     const int g = threadIdx.x / G, sub = threadIdx.x % G;
     const int rows_per = blockDim.x / G;
+    // grid-stride over row blocks in XCD-major order: in each pass the
+    // workgroups of one XCD take a contiguous run of rows (the gathered
+    // entries of neighbouring rows then meet in that XCD's L2), and the grid
+    // stays small enough for a short finalize
+    for (int L = xcd_tile(a.per_xcd); L < a.ntiles; L += gridDim.x) {
     const int row = L * rows_per + g;
-    if (L < a.ntiles && row < a.n[0]) {
+    if (row < a.n[0]) {
         // row range clamped to [0, nnz) and column indices checked against
         // n, so a malformed matrix cannot send a load out of bounds
         const int e0 = max(a.rowptr[row], 0), e1 = min(a.rowptr[row + 1], a.nnz);
@@ -44,8 +48,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
                 off += __shfl_xor(off, o, G);
             }
             if (sub == 0) {
-                s0 = dg - off;
-                s1 = dg + off;
+                s0 = fmin(s0, dg - off);
+                s1 = fmax(s1, dg + off);
             }
         } else {
             // first kBatch entries of the lane: all index and value loads,
@@ -88,16 +92,16 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
                     const TOUT pn = (TOUT)((TC)p[row] + (TC)a.d1 * (TC)wn);
                     out[row] = wn;
                     p[row] = pn;
-                    s1 = (double)wn * (double)wn;
-                    s2 = (double)pn * (double)pn;
+                    s1 += (double)wn * (double)wn;
+                    s2 += (double)pn * (double)pn;
                 } else if (EPI == EPI_FIRST) {
                     const TOUT wn = (TOUT)(alpha * acc + beta * wc);
                     const TOUT pn = (TOUT)((TC)a.d0 * wc + (TC)a.d1 * (TC)wn);
                     out[row] = wn;
                     p[row] = pn;
-                    s0 = (double)wc * (double)wc;
-                    s1 = (double)wn * (double)wn;
-                    s2 = (double)pn * (double)pn;
+                    s0 += (double)wc * (double)wc;
+                    s1 += (double)wn * (double)wn;
+                    s2 += (double)pn * (double)pn;
                 } else if (EPI == EPI_START) {
                     TC gv;
                     if (a.gmode == G_VEC) {
@@ -112,6 +116,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
                 }
             }
         }
+    }
     }
     if (EPI == EPI_NEWTON || EPI == EPI_FIRST || EPI == EPI_GERSH) finish_sweep<EPI>(a, s0, s1, s2);
 }

@@ -208,6 +208,9 @@ Geom make_geom(const Op& op, const Tiles& t) {
     const int64_t nt = (int64_t)g.tiles[0] * g.tiles[1] * g.tiles[2];
     g.ntiles = nt < 1 ? 1 : (int)nt;
     g.per_xcd = (g.ntiles + kXcd - 1) / kXcd;
+    // CSR sweeps loop over row blocks: at most kCsrGrid workgroups, so that
+    // the finalize kernel sums few partials
+    if (op.kind == 1 && g.per_xcd > kCsrGrid / kXcd) g.per_xcd = kCsrGrid / kXcd;
     g.grid = kXcd * g.per_xcd;
     return g;
 }
