@@ -182,9 +182,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
     __shared__ TC xdat[2 * 64][6];
     __shared__ RowW<TC> rowdat[kPairWaves];
-    // every ring entry holds a finite value before it is read
+    // every ring entry holds a finite value before it is read; the barrier
+    // keeps a slow wave's fill from landing on a fast wave's first writes
     for (int t = threadIdx.x; t < 3 * kPairLds; t += blockDim.x) ring[t] = 0;
     for (int t = threadIdx.x; t < 3 * kWRingLds; t += blockDim.x) wring[t] = 0;
+    __syncthreads();
     const TW* __restrict__ x = static_cast<const TW*>(a.x);
     TW* __restrict__ out = static_cast<TW*>(a.out);
     TW* __restrict__ pv = static_cast<TW*>(a.p);

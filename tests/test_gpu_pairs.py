@@ -169,3 +169,17 @@ def test_pair_fp32_constant_coefficient(E):
     yo2, _ = I.phi_action(A2, 1, tau, v, 1e-10)
     assert relerr(N(y2), yo2) <= 5e-6
     assert st2["timed_pairs"] >= 1
+
+
+@pytest.mark.parametrize("shape", [(256, 12, 9), (128, 30, 5), (64, 7, 17)])
+def test_pair_equals_single_products_elementwise(E, shape):
+    """Pair sweeps and single products give the same result to rounding at
+    every point (a tighter check than the oracle bar: it would show a stale
+    row or plane in the sweep's rings, e.g. at the first plane of a chunk)."""
+    op, A = make(E, shape, "dirichlet0", "const")
+    v = synth.uniform_vector(int(np.prod(shape)), 7)
+    a, b = O.gershgorin_interval(A)
+    for q in (2.0, 8.0, 30.0):
+        yp, sp, ys, ss = run_pair_and_single(E, op, v, q / (b - a), 1e-13)
+        assert sp["degree_last"] == ss["degree_last"]
+        assert np.max(np.abs(yp - ys)) <= 1e-12 * np.max(np.abs(ys)), (shape, q)
