@@ -382,6 +382,10 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         // network predicts the degree m; products up to m skip the norm
         // reductions except the last two, whose two-term stop test judges the
         // prediction.  If it is not met the plain loop below continues.
+        // products 1..3 with stop tests (t_0..t_4 are recorded by the tests)
+        int rc0 = C.pairs ? pair(j, true) : single(j, true);
+        if (rc0) return rc0;
+        j += C.pairs ? 2 : 1;
         for (; j < 4; ++j) {
             int rc = single(j, true);
             if (rc) return rc;
@@ -395,15 +399,14 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
             finished = true;
         } else {
             const int mh = std::min(std::max(last.pred_m, j + 1), C.m_max);
-            // unreduced products up to mh - 2, then the last two with tests
+            // unreduced products up to mh - 3, then the last two with tests
+            // (one pair sweep tests after each of its two products)
             if (mh - 2 > j) {
                 rc = advance(j, mh - 2 - j, false);
                 if (rc) return rc;
             }
-            for (; j < mh; ++j) {
-                rc = single(j, true);
-                if (rc) return rc;
-            }
+            rc = advance(j, mh - j, true);
+            if (rc) return rc;
             rc = sync_state(&last);
             if (rc) return rc;
             if (last.done) finished = true;
