@@ -35,6 +35,7 @@ namespace {
 
 constexpr int kPairWaves = 16;
 constexpr int kPairLds = kPairWaves * 128;   // points of one plane of the w_{j+1} ring
+constexpr int kZSeg = 248;                   // planes per marched segment at most
 constexpr int kWRingLds = 2560;              // points of one plane of the w_j ring:
                                              // (16/NX + 2) rows of 128 NX points
 
@@ -61,8 +62,9 @@ struct PlaneW {        // per (row, plane): weights A + B X of the y, z faces
     TC aym, bym, ayq, byq, azm, bzm, azq, bzq, ad, bd;
 };
 
+// zt: Z of planes zbase, zbase+1, ... (clamped into the grid), in LDS
 template <int COEF, class TC>
-__device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const double* __restrict__ tz,
+__device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const TC* zt, int zbase,
                                                     int q, int n2, bool dir, TC c0ihz, TC c1ihx) {
     PlaneW<TC> w;
     const bool ezm = q > 0, ezq = q < n2 - 1;
@@ -74,10 +76,9 @@ __device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const dou
     w.azq = eq * c0ihz;
     w.ad = r.ady + c0ihz * (dm + dq);
     if (COEF == EXPI_COEF_SEPARABLE) {
-        const int qc = min(max(q, 0), n2 - 1);
-        const TC zc = (TC)tz[qc];
-        const TC zfm = ezm ? (TC)0.5 * ((TC)tz[qc - 1] + zc) : zc;
-        const TC zfq = ezq ? (TC)0.5 * ((TC)tz[qc + 1] + zc) : zc;
+        const TC zc = zt[q - zbase];
+        const TC zfm = ezm ? (TC)0.5 * (zt[q - 1 - zbase] + zc) : zc;
+        const TC zfq = ezq ? (TC)0.5 * (zt[q + 1 - zbase] + zc) : zc;
         w.sx = c1ihx * (r.y * zc);
         w.bym = r.gym * zc;
         w.byq = r.gyq * zc;
@@ -182,6 +183,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
     __shared__ TC xdat[2 * 64][6];
     __shared__ RowW<TC> rowdat[kPairWaves];
+    // Z of the planes of the current segment: read where used through LDS
+    // (a vector load there would make the in-order memory counter wait for
+    // every prefetch issued before it)
+    __shared__ TC ztab[kZSeg + 8];
     // every ring entry holds a finite value before it is read; the barrier
     // keeps a slow wave's fill from landing on a fast wave's first writes
     for (int t = threadIdx.x; t < 3 * kPairLds; t += blockDim.x) ring[t] = 0;
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     const long long u_hi = min(u_lo + (long long)a.chunk, units);
     for (long long u = u_lo; u < u_hi;) {
         const int rt = (int)(u / n2), kb = (int)(u % n2);
-        const int ke = (int)min((long long)n2, kb + (u_hi - u));
+        const int ke = (int)min((long long)min(n2, kb + kZSeg), kb + (u_hi - u));
         u += ke - kb;
         // this wave's row: step 1 on rows rt*R-1 .. rt*R+R, step 2 on the inner R
         const int y = rt * R - 1 + ry;
@@ -266,6 +271,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         const bool hal = ry == 0 || ry == R + 1;
         const int rh = ry == 0 ? 0 : R + 3;               // the extra row
         const int hoff = ry == 0 ? (eym ? -n0 : 0) : (eyq ? n0 : 0);
+        // Z of planes kb-2 .. ke+5 (the ones this segment's iterations touch)
+        if (COEF == EXPI_COEF_SEPARABLE) {
+            const int zlen = ke - kb + 8;
+            for (int t = threadIdx.x; t < zlen; t += blockDim.x)
+                ztab[t] = (TC)a.tz[min(max(kb - 2 + t, 0), n2 - 1)];
+        }
         // y data of the row, kept in LDS (read where used)
         if (lane == 0) {
             const TC c0ihy = c0 * ihy, c1ihy = c1 * ihy;
@@ -288,128 +299,150 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             rw.hz = (c1 * ihz) * Y;
             rowdat[wv] = rw;
         }
-        __syncthreads();   // the x and row data are in LDS
-        const RowW<TC>& rw = rowdat[wv];
-        // a point of the outer layer has a zero row under interior_only
-        const bool yedge = !(eym && eyq);
 
-        // Iteration k: start the loads of w_j on plane k+3, of the y and edge
-        // neighbours of w_j on plane k+1 and of p on plane k; compute w_{j+2}
-        // on plane k-1 (inner rows); then w_{j+1} on plane k+1; one barrier.
-        // w_j of planes k, k+1, k+2 is in W[s], W[s+1], W[s+2] (mod 4);
-        // w_{j+1} of planes k-2, k-1, k in W1[s+2], W1[s+3], W1[s] and plane
-        // k+1 goes to W1[s+1]; p of plane k-1 in P[(s+1)&1].
+        // Iteration k, for the planes of this segment (kst = kb - 2):
+        //  (1) put w_j of plane k+2 (loaded two iterations ago) into the w_j
+        //      ring and start the load of plane k+4;
+        //  (2) inner rows: w_{j+2} on plane k-1 from the w_{j+1} ring, then
+        //      start the load of p on plane k+1;
+        //  (3) w_{j+1} on plane k+1 from the w_j ring, into the w_{j+1} ring;
+        //  (4) one barrier.
+        // Both rings hold three planes; a wave's own row is read back only by
+        // the wave itself, other rows only after the barrier that follows
+        // their write.  Registers carry only the loads in flight: w_j of two
+        // planes in L (plane q in L[q & 1]) and p of two planes in P (the
+        // first and last rows carry their extra row of w_j there instead).
         const int kst = kb - 2;
-        TC W[4][2], W1[4][2], P[2][2];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) W[q][0] = W[q][1] = W1[q][0] = W1[q][1] = 0;
+        TC L[2][2], P[2][2];
+        L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
         // ring slot of a plane: (plane - kst) mod 3.  Within an unrolled
-        // block the plane is k0 + c for a constant c, and k0 - kst = 4 * it
-        // is 'it' mod 3; so the slot is (b + c) mod 3 with b = it mod 3.
+        // block the plane is k0 + c for a constant c; b3 = (k0 - kst) mod 3
+        // advances by 2 per block, so the slot is (b3 + c) mod 3.
         int b3 = 0;
         auto slot_of = [&](int c) {   // c >= 0, constant after unrolling
             const int t = b3 + c % 3;
             return t >= 3 ? t - 3 : t;
         };
         auto wslot_c = [&](int c) { return &wring[slot_of(c) * kWRingLds]; };
+        auto vslot_c = [&](int c) { return &ring[slot_of(c) * kPairLds]; };
         auto put = [&](TC* base, int row, const TC (&v)[2]) {
             TC2 t;
             t.x = v[0];
             t.y = v[1];
             *reinterpret_cast<TC2*>(base + row * RW + i) = t;
         };
+        auto get = [&](const TC* base, int row, TC (&v)[2]) {
+            const TC2 t = *reinterpret_cast<const TC2*>(base + row * RW + i);
+            v[0] = t.x;
+            v[1] = t.y;
+        };
         {
-            TC h[2] = {0, 0};
+            // planes kst and kst+1 of w_j into the ring; kst+2 and kst+3 in flight
+            TC h0[2] = {0, 0}, h1[2] = {0, 0}, e0[2] = {0, 0}, e1[2] = {0, 0};
             if (yin) {
-                ld2(x, at(kst), W[0]);
-                ld2(x, at(kst + 1), W[1]);
-                ld2(x, at(kst + 2), W[2]);
+                ld2(x, at(kst), h0);
+                ld2(x, at(kst + 1), h1);
+                ld2(x, at(kst + 2), L[0]);
+                ld2(x, at(kst + 3), L[1]);
                 if (hal) {
-                    ld2(x, at(kst + 1) + hoff, h);
-                    ld2(x, at(kst + 2) + hoff, P[1]);
+                    ld2(x, at(kst) + hoff, e0);
+                    ld2(x, at(kst + 1) + hoff, e1);
+                    ld2(x, at(kst + 2) + hoff, P[0]);
+                    ld2(x, at(kst + 3) + hoff, P[1]);
                 }
             }
-            // plane kst+1 of w_j into the ring (iteration kst reads it)
-            put(wslot_c(1), rr, W[1]);
-            if (hal) put(wslot_c(1), rh, h);
+            put(wslot_c(0), rr, h0);
+            put(wslot_c(1), rr, h1);
+            if (hal) {
+                put(wslot_c(0), rh, e0);
+                put(wslot_c(1), rh, e1);
+            }
         }
-        for (int k0 = kst; k0 <= ke; k0 += 4) {
+        __syncthreads();   // x and row data, the first two ring planes
+        const RowW<TC>& rw = rowdat[wv];
+        // a point of the outer layer has a zero row under interior_only
+        const bool yedge = !(eym && eyq);
+        for (int k0 = kst; k0 <= ke; k0 += 2) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
+            for (int s = 0; s < 2; ++s) {
                 const int k = k0 + s;
-                // (1) loads: w_j on plane k+3 (and the extra row), p on plane k
-                if (yin) {
-                    ld2(x, at(k + 3), W[(s + 3) & 3]);
-                    if (outw) ld2(pv, at(k), P[s & 1]);
-                    else if (hal) ld2(x, at(k + 3) + hoff, P[s & 1]);
+                // (1) w_j of plane k+2 into the ring, then load plane k+4
+                {
+                    TC* wb = wslot_c(s + 2);
+                    put(wb, rr, L[s & 1]);
+                    if (hal) put(wb, rh, P[s & 1]);
+                    if (yin) {
+                        ld2(x, at(k + 4), L[s & 1]);
+                        if (hal) ld2(x, at(k + 4) + hoff, P[s & 1]);
+                    }
                 }
-                // w_j on plane k+2 (loaded one iteration ago) into the ring
-                put(wslot_c(s + 2), rr, W[(s + 2) & 3]);
-                if (hal) put(wslot_c(s + 2), rh, P[(s + 1) & 1]);
                 // (2) w_{j+2} on plane k-1 (inner rows)
                 const int kp = k - 1;
-                if (outw && kp >= kb && kp < ke) {
-                    const TC* base = &ring[slot_of(s + 2) * kPairLds];   // plane k-1 = k0 + s - 1
-                    const TC wc[2] = {W1[(s + 3) & 3][0], W1[(s + 3) & 3][1]};
-                    const TC2 ymv = *reinterpret_cast<const TC2*>(base + (ry - 1) * RW + i);
-                    const TC2 yqv = *reinterpret_cast<const TC2*>(base + (ry + 1) * RW + i);
-                    const TC el = base[ry * RW + (ic > 0 ? ic - 1 : ic)];
-                    const TC er = base[ry * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
-                    TC left, right;
-                    neighbours(wc, efac * el, efac * er, left, right);
-                    const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, a.tz, kp, n2, dir, c0ihz, c1ihx);
-                    const TC zm[2] = {W1[(s + 2) & 3][0], W1[(s + 2) & 3][1]};
-                    const TC zq[2] = {W1[s & 3][0], W1[s & 3][1]};
-                    const TC ym[2] = {ymv.x, ymv.y};
-                    const TC yq[2] = {yqv.x, yqv.y};
-                    TC aw[2];
-                    aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
-                    if (ionly) {
-                        const bool edge = yedge || kp == 0 || kp == n2 - 1;
-                        if (edge || lb) aw[0] = 0;
-                        if (edge || rb) aw[1] = 0;
-                    }
-                    TC wo[2], po[2];
-                    const TC* pp = P[(s + 1) & 1];
+                if (outw) {
+                    if (kp >= kb && kp < ke) {
+                        const TC* vb = vslot_c(s + 2);        // plane k-1
+                        TC wc[2], ym[2], yq[2], zm[2], zq[2];
+                        get(vb, ry, wc);
+                        get(vb, ry - 1, ym);
+                        get(vb, ry + 1, yq);
+                        get(vslot_c(s + 1), ry, zm);          // plane k-2
+                        get(vslot_c(s), ry, zq);              // plane k
+                        const TC el = vb[ry * RW + (ic > 0 ? ic - 1 : ic)];
+                        const TC er = vb[ry * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
+                        TC left, right;
+                        neighbours(wc, efac * el, efac * er, left, right);
+                        const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, kp, n2, dir, c0ihz, c1ihx);
+                        TC aw[2];
+                        aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
+                        if (ionly) {
+                            const bool edge = yedge || kp == 0 || kp == n2 - 1;
+                            if (edge || lb) aw[0] = 0;
+                            if (edge || rb) aw[1] = 0;
+                        }
+                        TC wo[2], po[2];
+                        const TC* pp = P[(s + 1) & 1];        // p of plane k-1
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) {
-                        const TC p1 = (TC)(TW)(pp[v] + d1 * wc[v]);
-                        const TC w2 = (TC)(TW)(alpha * aw[v] + beta2 * wc[v]);
-                        const TC p2 = (TC)(TW)(p1 + d2 * w2);
-                        wo[v] = w2;
-                        po[v] = p2;
+                        for (int v = 0; v < 2; ++v) {
+                            const TC p1 = (TC)(TW)(pp[v] + d1 * wc[v]);
+                            const TC w2 = (TC)(TW)(alpha * aw[v] + beta2 * wc[v]);
+                            const TC p2 = (TC)(TW)(p1 + d2 * w2);
+                            wo[v] = w2;
+                            po[v] = p2;
+                            if (xin) {
+                                s0 += (double)wc[v] * (double)wc[v];
+                                s1 += (double)p1 * (double)p1;
+                                s2 += (double)w2 * (double)w2;
+                                s3 += (double)p2 * (double)p2;
+                            }
+                        }
                         if (xin) {
-                            s0 += (double)wc[v] * (double)wc[v];
-                            s1 += (double)p1 * (double)p1;
-                            s2 += (double)w2 * (double)w2;
-                            s3 += (double)p2 * (double)p2;
+                            const int idx = at(kp);
+                            st2(out, idx, wo);
+                            st2(pv, idx, po);
                         }
                     }
-                    if (xin) {
-                        const int idx = at(kp);
-                        st2(out, idx, wo);
-                        st2(pv, idx, po);
-                    }
+                    // p of plane k+1 (used two iterations on) into the slot just read
+                    ld2(pv, at(k + 1), P[(s + 1) & 1]);
                 }
-                // (3) w_{j+1} on plane k+1 (values of planes outside the grid
-                // or of rows outside it are never used with a nonzero weight)
+                // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
+                // grid are never used with a nonzero weight)
                 {
                     const int q = k + 1;
                     const TC* wb = wslot_c(s + 1);
-                    const TC wc[2] = {W[(s + 1) & 3][0], W[(s + 1) & 3][1]};
-                    const TC2 ymv = *reinterpret_cast<const TC2*>(wb + (rr - 1) * RW + i);
-                    const TC2 yqv = *reinterpret_cast<const TC2*>(wb + (rr + 1) * RW + i);
-                    const TC Sym[2] = {ymv.x, ymv.y}, Syq[2] = {yqv.x, yqv.y};
+                    TC wc[2], ym[2], yq[2], zm[2], zq[2];
+                    get(wb, rr, wc);
+                    get(wb, rr - 1, ym);
+                    get(wb, rr + 1, yq);
+                    get(wslot_c(s), rr, zm);                  // plane k
+                    get(wslot_c(s + 2), rr, zq);              // plane k+2
                     const TC el = wb[rr * RW + (ic > 0 ? ic - 1 : ic)];
                     const TC er = wb[rr * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                     TC left, right;
                     neighbours(wc, efac * el, efac * er, left, right);
-                    const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, a.tz, q, n2, dir, c0ihz, c1ihx);
-                    const TC zm[2] = {W[s & 3][0], W[s & 3][1]};
-                    const TC zq[2] = {W[(s + 2) & 3][0], W[(s + 2) & 3][1]};
+                    const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, q, n2, dir, c0ihz, c1ihx);
                     TC aw[2];
-                    aw_pair<COEF, TC>(wc, left, right, Sym, Syq, zm, zq, pw, c0ihx, xd, aw);
+                    aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
                     if (ionly) {
                         const bool edge = yedge || q == 0 || q == n2 - 1;
                         if (edge || lb) aw[0] = 0;
@@ -418,16 +451,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     TC r[2];
 #pragma unroll
                     for (int v = 0; v < 2; ++v) r[v] = (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
-                    W1[(s + 1) & 3][0] = r[0];
-                    W1[(s + 1) & 3][1] = r[1];
-                    TC2 t;
-                    t.x = r[0];
-                    t.y = r[1];
-                    *reinterpret_cast<TC2*>(&ring[slot_of(s + 1) * kPairLds + ry * RW + i]) = t;
+                    put(vslot_c(s + 1), ry, r);
                 }
                 __syncthreads();
             }
-            b3 = b3 == 2 ? 0 : b3 + 1;   // 4 = 1 mod 3
+            b3 = b3 == 0 ? 2 : b3 - 1;   // + 2 mod 3
         }
     }
     finish_sweep4(a.partials, s0, s1, s2, s3);
