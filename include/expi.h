@@ -168,7 +168,7 @@ int64_t expi_op_size(const expi_op *op);
  * not depend on it beyond rounding order).  Stencils: vec = x points per
  * thread (1 or 2; 2 needs an even x size and 16-byte aligned arrays, else 1
  * is used), waves = 64-thread waves per workgroup (1..8, rows of a 3D tile),
- * march = points each thread marches along the slowest axis (4..256, a
+ * march = points each thread marches along the slowest axis (4..120, a
  * multiple of 4).
  * CSR: vec = lanes per row (4, 8 or 16), waves (1..8), march = 1.
  * EXPI_EINVAL for anything else.  The workspace size does not depend on it. */

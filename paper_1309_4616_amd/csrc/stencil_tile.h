@@ -33,6 +33,17 @@ __device__ __forceinline__ void vst(T* __restrict__ p, int idx, const TC (&v)[V]
     }
 }
 
+// Lane `t` of a value held one per lane (t the same in all lanes).
+__device__ __forceinline__ float lane_value(float v, int t) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), t));
+}
+__device__ __forceinline__ double lane_value(double v, int t) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, t);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), t);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <int V, class TC>
 __device__ __forceinline__ void vzero(TC (&o)[V]) {
 #pragma unroll
@@ -115,8 +126,12 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
             auto at = [&](int k) { return rowb + ss * min(max(k, 0), ns - 1); };
 
             // separable coefficient: x values of the thread's points and of
-            // their outer neighbours, y values of the row, a ring of z values
-            TC Xv[V], Xl = 0, Xr = 0, Ym = 0, Yc = 0, Yq = 0, Zr[4] = {0, 0, 0, 0};
+            // their outer neighbours, y values of the row; the values of the
+            // marched axis for planes kb-1 .. kb+126 sit one per lane in zr0,
+            // zr1 and are read with readlane (a vector load inside the march
+            // would make the in-order memory counter wait for the prefetches
+            // issued before it)
+            TC Xv[V], Xl = 0, Xr = 0, Ym = 0, Yc = 0, Yq = 0, zr0 = 0, zr1 = 0;
             vzero<V>(Xv);
             const double* Ts = (DIM == 3) ? a.tz : a.ty;
             if (COEF == EXPI_COEF_SEPARABLE) {
@@ -129,10 +144,13 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                     Ym = (TC)a.ty[max(jc - 1, 0)];
                     Yq = (TC)a.ty[min(jc + 1, n1 - 1)];
                 }
-                Zr[0] = (TC)Ts[max(kb - 1, 0)];
-                Zr[1] = (TC)Ts[kb];
-                Zr[2] = (TC)Ts[min(kb + 1, ns - 1)];
+                zr0 = (TC)Ts[min(max(kb - 1 + lane, 0), ns - 1)];
+                zr1 = (TC)Ts[min(max(kb + 63 + lane, 0), ns - 1)];
             }
+            auto zv = [&](int k) -> TC {   // k in [kb-1, kb+126], clamped into the grid
+                const int t = min(k, ns - 1) - (kb - 1);
+                return t < 64 ? lane_value(zr0, t) : lane_value(zr1, t - 64);
+            };
             // register queues: stage s (plane k = k0 + s) finds w at k-1, k,
             // k+1 in W[s&3], W[(s+1)&3], W[(s+2)&3] and loads k+2 into
             // W[(s+3)&3]; p and the side values alternate between two slots
@@ -191,14 +209,18 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                         if (kW) vld<V>(x, at(k + 2), W[(s + 3) & 3]);
                         if (kP) vld<V>(p, at(k + 1), P[nxt]);
                         if (kF) vld<V>(fld, at(k + 2), F[(s + 3) & 3]);
-                        if (COEF == EXPI_COEF_SEPARABLE) Zr[(s + 3) & 3] = (TC)Ts[min(k + 2, ns - 1)];
                         const TC* wm = W[s & 3];
                         const TC* wc = W[(s + 1) & 3];
                         const TC* wq = W[(s + 2) & 3];
                         const TC* Fm = F[s & 3];
                         const TC* Fc = F[(s + 1) & 3];
                         const TC* Fq = F[(s + 2) & 3];
-                        const TC Zm = Zr[s & 3], Zc = Zr[(s + 1) & 3], Zq = Zr[(s + 2) & 3];
+                        TC Zm = 0, Zc = 0, Zq = 0;
+                        if (COEF == EXPI_COEF_SEPARABLE) {
+                            Zm = zv(max(k - 1, 0));
+                            Zc = zv(k);
+                            Zq = zv(k + 1);
+                        }
                         const bool ezm = k > 0, ezq = k < ns - 1;
                         // (3) x neighbours of the outer points from adjacent lanes
                         TC left = 0, right = 0, Fleft = 0, Fright = 0;
