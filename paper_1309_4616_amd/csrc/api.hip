@@ -301,8 +301,6 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     a.d0 = d[0];
     a.d1 = d[1];
     a.guard = 0;
-    HIP_TRY(launch_sweep(*C.op, EPI_FIRST, tin, C.tw, a, C.s));
-    int finalized = 1;
     int cur = 0;   // w[cur] holds the latest w
 
     struct Launch {
@@ -310,6 +308,37 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         const void* out;
     };
     std::vector<Launch> log;
+
+    // Products 0 and 1 in one pair sweep when the start vector has the
+    // storage type and alignment the pair sweep reads (w_2 goes to w[0]:
+    // `src` may be w[1]).  Otherwise product 0 alone.
+    const bool first_pair = C.pairs && C.m_max >= 3 && tin == C.tw && (((uintptr_t)src & 15) == 0);
+    int finalized;
+    int j = 1;
+    if (first_pair) {
+        PairArgs b{};
+        b.x = src;
+        b.out = w[0];
+        b.p = p;
+        b.partials = C.partials;
+        b.st = C.st;
+        b.alpha = 1.0 / C.gamma;
+        b.beta1 = -(C.c / C.gamma + C.xi[0]);
+        b.beta2 = -(C.c / C.gamma + C.xi[1]);
+        b.d0 = d[0];
+        b.d1 = d[1];
+        b.d2 = d[2];
+        b.tol = C.tol;
+        b.j = 0;
+        b.guard = 0;
+        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, true));
+        log.push_back({0, 2, w[0]});
+        finalized = 2;
+        j = 2;
+    } else {
+        HIP_TRY(launch_sweep(*C.op, EPI_FIRST, tin, C.tw, a, C.s));
+        finalized = 1;
+    }
 
     // single product j (j >= 1); `fin` adds the norm reduction and stop test
     auto single = [&](int j, bool fin) -> int {
@@ -373,7 +402,6 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         return wait_slot(slot, st);
     };
 
-    int j = 1;
     NewtonState last{};
     bool finished = false;
     bool learned_tail = false;
@@ -382,7 +410,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         // network predicts the degree m; products up to m skip the norm
         // reductions except the last two, whose two-term stop test judges the
         // prediction.  If it is not met the plain loop below continues.
-        // products 1..3 with stop tests (t_0..t_4 are recorded by the tests)
+        // products up to 3 with stop tests (t_0..t_4 are recorded by the tests)
         int rc0 = C.pairs ? pair(j, true) : single(j, true);
         if (rc0) return rc0;
         j += C.pairs ? 2 : 1;
@@ -422,7 +450,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         // batches of 4 then 2 products run one batch ahead of the status
         // read-back.
         const int step = C.pairs ? 2 : 1;
-        int chunk = learned_tail ? step : (hint >= 2 ? hint - 1 : 4);
+        int chunk = learned_tail ? step : (hint >= 2 ? std::max(hint - j, 1) : 4);
         const bool ahead = !learned_tail && hint < 2;
         std::deque<int> pending;
         while (!finished) {
@@ -466,7 +494,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     if (C.profile && last.done != 2) {
         // launches that began before the stop did work and precede the read-back
         for (const Launch& L : log) {
-            if (L.j >= last.m) continue;
+            if (L.j == 0 || L.j >= last.m) continue;   // product 0 is not timed
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, tl_ctx.tev[2 * L.j], tl_ctx.tev[2 * L.j + 1]));
             out->ms += ms;

@@ -95,6 +95,7 @@ struct PairArgs {
     double c0, c1;
     double ih2[3];
     double alpha, beta1, beta2, d1, d2, tol;   // beta_j, beta_{j+1}, d_{j+1}, d_{j+2}
+    double d0;            // first pair of a loop: d_0 (p_1 = d_0 r + d_1 w_1)
     int n[3];
     int bc;
     int guard;
@@ -117,6 +118,7 @@ struct FinalArgs {
     int nparts;
     int j;
     int guard;
+    int first;            // pair sweeps: the pair starts the loop (5 partials, stride 8)
     double d0, d1, tol;
     double d2;            // pair sweeps: d_{j+2}
 };
@@ -200,10 +202,14 @@ hipError_t launch_reset(NewtonState* st, hipStream_t s);
 // kernel that applies the stop test after each of them.
 bool pair_supported(const Op& op, int tw);
 PairGeom pair_geom(const Op& op, int cus);
+// `first`: the pair starts the loop from the start vector r = w_0 (products
+// 0 and 1): p_1 = d_0 r + d_1 w_1, and the finalize records t_0, t_1 and
+// ||r|| before its stop test at m = 2.
 hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s,
-                       hipEvent_t after_sweep = nullptr, bool finalize = true);
+                       hipEvent_t after_sweep = nullptr, bool finalize = true, bool first = false);
 hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
-                                int guard, double d1, double d2, double tol, hipStream_t s);
+                                int guard, double d0, double d1, double d2, double tol, bool first,
+                                hipStream_t s);
 hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s);
 
 // Error reporting (api.hip).

@@ -174,7 +174,11 @@ __device__ __forceinline__ double dpp_shift(double edge, double src) {
 constexpr int kDppWaveShr1 = 0x138;   // lane l <- lane l-1
 constexpr int kDppWaveShl1 = 0x130;   // lane l <- lane l+1
 
-template <int COEF, int BC, class TW>
+// FIRST: the pair starts the loop.  It reads the start vector r (= w_0),
+// forms p_1 = d_0 r + d_1 w_1 instead of adding to a stored p, and reports
+// ||r||^2 as a fifth partial sum; the inner rows keep r of their own row
+// (the center of the first product) in the registers that otherwise hold p.
+template <int COEF, int BC, class TW, bool FIRST>
 __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
     typedef TC TC2 __attribute__((ext_vector_type(2)));
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     constexpr bool dir = BC == EXPI_DIRICHLET0, ionly = BC == EXPI_INTERIOR_ONLY;
     const TC ihx = (TC)a.ih2[0], ihy = (TC)a.ih2[1], ihz = (TC)a.ih2[2];
     const TC alpha = (TC)a.alpha, beta1 = (TC)a.beta1, beta2 = (TC)a.beta2;
-    const TC d1 = (TC)a.d1, d2 = (TC)a.d2;
+    const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2;
     const TC c0 = (TC)a.c0, c1 = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1 : (TC)0;
     const TC c0ihx = c0 * ihx, c0ihz = c0 * ihz, c1ihx = c1 * ihx;
     // Row ends.  The x neighbour of a point at a row end is 0 under
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     const TC* xd = xdat[xq * 64 + lane];
     // Dirichlet row ends: the edge lanes take in 0
     const TC efac = (dir && ((lane == 0 && lb) || (lane == 63 && rb))) ? (TC)0 : (TC)1;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 
     // the neighbours of the lane's pair from the adjacent lanes; el, er are
     // the values lanes 0 and 63 take in
@@ -401,10 +405,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             if (edge || rb) aw[1] = 0;
                         }
                         TC wo[2], po[2];
-                        const TC* pp = P[(s + 1) & 1];        // p of plane k-1
+                        const TC* pp = P[(s + 1) & 1];        // p (FIRST: r) of plane k-1
 #pragma unroll
                         for (int v = 0; v < 2; ++v) {
-                            const TC p1 = (TC)(TW)(pp[v] + d1 * wc[v]);
+                            const TC p1 = FIRST ? (TC)(TW)(d0 * pp[v] + d1 * wc[v])
+                                                : (TC)(TW)(pp[v] + d1 * wc[v]);
+                            if (FIRST && xin) s4 += (double)pp[v] * (double)pp[v];
                             const TC w2 = (TC)(TW)(alpha * aw[v] + beta2 * wc[v]);
                             const TC p2 = (TC)(TW)(p1 + d2 * w2);
                             wo[v] = w2;
@@ -423,7 +429,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         }
                     }
                     // p of plane k+1 (used two iterations on) into the slot just read
-                    ld2(pv, at(k + 1), P[(s + 1) & 1]);
+                    if (!FIRST) ld2(pv, at(k + 1), P[(s + 1) & 1]);
                 }
                 // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
                 // grid are never used with a nonzero weight)
@@ -452,35 +458,45 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
 #pragma unroll
                     for (int v = 0; v < 2; ++v) r[v] = (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
                     put(vslot_c(s + 1), ry, r);
+                    if (FIRST && outw) {   // r of plane k+1, used two iterations on
+                        P[(s + 1) & 1][0] = wc[0];
+                        P[(s + 1) & 1][1] = wc[1];
+                    }
                 }
                 __syncthreads();
             }
             b3 = b3 == 0 ? 2 : b3 - 1;   // + 2 mod 3
         }
     }
-    finish_sweep4(a.partials, s0, s1, s2, s3);
+    if (FIRST) {
+        const double v[5] = {s4, s0, s1, s2, s3};
+        finish_sweep_n<5>(a.partials, 8, v);
+    } else {
+        const double v[4] = {s0, s1, s2, s3};
+        finish_sweep_n<4>(a.partials, 4, v);
+    }
 }
 
-template <int COEF, class TW>
+template <int COEF, class TW, bool FIRST>
 void go_bc(const PairGeom& g, int bc, const PairArgs& a, hipStream_t s) {
     const dim3 grid(g.grid), block(kPairWaves * 64);
     switch (bc) {
         case EXPI_DIRICHLET0:
-            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW, FIRST>), grid, block, 0, s, a);
             break;
         case EXPI_NEUMANN0:
-            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_NEUMANN0, TW>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_NEUMANN0, TW, FIRST>), grid, block, 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_INTERIOR_ONLY, TW>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_INTERIOR_ONLY, TW, FIRST>), grid, block, 0, s, a);
             break;
     }
 }
 
-template <class TW>
+template <class TW, bool FIRST>
 hipError_t go(const PairGeom& g, int coef, int bc, const PairArgs& a, hipStream_t s) {
-    if (coef == EXPI_COEF_SEPARABLE) go_bc<EXPI_COEF_SEPARABLE, TW>(g, bc, a, s);
-    else go_bc<EXPI_COEF_CONST, TW>(g, bc, a, s);
+    if (coef == EXPI_COEF_SEPARABLE) go_bc<EXPI_COEF_SEPARABLE, TW, FIRST>(g, bc, a, s);
+    else go_bc<EXPI_COEF_CONST, TW, FIRST>(g, bc, a, s);
     return hipGetLastError();
 }
 
@@ -527,7 +543,7 @@ int device_cus() {
 }
 
 hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep,
-                       bool finalize) {
+                       bool finalize, bool first) {
     const PairGeom g = pair_geom(op, device_cus());
     for (int d = 0; d < 3; ++d) {
         a.n[d] = op.n[d];
@@ -544,14 +560,16 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent
     a.nrt = g.nrt;
     a.chunk = g.chunk;
     a.per_xcd = g.per_xcd;
-    hipError_t e = tw == 1 ? go<float>(g, op.coef, op.bc, a, s) : go<double>(g, op.coef, op.bc, a, s);
+    hipError_t e;
+    if (first) e = tw == 1 ? go<float, true>(g, op.coef, op.bc, a, s) : go<double, true>(g, op.coef, op.bc, a, s);
+    else e = tw == 1 ? go<float, false>(g, op.coef, op.bc, a, s) : go<double, false>(g, op.coef, op.bc, a, s);
     if (e != hipSuccess) return e;
     if (after_sweep) {
         e = hipEventRecord(after_sweep, s);
         if (e != hipSuccess) return e;
     }
     if (!finalize) return hipSuccess;
-    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d1, a.d2, a.tol, s);
+    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d0, a.d1, a.d2, a.tol, first, s);
 }
 
 }  // namespace expi

@@ -99,29 +99,39 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, double* out, con
 
 // Stop tests after a pair sweep: the two-term test at m = j+1 with
 // ||w_{j+1}||, ||p_{j+1}||, and, if that one fails, at m = j+2 with
-// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel).
+// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel).  A pair that
+// starts the loop (f.first, j = 0) brings ||r||^2 as a fifth partial sum
+// (stride 8): it records t_0 = |d_0| ||r|| and ||r||, and its first test
+// (m = 1) can only report a non-finite value.
 __global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
-    __shared__ double red[kMaxWaves][4];
+    __shared__ double red[kMaxWaves][5];
     NewtonState* st = f.st;
     if (f.guard && st->done != 0) return;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nq = f.first ? 5 : 4, stride = f.first ? 8 : 4;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
-        const double* part = f.partials + 4 * (size_t)b;
-        for (int q = 0; q < 4; ++q) s[q] += part[q];
+        const double* part = f.partials + stride * (size_t)b;
+        for (int q = 0; q < nq; ++q) s[q] += part[q];
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
-    for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
+    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
     if (lane == 0)
-        for (int q = 0; q < 4; ++q) red[wv][q] = s[q];
+        for (int q = 0; q < 5; ++q) red[wv][q] = s[q];
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 5; ++q) {
         s[q] = red[0][q];
         for (int w = 1; w < nw; ++w) s[q] += red[w][q];
     }
+    double tprev = st->t_prev;
+    if (f.first) {
+        tprev = fabs(f.d0) * sqrt(s[0]);
+        st->rnorm = sqrt(s[0]);
+        st->hist[0] = tprev;
+        for (int q = 0; q < 4; ++q) s[q] = s[q + 1];
+    }
     const double wn1 = sqrt(s[0]), pn1 = sqrt(s[1]), wn2 = sqrt(s[2]), pn2 = sqrt(s[3]);
-    const double tprev = st->t_prev;
     const double t1 = fabs(f.d1) * wn1;
     const int m1 = f.j + 1;
     const double num1 = tprev + t1;
@@ -251,6 +261,7 @@ size_t partials_bytes(const Op& op) {
         t.march = kMinMarch;
     }
     // also covers the pair sweep, whose grid never exceeds max(CU count, 8)
+    // workgroups of at most 8 partials each
     const size_t grid = std::max<size_t>((size_t)make_geom(op, t).grid, 1024);
     return grid * 4 * sizeof(double);
 }
@@ -332,13 +343,16 @@ hipError_t launch_update(int64_t n, double* out, const double* yin, const void* 
 }
 
 hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
-                                int guard, double d1, double d2, double tol, hipStream_t s) {
+                                int guard, double d0, double d1, double d2, double tol, bool first,
+                                hipStream_t s) {
     FinalArgs f{};
     f.partials = partials;
     f.st = st;
     f.nparts = nparts;
     f.j = j;
     f.guard = guard;
+    f.first = first ? 1 : 0;
+    f.d0 = d0;
     f.d1 = d1;
     f.d2 = d2;
     f.tol = tol;

@@ -82,37 +82,27 @@ __device__ void finish_sweep(const SweepArgs& a, double v0, double v1, double v2
     }
 }
 
-// Four per-thread sums combined over the block in a fixed order and written
-// as this workgroup's partials (the pair sweep: two products' norms).
-__device__ __forceinline__ void finish_sweep4(double* partials, double v0, double v1, double v2,
-                                              double v3) {
-    __shared__ double red[kMaxPairWaves][4];
+// N per-thread sums combined over the block in a fixed order and written as
+// this workgroup's partials at partials[stride * blockIdx.x + q] (the pair
+// sweep: the two products' norms).
+template <int N>
+__device__ __forceinline__ void finish_sweep_n(double* partials, int stride, const double (&vin)[N]) {
+    __shared__ double red[kMaxPairWaves][N];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
-    v0 = wave_sum(v0);
-    v1 = wave_sum(v1);
-    v2 = wave_sum(v2);
-    v3 = wave_sum(v3);
-    if (lane == 0) {
-        red[wv][0] = v0;
-        red[wv][1] = v1;
-        red[wv][2] = v2;
-        red[wv][3] = v3;
-    }
+    double v[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = wave_sum(vin[q]);
+    if (lane == 0)
+        for (int q = 0; q < N; ++q) red[wv][q] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a0 = red[0][0], a1 = red[0][1], a2 = red[0][2], a3 = red[0][3];
-        for (int w = 1; w < nw; ++w) {
-            a0 += red[w][0];
-            a1 += red[w][1];
-            a2 += red[w][2];
-            a3 += red[w][3];
+        double* part = partials + (size_t)stride * blockIdx.x;
+        for (int q = 0; q < N; ++q) {
+            double acc = red[0][q];
+            for (int w = 1; w < nw; ++w) acc += red[w][q];
+            part[q] = acc;
         }
-        double* part = partials + 4 * (size_t)blockIdx.x;
-        part[0] = a0;
-        part[1] = a1;
-        part[2] = a2;
-        part[3] = a3;
     }
 }
 
