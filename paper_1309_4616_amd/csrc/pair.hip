@@ -153,6 +153,17 @@ __device__ __forceinline__ void st2(T* __restrict__ p, int idx, const TC (&v)[2]
     *reinterpret_cast<T2*>(p + idx) = t;
 }
 
+// Streaming store: the line is not kept in L2 for reuse, which leaves L2 to
+// the w_j rows that neighbouring row tiles read again.
+template <class T, class TC>
+__device__ __forceinline__ void st2_stream(T* __restrict__ p, int idx, const TC (&v)[2]) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    T2 t;
+    t.x = (T)v[0];
+    t.y = (T)v[1];
+    __builtin_nontemporal_store(t, reinterpret_cast<T2*>(p + idx));
+}
+
 // Whole-wave shifts by one lane through DPP: lane l receives `src` of lane
 // l-1 (from_left) or l+1 (from_right); the lane without a source (0, resp.
 // 63) keeps `edge`.
@@ -423,9 +434,16 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             }
                         }
                         if (xin) {
+                            // streaming stores: measured faster in FP64,
+                            // slower in FP32
                             const int idx = at(kp);
-                            st2(out, idx, wo);
-                            st2(pv, idx, po);
+                            if (sizeof(TW) == 8) {
+                                st2_stream(out, idx, wo);
+                                st2_stream(pv, idx, po);
+                            } else {
+                                st2(out, idx, wo);
+                                st2(pv, idx, po);
+                            }
                         }
                     }
                     // p of plane k+1 (used two iterations on) into the slot just read
