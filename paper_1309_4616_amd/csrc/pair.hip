@@ -62,29 +62,32 @@ struct PlaneW {        // per (row, plane): weights A + B X of the y, z faces
     TC aym, bym, ayq, byq, azm, bzm, azq, bzq, ad, bd;
 };
 
-// zt: Z of planes zbase, zbase+1, ... (clamped into the grid), in LDS
+template <class TC>
+struct ZPlane {        // per plane of a segment: the z data of the weights
+    TC zc, zfm, zfq;   // Z(z); e_m times the face value towards z-1, e_q times the one towards z+1
+    TC zd;             // d_m (face value towards z-1) + d_q (face value towards z+1)
+};
+
+// zt: z data of planes zbase, zbase+1, ... in LDS (separable coefficient)
 template <int COEF, class TC>
-__device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const TC* zt, int zbase,
+__device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const ZPlane<TC>* zt, int zbase,
                                                     int q, int n2, bool dir, TC c0ihz, TC c1ihx) {
     PlaneW<TC> w;
     const bool ezm = q > 0, ezq = q < n2 - 1;
-    const TC em = ezm ? (TC)1 : (TC)0, eq = ezq ? (TC)1 : (TC)0;
     const TC dm = (ezm || dir) ? (TC)1 : (TC)0, dq = (ezq || dir) ? (TC)1 : (TC)0;
     w.aym = r.aym;
     w.ayq = r.ayq;
-    w.azm = em * c0ihz;
-    w.azq = eq * c0ihz;
+    w.azm = ezm ? c0ihz : (TC)0;
+    w.azq = ezq ? c0ihz : (TC)0;
     w.ad = r.ady + c0ihz * (dm + dq);
     if (COEF == EXPI_COEF_SEPARABLE) {
-        const TC zc = zt[q - zbase];
-        const TC zfm = ezm ? (TC)0.5 * (zt[q - 1 - zbase] + zc) : zc;
-        const TC zfq = ezq ? (TC)0.5 * (zt[q + 1 - zbase] + zc) : zc;
-        w.sx = c1ihx * (r.y * zc);
-        w.bym = r.gym * zc;
-        w.byq = r.gyq * zc;
-        w.bzm = em * (r.hz * zfm);
-        w.bzq = eq * (r.hz * zfq);
-        w.bd = r.gdy * zc + r.hz * (dm * zfm + dq * zfq);
+        const ZPlane<TC>& z = zt[q - zbase];
+        w.sx = c1ihx * (r.y * z.zc);
+        w.bym = r.gym * z.zc;
+        w.byq = r.gyq * z.zc;
+        w.bzm = r.hz * z.zfm;
+        w.bzq = r.hz * z.zfq;
+        w.bd = r.gdy * z.zc + r.hz * z.zd;
     } else {
         w.sx = w.bym = w.byq = w.bzm = w.bzq = w.bd = (TC)0;
     }
@@ -187,8 +190,9 @@ constexpr int kDppWaveShl1 = 0x130;   // lane l <- lane l+1
 
 // FIRST: the pair starts the loop.  It reads the start vector r (= w_0),
 // forms p_1 = d_0 r + d_1 w_1 instead of adding to a stored p, and reports
-// ||r||^2 as a fifth partial sum; the inner rows keep r of their own row
-// (the center of the first product) in the registers that otherwise hold p.
+// ||r||^2 where the other pairs report ||p_1||^2; the inner rows load r of
+// their own row a second time where the other pairs load p (a cache hit:
+// the same rows entered the w_j queue two planes earlier).
 template <int COEF, int BC, class TW, bool FIRST>
 __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
@@ -198,10 +202,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
     __shared__ TC xdat[2 * 64][6];
     __shared__ RowW<TC> rowdat[kPairWaves];
-    // Z of the planes of the current segment: read where used through LDS
-    // (a vector load there would make the in-order memory counter wait for
-    // every prefetch issued before it)
-    __shared__ TC ztab[kZSeg + 8];
+    // z data of the planes of the current segment: read where used through
+    // LDS (a vector load there would make the in-order memory counter wait
+    // for every prefetch issued before it)
+    __shared__ ZPlane<TC> ztab[kZSeg + 8];
     // every ring entry holds a finite value before it is read; the barrier
     // keeps a slow wave's fill from landing on a fast wave's first writes
     for (int t = threadIdx.x; t < 3 * kPairLds; t += blockDim.x) ring[t] = 0;
@@ -251,8 +255,8 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     }
     const TC* xd = xdat[xq * 64 + lane];
     // Dirichlet row ends: the edge lanes take in 0
-    const TC efac = (dir && ((lane == 0 && lb) || (lane == 63 && rb))) ? (TC)0 : (TC)1;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    const bool ezero = dir && ((lane == 0 && lb) || (lane == 63 && rb));
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 
     // the neighbours of the lane's pair from the adjacent lanes; el, er are
     // the values lanes 0 and 63 take in
@@ -286,11 +290,25 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         const bool hal = ry == 0 || ry == R + 1;
         const int rh = ry == 0 ? 0 : R + 3;               // the extra row
         const int hoff = ry == 0 ? (eym ? -n0 : 0) : (eyq ? n0 : 0);
-        // Z of planes kb-2 .. ke+5 (the ones this segment's iterations touch)
+        // z data of planes kb-2 .. ke+5 (the ones this segment's iterations
+        // touch; planes outside the grid get finite values that no nonzero
+        // weight uses)
         if (COEF == EXPI_COEF_SEPARABLE) {
             const int zlen = ke - kb + 8;
-            for (int t = threadIdx.x; t < zlen; t += blockDim.x)
-                ztab[t] = (TC)a.tz[min(max(kb - 2 + t, 0), n2 - 1)];
+            for (int t = threadIdx.x; t < zlen; t += blockDim.x) {
+                const int q = kb - 2 + t;
+                const bool ezm = q > 0, ezq = q < n2 - 1;
+                const TC dm = (ezm || dir) ? (TC)1 : (TC)0, dq = (ezq || dir) ? (TC)1 : (TC)0;
+                const TC zc = (TC)a.tz[min(max(q, 0), n2 - 1)];
+                const TC zfm = ezm ? (TC)0.5 * ((TC)a.tz[min(max(q - 1, 0), n2 - 1)] + zc) : zc;
+                const TC zfq = ezq ? (TC)0.5 * ((TC)a.tz[min(max(q + 1, 0), n2 - 1)] + zc) : zc;
+                ZPlane<TC> z;
+                z.zc = zc;
+                z.zfm = ezm ? zfm : (TC)0;
+                z.zfq = ezq ? zfq : (TC)0;
+                z.zd = dm * zfm + dq * zfq;
+                ztab[t] = z;
+            }
         }
         // y data of the row, kept in LDS (read where used)
         if (lane == 0) {
@@ -406,7 +424,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         const TC el = vb[ry * RW + (ic > 0 ? ic - 1 : ic)];
                         const TC er = vb[ry * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                         TC left, right;
-                        neighbours(wc, efac * el, efac * er, left, right);
+                        neighbours(wc, ezero ? (TC)0 : el, ezero ? (TC)0 : er, left, right);
                         const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, kp, n2, dir, c0ihz, c1ihx);
                         TC aw[2];
                         aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
@@ -421,14 +439,14 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         for (int v = 0; v < 2; ++v) {
                             const TC p1 = FIRST ? (TC)(TW)(d0 * pp[v] + d1 * wc[v])
                                                 : (TC)(TW)(pp[v] + d1 * wc[v]);
-                            if (FIRST && xin) s4 += (double)pp[v] * (double)pp[v];
                             const TC w2 = (TC)(TW)(alpha * aw[v] + beta2 * wc[v]);
                             const TC p2 = (TC)(TW)(p1 + d2 * w2);
                             wo[v] = w2;
                             po[v] = p2;
                             if (xin) {
                                 s0 += (double)wc[v] * (double)wc[v];
-                                s1 += (double)p1 * (double)p1;
+                                // FIRST: ||r||^2 in place of ||p_1||^2
+                                s1 += FIRST ? (double)pp[v] * (double)pp[v] : (double)p1 * (double)p1;
                                 s2 += (double)w2 * (double)w2;
                                 s3 += (double)p2 * (double)p2;
                             }
@@ -447,7 +465,8 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         }
                     }
                     // p of plane k+1 (used two iterations on) into the slot just read
-                    if (!FIRST) ld2(pv, at(k + 1), P[(s + 1) & 1]);
+                    if (FIRST) ld2(x, at(k + 1), P[(s + 1) & 1]);
+                    else ld2(pv, at(k + 1), P[(s + 1) & 1]);
                 }
                 // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
                 // grid are never used with a nonzero weight)
@@ -463,7 +482,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     const TC el = wb[rr * RW + (ic > 0 ? ic - 1 : ic)];
                     const TC er = wb[rr * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                     TC left, right;
-                    neighbours(wc, efac * el, efac * er, left, right);
+                    neighbours(wc, ezero ? (TC)0 : el, ezero ? (TC)0 : er, left, right);
                     const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, q, n2, dir, c0ihz, c1ihx);
                     TC aw[2];
                     aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
@@ -476,10 +495,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
 #pragma unroll
                     for (int v = 0; v < 2; ++v) r[v] = (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
                     put(vslot_c(s + 1), ry, r);
-                    if (FIRST && outw) {   // r of plane k+1, used two iterations on
-                        P[(s + 1) & 1][0] = wc[0];
-                        P[(s + 1) & 1][1] = wc[1];
-                    }
                 }
                 __syncthreads();
             }
@@ -487,7 +502,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         }
     }
     if (FIRST) {
-        const double v[5] = {s4, s0, s1, s2, s3};
+        // ||p_1|| is not formed: a non-finite p_1 makes p_2 non-finite,
+        // which the test at m = 2 reports; the slot holds 0
+        const double v[5] = {s1, s0, 0.0, s2, s3};
         finish_sweep_n<5>(a.partials, 8, v);
     } else {
         const double v[4] = {s0, s1, s2, s3};
