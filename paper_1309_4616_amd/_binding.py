@@ -74,7 +74,8 @@ class Params(ctypes.Structure):
                 ("max_retries", ctypes.c_int32), ("have_interval", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("interval_a", ctypes.c_double),
                 ("interval_b", ctypes.c_double), ("selector", ctypes.c_void_p),
-                ("selector_hidden", ctypes.c_int32), ("no_pairs", ctypes.c_int32)]
+                ("selector_hidden", ctypes.c_int32), ("no_pairs", ctypes.c_int32),
+                ("fuse_start", ctypes.c_int32)]
 
 
 @dataclass
@@ -87,6 +88,7 @@ class LejaParams:
     selector: object = None          # device float tensor (see selector.pack)
     selector_hidden: int = 64
     pairs: bool = True               # fuse consecutive Newton products where supported
+    fuse_start: int = 0              # Euler steps: 0 by degree parity, 1 never, 2 always
 
     def to_c(self) -> Params:
         p = Params()
@@ -95,6 +97,7 @@ class LejaParams:
         p.max_retries = int(self.max_retries)
         p.profile = 1 if self.profile else 0
         p.no_pairs = 0 if self.pairs else 1
+        p.fuse_start = int(self.fuse_start)
         if self.selector is not None:
             p.selector = ctypes.c_void_p(self.selector.data_ptr())
             p.selector_hidden = int(self.selector_hidden)

@@ -144,6 +144,7 @@ struct Params {
     const float* selector = nullptr;
     int hidden = 0;
     bool pairs = true;
+    int fuse_start = 0;
 };
 
 int read_params(const expi_params* p, Params* out) {
@@ -159,7 +160,9 @@ int read_params(const expi_params* p, Params* out) {
         q.selector = static_cast<const float*>(p->selector);
         q.hidden = p->selector_hidden;
         q.pairs = p->no_pairs == 0;
+        q.fuse_start = p->fuse_start;
     }
+    if (q.fuse_start < 0 || q.fuse_start > 2) return fail(EXPI_EINVAL, "params.fuse_start must be 0, 1 or 2");
     if (q.selector && (q.hidden < 1 || q.hidden > 256))
         return fail(EXPI_EINVAL, "params.selector_hidden must be in [1, 256]");
     if (!(q.l_max > 0) || !std::isfinite(q.l_max)) return fail(EXPI_EINVAL, "params.l_max must be positive and finite");
@@ -285,7 +288,10 @@ struct Ctx {
 // `p`.  Later products read the buffer holding the latest w and write the
 // other one: a single product j writes w_{j+1}, a pair sweep at j writes
 // w_{j+2} (w_{j+1} stays on chip).
-int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
+// start_u: an Euler step's first substep with its start vector fused into
+// the first pair sweep (PAIR_START): `src` is then u (FP64) and r is never
+// stored.
+int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool start_u = false) {
     const std::vector<double>& d = C.d;
     void* w[2] = {C.ws + C.L.w0, C.ws + C.L.w1};
     SweepArgs a{};
@@ -315,7 +321,27 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     const bool first_pair = C.pairs && C.m_max >= 3 && tin == C.tw && (((uintptr_t)src & 15) == 0);
     int finalized;
     int j = 1;
-    if (first_pair) {
+    if (start_u) {
+        // r and product 0 in one pair sweep (j = -1: its tests are those at
+        // m = 0 and m = 1, and neither can stop)
+        PairArgs b{};
+        b.x = src;
+        b.out = w[0];
+        b.p = p;
+        b.partials = C.partials;
+        b.st = C.st;
+        b.alpha = 1.0 / C.gamma;
+        b.sigma = 1.0;
+        b.beta2 = -(C.c / C.gamma + C.xi[0]);
+        b.d1 = d[0];
+        b.d2 = d[1];
+        b.tol = C.tol;
+        b.j = -1;
+        b.guard = 0;
+        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, PAIR_START));
+        log.push_back({-1, 2, w[0]});
+        finalized = 1;
+    } else if (first_pair) {
         PairArgs b{};
         b.x = src;
         b.out = w[0];
@@ -331,7 +357,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         b.tol = C.tol;
         b.j = 0;
         b.guard = 0;
-        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, true));
+        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, PAIR_FIRST));
         log.push_back({0, 2, w[0]});
         finalized = 2;
         j = 2;
@@ -410,13 +436,13 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
         // network predicts the degree m; products up to m skip the norm
         // reductions except the last two, whose two-term stop test judges the
         // prediction.  If it is not met the plain loop below continues.
-        // products up to 3 with stop tests (t_0..t_4 are recorded by the tests)
-        int rc0 = C.pairs ? pair(j, true) : single(j, true);
-        if (rc0) return rc0;
-        j += C.pairs ? 2 : 1;
-        for (; j < 4; ++j) {
-            int rc = single(j, true);
+        // products up to 3 (at least) with stop tests (t_0..t_4 are recorded
+        // by the tests); pair sweeps where allowed, so that a loop opened by
+        // the start-vector pair runs products 1-2 and 3-4 as pairs
+        while (j < 4) {
+            const int rc = C.pairs ? pair(j, true) : single(j, true);
             if (rc) return rc;
+            j += C.pairs ? 2 : 1;
         }
         HIP_TRY(launch_selector(C.selector, C.hidden, C.st, C.ia, C.ib, C.tau, C.m_max, C.s));
         int rc = sync_state(&last);
@@ -494,7 +520,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out) {
     if (C.profile && last.done != 2) {
         // launches that began before the stop did work and precede the read-back
         for (const Launch& L : log) {
-            if (L.j == 0 || L.j >= last.m) continue;   // product 0 is not timed
+            if (L.j <= 0 || L.j >= last.m) continue;   // product 0 is not timed
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, tl_ctx.tev[2 * L.j], tl_ctx.tev[2 * L.j + 1]));
             out->ms += ms;
@@ -700,17 +726,29 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
         HIP_TRY(launch_reset(C.st, s));
         bool ok = true;
         for (int l = 0; l < sub && ok; ++l) {
-            // r = A y_l + g(u), y_0 = u
-            SweepArgs a{};
-            a.x = (l == 0) ? (const void*)u : (const void*)yb;
-            a.out = ws + L.w1;
-            a.g = u;
-            a.gmode = (l == 0) ? G_CUBIC_SELF : G_CUBIC_OF;
-            a.sigma = 1.0;
-            HIP_TRY(launch_sweep(op, EPI_START, 0, tw, a, s));
+            // r = A y_l + g(u), y_0 = u: its own sweep, or (first substep)
+            // the first half of the loop's first pair sweep.  The fused form
+            // saves a sweep when the degree m is odd and costs one (a single
+            // product at the end) when it is even; the degree the last step
+            // with this step size stopped at decides.
+            const int hint = get_hint(op, C.key);
+            const bool fuse = l == 0 && tw == 0 && C.pairs && C.m_max >= 3 && pair_start_supported(op) &&
+                              (((uintptr_t)u & 15) == 0) &&
+                              (P.fuse_start == 2 || (P.fuse_start == 0 && hint >= 3 && hint % 2 == 1));
             acc.matvecs += 1;
             LoopOut lo;
-            rc = newton_loop(C, ws + L.w1, tw, p, &lo);
+            if (fuse) {
+                rc = newton_loop(C, u, 0, p, &lo, true);
+            } else {
+                SweepArgs a{};
+                a.x = (l == 0) ? (const void*)u : (const void*)yb;
+                a.out = ws + L.w1;
+                a.g = u;
+                a.gmode = (l == 0) ? G_CUBIC_SELF : G_CUBIC_OF;
+                a.sigma = 1.0;
+                HIP_TRY(launch_sweep(op, EPI_START, 0, tw, a, s));
+                rc = newton_loop(C, ws + L.w1, tw, p, &lo);
+            }
             if (rc) return rc;
             stats_add(&acc, lo);
             if (lo.done == 2) return fail(EXPI_ENONFINITE, "a norm became inf/NaN (non-finite input?)");

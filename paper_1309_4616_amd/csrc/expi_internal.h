@@ -83,6 +83,13 @@ struct SweepArgs {
 };
 
 // Arguments of the pair sweep (two Newton products in one pass, pair.hip).
+// What a pair sweep computes (see pair.hip):
+//   PAIR_NEWTON  products j and j+1 from w_j and p_j;
+//   PAIR_FIRST   products 0 and 1 from the start vector r = w_0 (no p in);
+//   PAIR_START   the start vector r = sigma A u + u - u^3 of an Euler step
+//                (on chip only) and product 0: w_1 and p_1 = d_0 r + d_1 w_1.
+enum PairMode : int { PAIR_NEWTON = 0, PAIR_FIRST = 1, PAIR_START = 2 };
+
 struct PairArgs {
     const void* x;        // w_j
     void* out;            // w_{j+2}
@@ -95,7 +102,9 @@ struct PairArgs {
     double c0, c1;
     double ih2[3];
     double alpha, beta1, beta2, d1, d2, tol;   // beta_j, beta_{j+1}, d_{j+1}, d_{j+2}
-    double d0;            // first pair of a loop: d_0 (p_1 = d_0 r + d_1 w_1)
+    double d0;            // PAIR_FIRST: d_0 (p_1 = d_0 r + d_1 w_1)
+    double sigma;         // PAIR_START: r = sigma A u + u - u^3 (then beta2 = beta_0,
+                          // d1 = d_0, d2 = d_1, j = -1)
     int n[3];
     int bc;
     int guard;
@@ -118,7 +127,7 @@ struct FinalArgs {
     int nparts;
     int j;
     int guard;
-    int first;            // pair sweeps: the pair starts the loop (5 partials, stride 8)
+    int mode;             // pair sweeps: PairMode (PAIR_FIRST: 5 partials, stride 8)
     double d0, d1, tol;
     double d2;            // pair sweeps: d_{j+2}
 };
@@ -201,14 +210,17 @@ hipError_t launch_reset(NewtonState* st, hipStream_t s);
 // Pair sweeps: two Newton products in one pass (pair.hip), then a finalize
 // kernel that applies the stop test after each of them.
 bool pair_supported(const Op& op, int tw);
+bool pair_start_supported(const Op& op);
 PairGeom pair_geom(const Op& op, int cus);
-// `first`: the pair starts the loop from the start vector r = w_0 (products
-// 0 and 1): p_1 = d_0 r + d_1 w_1, and the finalize records t_0, t_1 and
-// ||r|| before its stop test at m = 2.
+// `mode` (PairMode): PAIR_FIRST starts the loop from r = w_0 (products 0
+// and 1; the finalize records t_0, t_1 and ||r|| before its stop test at
+// m = 2); PAIR_START (FP64 storage only) forms r itself and takes product 0
+// (the finalize records t_0, t_1 and ||r||, and cannot stop at m = 1).
 hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s,
-                       hipEvent_t after_sweep = nullptr, bool finalize = true, bool first = false);
+                       hipEvent_t after_sweep = nullptr, bool finalize = true,
+                       int mode = PAIR_NEWTON);
 hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
-                                int guard, double d0, double d1, double d2, double tol, bool first,
+                                int guard, double d0, double d1, double d2, double tol, int mode,
                                 hipStream_t s);
 hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s);
 

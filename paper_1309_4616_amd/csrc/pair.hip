@@ -188,14 +188,21 @@ __device__ __forceinline__ double dpp_shift(double edge, double src) {
 constexpr int kDppWaveShr1 = 0x138;   // lane l <- lane l-1
 constexpr int kDppWaveShl1 = 0x130;   // lane l <- lane l+1
 
-// FIRST: the pair starts the loop.  It reads the start vector r (= w_0),
-// forms p_1 = d_0 r + d_1 w_1 instead of adding to a stored p, and reports
+// MODE (PairMode).  PAIR_FIRST: the pair starts the loop.  It reads the
+// start vector r (= w_0), forms p_1 = d_0 r + d_1 w_1 instead of adding to
+// a stored p, and reports
 // ||r||^2 where the other pairs report ||p_1||^2; the inner rows load r of
 // their own row a second time where the other pairs load p (a cache hit:
-// the same rows entered the w_j queue two planes earlier).
-template <int COEF, int BC, class TW, bool FIRST>
+// the same rows entered the w_j queue two planes earlier).  PAIR_START: x is
+// u; the first half forms the start vector r = sigma A u + u - u^3 of an
+// exponential Euler step instead of a product, and the second half is
+// product 0, w_1 = alpha A r + beta_0 r with p_1 = d_0 r + d_1 w_1 (here
+// beta2, d1, d2 carry beta_0, d_0, d_1); r never leaves the chip, and its
+// norm goes where the other pairs put ||w_{j+1}||.
+template <int COEF, int BC, class TW, int MODE>
 __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
+    constexpr bool FIRST = MODE == PAIR_FIRST, START = MODE == PAIR_START;
     typedef TC TC2 __attribute__((ext_vector_type(2)));
     if (a.guard && a.st->done != 0) return;
     __shared__ TC ring[3 * kPairLds];     // w_{j+1}: rows y0-1 .. y0+R of three planes
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     constexpr bool dir = BC == EXPI_DIRICHLET0, ionly = BC == EXPI_INTERIOR_ONLY;
     const TC ihx = (TC)a.ih2[0], ihy = (TC)a.ih2[1], ihz = (TC)a.ih2[2];
     const TC alpha = (TC)a.alpha, beta1 = (TC)a.beta1, beta2 = (TC)a.beta2;
-    const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2;
+    const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2, sigma = (TC)a.sigma;
     const TC c0 = (TC)a.c0, c1 = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1 : (TC)0;
     const TC c0ihx = c0 * ihx, c0ihz = c0 * ihz, c1ihx = c1 * ihx;
     // Row ends.  The x neighbour of a point at a row end is 0 under
@@ -440,13 +447,15 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             const TC p1 = FIRST ? (TC)(TW)(d0 * pp[v] + d1 * wc[v])
                                                 : (TC)(TW)(pp[v] + d1 * wc[v]);
                             const TC w2 = (TC)(TW)(alpha * aw[v] + beta2 * wc[v]);
-                            const TC p2 = (TC)(TW)(p1 + d2 * w2);
+                            const TC p2 = START ? (TC)(TW)(d1 * wc[v] + d2 * w2)
+                                                : (TC)(TW)(p1 + d2 * w2);
                             wo[v] = w2;
                             po[v] = p2;
                             if (xin) {
                                 s0 += (double)wc[v] * (double)wc[v];
                                 // FIRST: ||r||^2 in place of ||p_1||^2
-                                s1 += FIRST ? (double)pp[v] * (double)pp[v] : (double)p1 * (double)p1;
+                                if (FIRST) s1 += (double)pp[v] * (double)pp[v];
+                                else if (!START) s1 += (double)p1 * (double)p1;
                                 s2 += (double)w2 * (double)w2;
                                 s3 += (double)p2 * (double)p2;
                             }
@@ -466,7 +475,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     }
                     // p of plane k+1 (used two iterations on) into the slot just read
                     if (FIRST) ld2(x, at(k + 1), P[(s + 1) & 1]);
-                    else ld2(pv, at(k + 1), P[(s + 1) & 1]);
+                    else if (!START) ld2(pv, at(k + 1), P[(s + 1) & 1]);
                 }
                 // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
                 // grid are never used with a nonzero weight)
@@ -493,7 +502,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     }
                     TC r[2];
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) r[v] = (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
+                    for (int v = 0; v < 2; ++v)
+                        r[v] = START ? (TC)(TW)(sigma * aw[v] + (wc[v] - wc[v] * wc[v] * wc[v]))
+                                     : (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
                     put(vslot_c(s + 1), ry, r);
                 }
                 __syncthreads();
@@ -512,26 +523,29 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     }
 }
 
-template <int COEF, class TW, bool FIRST>
+template <int COEF, class TW, int MODE>
 void go_bc(const PairGeom& g, int bc, const PairArgs& a, hipStream_t s) {
     const dim3 grid(g.grid), block(kPairWaves * 64);
     switch (bc) {
         case EXPI_DIRICHLET0:
-            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW, FIRST>), grid, block, 0, s, a);
+            // not built: that variant would need more than 128 VGPRs
+            // (pair_start_supported keeps it from being asked for)
+            if constexpr (!(MODE == PAIR_START && COEF == EXPI_COEF_SEPARABLE))
+                hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW, MODE>), grid, block, 0, s, a);
             break;
         case EXPI_NEUMANN0:
-            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_NEUMANN0, TW, FIRST>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_NEUMANN0, TW, MODE>), grid, block, 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_INTERIOR_ONLY, TW, FIRST>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_INTERIOR_ONLY, TW, MODE>), grid, block, 0, s, a);
             break;
     }
 }
 
-template <class TW, bool FIRST>
+template <class TW, int MODE>
 hipError_t go(const PairGeom& g, int coef, int bc, const PairArgs& a, hipStream_t s) {
-    if (coef == EXPI_COEF_SEPARABLE) go_bc<EXPI_COEF_SEPARABLE, TW, FIRST>(g, bc, a, s);
-    else go_bc<EXPI_COEF_CONST, TW, FIRST>(g, bc, a, s);
+    if (coef == EXPI_COEF_SEPARABLE) go_bc<EXPI_COEF_SEPARABLE, TW, MODE>(g, bc, a, s);
+    else go_bc<EXPI_COEF_CONST, TW, MODE>(g, bc, a, s);
     return hipGetLastError();
 }
 
@@ -547,6 +561,13 @@ bool pair_supported(const Op& op, int tw) {
     (void)tw;
     return op.kind == 0 && op.dim == 3 && op.n[0] % 2 == 0 && op.n[0] <= 256 &&
            (op.coef == EXPI_COEF_CONST || op.coef == EXPI_COEF_SEPARABLE);
+}
+
+// The start vector fused into the first pair sweep (PAIR_START): FP64
+// storage, and not with the separable coefficient under Dirichlet
+// conditions, whose variant would spill registers.
+bool pair_start_supported(const Op& op) {
+    return pair_supported(op, 0) && !(op.coef == EXPI_COEF_SEPARABLE && op.bc == EXPI_DIRICHLET0);
 }
 
 PairGeom pair_geom(const Op& op, int cus) {
@@ -578,7 +599,8 @@ int device_cus() {
 }
 
 hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep,
-                       bool finalize, bool first) {
+                       bool finalize, int mode) {
+    if (mode == PAIR_START && (tw != 0 || !pair_start_supported(op))) return hipErrorInvalidValue;
     const PairGeom g = pair_geom(op, device_cus());
     for (int d = 0; d < 3; ++d) {
         a.n[d] = op.n[d];
@@ -596,15 +618,19 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent
     a.chunk = g.chunk;
     a.per_xcd = g.per_xcd;
     hipError_t e;
-    if (first) e = tw == 1 ? go<float, true>(g, op.coef, op.bc, a, s) : go<double, true>(g, op.coef, op.bc, a, s);
-    else e = tw == 1 ? go<float, false>(g, op.coef, op.bc, a, s) : go<double, false>(g, op.coef, op.bc, a, s);
+    if (mode == PAIR_START) e = go<double, PAIR_START>(g, op.coef, op.bc, a, s);
+    else if (mode == PAIR_FIRST)
+        e = tw == 1 ? go<float, PAIR_FIRST>(g, op.coef, op.bc, a, s) : go<double, PAIR_FIRST>(g, op.coef, op.bc, a, s);
+    else
+        e = tw == 1 ? go<float, PAIR_NEWTON>(g, op.coef, op.bc, a, s)
+                    : go<double, PAIR_NEWTON>(g, op.coef, op.bc, a, s);
     if (e != hipSuccess) return e;
     if (after_sweep) {
         e = hipEventRecord(after_sweep, s);
         if (e != hipSuccess) return e;
     }
     if (!finalize) return hipSuccess;
-    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d0, a.d1, a.d2, a.tol, first, s);
+    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d0, a.d1, a.d2, a.tol, mode, s);
 }
 
 }  // namespace expi

@@ -99,15 +99,19 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, double* out, con
 
 // Stop tests after a pair sweep: the two-term test at m = j+1 with
 // ||w_{j+1}||, ||p_{j+1}||, and, if that one fails, at m = j+2 with
-// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel).  A pair that
-// starts the loop (f.first, j = 0) brings ||r||^2 as a fifth partial sum
-// (stride 8): it records t_0 = |d_0| ||r|| and ||r||, and its first test
-// (m = 1) can only report a non-finite value.
+// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel: no stop at
+// m = 1).  A pair that starts the loop (PAIR_FIRST, j = 0) brings ||r||^2 as
+// a fifth partial sum (stride 8): it records t_0 = |d_0| ||r|| and ||r||,
+// and its first test (m = 1) can only report a non-finite value.  A
+// PAIR_START sweep comes with j = -1, d1 = d_0, d2 = d_1 and ||r||^2 in the
+// first slot: its two tests are those at m = 0 and m = 1 and it records
+// ||r||.
 __global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
     __shared__ double red[kMaxWaves][5];
     NewtonState* st = f.st;
     if (f.guard && st->done != 0) return;
-    const int nq = f.first ? 5 : 4, stride = f.first ? 8 : 4;
+    const bool first = f.mode == PAIR_FIRST;
+    const int nq = first ? 5 : 4, stride = first ? 8 : 4;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
         const double* part = f.partials + stride * (size_t)b;
@@ -125,7 +129,8 @@ __global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
         for (int w = 1; w < nw; ++w) s[q] += red[w][q];
     }
     double tprev = st->t_prev;
-    if (f.first) {
+    if (f.mode == PAIR_START) st->rnorm = sqrt(s[0]);
+    if (first) {
         tprev = fabs(f.d0) * sqrt(s[0]);
         st->rnorm = sqrt(s[0]);
         st->hist[0] = tprev;
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
     const double num2 = t1 + t2;
     if (m2 < kHist) st->hist[m2] = t2;
     if (!isfinite(wn2) || !isfinite(pn2)) done = 2;
-    else if (num2 <= f.tol * pn2) done = 1;
+    else if (m2 >= 2 && num2 <= f.tol * pn2) done = 1;
     st->t_prev = t2;
     st->err = (pn2 > 0.0) ? num2 / pn2 : (num2 == 0.0 ? 0.0 : INFINITY);
     st->pnorm = pn2;
@@ -343,7 +348,7 @@ hipError_t launch_update(int64_t n, double* out, const double* yin, const void* 
 }
 
 hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
-                                int guard, double d0, double d1, double d2, double tol, bool first,
+                                int guard, double d0, double d1, double d2, double tol, int mode,
                                 hipStream_t s) {
     FinalArgs f{};
     f.partials = partials;
@@ -351,7 +356,7 @@ hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int npa
     f.nparts = nparts;
     f.j = j;
     f.guard = guard;
-    f.first = first ? 1 : 0;
+    f.mode = mode;
     f.d0 = d0;
     f.d1 = d1;
     f.d2 = d2;

@@ -216,3 +216,55 @@ def test_first_pair_and_its_fallbacks(E):
     y0, s0 = E.phi_action(op, 1, 0.0, T(v), tol=1e-10)
     assert np.array_equal(N(y0), v)
     assert s0["degree_last"] == 2
+
+
+@pytest.mark.parametrize("bc,kind", [("neumann0", "separable"), ("neumann0", "const"),
+                                     ("dirichlet0", "const"), ("interior_only", "separable")])
+def test_start_vector_fused_into_first_pair(E, bc, kind):
+    """Euler steps whose start vector r = A u + u - u^3 is formed inside the
+    first pair sweep (fuse_start = 2) agree with the oracle and, point by
+    point, with the separate start sweep (fuse_start = 1), for stops at odd
+    and even degrees; several substeps fuse only the first."""
+    shape = (256, 10, 7)
+    op, A = make(E, shape, bc, kind)
+    n = int(np.prod(shape))
+    u0 = 0.5 + 0.1 * synth.uniform_vector(n, 12)
+    a, b = O.gershgorin_interval(A)
+    degrees = set()
+    for q in (3.0, 9.0, 21.0, 30.0, 230.0):
+        tau = q / (b - a)
+        uo, so = I.expeuler_step(A, tau, u0, 1e-10)
+        got = {}
+        for fs in (1, 2):
+            u = T(u0)
+            print(f"fused start {bc} {kind} q={q} fuse_start={fs}", flush=True)
+            st = E.expeuler_step(op, tau, u, tol=1e-10, params=E.LejaParams(fuse_start=fs))
+            assert st["converged"] == 1
+            assert relerr(N(u), uo) <= TOL_F64, (q, fs, relerr(N(u), uo))
+            got[fs] = (N(u), st)
+        assert got[1][1]["degree_last"] == got[2][1]["degree_last"]
+        assert got[1][1]["matvecs"] == got[2][1]["matvecs"]
+        assert got[1][1]["substeps"] == got[2][1]["substeps"] == so.substeps
+        assert np.max(np.abs(got[1][0] - got[2][0])) <= 1e-12 * np.max(np.abs(uo))
+        degrees.add(got[2][1]["degree_last"] % 2)
+    assert degrees == {0, 1}
+
+
+def test_fused_start_by_degree_parity(E):
+    """The automatic choice (fuse_start = 0) over a run of steps gives the
+    same states as never fusing."""
+    shape = (256, 12, 9)
+    op, A = make(E, shape, "neumann0", "separable")
+    n = int(np.prod(shape))
+    a, b = O.gershgorin_interval(A)
+    for q in (7.0, 12.0):
+        tau = q / (b - a)
+        ua, ub = T(0.5 + 0.1 * synth.uniform_vector(n, 2)), None
+        ub = ua.clone()
+        uo = N(ua).copy()
+        for step in range(4):
+            E.expeuler_step(op, tau, ua, tol=1e-10, params=E.LejaParams(fuse_start=0))
+            E.expeuler_step(op, tau, ub, tol=1e-10, params=E.LejaParams(fuse_start=1))
+            uo, _ = I.expeuler_step(A, tau, uo, 1e-10)
+            assert np.max(np.abs(N(ua) - N(ub))) <= 1e-12 * np.max(np.abs(N(ub))), (q, step)
+            assert relerr(N(ua), uo) <= TOL_F64

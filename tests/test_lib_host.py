@@ -130,6 +130,9 @@ def test_call_validation_before_any_hip_call(L):
     bad = _binding.LejaParams(interval=(0.0, -1.0)).to_c()
     assert call(params=ctypes.byref(bad)) == -1
     assert b"interval" in L.expi_last_error()
+    bad = _binding.LejaParams(fuse_start=3).to_c()
+    assert call(params=ctypes.byref(bad)) == -1
+    assert b"fuse_start" in L.expi_last_error()
     x = ctypes.c_void_p(ctypes.addressof(v))
     assert L.apply_op(op, 1.0, 0.0, x, x, 0, None) == -2
     assert L.apply_op(op, float("inf"), 0.0, x, yp, 0, None) == -1
