@@ -41,17 +41,20 @@ HBM_PEAK_GBS = 8000.0
 NEWTON_BYTES_PER_PT = {"f64": 32, "f32": 16}
 
 
-def step_bytes_per_pt(singles: int, pairs: int, dt: str) -> int:
-    """Algorithmic bytes per point of one exponential Euler step: start
-    vector (read u, write r), first product (read r, write w_1 and p), the
-    single Newton products and the pair sweeps (read w and p, write w and p
-    each), update (read u and p, write u)."""
+def step_bytes_per_pt(launches: int, loops: int, fused_starts: int, dt: str) -> int:
+    """Algorithmic bytes per point of a run of exponential Euler steps from
+    its launch counts: each Newton loop (one per substep) opens with a launch
+    that moves three vectors (read r or u, write w and p), every further
+    pair sweep or single product reads w and p and writes w and p, each
+    start vector not formed inside the opening pair sweep reads u and writes
+    r, and each substep's update reads u and p and writes u."""
     s = 8 if dt == "f64" else 4
-    start = 8 + s
-    first = 3 * s
+    opening = 3 * s
     newton = 4 * s
+    start = 8 + s
     update = 8 + s + 8
-    return start + first + (singles + pairs) * newton + update
+    return ((launches - loops) * newton + loops * (opening + update) +
+            (loops - fused_starts) * start)
 
 
 def counter_traffic(kernel_sub: str):
@@ -92,12 +95,16 @@ def run_gpu(args, dtype: str):
                      coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
     u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=0), device="cuda:0")
     ws = op.workspace(dtype)
-    params = E.LejaParams(profile=True, pairs=not args.no_pairs)
+    # profile=2: HIP events around the first Newton launch of each loop
+    # only (a pair sweep unless --no-pairs), so that timing costs two events
+    # per step instead of two per launch
+    params = E.LejaParams(profile=2, pairs=not args.no_pairs)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         E.expeuler_step(op, args.tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
     torch.cuda.synchronize()
     matvecs = newton = timed = pairs = 0
+    pair_launches = single_launches = loops = fused = 0
     newton_ms = pair_ms = 0.0
     degrees = []
     t0 = time.perf_counter()
@@ -109,16 +116,17 @@ def run_gpu(args, dtype: str):
         newton_ms += st["newton_ms"]
         pairs += st["timed_pairs"]
         pair_ms += st["pair_ms"]
+        pair_launches += st["pair_launches"]
+        single_launches += st["single_launches"]
+        loops += st["substeps"]
+        fused += st["fused_starts"]
         degrees.append(st["degree_last"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     del stream
     pts = n ** 3
-    singles = timed - 2 * pairs
-    # start vector, first product and update of every step, plus every launch
-    # of the Newton loops that did work
-    bytes_total = pts * (args.steps * step_bytes_per_pt(0, 0, dtype) +
-                         (singles + pairs) * NEWTON_BYTES_PER_PT[dtype])
+    singles = timed - 2 * pairs          # timed single products (sampled)
+    bytes_total = pts * step_bytes_per_pt(pair_launches + single_launches, loops, fused, dtype)
     per_launch = NEWTON_BYTES_PER_PT[dtype] * pts
     single_us = 1e3 * (newton_ms - pair_ms) / max(singles, 1)
     pair_us = 1e3 * pair_ms / max(pairs, 1)
@@ -131,8 +139,10 @@ def run_gpu(args, dtype: str):
         "degrees": sorted(set(degrees)),
         "point_products_per_s": pts * matvecs / wall,
         "step_gbs": bytes_total / wall / 1e9,
-        "pairs_per_step": pairs / args.steps,
-        "singles_per_step": singles / args.steps,
+        "pairs_per_step": pair_launches / args.steps,
+        "singles_per_step": single_launches / args.steps,
+        "fused_starts_per_step": fused / args.steps,
+        "timed_launches": pairs + singles,
         "pair_avg_us": pair_us if pairs else None,
         "pair_gbs": per_launch / (pair_us * 1e-6) / 1e9 if pairs else None,
         "single_avg_us": single_us if singles else None,
@@ -482,7 +492,7 @@ def main():
     if r64["pair_avg_us"]:
         # the dominant kernel: the pair sweep (two Newton products per launch;
         # algorithmic traffic read w_j and p, write w_{j+2} and p)
-        traffic = counter_traffic("pair_sweep<1, 1, double>") if n == 256 else None
+        traffic = counter_traffic("pair_sweep<1, 1, double, 0>") if n == 256 else None
         roofline = {
             "bound": "hbm",
             "kernel": "pair sweep: two fused Newton products per launch (3D separable stencil, f64)",

@@ -105,6 +105,10 @@ typedef struct {
     int32_t timed_pairs;    /* pair sweeps among the timed launches (each covers
                                two products; timed_products counts both)       */
     double  pair_ms;        /* summed device time of those pair sweeps          */
+    int32_t pair_launches;  /* pair sweeps that did work (began before the stop) */
+    int32_t single_launches;/* single-product sweeps that did work              */
+    int32_t fused_starts;   /* start vectors formed inside a pair sweep         */
+    int32_t reserved3;
 } expi_stats;
 
 /* Interpolation parameters; pass NULL for the defaults
@@ -115,7 +119,10 @@ typedef struct {
     int32_t m_max;          /* largest number of Newton products per substep    */
     int32_t max_retries;    /* substep doublings after a non-converged substep  */
     int32_t have_interval;  /* 1: use [interval_a, interval_b] below            */
-    int32_t profile;        /* 1: time each fused Newton product (stats)        */
+    int32_t profile;        /* 1: time each fused Newton launch from product 1
+                             * on (stats); 2: only the first of each Newton
+                             * loop (two timing events per loop instead of two
+                             * per launch); other values: EXPI_EINVAL         */
     double  interval_a;
     double  interval_b;
     /* Learned step selector (optional): device float buffer laid out as

@@ -51,7 +51,9 @@ class Stats(ctypes.Structure):
                 ("rnorm", ctypes.c_double), ("t_first", ctypes.c_double * 5),
                 ("pred_degree", ctypes.c_int32), ("pred_substeps", ctypes.c_int32),
                 ("fallback", ctypes.c_int32), ("finalized", ctypes.c_int32),
-                ("timed_pairs", ctypes.c_int32), ("pair_ms", ctypes.c_double)]
+                ("timed_pairs", ctypes.c_int32), ("pair_ms", ctypes.c_double),
+                ("pair_launches", ctypes.c_int32), ("single_launches", ctypes.c_int32),
+                ("fused_starts", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -84,7 +86,7 @@ class LejaParams:
     m_max: int = 100
     max_retries: int = 4
     interval: tuple | None = None
-    profile: bool = False
+    profile: int = 0                 # 0 off, 1 / True every launch, 2 one launch per loop
     selector: object = None          # device float tensor (see selector.pack)
     selector_hidden: int = 64
     pairs: bool = True               # fuse consecutive Newton products where supported
@@ -95,7 +97,7 @@ class LejaParams:
         p.l_max = float(self.l_max)
         p.m_max = int(self.m_max)
         p.max_retries = int(self.max_retries)
-        p.profile = 1 if self.profile else 0
+        p.profile = int(self.profile)
         p.no_pairs = 0 if self.pairs else 1
         p.fuse_start = int(self.fuse_start)
         if self.selector is not None:

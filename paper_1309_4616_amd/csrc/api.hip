@@ -139,7 +139,7 @@ struct Params {
     int m_max = 100;
     int max_retries = 4;
     bool have_interval = false;
-    bool profile = false;
+    int profile = 0;        // 0 off, 1 every launch, 2 one launch per Newton loop
     double ia = 0, ib = 0;
     const float* selector = nullptr;
     int hidden = 0;
@@ -154,7 +154,7 @@ int read_params(const expi_params* p, Params* out) {
         q.m_max = p->m_max;
         q.max_retries = p->max_retries;
         q.have_interval = p->have_interval != 0;
-        q.profile = p->profile != 0;
+        q.profile = p->profile;
         q.ia = p->interval_a;
         q.ib = p->interval_b;
         q.selector = static_cast<const float*>(p->selector);
@@ -163,6 +163,7 @@ int read_params(const expi_params* p, Params* out) {
         q.fuse_start = p->fuse_start;
     }
     if (q.fuse_start < 0 || q.fuse_start > 2) return fail(EXPI_EINVAL, "params.fuse_start must be 0, 1 or 2");
+    if (q.profile < 0 || q.profile > 2) return fail(EXPI_EINVAL, "params.profile must be 0, 1 or 2");
     if (q.selector && (q.hidden < 1 || q.hidden > 256))
         return fail(EXPI_EINVAL, "params.selector_hidden must be in [1, 256]");
     if (!(q.l_max > 0) || !std::isfinite(q.l_max)) return fail(EXPI_EINVAL, "params.l_max must be positive and finite");
@@ -255,6 +256,7 @@ struct LoopOut {
     double ms = 0;        // their summed device time
     int pairs_timed = 0;  // pair sweeps among them
     double pair_ms = 0;   // and their device time
+    int pair_launches = 0, single_launches = 0;   // launches that did work
     double rnorm = 0;     // ||r||
     double hist[kHist] = {0, 0, 0, 0, 0};
     int pred_m = 0, pred_s = 0;
@@ -277,7 +279,7 @@ struct Ctx {
     double c, gamma, tol;
     int m_max;
     DdKey key;
-    bool profile;
+    int profile;            // Params::profile
     const float* selector;
     int hidden;
     double ia, ib, tau;
@@ -312,8 +314,16 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
     struct Launch {
         int j, n;        // first product index, products covered
         const void* out;
+        bool timed;      // events recorded around it
     };
     std::vector<Launch> log;
+    // profile 1: time every launch from product 1 on; 2: only the first one
+    bool sampled = false;
+    auto timing = [&]() {
+        if (C.profile == 1) return true;
+        if (C.profile == 2 && !sampled) return sampled = true;
+        return false;
+    };
 
     // Products 0 and 1 in one pair sweep when the start vector has the
     // storage type and alignment the pair sweep reads (w_2 goes to w[0]:
@@ -339,7 +349,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.j = -1;
         b.guard = 0;
         HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, PAIR_START));
-        log.push_back({-1, 2, w[0]});
+        log.push_back({-1, 2, w[0], false});
         finalized = 1;
     } else if (first_pair) {
         PairArgs b{};
@@ -358,11 +368,12 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.j = 0;
         b.guard = 0;
         HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, PAIR_FIRST));
-        log.push_back({0, 2, w[0]});
+        log.push_back({0, 2, w[0], false});
         finalized = 2;
         j = 2;
     } else {
         HIP_TRY(launch_sweep(*C.op, EPI_FIRST, tin, C.tw, a, C.s));
+        log.push_back({0, 1, w[0], false});
         finalized = 1;
     }
 
@@ -374,10 +385,11 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         a.beta = -(C.c / C.gamma + C.xi[j]);
         a.d1 = d[j + 1];
         a.guard = 1;
-        if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
-        HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s,
-                             C.profile ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
-        log.push_back({j, 1, w[cur ^ 1]});
+        const bool tm = timing();
+        if (tm) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
+        HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s, tm ? tl_ctx.tev[2 * j + 1] : nullptr,
+                             fin));
+        log.push_back({j, 1, w[cur ^ 1], tm});
         cur ^= 1;
         if (fin) ++finalized;
         return EXPI_OK;
@@ -398,9 +410,10 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.tol = C.tol;
         b.j = j;
         b.guard = 1;
-        if (C.profile) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
-        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, C.profile ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
-        log.push_back({j, 2, w[cur ^ 1]});
+        const bool tm = timing();
+        if (tm) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
+        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, tm ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
+        log.push_back({j, 2, w[cur ^ 1], tm});
         cur ^= 1;
         if (fin) finalized += 2;
         return EXPI_OK;
@@ -517,10 +530,19 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         out->fix = last.fix;
     }
     if (last.done == 1) set_hint(*C.op, C.key, last.m);
+    if (last.done != 2) {
+        // launches that began before the stop did work (the opening ones
+        // always do); later ones returned at once
+        for (const Launch& L : log) {
+            if (L.j >= last.m && L.j > 0) continue;
+            if (L.n == 2) ++out->pair_launches;
+            else ++out->single_launches;
+        }
+    }
     if (C.profile && last.done != 2) {
         // launches that began before the stop did work and precede the read-back
         for (const Launch& L : log) {
-            if (L.j <= 0 || L.j >= last.m) continue;   // product 0 is not timed
+            if (!L.timed || L.j >= last.m) continue;
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, tl_ctx.tev[2 * L.j], tl_ctx.tev[2 * L.j + 1]));
             out->ms += ms;
@@ -553,6 +575,8 @@ void stats_add(expi_stats* st, const LoopOut& lo) {
     st->newton_ms += lo.ms;
     st->timed_pairs += lo.pairs_timed;
     st->pair_ms += lo.pair_ms;
+    st->pair_launches += lo.pair_launches;
+    st->single_launches += lo.single_launches;
 }
 
 int common_setup(Op& op, double tau, double tol, int dtype, const Params& P, char* ws,
@@ -739,6 +763,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
             LoopOut lo;
             if (fuse) {
                 rc = newton_loop(C, u, 0, p, &lo, true);
+                acc.fused_starts += 1;
             } else {
                 SweepArgs a{};
                 a.x = (l == 0) ? (const void*)u : (const void*)yb;

@@ -154,6 +154,13 @@ def test_pair_profile_accounting(E):
     assert sp["timed_pairs"] >= (m - 2) // 2 - 1
     assert 0 < sp["pair_ms"] <= sp["newton_ms"]
     assert ss["timed_products"] == m - 1 and ss["timed_pairs"] == 0
+    # launches that did work: products 0 .. m-1 (a pair may end one past m)
+    assert 2 * sp["pair_launches"] + sp["single_launches"] in (m, m + 1)
+    assert ss["single_launches"] == m and ss["pair_launches"] == 0
+    # profile = 2 times only the first launch after the opening pair sweep
+    y2, s2 = E.phi_action(op, 1, 30.0 / (b - a), T(v), tol=1e-10, params=E.LejaParams(profile=2))
+    assert s2["timed_pairs"] == 1 and s2["timed_products"] == 2 and s2["pair_ms"] > 0
+    assert np.max(np.abs(N(y2) - yp)) <= 1e-12 * np.max(np.abs(yp))
 
 
 def test_pair_fp32_constant_coefficient(E):
