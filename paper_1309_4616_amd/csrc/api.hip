@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <string>
 
 #include "expi_internal.h"
@@ -264,6 +265,7 @@ struct LoopOut {
     int finalized = 0;    // products followed by a norm reduction and stop test
     double fix = 0;       // p holds d_{m+1} w_{m+1} too many (pair stopped at its first product)
     const void* fix_w = nullptr;   // where w_{m+1} is
+    bool updated = false;          // the caller's update is already in the stream
 };
 
 struct Ctx {
@@ -293,7 +295,14 @@ struct Ctx {
 // start_u: an Euler step's first substep with its start vector fused into
 // the first pair sweep (PAIR_START): `src` is then u (FP64) and r is never
 // stored.
-int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool start_u = false) {
+//
+// spec: the caller's update, enqueued after each status read-back of the
+// plain loop when it runs one batch at a time (a degree hint is known); it
+// must run only if the loop has stopped (launch_update_st).  The host then
+// needs no round trip between the stop and the update: out->updated tells
+// that the update after the deciding read-back is in the stream.
+int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool start_u = false,
+                const std::function<hipError_t()>* spec = nullptr) {
     const std::vector<double>& d = C.d;
     void* w[2] = {C.ws + C.L.w0, C.ws + C.L.w1};
     SweepArgs a{};
@@ -410,6 +419,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.tol = C.tol;
         b.j = j;
         b.guard = 1;
+        b.outbuf = cur ^ 1;
         const bool tm = timing();
         if (tm) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
         HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, tm ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
@@ -501,6 +511,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
                 rc = readback(C.st, C.s, &slot);
                 if (rc) return rc;
                 pending.push_back(slot);
+                if (spec && !ahead) HIP_TRY((*spec)());
                 chunk = ahead ? 2 : step;
             }
             const size_t keep = ahead ? 1 : 0;
@@ -515,6 +526,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
             }
             if (!finished && pending.empty() && j >= C.m_max) finished = true;
         }
+        out->updated = spec && !ahead && last.done == 1;
     }
     out->m = last.m;
     out->done = last.done;
@@ -685,7 +697,14 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
             }
             LoopOut lo;
             C.pairs = P.pairs && pair_supported(op, tw) && (((uintptr_t)p & 15) == 0);
-            rc = newton_loop(C, src, tin, p, &lo);
+            // the update of this substep, enqueued ahead of the status
+            // read-back where it always runs (p_in_y needs one only for a fix)
+            const double* yin = (k == 1 && l > 0) ? y : nullptr;
+            const double scale = (k == 1) ? 1.0 / sub : 1.0;
+            const std::function<hipError_t()> spec = [&]() {
+                return launch_update_st(n, y, yin, p, tw, scale, C.st, ws + L.w0, ws + L.w1, s);
+            };
+            rc = newton_loop(C, src, tin, p, &lo, false, p_in_y ? nullptr : &spec);
             if (rc) return rc;
             stats_add(&acc, lo);
             if (lo.done == 2) return fail(EXPI_ENONFINITE, "a norm became inf/NaN (non-finite input?)");
@@ -694,14 +713,10 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
                 break;
             }
             if (!p_in_y) {
-                if (k == 1) {
-                    // y' <- y' + p / s   (y' = 0 before the first substep)
-                    HIP_TRY(launch_update(n, y, l == 0 ? nullptr : y, p, tw, 1.0 / sub, C.st, 1, s,
-                                          lo.fix_w, lo.fix));
-                } else {
-                    // e^{delta A} (or phi_k, single substep) applied: y <- p
-                    HIP_TRY(launch_update(n, y, nullptr, p, tw, 1.0, C.st, 1, s, lo.fix_w, lo.fix));
-                }
+                // k = 1: y' <- y' + p / s (y' = 0 before the first substep);
+                // otherwise e^{delta A} (or phi_k, single substep) applied: y <- p
+                if (!lo.updated)
+                    HIP_TRY(launch_update(n, y, yin, p, tw, scale, C.st, 1, s, lo.fix_w, lo.fix));
             } else if (lo.fix != 0.0) {
                 // y holds p: remove the one term too many in place
                 HIP_TRY(launch_update(n, y, nullptr, y, 0, 1.0, C.st, 1, s, lo.fix_w, lo.fix));
@@ -760,9 +775,15 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
                               (((uintptr_t)u & 15) == 0) &&
                               (P.fuse_start == 2 || (P.fuse_start == 0 && hint >= 3 && hint % 2 == 1));
             acc.matvecs += 1;
+            // y_{l+1} = y_l + delta p; the last substep writes u
+            const double* yin = (l == 0) ? u : yb;
+            double* yout = (l == sub - 1) ? u : yb;
+            const std::function<hipError_t()> spec = [&]() {
+                return launch_update_st(n, yout, yin, p, tw, delta, C.st, ws + L.w0, ws + L.w1, s);
+            };
             LoopOut lo;
             if (fuse) {
-                rc = newton_loop(C, u, 0, p, &lo, true);
+                rc = newton_loop(C, u, 0, p, &lo, true, &spec);
                 acc.fused_starts += 1;
             } else {
                 SweepArgs a{};
@@ -772,7 +793,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
                 a.gmode = (l == 0) ? G_CUBIC_SELF : G_CUBIC_OF;
                 a.sigma = 1.0;
                 HIP_TRY(launch_sweep(op, EPI_START, 0, tw, a, s));
-                rc = newton_loop(C, ws + L.w1, tw, p, &lo);
+                rc = newton_loop(C, ws + L.w1, tw, p, &lo, false, &spec);
             }
             if (rc) return rc;
             stats_add(&acc, lo);
@@ -781,10 +802,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
                 ok = false;
                 break;
             }
-            // y_{l+1} = y_l + delta p; the last substep writes u
-            const double* yin = (l == 0) ? u : yb;
-            double* yout = (l == sub - 1) ? u : yb;
-            HIP_TRY(launch_update(n, yout, yin, p, tw, delta, C.st, 1, s, lo.fix_w, lo.fix));
+            if (!lo.updated) HIP_TRY(launch_update(n, yout, yin, p, tw, delta, C.st, 1, s, lo.fix_w, lo.fix));
         }
         acc.converged = ok ? 1 : 0;
         if (ok) {

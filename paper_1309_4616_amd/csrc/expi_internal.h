@@ -26,7 +26,7 @@ struct alignas(64) NewtonState {
     unsigned int arrive;  // reserved
     int done;             // 0 running, 1 stop test met, 2 non-finite norm
     int m;                // products taken in this loop
-    int pad;
+    int fixbuf;           // with fix: which of the two w buffers holds w_{m+1}
     double t_prev;        // |d_m| ||w_m|| of the latest product
     double err;           // (t_{m-1} + t_m) / ||p|| at the latest test
     double pnorm;         // ||p||
@@ -108,6 +108,7 @@ struct PairArgs {
     int n[3];
     int bc;
     int guard;
+    int outbuf;           // index of `out` among the loop's two w buffers (stop tests record it)
     int j;
     int nxw;              // waves per grid row (1 or 2)
     int rows;             // output rows per row tile
@@ -128,6 +129,7 @@ struct FinalArgs {
     int j;
     int guard;
     int mode;             // pair sweeps: PairMode (PAIR_FIRST: 5 partials, stride 8)
+    int outbuf;           // pair sweeps: index of the w buffer the sweep writes
     double d0, d1, tol;
     double d2;            // pair sweeps: d_{j+2}
 };
@@ -205,6 +207,13 @@ hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs
 hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
                          double scale, const NewtonState* st, int guard, hipStream_t s,
                          const void* wfix = nullptr, double fix = 0.0);
+// The same update with the correction taken from the device: runs only if
+// st->done == 1, and subtracts st->fix * w (w = w1 if st->fixbuf, else w0)
+// when st->fix is nonzero.  Lets the host enqueue the update before it has
+// read the loop's status.
+hipError_t launch_update_st(int64_t n, double* out, const double* yin, const void* p, int tp,
+                            double scale, const NewtonState* st, const void* w0, const void* w1,
+                            hipStream_t s);
 hipError_t launch_reset(NewtonState* st, hipStream_t s);
 
 // Pair sweeps: two Newton products in one pass (pair.hip), then a finalize
@@ -221,7 +230,7 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s,
                        int mode = PAIR_NEWTON);
 hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
                                 int guard, double d0, double d1, double d2, double tol, int mode,
-                                hipStream_t s);
+                                int outbuf, hipStream_t s);
 hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s);
 
 // Error reporting (api.hip).

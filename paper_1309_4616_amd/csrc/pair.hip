@@ -630,7 +630,7 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent
         if (e != hipSuccess) return e;
     }
     if (!finalize) return hipSuccess;
-    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d0, a.d1, a.d2, a.tol, mode, s);
+    return launch_pair_finalize(a.partials, a.st, g.grid, a.j, a.guard, a.d0, a.d1, a.d2, a.tol, mode, a.outbuf, s);
 }
 
 }  // namespace expi

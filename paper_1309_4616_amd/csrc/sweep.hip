@@ -97,76 +97,29 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, double* out, con
     }
 }
 
-// Stop tests after a pair sweep: the two-term test at m = j+1 with
-// ||w_{j+1}||, ||p_{j+1}||, and, if that one fails, at m = j+2 with
-// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel: no stop at
-// m = 1).  A pair that starts the loop (PAIR_FIRST, j = 0) brings ||r||^2 as
-// a fifth partial sum (stride 8): it records t_0 = |d_0| ||r|| and ||r||,
-// and its first test (m = 1) can only report a non-finite value.  A
-// PAIR_START sweep comes with j = -1, d1 = d_0, d2 = d_1 and ||r||^2 in the
-// first slot: its two tests are those at m = 0 and m = 1 and it records
-// ||r||.
+// update_kernel with the correction read from the state (see launch_update_st)
+template <class TP>
+__global__ __launch_bounds__(256) void update_st_kernel(int64_t n, double* out, const double* yin,
+                                                        const TP* p, double scale,
+                                                        const NewtonState* st, const TP* w0,
+                                                        const TP* w1) {
+    if (st->done != 1) return;
+    const double fix = st->fix;
+    const TP* wfix = st->fixbuf ? w1 : w0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (fix != 0.0) {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            out[i] = (yin ? yin[i] : 0.0) + scale * ((double)p[i] - fix * (double)wfix[i]);
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            out[i] = (yin ? yin[i] : 0.0) + scale * (double)p[i];
+    }
+}
+
+// Stop tests after a pair sweep (pair_tests) as a kernel of its own.
 __global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
-    __shared__ double red[kMaxWaves][5];
-    NewtonState* st = f.st;
-    if (f.guard && st->done != 0) return;
-    const bool first = f.mode == PAIR_FIRST;
-    const int nq = first ? 5 : 4, stride = first ? 8 : 4;
-    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
-        const double* part = f.partials + stride * (size_t)b;
-        for (int q = 0; q < nq; ++q) s[q] += part[q];
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
-    if (lane == 0)
-        for (int q = 0; q < 5; ++q) red[wv][q] = s[q];
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int q = 0; q < 5; ++q) {
-        s[q] = red[0][q];
-        for (int w = 1; w < nw; ++w) s[q] += red[w][q];
-    }
-    double tprev = st->t_prev;
-    if (f.mode == PAIR_START) st->rnorm = sqrt(s[0]);
-    if (first) {
-        tprev = fabs(f.d0) * sqrt(s[0]);
-        st->rnorm = sqrt(s[0]);
-        st->hist[0] = tprev;
-        for (int q = 0; q < 4; ++q) s[q] = s[q + 1];
-    }
-    const double wn1 = sqrt(s[0]), pn1 = sqrt(s[1]), wn2 = sqrt(s[2]), pn2 = sqrt(s[3]);
-    const double t1 = fabs(f.d1) * wn1;
-    const int m1 = f.j + 1;
-    const double num1 = tprev + t1;
-    if (m1 < kHist) st->hist[m1] = t1;
-    int done = 0;
-    if (!isfinite(wn1) || !isfinite(pn1) || !isfinite(tprev)) done = 2;
-    else if (m1 >= 2 && num1 <= f.tol * pn1) done = 1;
-    if (done) {
-        st->t_prev = t1;
-        st->err = (pn1 > 0.0) ? num1 / pn1 : (num1 == 0.0 ? 0.0 : INFINITY);
-        st->pnorm = pn1;
-        st->wnorm = wn1;
-        st->m = m1;
-        st->fix = (done == 1) ? f.d2 : 0.0;
-        st->done = done;
-        return;
-    }
-    const double t2 = fabs(f.d2) * wn2;
-    const int m2 = f.j + 2;
-    const double num2 = t1 + t2;
-    if (m2 < kHist) st->hist[m2] = t2;
-    if (!isfinite(wn2) || !isfinite(pn2)) done = 2;
-    else if (m2 >= 2 && num2 <= f.tol * pn2) done = 1;
-    st->t_prev = t2;
-    st->err = (pn2 > 0.0) ? num2 / pn2 : (num2 == 0.0 ? 0.0 : INFINITY);
-    st->pnorm = pn2;
-    st->wnorm = wn2;
-    st->m = m2;
-    st->fix = 0.0;
-    st->done = done;
+    if (f.guard && f.st->done != 0) return;
+    pair_tests(f);
 }
 
 __global__ void reset_kernel(NewtonState* st) {
@@ -174,7 +127,7 @@ __global__ void reset_kernel(NewtonState* st) {
         st->arrive = 0;
         st->done = 0;
         st->m = 0;
-        st->pad = 0;
+        st->fixbuf = 0;
         st->t_prev = 0.0;
         st->err = 0.0;
         st->pnorm = 0.0;
@@ -347,9 +300,26 @@ hipError_t launch_update(int64_t n, double* out, const double* yin, const void* 
     return hipGetLastError();
 }
 
+hipError_t launch_update_st(int64_t n, double* out, const double* yin, const void* p, int tp,
+                            double scale, const NewtonState* st, const void* w0, const void* w1,
+                            hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    if (tp == 0)
+        hipLaunchKernelGGL(update_st_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, n, out,
+                           yin, static_cast<const double*>(p), scale, st,
+                           static_cast<const double*>(w0), static_cast<const double*>(w1));
+    else
+        hipLaunchKernelGGL(update_st_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, n, out,
+                           yin, static_cast<const float*>(p), scale, st,
+                           static_cast<const float*>(w0), static_cast<const float*>(w1));
+    return hipGetLastError();
+}
+
 hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int nparts, int j,
                                 int guard, double d0, double d1, double d2, double tol, int mode,
-                                hipStream_t s) {
+                                int outbuf, hipStream_t s) {
     FinalArgs f{};
     f.partials = partials;
     f.st = st;
@@ -357,6 +327,7 @@ hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int npa
     f.j = j;
     f.guard = guard;
     f.mode = mode;
+    f.outbuf = outbuf;
     f.d0 = d0;
     f.d1 = d1;
     f.d2 = d2;

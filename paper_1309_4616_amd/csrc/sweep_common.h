@@ -106,6 +106,80 @@ __device__ __forceinline__ void finish_sweep_n(double* partials, int stride, con
     }
 }
 
+// Stop tests after a pair sweep: the two-term test at m = j+1 with
+// ||w_{j+1}||, ||p_{j+1}||, and, if that one fails, at m = j+2 with
+// ||w_{j+2}||, ||p_{j+2}|| (same rule as finalize_kernel: no stop at
+// m = 1).  A pair that starts the loop (PAIR_FIRST, j = 0) brings ||r||^2 as
+// a fifth partial sum (stride 8): it records t_0 = |d_0| ||r|| and ||r||,
+// and its first test (m = 1) can only report a non-finite value.  A
+// PAIR_START sweep comes with j = -1, d1 = d_0, d2 = d_1 and ||r||^2 in the
+// first slot: its two tests are those at m = 0 and m = 1 and it records
+// ||r||.
+//
+// Called by every thread of one workgroup (up to kMaxPairWaves waves).
+__device__ inline void pair_tests(const FinalArgs& f) {
+    __shared__ double red[kMaxPairWaves][5];
+    NewtonState* st = f.st;
+    const bool first = f.mode == PAIR_FIRST;
+    const int nq = first ? 5 : 4, stride = first ? 8 : 4;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
+        const double* part = f.partials + stride * (size_t)b;
+        for (int q = 0; q < nq; ++q) s[q] += part[q];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
+    if (lane == 0)
+        for (int q = 0; q < 5; ++q) red[wv][q] = s[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < 5; ++q) {
+        s[q] = red[0][q];
+        for (int w = 1; w < nw; ++w) s[q] += red[w][q];
+    }
+    double tprev = st->t_prev;
+    if (f.mode == PAIR_START) st->rnorm = sqrt(s[0]);
+    if (first) {
+        tprev = fabs(f.d0) * sqrt(s[0]);
+        st->rnorm = sqrt(s[0]);
+        st->hist[0] = tprev;
+        for (int q = 0; q < 4; ++q) s[q] = s[q + 1];
+    }
+    const double wn1 = sqrt(s[0]), pn1 = sqrt(s[1]), wn2 = sqrt(s[2]), pn2 = sqrt(s[3]);
+    const double t1 = fabs(f.d1) * wn1;
+    const int m1 = f.j + 1;
+    const double num1 = tprev + t1;
+    if (m1 < kHist) st->hist[m1] = t1;
+    int done = 0;
+    if (!isfinite(wn1) || !isfinite(pn1) || !isfinite(tprev)) done = 2;
+    else if (m1 >= 2 && num1 <= f.tol * pn1) done = 1;
+    if (done) {
+        st->t_prev = t1;
+        st->err = (pn1 > 0.0) ? num1 / pn1 : (num1 == 0.0 ? 0.0 : INFINITY);
+        st->pnorm = pn1;
+        st->wnorm = wn1;
+        st->m = m1;
+        st->fix = (done == 1) ? f.d2 : 0.0;
+        st->fixbuf = f.outbuf;
+        st->done = done;
+        return;
+    }
+    const double t2 = fabs(f.d2) * wn2;
+    const int m2 = f.j + 2;
+    const double num2 = t1 + t2;
+    if (m2 < kHist) st->hist[m2] = t2;
+    if (!isfinite(wn2) || !isfinite(pn2)) done = 2;
+    else if (m2 >= 2 && num2 <= f.tol * pn2) done = 1;
+    st->t_prev = t2;
+    st->err = (pn2 > 0.0) ? num2 / pn2 : (num2 == 0.0 ? 0.0 : INFINITY);
+    st->pnorm = pn2;
+    st->wnorm = wn2;
+    st->m = m2;
+    st->fix = 0.0;
+    st->done = done;
+}
+
 // Face weight of the face of cell c towards a neighbour with coefficient
 // anb: the mean of the two coefficients if the neighbour exists; for a
 // missing neighbour the cell's own coefficient under homogeneous Dirichlet

@@ -275,3 +275,32 @@ def test_fused_start_by_degree_parity(E):
             uo, _ = I.expeuler_step(A, tau, uo, 1e-10)
             assert np.max(np.abs(N(ua) - N(ub))) <= 1e-12 * np.max(np.abs(N(ub))), (q, step)
             assert relerr(N(ua), uo) <= TOL_F64
+
+
+def test_update_enqueued_ahead_of_status_with_wrong_hints(E):
+    """With a degree hint the update is enqueued right after each status
+    read-back and runs only once the loop has stopped.  Steps whose hint is
+    too small (several batches) or too large (guarded launches past the
+    stop) still give the oracle's result, for Euler steps and for phi_1 with
+    several substeps."""
+    shape = (256, 10, 7)
+    op, A = make(E, shape, "neumann0", "separable")
+    n = int(np.prod(shape))
+    a, b = O.gershgorin_interval(A)
+    smooth = 0.5 + 1e-6 * synth.uniform_vector(n, 4)
+    rough = 0.5 + 0.4 * synth.uniform_vector(n, 5)
+    tau = 20.0 / (b - a)
+    for name, u0 in (("smooth", smooth), ("rough", rough), ("smooth", smooth), ("rough", rough)):
+        u = T(u0)
+        print(f"euler with hint: {name}", flush=True)
+        st = E.expeuler_step(op, tau, u, tol=1e-10)
+        uo, so = I.expeuler_step(A, tau, u0, 1e-10)
+        assert relerr(N(u), uo) <= TOL_F64, (name, relerr(N(u), uo))
+        assert abs(st["degree_last"] - so.degrees[-1]) <= 1
+    tau3 = 230.0 / (b - a)                      # three substeps
+    for name, v in (("smooth", smooth), ("rough", rough), ("smooth", smooth)):
+        print(f"phi1 with hint: {name}", flush=True)
+        y, st = E.phi_action(op, 1, tau3, T(v), tol=1e-10)
+        yo, so = I.phi_action(A, 1, tau3, v, 1e-10)
+        assert st["substeps"] == 3
+        assert relerr(N(y), yo) <= TOL_F64, (name, relerr(N(y), yo))
