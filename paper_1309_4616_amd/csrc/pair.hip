@@ -407,12 +407,16 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int k = k0 + s;
+                // the last output plane ke-1 is done at k = ke; an odd count
+                // of iterations leaves nothing for the last one
+                if (k > ke) break;
                 // (1) w_j of plane k+2 into the ring, then load plane k+4
+                // (planes past ke+1 feed no needed value: not loaded)
                 {
                     TC* wb = wslot_c(s + 2);
                     put(wb, rr, L[s & 1]);
                     if (hal) put(wb, rh, P[s & 1]);
-                    if (yin) {
+                    if (yin && k + 4 <= ke + 1) {
                         ld2(x, at(k + 4), L[s & 1]);
                         if (hal) ld2(x, at(k + 4) + hoff, P[s & 1]);
                     }
@@ -473,9 +477,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             }
                         }
                     }
-                    // p of plane k+1 (used two iterations on) into the slot just read
-                    if (FIRST) ld2(x, at(k + 1), P[(s + 1) & 1]);
-                    else if (!START) ld2(pv, at(k + 1), P[(s + 1) & 1]);
+                    // p of plane k+1 (used two iterations on, if it is an
+                    // output plane) into the slot just read
+                    if (k + 1 >= kb && k + 1 < ke) {
+                        if (FIRST) ld2(x, at(k + 1), P[(s + 1) & 1]);
+                        else if (!START) ld2(pv, at(k + 1), P[(s + 1) & 1]);
+                    }
                 }
                 // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
                 // grid are never used with a nonzero weight)
