@@ -144,8 +144,7 @@ typedef struct {
     /* Exponential Euler steps: the start-vector sweep r = A u + u - u^3 of
      * the first substep can run as the first half of a pair sweep whose
      * second half is Newton product 0 (FP64 storage, pair sweeps on, u
-     * 16-byte aligned, not the separable coefficient under Dirichlet
-     * conditions); a stop at degree m then takes ceil((m+1)/2) sweeps
+     * 16-byte aligned); a stop at degree m then takes ceil((m+1)/2) sweeps
      * instead of 1 + ceil(m/2).  0: fuse when the previous step with the
      * same step size stopped at an odd degree; 1: never; 2: whenever it
      * applies.  Other values: EXPI_EINVAL. */

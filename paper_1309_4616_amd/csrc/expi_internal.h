@@ -99,8 +99,8 @@ struct PairArgs {
     const double* tz;
     double* partials;     // [grid][4]: ||w_{j+1}||^2, ||p_{j+1}||^2, ||w_{j+2}||^2, ||p_{j+2}||^2
     NewtonState* st;
-    double c0, c1;
     double ih2[3];
+    double c0ih[3], c1ih[3];   // c0 / h_d^2, c1 / h_d^2 (coefficient c0 + c1 X Y Z)
     double alpha, beta1, beta2, d1, d2, tol;   // beta_j, beta_{j+1}, d_{j+1}, d_{j+2}
     double d0;            // PAIR_FIRST: d_0 (p_1 = d_0 r + d_1 w_1)
     double sigma;         // PAIR_START: r = sigma A u + u - u^3 (then beta2 = beta_0,

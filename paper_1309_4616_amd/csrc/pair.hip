@@ -167,6 +167,28 @@ __device__ __forceinline__ void st2_stream(T* __restrict__ p, int idx, const TC 
     __builtin_nontemporal_store(t, reinterpret_cast<T2*>(p + idx));
 }
 
+// Two values to p[idx], idx < 0 dropping the store (buffer store with range
+// checking: an offset past the buffer's end writes nothing).  Lets a wave
+// issue the same stores on every path, so that the in-order memory counter
+// keeps exact counts and waits only for the loads it needs.
+template <class T, class TC>
+__device__ __forceinline__ void st2_buf(__amdgpu_buffer_rsrc_t r, int idx, const TC (&v)[2], bool stream) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    T2 t;
+    t.x = (T)v[0];
+    t.y = (T)v[1];
+    const int off = idx >= 0 ? idx * (int)sizeof(T) : 0x7ffffff0;
+    if constexpr (sizeof(T) == 8) {
+        typedef unsigned U4 __attribute__((ext_vector_type(4)));
+        if (stream) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, t), r, off, 0, 2);
+        else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, t), r, off, 0, 0);
+    } else {
+        typedef unsigned U2 __attribute__((ext_vector_type(2)));
+        if (stream) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, t), r, off, 0, 2);
+        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, t), r, off, 0, 0);
+    }
+}
+
 // Whole-wave shifts by one lane through DPP: lane l receives `src` of lane
 // l-1 (from_left) or l+1 (from_right); the lane without a source (0, resp.
 // 63) keeps `edge`.
@@ -221,6 +243,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     const TW* __restrict__ x = static_cast<const TW*>(a.x);
     TW* __restrict__ out = static_cast<TW*>(a.out);
     TW* __restrict__ pv = static_cast<TW*>(a.p);
+    // w_{j+2} and p are written through buffer resources (range-checked
+    // stores; the grid holds fewer than 2^31 bytes, see pair_supported)
+    const int nbytes = a.n[0] * a.n[1] * a.n[2] * (int)sizeof(TW);
+    const __amdgpu_buffer_rsrc_t out_r = __builtin_amdgcn_make_buffer_rsrc(out, 0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t pv_r = __builtin_amdgcn_make_buffer_rsrc(pv, 0, nbytes, 0x00020000);
     // the wave index is the same in every lane; saying so keeps the row data
     // (and everything derived from it) in scalar registers
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -233,11 +260,13 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     const bool xin = i < n0;                      // n0 is even: both points in the row
     const int ic = xin ? i : n0 - 2;
     constexpr bool dir = BC == EXPI_DIRICHLET0, ionly = BC == EXPI_INTERIOR_ONLY;
-    const TC ihx = (TC)a.ih2[0], ihy = (TC)a.ih2[1], ihz = (TC)a.ih2[2];
+    // coefficient times 1/h^2 per axis, formed on the host (kernel
+    // arguments stay in scalar registers; products formed here would hold
+    // vector registers for the whole sweep)
     const TC alpha = (TC)a.alpha, beta1 = (TC)a.beta1, beta2 = (TC)a.beta2;
     const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2, sigma = (TC)a.sigma;
-    const TC c0 = (TC)a.c0, c1 = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1 : (TC)0;
-    const TC c0ihx = c0 * ihx, c0ihz = c0 * ihz, c1ihx = c1 * ihx;
+    const TC c0ihx = (TC)a.c0ih[0], c0ihz = (TC)a.c0ih[2];
+    const TC c1ihx = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[0] : (TC)0;
     // Row ends.  The x neighbour of a point at a row end is 0 under
     // Dirichlet and the point's own value otherwise (no flux), so that one
     // formula serves all points.  The first lane of a row has no left
@@ -319,7 +348,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         }
         // y data of the row, kept in LDS (read where used)
         if (lane == 0) {
-            const TC c0ihy = c0 * ihy, c1ihy = c1 * ihy;
+            const TC c0ihy = (TC)a.c0ih[1];
+            const TC c1ihy = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[1] : (TC)0;
+            const TC c1ihz = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[2] : (TC)0;
             const TC em = eym ? (TC)1 : (TC)0, eq = eyq ? (TC)1 : (TC)0;
             const TC dm = (eym || dir) ? (TC)1 : (TC)0, dq = (eyq || dir) ? (TC)1 : (TC)0;
             TC Y = 1, yfm = 1, yfq = 1;
@@ -336,22 +367,25 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             rw.ayq = eq * c0ihy;
             rw.ady = c0ihy * (dm + dq);
             rw.gdy = c1ihy * (dm * yfm + dq * yfq);
-            rw.hz = (c1 * ihz) * Y;
+            rw.hz = c1ihz * Y;
             rowdat[wv] = rw;
         }
 
         // Iteration k, for the planes of this segment (kst = kb - 2):
         //  (1) put w_j of plane k+2 (loaded two iterations ago) into the w_j
         //      ring and start the load of plane k+4;
-        //  (2) inner rows: w_{j+2} on plane k-1 from the w_{j+1} ring, then
-        //      start the load of p on plane k+1;
+        //  (2) inner rows: w_{j+2} on plane k-1 from the w_{j+1} ring; the
+        //      stores; then the load of p on plane k+1 (the first and last
+        //      rows load their extra row of w_j, plane k+4, instead);
         //  (3) w_{j+1} on plane k+1 from the w_j ring, into the w_{j+1} ring;
         //  (4) one barrier.
         // Both rings hold three planes; a wave's own row is read back only by
         // the wave itself, other rows only after the barrier that follows
         // their write.  Registers carry only the loads in flight: w_j of two
-        // planes in L (plane q in L[q & 1]) and p of two planes in P (the
-        // first and last rows carry their extra row of w_j there instead).
+        // planes in L (plane q in L[q & 1]) and p (or the extra row) of two
+        // planes in P.  Every wave issues the same global loads and stores
+        // on every path (clamped addresses, range-checked stores), so the
+        // in-order memory counter waits only for the load that is needed.
         const int kst = kb - 2;
         TC L[2][2], P[2][2];
         L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
@@ -379,19 +413,18 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         };
         {
             // planes kst and kst+1 of w_j into the ring; kst+2 and kst+3 in flight
-            TC h0[2] = {0, 0}, h1[2] = {0, 0}, e0[2] = {0, 0}, e1[2] = {0, 0};
-            if (yin) {
-                ld2(x, at(kst), h0);
-                ld2(x, at(kst + 1), h1);
-                ld2(x, at(kst + 2), L[0]);
-                ld2(x, at(kst + 3), L[1]);
-                if (hal) {
-                    ld2(x, at(kst) + hoff, e0);
-                    ld2(x, at(kst + 1) + hoff, e1);
-                    ld2(x, at(kst + 2) + hoff, P[0]);
-                    ld2(x, at(kst + 3) + hoff, P[1]);
-                }
-            }
+            // (rows outside the grid load a clamped row: finite values that
+            // no nonzero weight uses; the inner rows load their own row a
+            // second time where the outer rows load their extra row)
+            TC h0[2], h1[2], e0[2], e1[2];
+            ld2(x, at(kst), h0);
+            ld2(x, at(kst + 1), h1);
+            ld2(x, at(kst + 2), L[0]);
+            ld2(x, at(kst + 3), L[1]);
+            ld2(x, at(kst) + hoff, e0);
+            ld2(x, at(kst + 1) + hoff, e1);
+            ld2(x, at(kst + 2) + hoff, P[1]);   // put at iteration kst from P[1]
+            ld2(x, at(kst + 3) + hoff, P[0]);
             put(wslot_c(0), rr, h0);
             put(wslot_c(1), rr, h1);
             if (hal) {
@@ -415,16 +448,15 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 {
                     TC* wb = wslot_c(s + 2);
                     put(wb, rr, L[s & 1]);
-                    if (hal) put(wb, rh, P[s & 1]);
-                    if (yin && k + 4 <= ke + 1) {
-                        ld2(x, at(k + 4), L[s & 1]);
-                        if (hal) ld2(x, at(k + 4) + hoff, P[s & 1]);
-                    }
+                    if (hal) put(wb, rh, P[(s + 1) & 1]);   // loaded two iterations ago
+                    ld2(x, at(k + 4), L[s & 1]);
                 }
                 // (2) w_{j+2} on plane k-1 (inner rows)
                 const int kp = k - 1;
-                if (outw) {
-                    if (kp >= kb && kp < ke) {
+                const bool outp = outw && kp >= kb && kp < ke;
+                TC wo[2] = {0, 0}, po[2] = {0, 0};
+                {
+                    if (outp) {
                         const TC* vb = vslot_c(s + 2);        // plane k-1
                         TC wc[2], ym[2], yq[2], zm[2], zq[2];
                         get(vb, ry, wc);
@@ -444,7 +476,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             if (edge || lb) aw[0] = 0;
                             if (edge || rb) aw[1] = 0;
                         }
-                        TC wo[2], po[2];
                         const TC* pp = P[(s + 1) & 1];        // p (FIRST: r) of plane k-1
 #pragma unroll
                         for (int v = 0; v < 2; ++v) {
@@ -464,25 +495,18 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                                 s3 += (double)p2 * (double)p2;
                             }
                         }
-                        if (xin) {
-                            // streaming stores: measured faster in FP64,
-                            // slower in FP32
-                            const int idx = at(kp);
-                            if (sizeof(TW) == 8) {
-                                st2_stream(out, idx, wo);
-                                st2_stream(pv, idx, po);
-                            } else {
-                                st2(out, idx, wo);
-                                st2(pv, idx, po);
-                            }
-                        }
                     }
-                    // p of plane k+1 (used two iterations on, if it is an
-                    // output plane) into the slot just read
-                    if (k + 1 >= kb && k + 1 < ke) {
-                        if (FIRST) ld2(x, at(k + 1), P[(s + 1) & 1]);
-                        else if (!START) ld2(pv, at(k + 1), P[(s + 1) & 1]);
-                    }
+                    // the stores, on every path (dropped where there is no
+                    // output point); streaming: measured faster in FP64,
+                    // slower in FP32
+                    const int sidx = (outp && xin) ? at(kp) : -1;
+                    st2_buf<TW>(out_r, sidx, wo, sizeof(TW) == 8);
+                    st2_buf<TW>(pv_r, sidx, po, sizeof(TW) == 8);
+                    // into the slot just read: p (FIRST: r) of plane k+1,
+                    // used two iterations on; the outer rows load their
+                    // extra row of w_j, plane k+4
+                    const TW* psrc = (FIRST || START || hal) ? x : static_cast<const TW*>(pv);
+                    ld2(psrc, hal ? at(k + 4) + hoff : at(k + 1), P[(s + 1) & 1]);
                 }
                 // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
                 // grid are never used with a nonzero weight)
@@ -535,10 +559,7 @@ void go_bc(const PairGeom& g, int bc, const PairArgs& a, hipStream_t s) {
     const dim3 grid(g.grid), block(kPairWaves * 64);
     switch (bc) {
         case EXPI_DIRICHLET0:
-            // not built: that variant would need more than 128 VGPRs
-            // (pair_start_supported keeps it from being asked for)
-            if constexpr (!(MODE == PAIR_START && COEF == EXPI_COEF_SEPARABLE))
-                hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW, MODE>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pair_sweep<COEF, EXPI_DIRICHLET0, TW, MODE>), grid, block, 0, s, a);
             break;
         case EXPI_NEUMANN0:
             hipLaunchKernelGGL((pair_sweep<COEF, EXPI_NEUMANN0, TW, MODE>), grid, block, 0, s, a);
@@ -559,23 +580,20 @@ hipError_t go(const PairGeom& g, int coef, int bc, const PairArgs& a, hipStream_
 }  // namespace
 
 // Pair sweeps need a 3D stencil with a constant or separable coefficient,
-// rows of at most 256 points (even, for the two-point vector accesses), and
-// 16-byte aligned vectors.  (With float storage and the separable
-// coefficient one pair sweep takes about as long as two single products,
-// bound by its arithmetic; the Euler step still gains a few percent from
-// the fewer launches and stop tests.)
+// rows of at most 256 points (even, for the two-point vector accesses),
+// fewer than 2^28 points, and 16-byte aligned vectors.
 bool pair_supported(const Op& op, int tw) {
     (void)tw;
+    // the stores address a vector with 32-bit byte offsets: below 2^31
+    // bytes in FP64 (2^28 points)
     return op.kind == 0 && op.dim == 3 && op.n[0] % 2 == 0 && op.n[0] <= 256 &&
-           (op.coef == EXPI_COEF_CONST || op.coef == EXPI_COEF_SEPARABLE);
+           (op.coef == EXPI_COEF_CONST || op.coef == EXPI_COEF_SEPARABLE) &&
+           op.size * 8 < ((int64_t)1 << 31) - 64;
 }
 
 // The start vector fused into the first pair sweep (PAIR_START): FP64
-// storage, and not with the separable coefficient under Dirichlet
-// conditions, whose variant would spill registers.
-bool pair_start_supported(const Op& op) {
-    return pair_supported(op, 0) && !(op.coef == EXPI_COEF_SEPARABLE && op.bc == EXPI_DIRICHLET0);
-}
+// storage.
+bool pair_start_supported(const Op& op) { return pair_supported(op, 0); }
 
 PairGeom pair_geom(const Op& op, int cus) {
     PairGeom g{};
@@ -614,8 +632,10 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent
         a.ih2[d] = 1.0 / (op.h[d] * op.h[d]);
     }
     a.bc = op.bc;
-    a.c0 = op.c0;
-    a.c1 = op.c1;
+    for (int d = 0; d < 3; ++d) {
+        a.c0ih[d] = op.c0 * a.ih2[d];
+        a.c1ih[d] = op.c1 * a.ih2[d];
+    }
     a.tx = op.tx;
     a.ty = op.ty;
     a.tz = op.tz;
