@@ -102,7 +102,7 @@ __device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const ZPl
 template <int COEF, class TC>
 __device__ __forceinline__ void aw_pair(const TC (&wc)[2], TC wl, TC wr, const TC (&ym)[2],
                                         const TC (&yq)[2], const TC (&zm)[2], const TC (&zq)[2],
-                                        const PlaneW<TC>& w, TC c0ihx, const TC* xd, TC (&aw)[2]) {
+                                        const PlaneW<TC>& w, TC c0ihx, const TC (&xd)[5], TC (&aw)[2]) {
     // xd: X of the two points, face values left, between, right
     TC wxl, wxc, wxr, X[2] = {1, 1};
     if (COEF == EXPI_COEF_SEPARABLE) {
@@ -229,7 +229,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     if (a.guard && a.st->done != 0) return;
     __shared__ TC ring[3 * kPairLds];     // w_{j+1}: rows y0-1 .. y0+R of three planes
     __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
-    __shared__ TC xdat[2 * 64][6];
     __shared__ RowW<TC> rowdat[kPairWaves];
     // z data of the planes of the current segment: read where used through
     // LDS (a vector load there would make the in-order memory counter wait
@@ -274,22 +273,18 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     // wave, the lanes past the end offer the last point's value (or 0).
     const bool lb = ic == 0, rb = ic + 2 >= n0;
     const bool partial = (xq + 1) * 128 > n0;     // the row ends inside this wave
-    // x data of the lane in LDS: table values of its points, face values
-    // left of point 0, between the points and right of point 1 (own value
-    // where the row ends); reading them where they are used costs less than
-    // holding them in registers all along
+    // x data of the lane, in registers for the whole sweep: table values of
+    // its points, face values left of point 0, between the points and right
+    // of point 1 (own value where the row ends)
+    TC xd[5] = {1, 1, 1, 1, 1};
     if (COEF == EXPI_COEF_SEPARABLE) {
-        if (ry == 0) {
-            const TC X0 = (TC)a.tx[ic], X1 = (TC)a.tx[ic + 1];
-            TC* e = xdat[xq * 64 + lane];
-            e[0] = X0;
-            e[1] = X1;
-            e[2] = lb ? X0 : (TC)0.5 * ((TC)a.tx[ic - 1] + X0);
-            e[3] = (TC)0.5 * (X0 + X1);
-            e[4] = rb ? X1 : (TC)0.5 * (X1 + (TC)a.tx[ic + 2]);
-        }
+        const TC X0 = (TC)a.tx[ic], X1 = (TC)a.tx[ic + 1];
+        xd[0] = X0;
+        xd[1] = X1;
+        xd[2] = lb ? X0 : (TC)0.5 * ((TC)a.tx[max(ic - 1, 0)] + X0);
+        xd[3] = (TC)0.5 * (X0 + X1);
+        xd[4] = rb ? X1 : (TC)0.5 * (X1 + (TC)a.tx[min(ic + 2, n0 - 1)]);
     }
-    const TC* xd = xdat[xq * 64 + lane];
     // Dirichlet row ends: the edge lanes take in 0
     const bool ezero = dir && ((lane == 0 && lb) || (lane == 63 && rb));
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
