@@ -189,6 +189,17 @@ __device__ __forceinline__ void st2_buf(__amdgpu_buffer_rsrc_t r, int idx, const
     }
 }
 
+// A value that is the same in every lane, in scalar registers.
+__device__ __forceinline__ float uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Whole-wave shifts by one lane through DPP: lane l receives `src` of lane
 // l-1 (from_left) or l+1 (from_right); the lane without a source (0, resp.
 // 63) keeps `edge`.
@@ -229,7 +240,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     if (a.guard && a.st->done != 0) return;
     __shared__ TC ring[3 * kPairLds];     // w_{j+1}: rows y0-1 .. y0+R of three planes
     __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
-    __shared__ RowW<TC> rowdat[kPairWaves];
     // z data of the planes of the current segment: read where used through
     // LDS (a vector load there would make the in-order memory counter wait
     // for every prefetch issued before it)
@@ -341,8 +351,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 ztab[t] = z;
             }
         }
-        // y data of the row, kept in LDS (read where used)
-        if (lane == 0) {
+        // y data of the row: the same in every lane, moved to scalar
+        // registers for the march
+        RowW<TC> rw;
+        {
             const TC c0ihy = (TC)a.c0ih[1];
             const TC c1ihy = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[1] : (TC)0;
             const TC c1ihz = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[2] : (TC)0;
@@ -354,7 +366,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 yfm = eym ? (TC)0.5 * ((TC)a.ty[yc - 1] + Y) : Y;
                 yfq = eyq ? (TC)0.5 * ((TC)a.ty[yc + 1] + Y) : Y;
             }
-            RowW<TC> rw;
             rw.y = Y;
             rw.gym = em * (c1ihy * yfm);
             rw.gyq = eq * (c1ihy * yfq);
@@ -363,7 +374,14 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             rw.ady = c0ihy * (dm + dq);
             rw.gdy = c1ihy * (dm * yfm + dq * yfq);
             rw.hz = c1ihz * Y;
-            rowdat[wv] = rw;
+            rw.y = uniform(rw.y);
+            rw.gym = uniform(rw.gym);
+            rw.gyq = uniform(rw.gyq);
+            rw.aym = uniform(rw.aym);
+            rw.ayq = uniform(rw.ayq);
+            rw.ady = uniform(rw.ady);
+            rw.gdy = uniform(rw.gdy);
+            rw.hz = uniform(rw.hz);
         }
 
         // Iteration k, for the planes of this segment (kst = kb - 2):
@@ -428,7 +446,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             }
         }
         __syncthreads();   // x and row data, the first two ring planes
-        const RowW<TC>& rw = rowdat[wv];
         // a point of the outer layer has a zero row under interior_only
         const bool yedge = !(eym && eyq);
         for (int k0 = kst; k0 <= ke; k0 += 2) {
