@@ -461,7 +461,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     TC* wb = wslot_c(s + 2);
                     put(wb, rr, L[s & 1]);
                     if (hal) put(wb, rh, P[(s + 1) & 1]);   // loaded two iterations ago
-                    ld2(x, at(k + 4), L[s & 1]);
+                    // (planes past ke+1 feed no needed value: the last
+                    // needed one is loaded again, a cache hit)
+                    ld2(x, at(min(k + 4, ke + 1)), L[s & 1]);
                 }
                 // (2) w_{j+2} on plane k-1 (inner rows)
                 const int kp = k - 1;
@@ -518,7 +520,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     // used two iterations on; the outer rows load their
                     // extra row of w_j, plane k+4
                     const TW* psrc = (FIRST || START || hal) ? x : static_cast<const TW*>(pv);
-                    ld2(psrc, hal ? at(k + 4) + hoff : at(k + 1), P[(s + 1) & 1]);
+                    // (p outside the output planes: a neighbouring output
+                    // plane's p instead, a cache hit)
+                    ld2(psrc, hal ? at(min(k + 4, ke + 1)) + hoff : at(min(max(k + 1, kb), ke - 1)),
+                        P[(s + 1) & 1]);
                 }
                 // (3) w_{j+1} on plane k+1 (values of planes or rows outside the
                 // grid are never used with a nonzero weight)
