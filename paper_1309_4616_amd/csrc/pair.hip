@@ -401,6 +401,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         // in-order memory counter waits only for the load that is needed.
         const int kst = kb - 2;
         TC L[2][2], P[2][2];
+        TC Wm[2], Wc[2], Wq[2];   // the wave's own row of w_j: planes k, k+1, k+2
         L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
         // ring slot of a plane: (plane - kst) mod 3.  Within an unrolled
@@ -440,6 +441,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             ld2(x, at(kst + 3) + hoff, P[0]);
             put(wslot_c(0), rr, h0);
             put(wslot_c(1), rr, h1);
+            Wm[0] = h0[0];
+            Wm[1] = h0[1];
+            Wc[0] = h1[0];
+            Wc[1] = h1[1];
             if (hal) {
                 put(wslot_c(0), rh, e0);
                 put(wslot_c(1), rh, e1);
@@ -455,10 +460,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 // the last output plane ke-1 is done at k = ke; an odd count
                 // of iterations leaves nothing for the last one
                 if (k > ke) break;
-                // (1) w_j of plane k+2 into the ring, then load plane k+4
-                // (planes past ke+1 feed no needed value: not loaded)
+                // (1) w_j of plane k+2 into the ring (and the wave's own
+                // registers), then load plane k+4
                 {
                     TC* wb = wslot_c(s + 2);
+                    Wq[0] = L[s & 1][0];
+                    Wq[1] = L[s & 1][1];
                     put(wb, rr, L[s & 1]);
                     if (hal) put(wb, rh, P[(s + 1) & 1]);   // loaded two iterations ago
                     // (planes past ke+1 feed no needed value: the last
@@ -530,12 +537,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 {
                     const int q = k + 1;
                     const TC* wb = wslot_c(s + 1);
-                    TC wc[2], ym[2], yq[2], zm[2], zq[2];
-                    get(wb, rr, wc);
+                    // own row from registers: planes k, k+1, k+2
+                    const TC wc[2] = {Wc[0], Wc[1]}, zm[2] = {Wm[0], Wm[1]}, zq[2] = {Wq[0], Wq[1]};
+                    TC ym[2], yq[2];
                     get(wb, rr - 1, ym);
                     get(wb, rr + 1, yq);
-                    get(wslot_c(s), rr, zm);                  // plane k
-                    get(wslot_c(s + 2), rr, zq);              // plane k+2
                     const TC el = wb[rr * RW + (ic > 0 ? ic - 1 : ic)];
                     const TC er = wb[rr * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                     TC left, right;
@@ -554,6 +560,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         r[v] = START ? (TC)(TW)(sigma * aw[v] + (wc[v] - wc[v] * wc[v] * wc[v]))
                                      : (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
                     put(vslot_c(s + 1), ry, r);
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        Wm[v] = Wc[v];
+                        Wc[v] = Wq[v];
+                    }
                 }
                 __syncthreads();
             }
