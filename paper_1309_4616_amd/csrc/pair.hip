@@ -402,6 +402,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         const int kst = kb - 2;
         TC L[2][2], P[2][2];
         TC Wm[2], Wc[2], Wq[2];   // the wave's own row of w_j: planes k, k+1, k+2
+        // FP32 (registers to spare): the own row of w_{j+1} too, planes
+        // k, k-1, k-2 (values from the rings' zero fill before the first)
+        constexpr bool kOwnW1 = sizeof(TW) == 4;
+        TC Q0[2] = {0, 0}, Q1[2] = {0, 0}, Q2[2] = {0, 0};
         L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
         // ring slot of a plane: (plane - kst) mod 3.  Within an unrolled
@@ -480,11 +484,20 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     if (outp) {
                         const TC* vb = vslot_c(s + 2);        // plane k-1
                         TC wc[2], ym[2], yq[2], zm[2], zq[2];
-                        get(vb, ry, wc);
+                        if constexpr (kOwnW1) {               // own row from registers
+#pragma unroll
+                            for (int v = 0; v < 2; ++v) {
+                                wc[v] = Q1[v];
+                                zm[v] = Q2[v];
+                                zq[v] = Q0[v];
+                            }
+                        } else {
+                            get(vb, ry, wc);
+                            get(vslot_c(s + 1), ry, zm);      // plane k-2
+                            get(vslot_c(s), ry, zq);          // plane k
+                        }
                         get(vb, ry - 1, ym);
                         get(vb, ry + 1, yq);
-                        get(vslot_c(s + 1), ry, zm);          // plane k-2
-                        get(vslot_c(s), ry, zq);              // plane k
                         const TC el = vb[ry * RW + (ic > 0 ? ic - 1 : ic)];
                         const TC er = vb[ry * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                         TC left, right;
@@ -564,6 +577,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     for (int v = 0; v < 2; ++v) {
                         Wm[v] = Wc[v];
                         Wc[v] = Wq[v];
+                        if constexpr (kOwnW1) {
+                            Q2[v] = Q1[v];
+                            Q1[v] = Q0[v];
+                            Q0[v] = r[v];
+                        }
                     }
                 }
                 __syncthreads();
