@@ -184,6 +184,7 @@ struct Op {
 
 constexpr int kXcd = 8;          // XCDs of gfx950; workgroup b runs on XCD b % 8
 constexpr int kMaxWaves = 8;     // waves per workgroup at most (512 threads)
+constexpr int kFinalThreads = 256;   // threads of a finalize workgroup
 constexpr int kMinMarch = 4;     // accepted march lengths of a stencil sweep (multiples of 4)
 constexpr int kMaxMarch = 120;  // the marched-axis table of a separable coefficient holds 128 planes
 constexpr int kCsrGrid = 2048;   // workgroups of a CSR sweep at most (grid-stride over row blocks)

@@ -237,18 +237,19 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
     constexpr bool FIRST = MODE == PAIR_FIRST, START = MODE == PAIR_START;
     typedef TC TC2 __attribute__((ext_vector_type(2)));
-    if (a.guard && a.st->done != 0) return;
+    // the status flag (the loop has stopped: do nothing) is looked at only
+    // at the first barrier, so its load overlaps the first plane loads
+    // (a.st is always a valid state record).  A buffer load: a scalar load
+    // would be waited for with the first kernel-argument load after it.
+    const __amdgpu_buffer_rsrc_t st_r =
+        __builtin_amdgcn_make_buffer_rsrc(a.st, 0, (int)sizeof(NewtonState), 0x00020000);
+    const int done_v = (int)__builtin_amdgcn_raw_buffer_load_b32(st_r, (int)offsetof(NewtonState, done), 0, 0);
     __shared__ TC ring[3 * kPairLds];     // w_{j+1}: rows y0-1 .. y0+R of three planes
     __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
     // z data of the planes of the current segment: read where used through
     // LDS (a vector load there would make the in-order memory counter wait
     // for every prefetch issued before it)
     __shared__ ZPlane<TC> ztab[kZSeg + 8];
-    // every ring entry holds a finite value before it is read; the barrier
-    // keeps a slow wave's fill from landing on a fast wave's first writes
-    for (int t = threadIdx.x; t < 3 * kPairLds; t += blockDim.x) ring[t] = 0;
-    for (int t = threadIdx.x; t < 3 * kWRingLds; t += blockDim.x) wring[t] = 0;
-    __syncthreads();
     const TW* __restrict__ x = static_cast<const TW*>(a.x);
     TW* __restrict__ out = static_cast<TW*>(a.out);
     TW* __restrict__ pv = static_cast<TW*>(a.p);
@@ -288,13 +289,21 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     // of point 1 (own value where the row ends)
     TC xd[5] = {1, 1, 1, 1, 1};
     if (COEF == EXPI_COEF_SEPARABLE) {
+        // four loads issued together (clamped, none behind a branch)
         const TC X0 = (TC)a.tx[ic], X1 = (TC)a.tx[ic + 1];
+        const TC Xm = (TC)a.tx[max(ic - 1, 0)], Xq = (TC)a.tx[min(ic + 2, n0 - 1)];
         xd[0] = X0;
         xd[1] = X1;
-        xd[2] = lb ? X0 : (TC)0.5 * ((TC)a.tx[max(ic - 1, 0)] + X0);
+        xd[2] = lb ? X0 : (TC)0.5 * (Xm + X0);
         xd[3] = (TC)0.5 * (X0 + X1);
-        xd[4] = rb ? X1 : (TC)0.5 * (X1 + (TC)a.tx[min(ic + 2, n0 - 1)]);
+        xd[4] = rb ? X1 : (TC)0.5 * (X1 + Xq);
     }
+    // (after the loads above are on their way) every ring entry holds a
+    // finite value before it is read; the barrier keeps a slow wave's fill
+    // from landing on a fast wave's first writes
+    for (int t = threadIdx.x; t < 3 * kPairLds; t += blockDim.x) ring[t] = 0;
+    for (int t = threadIdx.x; t < 3 * kWRingLds; t += blockDim.x) wring[t] = 0;
+    __syncthreads();
     // Dirichlet row ends: the edge lanes take in 0
     const bool ezero = dir && ((lane == 0 && lb) || (lane == 63 && rb));
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -340,9 +349,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 const int q = kb - 2 + t;
                 const bool ezm = q > 0, ezq = q < n2 - 1;
                 const TC dm = (ezm || dir) ? (TC)1 : (TC)0, dq = (ezq || dir) ? (TC)1 : (TC)0;
+                // three loads issued together (clamped, none behind a branch)
                 const TC zc = (TC)a.tz[min(max(q, 0), n2 - 1)];
-                const TC zfm = ezm ? (TC)0.5 * ((TC)a.tz[min(max(q - 1, 0), n2 - 1)] + zc) : zc;
-                const TC zfq = ezq ? (TC)0.5 * ((TC)a.tz[min(max(q + 1, 0), n2 - 1)] + zc) : zc;
+                const TC zm = (TC)a.tz[min(max(q - 1, 0), n2 - 1)];
+                const TC zq = (TC)a.tz[min(max(q + 1, 0), n2 - 1)];
+                const TC zfm = ezm ? (TC)0.5 * (zm + zc) : zc;
+                const TC zfq = ezq ? (TC)0.5 * (zq + zc) : zc;
                 ZPlane<TC> z;
                 z.zc = zc;
                 z.zfm = ezm ? zfm : (TC)0;
@@ -363,8 +375,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             TC Y = 1, yfm = 1, yfq = 1;
             if (COEF == EXPI_COEF_SEPARABLE) {
                 Y = (TC)a.ty[yc];
-                yfm = eym ? (TC)0.5 * ((TC)a.ty[yc - 1] + Y) : Y;
-                yfq = eyq ? (TC)0.5 * ((TC)a.ty[yc + 1] + Y) : Y;
+                const TC Ym = (TC)a.ty[max(yc - 1, 0)], Yq = (TC)a.ty[min(yc + 1, n1 - 1)];
+                yfm = eym ? (TC)0.5 * (Ym + Y) : Y;
+                yfq = eyq ? (TC)0.5 * (Yq + Y) : Y;
             }
             rw.y = Y;
             rw.gym = em * (c1ihy * yfm);
@@ -454,6 +467,8 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 put(wslot_c(1), rh, e1);
             }
         }
+        if (a.guard && __builtin_amdgcn_readfirstlane(done_v) != 0)
+            return;   // the same in every thread; nothing stored yet
         __syncthreads();   // x and row data, the first two ring planes
         // a point of the outer layer has a zero row under interior_only
         const bool yedge = !(eym && eyq);
@@ -589,6 +604,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             b3 = b3 == 0 ? 2 : b3 - 1;   // + 2 mod 3
         }
     }
+    if (a.guard && __builtin_amdgcn_readfirstlane(done_v) != 0) return;   // a workgroup without a unit
     if (FIRST) {
         // ||p_1|| is not formed: a non-finite p_1 makes p_2 non-finite,
         // which the test at m = 2 reports; the slot holds 0

@@ -26,10 +26,13 @@ namespace expi {
 namespace {
 
 template <int EPI>
-__global__ __launch_bounds__(256) void finalize_kernel(FinalArgs f) {
+__global__ __launch_bounds__(kFinalThreads) void finalize_kernel(FinalArgs f) {
     __shared__ double red[kMaxWaves][3];
     NewtonState* st = f.st;
-    if (f.guard && st->done != 0) return;
+    // every load goes out before the status flag is looked at: the flag,
+    // the partials and the previous term arrive in one memory round trip
+    const int done_in = st->done;
+    const double tprev_in = st->t_prev;
     double s0, s1, s2 = 0.0;
     if (EPI == EPI_GERSH) {
         s0 = INFINITY;
@@ -38,7 +41,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs f) {
         s0 = 0.0;
         s1 = 0.0;
     }
-    for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
+    for (int b = threadIdx.x; b < f.nparts; b += kFinalThreads) {
         const double* part = f.partials + 4 * (size_t)b;
         if (EPI == EPI_GERSH) {
             s0 = fmin(s0, part[0]);
@@ -49,6 +52,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs f) {
             s2 += part[2];
         }
     }
+    if (f.guard && done_in != 0) return;   // the same in every thread
     block_combine<EPI>(s0, s1, s2, red);
     if (threadIdx.x != 0) return;
     if (EPI == EPI_GERSH) {
@@ -58,7 +62,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs f) {
     }
     const double wn = sqrt(s1), pn = sqrt(s2);
     const double t = fabs(f.d1) * wn;
-    const double tprev = (EPI == EPI_FIRST) ? fabs(f.d0) * sqrt(s0) : st->t_prev;
+    const double tprev = (EPI == EPI_FIRST) ? fabs(f.d0) * sqrt(s0) : tprev_in;
     const int m = f.j + 1;
     const double num = tprev + t;
     const double err = (pn > 0.0) ? num / pn : (num == 0.0 ? 0.0 : INFINITY);
@@ -117,10 +121,7 @@ __global__ __launch_bounds__(256) void update_st_kernel(int64_t n, double* out, 
 }
 
 // Stop tests after a pair sweep (pair_tests) as a kernel of its own.
-__global__ __launch_bounds__(256) void pair_finalize_kernel(FinalArgs f) {
-    if (f.guard && f.st->done != 0) return;
-    pair_tests(f);
-}
+__global__ __launch_bounds__(kFinalThreads) void pair_finalize_kernel(FinalArgs f) { pair_tests(f); }
 
 __global__ void reset_kernel(NewtonState* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -276,9 +277,9 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
     f.tol = a.tol;
     f.j = a.j;
     f.guard = a.guard;
-    if (epi == EPI_NEWTON) hipLaunchKernelGGL(finalize_kernel<EPI_NEWTON>, dim3(1), dim3(256), 0, s, f);
-    else if (epi == EPI_FIRST) hipLaunchKernelGGL(finalize_kernel<EPI_FIRST>, dim3(1), dim3(256), 0, s, f);
-    else hipLaunchKernelGGL(finalize_kernel<EPI_GERSH>, dim3(1), dim3(256), 0, s, f);
+    if (epi == EPI_NEWTON) hipLaunchKernelGGL(finalize_kernel<EPI_NEWTON>, dim3(1), dim3(kFinalThreads), 0, s, f);
+    else if (epi == EPI_FIRST) hipLaunchKernelGGL(finalize_kernel<EPI_FIRST>, dim3(1), dim3(kFinalThreads), 0, s, f);
+    else hipLaunchKernelGGL(finalize_kernel<EPI_GERSH>, dim3(1), dim3(kFinalThreads), 0, s, f);
     return hipGetLastError();
 }
 
@@ -332,7 +333,7 @@ hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int npa
     f.d1 = d1;
     f.d2 = d2;
     f.tol = tol;
-    hipLaunchKernelGGL(pair_finalize_kernel, dim3(1), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(pair_finalize_kernel, dim3(1), dim3(kFinalThreads), 0, s, f);
     return hipGetLastError();
 }
 

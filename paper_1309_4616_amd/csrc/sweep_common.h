@@ -116,19 +116,32 @@ __device__ __forceinline__ void finish_sweep_n(double* partials, int stride, con
 // first slot: its two tests are those at m = 0 and m = 1 and it records
 // ||r||.
 //
-// Called by every thread of one workgroup (up to kMaxPairWaves waves).
+// Called by every thread of one workgroup of kFinalThreads threads.
+// With f.guard, nothing happens once the state says the loop has stopped;
+// the flag, the partials and the previous term are all loaded before the
+// flag is looked at, so the three reads cost one memory round trip.
 __device__ inline void pair_tests(const FinalArgs& f) {
-    __shared__ double red[kMaxPairWaves][5];
+    __shared__ double red[kFinalThreads / 64][5];
     NewtonState* st = f.st;
     const bool first = f.mode == PAIR_FIRST;
     const int nq = first ? 5 : 4, stride = first ? 8 : 4;
+    const int done_in = st->done;
+    double tprev = st->t_prev;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < f.nparts; b += blockDim.x) {
+    for (int b = threadIdx.x; b < f.nparts; b += kFinalThreads) {
+        // all five loads at once (the fifth repeats the first where there
+        // are four partials)
         const double* part = f.partials + stride * (size_t)b;
-        for (int q = 0; q < nq; ++q) s[q] += part[q];
+        double v[5];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = part[q];
+        v[4] = part[nq == 5 ? 4 : 0];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s[q] += q < nq ? v[q] : 0.0;
     }
+    if (f.guard && done_in != 0) return;   // the same in every thread
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
+    constexpr int nw = kFinalThreads / 64;
     for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
     if (lane == 0)
         for (int q = 0; q < 5; ++q) red[wv][q] = s[q];
@@ -138,7 +151,6 @@ __device__ inline void pair_tests(const FinalArgs& f) {
         s[q] = red[0][q];
         for (int w = 1; w < nw; ++w) s[q] += red[w][q];
     }
-    double tprev = st->t_prev;
     if (f.mode == PAIR_START) st->rnorm = sqrt(s[0]);
     if (first) {
         tprev = fabs(f.d0) * sqrt(s[0]);
