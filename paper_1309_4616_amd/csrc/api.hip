@@ -83,6 +83,7 @@ constexpr int kSlots = 64;
 struct HostCtx {
     int device = -1;
     NewtonState* pinned = nullptr;
+    NewtonState* pinned_dev = nullptr;   // device address of `pinned`
     hipEvent_t ev[kSlots];
     bool inflight[kSlots];
     int next = 0;
@@ -95,7 +96,9 @@ int ctx_init() {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (tl_ctx.device == dev && tl_ctx.pinned) return EXPI_OK;
-    HIP_TRY(hipHostMalloc((void**)&tl_ctx.pinned, kSlots * sizeof(NewtonState), hipHostMallocDefault));
+    // coherent: the finalize kernels write the slots directly
+    HIP_TRY(hipHostMalloc((void**)&tl_ctx.pinned, kSlots * sizeof(NewtonState), hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer((void**)&tl_ctx.pinned_dev, tl_ctx.pinned, 0));
     for (int i = 0; i < kSlots; ++i) {
         HIP_TRY(hipEventCreateWithFlags(&tl_ctx.ev[i], hipEventDisableTiming));
         tl_ctx.inflight[i] = false;
@@ -113,13 +116,22 @@ int timing_events() {
     return EXPI_OK;
 }
 
-int readback(const NewtonState* st, hipStream_t s, int* slot_out) {
+// The next free slot (waits for its previous use to end).
+int reserve_slot(int* slot_out) {
     const int slot = tl_ctx.next;
     tl_ctx.next = (tl_ctx.next + 1) % kSlots;
     if (tl_ctx.inflight[slot]) {
         HIP_TRY(hipEventSynchronize(tl_ctx.ev[slot]));
         tl_ctx.inflight[slot] = false;
     }
+    *slot_out = slot;
+    return EXPI_OK;
+}
+
+int readback(const NewtonState* st, hipStream_t s, int* slot_out) {
+    int slot;
+    int rc = reserve_slot(&slot);
+    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(&tl_ctx.pinned[slot], st, sizeof(NewtonState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(tl_ctx.ev[slot], s));
     tl_ctx.inflight[slot] = true;
@@ -127,10 +139,31 @@ int readback(const NewtonState* st, hipStream_t s, int* slot_out) {
     return EXPI_OK;
 }
 
-int wait_slot(int slot, NewtonState* out) {
+// A batch whose last finalize kernel writes the state into a slot (device
+// address tl_ctx.pinned_dev + slot): the slot is marked (done = -1, a value
+// no kernel writes) before the launches and an event follows them.  A slot
+// still marked when it is read (no finalize ran) is filled by a plain copy
+// (wait_slot).
+int mirror_begin(int* slot_out) {
+    int slot;
+    int rc = reserve_slot(&slot);
+    if (rc) return rc;
+    tl_ctx.pinned[slot].done = -1;
+    *slot_out = slot;
+    return EXPI_OK;
+}
+
+int mirror_end(int slot, hipStream_t s) {
+    HIP_TRY(hipEventRecord(tl_ctx.ev[slot], s));
+    tl_ctx.inflight[slot] = true;
+    return EXPI_OK;
+}
+
+int wait_slot(int slot, NewtonState* out, const NewtonState* st = nullptr) {
     HIP_TRY(hipEventSynchronize(tl_ctx.ev[slot]));
     tl_ctx.inflight[slot] = false;
     std::memcpy(out, &tl_ctx.pinned[slot], sizeof(NewtonState));
+    if (out->done == -1 && st) HIP_TRY(hipMemcpy(out, st, sizeof(NewtonState), hipMemcpyDeviceToHost));
     return EXPI_OK;
 }
 
@@ -428,18 +461,22 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         if (fin) finalized += 2;
         return EXPI_OK;
     };
-    // `count` products from j on (pairs where allowed), advancing j
-    auto advance = [&](int& j, int count, bool fin) -> int {
+    // `count` products from j on (pairs where allowed), advancing j; the
+    // finalize of the last launch writes the state into `mirror` if given
+    auto advance = [&](int& j, int count, bool fin, NewtonState* mirror = nullptr) -> int {
         const int end = j + count;
         while (j < end) {
             int rc;
-            if (C.pairs && end - j >= 2) {
+            const bool two = C.pairs && end - j >= 2;
+            if (j + (two ? 2 : 1) == end) set_state_mirror(mirror);
+            if (two) {
                 rc = pair(j, fin);
                 j += 2;
             } else {
                 rc = single(j, fin);
                 j += 1;
             }
+            set_state_mirror(nullptr);
             if (rc) return rc;
         }
         return EXPI_OK;
@@ -505,10 +542,12 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         while (!finished) {
             if (j < C.m_max) {
                 const int cnt = std::min(chunk, C.m_max - j);
-                int rc = advance(j, cnt, true);
-                if (rc) return rc;
                 int slot;
-                rc = readback(C.st, C.s, &slot);
+                int rc = mirror_begin(&slot);
+                if (rc) return rc;
+                rc = advance(j, cnt, true, tl_ctx.pinned_dev + slot);
+                if (rc) return rc;
+                rc = mirror_end(slot, C.s);
                 if (rc) return rc;
                 pending.push_back(slot);
                 if (spec && !ahead) HIP_TRY((*spec)());
@@ -516,7 +555,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
             }
             const size_t keep = ahead ? 1 : 0;
             while (!pending.empty() && (pending.size() > keep || j >= C.m_max)) {
-                int rc = wait_slot(pending.front(), &last);
+                int rc = wait_slot(pending.front(), &last, C.st);
                 if (rc) return rc;
                 pending.pop_front();
                 if (last.done) {

@@ -132,7 +132,15 @@ struct FinalArgs {
     int outbuf;           // pair sweeps: index of the w buffer the sweep writes
     double d0, d1, tol;
     double d2;            // pair sweeps: d_{j+2}
+    NewtonState* mirror;  // device address of a host copy of the state, written
+                          // after the tests (null: none)
 };
+
+// Host copy of the state that the finalize kernels enqueued next by this
+// host thread write after their tests (null: none).  The host sets it around
+// a batch of launches and reads the copy after an event that follows them,
+// which takes the place of a device-to-host copy of the record.
+void set_state_mirror(NewtonState* mirror);
 
 // Step-selector network (mlp.hip): predicted (substeps, degree) from the
 // interval, tau, ||r|| and t_0..t_4 in `st`; written to st->pred_s/pred_m.

@@ -25,8 +25,21 @@
 namespace expi {
 namespace {
 
+// The whole record to the host copy (thread 0, after its own writes).
+__device__ __forceinline__ void mirror_state(const FinalArgs& f) {
+    if (f.mirror == nullptr || threadIdx.x != 0) return;
+    const unsigned long long* from = reinterpret_cast<const unsigned long long*>(f.st);
+    unsigned long long* to = reinterpret_cast<unsigned long long*>(f.mirror);
+    constexpr int kWords = (int)(sizeof(NewtonState) / 8);
+    unsigned long long v[kWords];   // all loads, then all stores (one round trip)
+#pragma unroll
+    for (int q = 0; q < kWords; ++q) v[q] = from[q];
+#pragma unroll
+    for (int q = 0; q < kWords; ++q) to[q] = v[q];
+}
+
 template <int EPI>
-__global__ __launch_bounds__(kFinalThreads) void finalize_kernel(FinalArgs f) {
+__device__ void finalize_tests(const FinalArgs& f) {
     __shared__ double red[kMaxWaves][3];
     NewtonState* st = f.st;
     // every load goes out before the status flag is looked at: the flag,
@@ -82,6 +95,12 @@ __global__ __launch_bounds__(kFinalThreads) void finalize_kernel(FinalArgs f) {
     if (m < kHist) st->hist[m] = t;
 }
 
+template <int EPI>
+__global__ __launch_bounds__(kFinalThreads) void finalize_kernel(FinalArgs f) {
+    finalize_tests<EPI>(f);
+    mirror_state(f);
+}
+
 // out = yin + scale * p (yin may be NULL for 0).  After a pair sweep that
 // met the stop test at its first product, p holds one term too many:
 // p - fix * wfix removes d_{m+1} w_{m+1} (wfix NULL otherwise).
@@ -121,7 +140,10 @@ __global__ __launch_bounds__(256) void update_st_kernel(int64_t n, double* out, 
 }
 
 // Stop tests after a pair sweep (pair_tests) as a kernel of its own.
-__global__ __launch_bounds__(kFinalThreads) void pair_finalize_kernel(FinalArgs f) { pair_tests(f); }
+__global__ __launch_bounds__(kFinalThreads) void pair_finalize_kernel(FinalArgs f) {
+    pair_tests(f);
+    mirror_state(f);
+}
 
 __global__ void reset_kernel(NewtonState* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -153,7 +175,11 @@ __global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ out, int64_t 
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+thread_local NewtonState* tl_mirror = nullptr;
+
 }  // namespace
+
+void set_state_mirror(NewtonState* mirror) { tl_mirror = mirror; }
 
 Geom make_geom(const Op& op, const Tiles& t) {
     Geom g{};
@@ -268,7 +294,8 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
     }
     if (epi != EPI_NEWTON && epi != EPI_FIRST && epi != EPI_GERSH) return hipSuccess;
     if (!finalize) return hipSuccess;
-    FinalArgs f;
+    FinalArgs f{};
+    f.mirror = tl_mirror;
     f.partials = a.partials;
     f.st = a.st;
     f.nparts = g.grid;
@@ -322,6 +349,7 @@ hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int npa
                                 int guard, double d0, double d1, double d2, double tol, int mode,
                                 int outbuf, hipStream_t s) {
     FinalArgs f{};
+    f.mirror = tl_mirror;
     f.partials = partials;
     f.st = st;
     f.nparts = nparts;
