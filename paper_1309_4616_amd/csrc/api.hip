@@ -111,7 +111,10 @@ int ctx_init() {
 
 int timing_events() {
     if (tl_ctx.have_tev) return EXPI_OK;
-    for (int i = 0; i < 2 * kMaxLeja; ++i) HIP_TRY(hipEventCreate(&tl_ctx.tev[i]));
+    // timing only: no system-scope fence (cache writeback and invalidate)
+    // at each record, which would slow the work that follows it
+    for (int i = 0; i < 2 * kMaxLeja; ++i)
+        HIP_TRY(hipEventCreateWithFlags(&tl_ctx.tev[i], hipEventDisableSystemFence));
     tl_ctx.have_tev = true;
     return EXPI_OK;
 }
@@ -999,9 +1002,9 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
     // deterministic data in w0 and p; w1 is written by the sweep
     HIP_TRY(launch_fill(w + L.w0, o.size, tw, 1.0, s));
     HIP_TRY(launch_fill(w + L.p, o.size, tw, 0.5, s));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    hipEvent_t e0, e1;   // timing only (no system-scope fence)
+    HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     SweepArgs a{};
     a.x = w + L.w0;
     a.out = w + L.w1;
