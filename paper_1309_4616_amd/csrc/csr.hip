@@ -29,12 +29,28 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
     // workgroups of one XCD take a contiguous run of rows (the gathered
     // entries of neighbouring rows then meet in that XCD's L2), and the grid
     // stays small enough for a short finalize
-    for (int L = xcd_tile(a.per_xcd); L < a.ntiles; L += gridDim.x) {
+    // each pass loads the next pass's row pointers ahead of its own entries
+    // (clamped to a row that exists, unconditionally), so that they are not
+    // a memory round trip of their own at the head of every pass
+    const int nrow = a.n[0];
+    int L = xcd_tile(a.per_xcd);
+    int pa = 0, pb = 0;
+    if (nrow > 0) {
+        const int r = min(L * rows_per + g, nrow - 1);
+        pa = a.rowptr[r];
+        pb = a.rowptr[r + 1];
+    }
+    for (; L < a.ntiles; L += gridDim.x) {
     const int row = L * rows_per + g;
-    if (row < a.n[0]) {
-        // row range clamped to [0, nnz) and column indices checked against
-        // n, so a malformed matrix cannot send a load out of bounds
-        const int e0 = max(a.rowptr[row], 0), e1 = min(a.rowptr[row + 1], a.nnz);
+    // row range clamped to [0, nnz) and column indices checked against n, so
+    // a malformed matrix cannot send a load out of bounds
+    const int e0 = max(pa, 0), e1 = min(pb, a.nnz);
+    {
+        const int rn = min(min(L + (int)gridDim.x, a.ntiles - 1) * rows_per + g, nrow - 1);
+        pa = a.rowptr[rn];
+        pb = a.rowptr[rn + 1];
+    }
+    if (row < nrow) {
         const unsigned nrows = (unsigned)a.n[0];
         if (EPI == EPI_GERSH) {
             double dg = 0.0, off = 0.0;
