@@ -50,8 +50,55 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
         pa = a.rowptr[rn];
         pb = a.rowptr[rn + 1];
     }
+    const unsigned nrows = (unsigned)nrow;
+    // Products of the wave's rows (contiguous entries [wb, we)), staged in
+    // LDS: every lane of the wave takes consecutive entries, so each index,
+    // value and gather instruction covers 64 consecutive entries; the G
+    // lanes of a row then sum its products from LDS.  Entries past the
+    // first kStage of the wave are taken directly by the row's lanes.
+    TC acc = 0;
+    if (EPI != EPI_GERSH) {
+        constexpr int kStage = 2048 / G;   // 32 entries per row of the wave
+        __shared__ TC stage[kMaxWaves][kStage];
+        TC* st = stage[threadIdx.x >> 6];
+        const int lane = threadIdx.x & 63;
+        const int wb = __shfl(e0, 0), we = __shfl(e1, 63);
+        const int lastw = max(we - 1, 0);
+        const bool any = a.nnz > 0;   // an empty matrix may come without arrays
+        constexpr int kQ = kStage / 64;
+        int col[kQ];
+        TC vv[kQ], xv[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int e = min(wb + lane + 64 * q, lastw);   // clamped: no branch
+            col[q] = any ? a.colind[e] : 0;
+            vv[q] = any ? (TC)a.val[e] : (TC)0;
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const bool ok = (wb + lane + 64 * q < we) && ((unsigned)col[q] < nrows);
+            xv[q] = (TC)x[ok ? col[q] : 0];
+            st[lane + 64 * q] = ok ? vv[q] * xv[q] : (TC)0;
+        }
+        // the same wave reads what it wrote: LDS operations of a wave
+        // complete in order; the fences keep the compiler from moving them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (row < nrow) {
+            const int lo = max(e0 - wb, 0), hi = min(e1 - wb, kStage);
+            for (int i = lo + sub; i < hi; i += G) acc += st[i];
+            for (int e = max(e0, wb + kStage) + sub; e < e1; e += G) {
+                const int c = a.colind[e];
+                if ((unsigned)c < nrows) acc += (TC)a.val[e] * (TC)x[c];
+            }
+        }
+        // no wave rewrites its stage before all its lanes have read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     if (row < nrow) {
-        const unsigned nrows = (unsigned)a.n[0];
         if (EPI == EPI_GERSH) {
             double dg = 0.0, off = 0.0;
             for (int e = e0 + sub; e < e1; e += G) {
@@ -68,34 +115,6 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
                 s1 = fmax(s1, dg + off);
             }
         } else {
-            // first kBatch entries of the lane: all index and value loads,
-            // then all gathers, then the sums (three independent waves of
-            // memory traffic instead of a load -> gather chain per entry);
-            // indices are clamped so the loads need no branches
-            TC acc = 0;
-            constexpr int kBatch = 4;
-            int col[kBatch];
-            TC vv[kBatch], xv[kBatch];
-            const int last = max(e1 - 1, 0);
-            const bool any = a.nnz > 0;   // an empty matrix may come without arrays
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                const int e = min(e0 + sub + q * G, last);
-                col[q] = any ? a.colind[e] : row;
-                vv[q] = any ? (TC)a.val[e] : (TC)0;
-            }
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                const bool ok = (e0 + sub + q * G < e1) && ((unsigned)col[q] < nrows);
-                xv[q] = (TC)x[ok ? col[q] : row];
-                if (!ok) vv[q] = 0;
-            }
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) acc += vv[q] * xv[q];
-            for (int e = e0 + sub + kBatch * G; e < e1; e += G) {
-                const int c = a.colind[e];
-                if ((unsigned)c < nrows) acc += (TC)a.val[e] * (TC)x[c];
-            }
 #pragma unroll
             for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
             if (sub == 0) {
