@@ -75,6 +75,11 @@ hipError_t dispatch(const Geom& g, int epi, int tin, int tout, const SweepArgs& 
             if (tin == 1 && tout == 1) return go<DIM, COEF, EPI_FIRST, float, float>(g, a, s);
             break;
         case EPI_START:
+            if (a.gmode == G_CUBIC_SELF) {
+                if (tin == 0 && tout == 0) return go<DIM, COEF, EPI_START_SELF, double, double>(g, a, s);
+                if (tin == 0 && tout == 1) return go<DIM, COEF, EPI_START_SELF, double, float>(g, a, s);
+                break;
+            }
             if (tin == 0 && tout == 0) return go<DIM, COEF, EPI_START, double, double>(g, a, s);
             if (tin == 0 && tout == 1) return go<DIM, COEF, EPI_START, double, float>(g, a, s);
             break;

@@ -329,6 +329,8 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                                         s0 += (double)w_c * (double)w_c;
                                         s1 += (double)wn_ * (double)wn_;
                                         s2 += (double)pn_ * (double)pn_;
+                                    } else if (EPI == EPI_START_SELF) {
+                                        wo[v] = sigma * Aw + (w_c - w_c * w_c * w_c);
                                     } else if (EPI == EPI_START) {
                                         TC gv;
                                         if (a.gmode == G_VEC) {
