@@ -48,9 +48,6 @@ enum Epilogue : int {
     EPI_FIRST = 2,   // w' = alpha A w + beta w; p = d0 w + d1 w'; norms
     EPI_START = 3,   // r = sigma A x + g
     EPI_GERSH = 4,   // per-row Gershgorin bounds, min/max over rows
-    // EPI_START with g = x - x^3 as a kernel of its own (no g operand, so no
-    // load inside the march); chosen by the stencil launcher
-    EPI_START_SELF = 5,
 };
 
 // Source of g in EPI_START.

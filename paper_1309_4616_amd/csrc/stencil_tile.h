@@ -6,6 +6,11 @@
 #include "sweep_common.h"
 
 namespace expi {
+// EPI_START with g = x - x^3 as a stencil kernel of its own (no g operand,
+// so no load inside the march); chosen by the stencil launcher for
+// G_CUBIC_SELF
+constexpr int EPI_START_SELF = 5;
+
 namespace tile {
 
 template <int V, class T, class TC>
