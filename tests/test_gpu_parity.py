@@ -325,6 +325,29 @@ def test_csr_apply_and_interval(E):
     assert a == ao and b == bo
 
 
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_csr_uneven_rows_apply(E, lanes):
+    """Rows of 0, 1..40 and 300 stored entries (duplicate columns allowed):
+    empty rows, waves whose entries run past the LDS stage into the direct
+    tail, and a ragged last row block, for each lane count."""
+    rng = np.random.default_rng(11)
+    n = 5003
+    deg = rng.integers(1, 41, size=n)
+    deg[::97] = 0
+    deg[5::101] = 300
+    rowptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    nnz = int(rowptr[-1])
+    colind = rng.integers(0, n, size=nnz).astype(np.int32)
+    val = rng.standard_normal(nnz)
+    op = E.CsrOp(n, rowptr, colind, val)
+    op.set_tiles(lanes, 4, 1)
+    A = O.csr_matrix(n, rowptr, colind, val)
+    x = synth.uniform_vector(n, 7)
+    y = E.apply_op(op, 0.75, -1.5, T(x))
+    want = O.apply_op(A, 0.75, -1.5, x)
+    assert np.max(np.abs(N(y) - want)) <= 1e-13 * np.abs(want).max()
+
+
 def test_csr_phi1(E):
     op, A, g = csr_pair(E, 30007, seed=5)
     rho = synth.spectral_radius_symmetric(g)
