@@ -522,12 +522,22 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
                 rc = advance(j, mh - 2 - j, false);
                 if (rc) return rc;
             }
-            rc = advance(j, mh - j, true);
+            // the last two with tests; as in the plain loop, their state
+            // comes back through a pinned slot and the update (guarded by
+            // the stop flag) is enqueued before the host waits for it
+            int slot;
+            rc = mirror_begin(&slot);
             if (rc) return rc;
-            rc = sync_state(&last);
+            rc = advance(j, mh - j, true, tl_ctx.pinned_dev + slot);
+            if (rc) return rc;
+            rc = mirror_end(slot, C.s);
+            if (rc) return rc;
+            if (spec) HIP_TRY((*spec)());
+            rc = wait_slot(slot, &last, C.st);
             if (rc) return rc;
             if (last.done) finished = true;
             else out->fallback = 1;
+            out->updated = spec && last.done == 1;
         }
         learned_tail = true;
     }
