@@ -18,7 +18,8 @@
  *   creation; they must stay valid until the handle is destroyed.
  * - Streams.  `stream` is a hipStream_t passed as `void *` (NULL = the null
  *   stream).  All device work of a call is enqueued on it.  phi_action and
- *   expeuler_step read a 64-byte status record back to pinned host memory a
+ *   expeuler_step bring a 128-byte status record back to pinned host memory
+ *   (the last stop-test kernel of a batch of launches writes it there) a
  *   few times per Newton loop to decide how many further products to
  *   enqueue, so they return only after their device work has completed.
  *   apply_op and expi_op_interval(cached) return without synchronising.
@@ -210,7 +211,7 @@ size_t expi_workspace_bytes(const expi_op *op, int dtype);
 /* Gershgorin interval [a, b] of A (Sec. II-C needs an a-priori bound of the
  * field of values): a = min_i (A_ii - R_i), b = max_i (A_ii + R_i),
  * R_i = sum_{j != i} |A_ij|.  Computed on the device once per handle (one
- * sweep over the operator, then a 64-byte read-back on `stream`) and cached. */
+ * sweep over the operator, then a 128-byte read-back on `stream`) and cached. */
 int expi_op_interval(expi_op *op, double *a, double *b, void *ws, size_t ws_bytes,
                      void *stream);
 
