@@ -526,6 +526,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             if (edge || rb) aw[1] = 0;
                         }
                         const TC* pp = P[(s + 1) & 1];        // p (FIRST: r) of plane k-1
+                        // FP32: the lane's two squares are summed in FP32 and
+                        // added to the FP64 sums once (one rounding to FP32 per
+                        // pair of terms); FP64 adds each square
+                        constexpr bool kPairSq = sizeof(TW) == 4;
+                        TC q0 = 0, q1 = 0, q2 = 0, q3 = 0;
 #pragma unroll
                         for (int v = 0; v < 2; ++v) {
                             const TC p1 = FIRST ? (TC)(TW)(d0 * pp[v] + d1 * wc[v])
@@ -535,14 +540,25 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                                                 : (TC)(TW)(p1 + d2 * w2);
                             wo[v] = w2;
                             po[v] = p2;
-                            if (xin) {
+                            // FIRST: ||r||^2 in place of ||p_1||^2
+                            const TC n1 = FIRST ? pp[v] : p1;
+                            if constexpr (kPairSq) {
+                                q0 += wc[v] * wc[v];
+                                if (!START) q1 += n1 * n1;
+                                q2 += w2 * w2;
+                                q3 += p2 * p2;
+                            } else if (xin) {
                                 s0 += (double)wc[v] * (double)wc[v];
-                                // FIRST: ||r||^2 in place of ||p_1||^2
-                                if (FIRST) s1 += (double)pp[v] * (double)pp[v];
-                                else if (!START) s1 += (double)p1 * (double)p1;
+                                if (!START) s1 += (double)n1 * (double)n1;
                                 s2 += (double)w2 * (double)w2;
                                 s3 += (double)p2 * (double)p2;
                             }
+                        }
+                        if (kPairSq && xin) {
+                            s0 += (double)q0;
+                            if (!START) s1 += (double)q1;
+                            s2 += (double)q2;
+                            s3 += (double)q3;
                         }
                     }
                     // the stores, on every path (dropped where there is no
