@@ -421,14 +421,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         TC Q0[2] = {0, 0}, Q1[2] = {0, 0}, Q2[2] = {0, 0};
         L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
-        // ring slot of a plane: (plane - kst) mod 3.  Within an unrolled
-        // block the plane is k0 + c for a constant c; b3 = (k0 - kst) mod 3
-        // advances by 2 per block, so the slot is (b3 + c) mod 3.
-        int b3 = 0;
-        auto slot_of = [&](int c) {   // c >= 0, constant after unrolling
-            const int t = b3 + c % 3;
-            return t >= 3 ? t - 3 : t;
-        };
+        // ring slot of a plane: (plane - kst) mod 3.  The march is unrolled
+        // six planes per block (a multiple of both the three-plane rings and
+        // the two-slot load queues, so every rotation is a renaming): within
+        // a block the plane is k0 + c for a constant c, and k0 - kst is a
+        // multiple of 6, so the slot is the constant c mod 3.
+        auto slot_of = [&](int c) { return c % 3; };   // c >= 0
         auto wslot_c = [&](int c) { return &wring[slot_of(c) * kWRingLds]; };
         auto vslot_c = [&](int c) { return &ring[slot_of(c) * kPairLds]; };
         auto put = [&](TC* base, int row, const TC (&v)[2]) {
@@ -472,12 +470,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         __syncthreads();   // x and row data, the first two ring planes
         // a point of the outer layer has a zero row under interior_only
         const bool yedge = !(eym && eyq);
-        for (int k0 = kst; k0 <= ke; k0 += 2) {
+        for (int k0 = kst; k0 <= ke; k0 += 6) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
+            for (int s = 0; s < 6; ++s) {
                 const int k = k0 + s;
-                // the last output plane ke-1 is done at k = ke; an odd count
-                // of iterations leaves nothing for the last one
+                // the last output plane ke-1 is done at k = ke; the rest of
+                // the last block has nothing to do
                 if (k > ke) break;
                 // (1) w_j of plane k+2 into the ring (and the wave's own
                 // registers), then load plane k+4
@@ -617,7 +615,6 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 }
                 __syncthreads();
             }
-            b3 = b3 == 0 ? 2 : b3 - 1;   // + 2 mod 3
         }
     }
     if (a.guard && __builtin_amdgcn_readfirstlane(done_v) != 0) return;   // a workgroup without a unit
