@@ -369,38 +369,98 @@ def run_csr(args):
     }
 
 
-def cpu_baseline(args):
-    """The oracle on a bounded sample: the same problem on the 128^3 grid with
-    tau scaled by (256/128)^2, which keeps tau*(b-a) and hence the number of
-    Newton products per step; a few steps, wall time per solved grid point."""
+def gpu_states(args, dtype: str, steps: int):
+    """The first `steps` exponential Euler steps of the benchmark workload
+    from its u0 on the GPU (the timed configuration: pair sweeps, the given
+    storage), states copied to the host after each step."""
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+
+    n = args.n
+    h = 1.0 / n
+    coef = synth.sine_coefficient(n, 0.5)
+    op = E.StencilOp((n, n, n), (h, h, h), "neumann0",
+                     coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
+    u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=0), device="cuda:0")
+    ws = op.workspace(dtype)
+    out = []
+    for _ in range(steps):
+        E.expeuler_step(op, args.tau, u, tol=args.tol, dtype=dtype, ws=ws)
+        out.append(u.cpu().numpy())
+    del u, ws, op
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, gpu64, gpu32):
+    """The oracle on a bounded sample of the same workload: the first
+    `cpu_steps` exponential Euler steps of the 256^3 problem from the same
+    u0 at the same tol, on one thread (scipy's sparse product is
+    single-threaded; the BLAS pool is limited to one thread).  Operator
+    assembly and the interval are not timed.  The GPU's states after the
+    same steps (FP64 and FP32 storage) are compared with the oracle's, and
+    one more oracle step at tol 1e-12 (untimed) gives the accuracy of the
+    first step against a tighter reference."""
     import numpy as np
     import synth
+    from threadpoolctl import threadpool_limits
     from oracle import integrators as I
     from oracle import operators as O
 
-    n = args.cpu_n
+    def relerr(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    n = args.n
     h = 1.0 / n
-    tau = args.tau * (args.n / n) ** 2
-    A = O.stencil_matrix((n, n, n), (h, h, h), "neumann0",
-                         coef=synth.sine_coefficient(n, 0.5).field())
-    interval = O.gershgorin_interval(A)
-    u = synth.gaussian_bump_3d(n, seed=0)
-    c0 = time.process_time()
-    t0 = time.perf_counter()
-    for _ in range(args.cpu_steps):
-        u, st = I.expeuler_step(A, tau, u, args.tol, interval=interval)
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
+    with threadpool_limits(limits=1):
+        time.sleep(0.5)   # BLAS threads used by earlier legs stop spinning
+        A = O.stencil_matrix((n, n, n), (h, h, h), "neumann0",
+                             coef=synth.sine_coefficient(n, 0.5).field())
+        interval = O.gershgorin_interval(A)
+        u0 = synth.gaussian_bump_3d(n, seed=0)
+        u = u0
+        states = []
+        c0 = time.process_time()
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_steps):
+            u, st = I.expeuler_step(A, args.tau, u, args.tol, interval=interval)
+            states.append(u)
+        wall = time.perf_counter() - t0
+        cpu = time.process_time() - c0
+        ref, _ = I.expeuler_step(A, args.tau, u0, 1e-12, interval=interval)
+    del A
+    k = args.cpu_steps
+    prev = states[-2] if k > 1 else u0
+    errs = {
+        "f64": {"state": relerr(gpu64[k - 1], states[-1]),
+                "increment_last_step": relerr(gpu64[k - 1] - prev, states[-1] - prev),
+                "first_step_increment_vs_tol_1e-12": relerr(gpu64[0] - u0, ref - u0)},
+        "f32": {"state": relerr(gpu32[k - 1], states[-1]),
+                "increment_last_step": relerr(gpu32[k - 1] - prev, states[-1] - prev),
+                "first_step_increment_vs_tol_1e-12": relerr(gpu32[0] - u0, ref - u0)},
+    }
     return {
-        "value": n ** 3 * args.cpu_steps / wall,
+        "value": n ** 3 * k / wall,
         "unit": "grid-pts/s",
-        "cores": max(1, round(cpu / wall)),
+        "cores": 1,
         "kind": "oracle",
-        "sample": (f"{args.cpu_steps} exponential Euler steps of the same problem on the "
-                   f"{n}^3 grid, tau={tau:g} (same tau*(b-a) as {args.n}^3 at tau={args.tau:g}), "
-                   f"tol {args.tol:g}, float64 scipy.sparse; operator assembly not timed; "
-                   f"host has {os.cpu_count()} logical CPUs"),
+        "sample": (f"the first {k} exponential Euler steps of the same {n}^3 workload "
+                   f"(tau={args.tau:g}, tol {args.tol:g}), float64 scipy.sparse on one thread "
+                   f"of {cpu_model()} ({os.cpu_count()} logical CPUs on the host); "
+                   f"operator assembly not timed; cpu/wall {cpu / wall:.2f}"),
         "wall_s": wall,
+        "errors": errs,
     }
 
 
@@ -412,8 +472,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--tau", type=float, default=1e-5)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
@@ -484,8 +543,12 @@ def main():
         print(f"[bench] csr done: {csr['product_avg_us']:.1f} us per product", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args)
+        print(f"[bench] gpu states of the first {args.cpu_steps} steps (f64, f32)", file=sys.stderr, flush=True)
+        g64 = gpu_states(args, "f64", args.cpu_steps)
+        g32 = gpu_states(args, "f32", args.cpu_steps)
+        print("[bench] cpu baseline (oracle, one thread) and errors vs the oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args, g64, g32)
+        del g64, g32
 
     n = args.n
     alg = NEWTON_BYTES_PER_PT["f64"] * n ** 3
@@ -557,6 +620,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")}
                          if cpu else None),
+        "err_vs_oracle": (dict(cpu["errors"]["f64"], vs=(
+            f"FP64 oracle, same u0 and tol, after {args.cpu_steps} steps; the last key: "
+            f"step 1 against the oracle at tol 1e-12")) if cpu else None),
     }
     if r32:
         out["fp32_storage"] = {
@@ -571,6 +637,7 @@ def main():
             "pair_avg_us": r32["pair_avg_us"],
             "pair_gbs": r32["pair_gbs"],
             "note": "w, p stored in float32; divided differences, norms, stop test and u in float64",
+            "err_vs_oracle": cpu["errors"]["f32"] if cpu else None,
         }
     if learned:
         out["learned_vs_plain"] = learned

@@ -341,6 +341,10 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
                 const std::function<hipError_t()>* spec = nullptr) {
     const std::vector<double>& d = C.d;
     void* w[2] = {C.ws + C.L.w0, C.ws + C.L.w1};
+    // tolerance of the stop tests of the launches enqueued next; 0 makes a
+    // finalize record the norms and the latest term t_m without stopping
+    // (the test t_{m-1} + t_m <= 0 holds only for an exactly zero sum)
+    double tol_now = C.tol;
     SweepArgs a{};
     a.st = C.st;
     a.partials = C.partials;
@@ -430,6 +434,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         a.beta = -(C.c / C.gamma + C.xi[j]);
         a.d1 = d[j + 1];
         a.guard = 1;
+        a.tol = tol_now;
         const bool tm = timing();
         if (tm) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
         HIP_TRY(launch_sweep(*C.op, EPI_NEWTON, C.tw, C.tw, a, C.s, tm ? tl_ctx.tev[2 * j + 1] : nullptr,
@@ -452,7 +457,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.beta2 = -(C.c / C.gamma + C.xi[j + 1]);
         b.d1 = d[j + 1];
         b.d2 = d[j + 2];
-        b.tol = C.tol;
+        b.tol = tol_now;
         b.j = j;
         b.guard = 1;
         b.outbuf = cur ^ 1;
@@ -465,20 +470,28 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         return EXPI_OK;
     };
     // `count` products from j on (pairs where allowed), advancing j; the
-    // finalize of the last launch writes the state into `mirror` if given
+    // finalize of the last launch writes the state into `mirror` if given.
+    // fin = false: no norm reductions, except that the last launch records
+    // its norms and terms (a finalize with tol 0, which cannot stop on
+    // finite values), so that the next test's t_{m-1} is the term of the
+    // product just before it, not that of the last tested one.
     auto advance = [&](int& j, int count, bool fin, NewtonState* mirror = nullptr) -> int {
         const int end = j + count;
         while (j < end) {
             int rc;
             const bool two = C.pairs && end - j >= 2;
-            if (j + (two ? 2 : 1) == end) set_state_mirror(mirror);
+            const bool last = j + (two ? 2 : 1) == end;
+            if (last) set_state_mirror(mirror);
+            const bool record = !fin && last;
+            if (record) tol_now = 0.0;
             if (two) {
-                rc = pair(j, fin);
+                rc = pair(j, fin || record);
                 j += 2;
             } else {
-                rc = single(j, fin);
+                rc = single(j, fin || record);
                 j += 1;
             }
+            tol_now = C.tol;
             set_state_mirror(nullptr);
             if (rc) return rc;
         }
@@ -516,8 +529,9 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
             finished = true;
         } else {
             const int mh = std::min(std::max(last.pred_m, j + 1), C.m_max);
-            // unreduced products up to mh - 3, then the last two with tests
-            // (one pair sweep tests after each of its two products)
+            // products up to mh - 2 without stop tests (the last of them
+            // records t_{mh-2}), then the last two with tests (one pair
+            // sweep tests after each of its two products)
             if (mh - 2 > j) {
                 rc = advance(j, mh - 2 - j, false);
                 if (rc) return rc;

@@ -1,0 +1,153 @@
+"""GPU parity at full size: the 256^3 reaction-diffusion step against the oracle.
+
+The exponential Euler step of eq. (2) on the 256^3 cell-centred grid (the
+benchmark's workload: zero-flux boundaries, a = 1 + 0.5 sin 2 pi x sin 2 pi y
+sin 2 pi z, Gaussian bump plus noise, tau = 1e-5), computed by the HIP library
+in the launch configuration the benchmark times (pair sweeps, FP64), compared
+element by element with the FP64 oracle on the assembled 256^3 operator
+(about 1.2e8 stored entries, 7 GB of host memory, some 30 s of CPU).  The
+single-product kernels on the same step are compared too, and so is the
+FP32-storage step.  A 100-step trajectory on the 64^3 grid runs against the
+oracle step by step.
+
+Also: the pair sweep's multi-segment march (a workgroup whose chunk of
+(row tile, plane) units is longer than one segment of planes), forced by a
+grid with 65536 planes, against the oracle.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrators as I
+from oracle import operators as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def E(device):
+    import paper_1309_4616_amd as E
+    E.lib()
+    return E
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def rd_op(E, n, amp=0.5):
+    coef = synth.sine_coefficient(n, amp)
+    h = 1.0 / n
+    op = E.StencilOp((n, n, n), (h, h, h), "neumann0",
+                     coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
+    return op, coef
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_expeuler_256_step_matches_oracle_elementwise(E):
+    import torch
+    n = 256
+    tau = 1e-5
+    op, coef = rd_op(E, n)
+    u0 = synth.gaussian_bump_3d(n, seed=0)
+    print("256^3 step: GPU pair sweeps (f64), single products (f64), f32 storage", flush=True)
+    u = T(u0)
+    st = E.expeuler_step(op, tau, u, tol=1e-10)
+    got = N(u)
+    u.copy_(T(u0))
+    ss = E.expeuler_step(op, tau, u, tol=1e-10, params=E.LejaParams(pairs=False))
+    got_single = N(u)
+    u.copy_(T(u0))
+    E.expeuler_step(op, tau, u, tol=1e-8, dtype="f32")
+    got32 = N(u)
+    del u
+    torch.cuda.empty_cache()
+    assert st["pair_launches"] >= 1 and ss["pair_launches"] == 0
+    print("256^3 step: oracle (assembly, interval, step)", flush=True)
+    A = O.stencil_matrix((n, n, n), (1.0 / n,) * 3, "neumann0", coef=coef.field())
+    a, b = O.gershgorin_interval(A)
+    uo, sto = I.expeuler_step(A, tau, u0, 1e-10, interval=(a, b))
+    del A
+    assert st["interval_a"] == pytest.approx(a, rel=1e-13)
+    assert abs(st["degree_last"] - sto.degrees[-1]) <= 1
+    e_state, e_inc = relerr(got, uo), relerr(got - u0, uo - u0)
+    e_single = relerr(got_single - u0, uo - u0)
+    e32 = relerr(got32, uo)
+    print(f"256^3 step vs oracle: state {e_state:.2e}, increment {e_inc:.2e}, "
+          f"single products increment {e_single:.2e}, f32 storage state {e32:.2e}", flush=True)
+    assert e_state <= TOL_F64
+    # the increment tau phi_1(tau A) F(u0) alone, which the state would hide
+    assert e_inc <= TOL_F64
+    assert e_single <= TOL_F64
+    assert relerr(got - u0, got_single - u0) <= 1e-12
+    # FP32 storage of the Newton vectors (the state's error floor, not tol)
+    assert e32 <= 1e-6
+    # mass identity under zero-flux boundaries
+    g = u0 - u0 ** 3
+    assert abs(got.sum() - (u0.sum() + tau * g.sum())) <= 1e-9 * np.abs(u0).sum()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_expeuler_64_hundred_steps_match_oracle(E):
+    """The 3D workload's 100 steps on the 64^3 grid (tau scaled to keep
+    tau (b - a) of the 256^3 grid at 1e-5), every step against the oracle."""
+    n = 64
+    op, coef = rd_op(E, n)
+    A = O.stencil_matrix((n, n, n), (1 / n,) * 3, "neumann0", coef=coef.field())
+    a, b = O.gershgorin_interval(A)
+    tau = 1e-5 * (256 / n) ** 2
+    u0 = synth.gaussian_bump_3d(n, seed=0)
+    u = T(u0)
+    uo = u0.copy()
+    worst = worst_inc = 0.0
+    for step in range(100):
+        prev = uo.copy()
+        E.expeuler_step(op, tau, u, tol=1e-10)
+        uo, _ = I.expeuler_step(A, tau, uo, 1e-10, interval=(a, b))
+        got = N(u)
+        e, ei = relerr(got, uo), relerr(got - prev, uo - prev)
+        worst, worst_inc = max(worst, e), max(worst_inc, ei)
+        assert e <= TOL_F64, (step, e)
+    print(f"64^3, 100 steps: worst state error {worst:.2e}, worst increment error {worst_inc:.2e}")
+    # increments compared against the oracle's own previous state carry the
+    # accumulated state difference; they stay far below the tolerance
+    assert worst_inc <= 1e-8
+
+
+def test_pair_sweep_multi_segment_march(E):
+    """65536 planes of 2 x 6 points: one row tile, 65536 (row tile, plane)
+    units, so on a 256-CU part each workgroup's chunk holds 256 planes,
+    more than one segment (248 planes), and the march refills its plane
+    table and restarts its rings mid-chunk."""
+    shape = (2, 6, 65536)
+    h = (1.0 / 2, 1.0 / 6, 1.0 / 65536)
+    tabs = [np.cos(2 * np.pi * (np.arange(s) + 0.5) / s) for s in shape]
+    c0, c1 = 1.0, 0.45
+    fld = c0 + c1 * ((tabs[2][:, None, None] * tabs[1][None, :, None]) * tabs[0][None, None, :])
+    for bc in ("neumann0", "dirichlet0"):
+        op = E.StencilOp(shape, h, bc, coef=("separable", c0, c1, *tabs))
+        A = O.stencil_matrix(shape, h, bc, coef=fld.reshape(-1))
+        a, b = O.gershgorin_interval(A)
+        tau = 12.0 / (b - a)
+        v = synth.uniform_vector(A.shape[0], 11)
+        print(f"multi-segment march {shape} {bc}", flush=True)
+        y, st = E.phi_action(op, 1, tau, T(v), tol=1e-10, params=E.LejaParams(profile=1))
+        ys, _ = E.phi_action(op, 1, tau, T(v), tol=1e-10, params=E.LejaParams(pairs=False))
+        yo, so = I.phi_action(A, 1, tau, v, 1e-10, interval=(a, b))
+        assert st["timed_pairs"] >= 1
+        assert relerr(N(y), yo) <= TOL_F64, (bc, relerr(N(y), yo))
+        assert relerr(N(y), N(ys)) <= 1e-12

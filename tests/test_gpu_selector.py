@@ -153,3 +153,35 @@ def test_learned_mode_matches_oracle(E):
     got = u.cpu().numpy()
     assert np.linalg.norm(got - uo) / np.linalg.norm(uo) <= 1e-10
     assert st["pred_degree"] > 0
+
+
+def test_learned_mode_near_l_max_matches_oracle(E):
+    """tau (b - a) close to l_max = 100 (one substep, degree about 45 at
+    1e-10): the Newton terms still grow past the fourth product, so the
+    first stop test after the unreduced products must use the term of the
+    product just before it.  Learned mode against the oracle at 1e-10."""
+    import torch
+    n = 20
+    coef = synth.sine_coefficient(n, 0.5)
+    A = O.stencil_matrix((n, n, n), (1 / n,) * 3, "neumann0", coef=coef.field())
+    a, b = O.gershgorin_interval(A)
+    tau = 95.0 / (b - a)
+    X, Y, _ = log_plain(E, n, [0.3, 0.5, 0.7], 4, tau, 1e-10, seed0=40)
+    net, norms, _ = E.selector.train(X, Y, hidden=32, epochs=800, lr=3e-3, seed=2)
+    sel = E.selector.pack(net, norms)
+    op = rd_op(E, n, 0.5)
+    for seed in (41, 42):
+        u0 = synth.gaussian_bump_3d(n, seed=seed)
+        u = torch.as_tensor(u0, device="cuda:0")
+        st = E.expeuler_step(op, tau, u, tol=1e-10,
+                             params=E.LejaParams(selector=sel, selector_hidden=32))
+        uo, sto = I.expeuler_step(A, tau, u0, 1e-10, interval=(a, b))
+        got = u.cpu().numpy()
+        assert st["substeps"] == 1 and st["pred_degree"] > 8
+        # a stop at m needs the two-term test at m, so the learned loop never
+        # stops before the oracle's first m (up to rounding at the threshold)
+        assert st["degree_last"] >= sto.degrees[-1] - 1
+        assert np.linalg.norm(got - uo) / np.linalg.norm(uo) <= 1e-10
+        # the increment alone: the two differ by at most the oracle's own
+        # truncation (the stop test holds it to 1e-10 of ||p||)
+        assert np.linalg.norm((got - u0) - (uo - u0)) / np.linalg.norm(uo - u0) <= 1e-9
