@@ -33,7 +33,15 @@ points.  The steps, in the order this module performs them:
    ``y(0) = 0``, and ``e^{dA} = I + dA phi_1(dA)``, hence
    ``y_{l+1} = y_l + delta phi_1(delta A)(A y_l + v)`` and
    ``phi_1(tau A) v = y_s / tau``.  For phi_0, ``y_{l+1} = e^{delta A} y_l``.
-   For k >= 2 only ``s = 1`` is supported.
+   For k >= 2, ``y(t) = t^k phi_k(tA) v`` solves ``y' = A y + t^(k-1)/(k-1)! v``,
+   ``y(0) = 0``; by variation of constants one substep from ``t = l delta`` is
+   ``y_{l+1} = e^{X} y_l + sum_{j=1..k} delta^j t^(k-j)/(k-j)! phi_j(X) v``
+   with ``X = delta A``.  Any sum ``sum_{j=0..k} phi_j(X) b_j`` equals
+   ``sum_{j<k} w_j / j! + phi_k(X) w_k`` with ``w_0 = b_0``,
+   ``w_j = X w_{j-1} + b_j`` (from ``phi_j(X) = I/j! + X phi_{j+1}(X)``), so a
+   substep costs k products plus one Newton loop for phi_k.  The module
+   carries ``z_l = y_l / tau^k``, for which ``b_0 = z_l`` and
+   ``b_j = s^-j (l/s)^(k-j)/(k-j)! v``, and returns ``z_s``.
 7. Exponential Euler, eq. (2), for ``u' = A u + g(u)`` (the paper writes
    ``u' + A u = g`` with A having large negative eigenvalues; with A the
    discrete Laplacian itself, whose eigenvalues are negative, the sign of A
@@ -42,6 +50,10 @@ points.  The steps, in the order this module performs them:
    ``u_n + tau phi_1(tau A)(A u_n + g(u_n))``; with substeps,
    ``y_0 = u_n``, ``y_{l+1} = y_l + delta phi_1(delta A)(A y_l + g(u_n))``,
    ``u_{n+1} = y_s``.
+8. The second-order exponential Runge-Kutta method with c_2 = 1 (one of the
+   higher-order methods the paper points to, Sec. II-C; Hochbruck and
+   Ostermann's review): the exponential Euler step gives the stage U, then
+   ``u_{n+1} = U + tau phi_2(tau A)(g(U) - g(u_n))``.
 """
 from __future__ import annotations
 
@@ -123,8 +135,6 @@ def phi_action(A, k: int, tau: float, v: np.ndarray, tol: float,
     xi = leja.leja_points(params.m_max + 1)
     st = Stats(interval=(a, b))
     for attempt in range(params.max_retries + 1):
-        if k >= 2 and s > 1:
-            raise NotImplementedError("phi_k with k >= 2 needs a single substep")
         delta = tau / s
         d = leja.divided_differences(k, delta, c, gamma, xi)
         st = Stats(interval=(a, b), substeps=s, retries=attempt)
@@ -151,12 +161,34 @@ def phi_action(A, k: int, tau: float, v: np.ndarray, tol: float,
                 ok &= conv
                 y = y + delta * p
             out = y / tau
-        else:
+        elif s == 1:
             out, m, err, conv = newton_leja(A, v, d, xi, c, gamma, tol, params.m_max)
             st.newton_steps += m
             st.degrees.append(m)
             st.err_est = err
             ok = conv
+        else:
+            # k >= 2 with substeps (step 6): z_l = y(l delta) / tau^k
+            z = np.zeros_like(v)
+            for l in range(s):
+                w = z.copy()                  # w_0 = b_0 = z_l
+                acc = w.copy()                # sum_{j<k} w_j / j!
+                for j in range(1, k + 1):
+                    b_j = (s ** -j) * (l / s) ** (k - j) / math.factorial(k - j) * v
+                    if np.any(w):
+                        w = delta * (A @ w) + b_j
+                        st.matvecs += 1
+                    else:
+                        w = b_j
+                    if j < k:
+                        acc = acc + w / math.factorial(j)
+                p, m, err, conv = newton_leja(A, w, d, xi, c, gamma, tol, params.m_max)
+                st.newton_steps += m
+                st.degrees.append(m)
+                st.err_est = max(st.err_est, err)
+                ok &= conv
+                z = acc + p
+            out = z
         st.matvecs += st.newton_steps
         st.converged = ok
         if ok:
@@ -170,15 +202,29 @@ def cubic(u: np.ndarray) -> np.ndarray:
     return u - u * u * u
 
 
+def combustion(u: np.ndarray) -> np.ndarray:
+    """The combustion nonlinearity of Sec. III-C, computed pointwise:
+    ``g(u) = (2 - u)/4 exp(20 (1 - 1/u))`` (g(0) = 0 as the limit from above,
+    which the float64 evaluation reaches through 1/0 = inf)."""
+    u = np.asarray(u, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return 0.25 * (2.0 - u) * np.exp(20.0 * (1.0 - 1.0 / u))
+
+
 def expeuler_step(A, tau: float, u: np.ndarray, tol: float, g=cubic,
-                  interval=None, params: LejaParams = LejaParams()):
-    """One exponential Euler step (step 7).  Returns ``(u_next, Stats)``."""
+                  interval=None, params: LejaParams = LejaParams(), forcing=None):
+    """One exponential Euler step (step 7).  Returns ``(u_next, Stats)``.
+    ``forcing``: a constant vector added to g(u) (the boundary term b_f of
+    inhomogeneous Dirichlet data, for which the right-hand side is
+    ``A_0 u + b_f + g(u)``)."""
     u = np.asarray(u, dtype=np.float64)
     a, b = _interval(A, interval)
     c, gamma = 0.5 * (a + b), 0.25 * (b - a)
     s = substep_count(tau, a, b, params.l_max)
     xi = leja.leja_points(params.m_max + 1)
     gn = g(u)
+    if forcing is not None:
+        gn = gn + np.asarray(forcing, dtype=np.float64)
     st = Stats(interval=(a, b))
     for attempt in range(params.max_retries + 1):
         delta = tau / s
@@ -201,3 +247,15 @@ def expeuler_step(A, tau: float, u: np.ndarray, tol: float, g=cubic,
             return y, st
         s *= 2
     return y, st
+
+
+def exprk2_step(A, tau: float, u: np.ndarray, tol: float, g=cubic,
+                interval=None, params: LejaParams = LejaParams(), forcing=None):
+    """One step of the second-order exponential Runge-Kutta method (step 8):
+    ``U = u + tau phi_1(tau A)(A u + g(u))`` (the exponential Euler step),
+    then ``u_{n+1} = U + tau phi_2(tau A)(g(U) - g(u))``.  Returns
+    ``(u_next, (Stats of the stage, Stats of the phi_2 action))``."""
+    u = np.asarray(u, dtype=np.float64)
+    U, st1 = expeuler_step(A, tau, u, tol, g, interval, params, forcing)
+    p2, st2 = phi_action(A, 2, tau, g(U) - g(u), tol, interval, params)
+    return U + tau * p2, (st1, st2)

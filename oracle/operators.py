@@ -24,6 +24,23 @@ with ``a_{c,c'} = (a_c + a_{c'}) / 2``.  Boundary handling is folded into A
 
 With a = 1 and dirichlet0, ``h^2 (A u)`` is exactly the seven-point formula of
 Sec. III-A (five-point in 2D).
+
+Grid positions (needed where data depend on position): index i along an
+axis of spacing h sits at ``(i + 1) h`` under dirichlet0 (nodes strictly
+inside the unit interval, boundary nodes at 0 and ``(n + 1) h``),
+``(i + 1/2) h`` under neumann0 (cell centres) and ``i h`` under
+interior_only (the array includes the boundary layer).
+
+Two further operators of the paper:
+
+* inhomogeneous Dirichlet data (Sec. III-A, the rows of Table I with
+  boundary values f = z(1-z)xy and f = sin(pi z) exp(-xy)): the stencil reads
+  f at a neighbour position on the boundary instead of 0, which makes the
+  product affine, ``A_0 u + b_f``, with A_0 the dirichlet0 operator and b_f
+  the boundary term (``dirichlet_boundary_term``);
+* the position-dependent coefficient of Sec. III-B in the form the paper
+  times (Table II), ``D(x, y, z) times the discrete Laplacian`` with
+  ``D = 1/sqrt(1 + x^2 + y^2)`` (``dlap_matrix``).
 """
 from __future__ import annotations
 
@@ -138,10 +155,19 @@ def gershgorin_interval(A) -> tuple[float, float]:
     return float(np.min(d - r)), float(np.max(d + r))
 
 
-def apply_at(shape, h, bc: str, u: np.ndarray, points, coef=None) -> np.ndarray:
+def apply_at(shape, h, bc: str, u: np.ndarray, points, coef=None, bdata=None,
+             dlap: bool = False) -> np.ndarray:
     """``(A u)`` at the flat indices ``points``, evaluated one point at a time
     from the definition in the module docstring, without assembling A (for
-    grids too large to assemble).  ``coef`` as in ``stencil_matrix``."""
+    grids too large to assemble).  ``coef`` as in ``stencil_matrix``.
+    ``bdata``: Dirichlet data f (``boundary_values`` kind, dirichlet0, 3D):
+    a missing neighbour reads f at its boundary position instead of 0, so
+    the result is ``(A_0 u + b_f)``.  ``dlap``: the operator D times the
+    Laplacian (``dlap_matrix``; coef must be None)."""
+    if bdata is not None and (bc != "dirichlet0" or len(shape) != 3):
+        raise ValueError("boundary data need dirichlet0 on a 3D grid")
+    if dlap and coef is not None:
+        raise ValueError("dlap takes no coefficient")
     if bc not in BCS:
         raise ValueError(f"unknown boundary condition {bc!r}")
     shape = tuple(int(s) for s in shape)
@@ -174,7 +200,15 @@ def apply_at(shape, h, bc: str, u: np.ndarray, points, coef=None) -> np.ndarray:
                     nb = flat + s * strides[d]
                     total += 0.5 * (ac + a(nb)) * (u[nb] - u[flat]) / (h[d] * h[d])
                 elif bc == "dirichlet0":
-                    total += ac * (0.0 - u[flat]) / (h[d] * h[d])
+                    ghost = 0.0
+                    if bdata is not None:
+                        xyz = [(pos[e] + 1) * h[e] for e in range(3)]
+                        xyz[d] = 0.0 if p < 0 else (shape[d] + 1) * h[d]
+                        ghost = float(boundary_values(bdata, *xyz))
+                    total += ac * (ghost - u[flat]) / (h[d] * h[d])
+        if dlap:
+            xy = [float(positions(shape[e], h[e], bc)[pos[e]]) for e in range(2)]
+            total *= float(d_coefficient(xy[0], xy[1]))
         out[q] = total
     return out
 
@@ -230,3 +264,76 @@ def dirichlet_box_phi(k: int, shape, h, tau: float, v: np.ndarray, coef: float =
     V = np.asarray(v, dtype=np.float64).reshape(shape[::-1])
     modes = F.dstn(V, type=1, norm="ortho")
     return F.dstn(phi_values(k, tau * lam) * modes, type=1, norm="ortho").reshape(-1)
+
+
+def positions(n: int, h: float, bc: str) -> np.ndarray:
+    """Coordinates of the n grid indices of one axis (module docstring)."""
+    off = {"dirichlet0": 1.0, "neumann0": 0.5, "interior_only": 0.0}[bc]
+    return (np.arange(n) + off) * h
+
+
+def boundary_values(kind: str, x, y, z):
+    """The boundary data of Sec. III-A: ``z1mz_xy`` is f = z(1-z)xy,
+    ``sinpiz_expmxy`` is f = sin(pi z) exp(-x y)."""
+    if kind == "z1mz_xy":
+        return z * (1.0 - z) * x * y
+    if kind == "sinpiz_expmxy":
+        return np.sin(np.pi * z) * np.exp(-x * y)
+    raise ValueError(f"unknown boundary data {kind!r}")
+
+
+def dirichlet_boundary_term(shape, h, kind: str, coef=None) -> np.ndarray:
+    """b_f of the affine product ``A_0 u + b_f`` for Dirichlet data f on the
+    boundary of the unit cube (3D, node grid of dirichlet0).  For every grid
+    point and every axis direction whose neighbour index falls outside the
+    array, the neighbour is the boundary node at coordinate 0 or
+    ``(n + 1) h`` on that axis, and the face term ``a_c f(neighbour) / h^2``
+    (the cell's own coefficient on the boundary face, as for dirichlet0) is
+    added at the point."""
+    shape = tuple(int(s) for s in shape)
+    if len(shape) != 3:
+        raise ValueError("boundary data are defined on 3D grids")
+    n = int(np.prod(shape))
+    a = np.ones(n) if coef is None else (np.full(n, float(coef)) if np.isscalar(coef)
+                                         else np.asarray(coef, np.float64).reshape(-1))
+    a = a.reshape(shape[::-1])
+    X = positions(shape[0], h[0], "dirichlet0")[None, None, :]
+    Y = positions(shape[1], h[1], "dirichlet0")[None, :, None]
+    Z = positions(shape[2], h[2], "dirichlet0")[:, None, None]
+    out = np.zeros(shape[::-1])
+    full = lambda v: np.broadcast_to(v, shape[::-1])
+    for d, (lo, hi) in enumerate(((0.0, (shape[0] + 1) * h[0]), (0.0, (shape[1] + 1) * h[1]),
+                                  (0.0, (shape[2] + 1) * h[2]))):
+        ax = 2 - d
+        for end, coord in ((0, lo), (-1, hi)):
+            sl = [slice(None)] * 3
+            sl[ax] = end
+            sl = tuple(sl)
+            xyz = [full(X), full(Y), full(Z)]
+            xyz[d] = np.full(shape[::-1], coord)
+            f = boundary_values(kind, xyz[0][sl], xyz[1][sl], xyz[2][sl])
+            out[sl] += a[sl] * f / (h[d] * h[d])
+    return out.reshape(-1)
+
+
+def d_coefficient(x, y) -> np.ndarray:
+    """D(x, y, z) = 1/sqrt(1 + x^2 + y^2) of Sec. III-B (Table II)."""
+    return 1.0 / np.sqrt(1.0 + x * x + y * y)
+
+
+def dlap_matrix(shape, h, bc: str) -> sp.csr_matrix:
+    """D times the constant-coefficient stencil Laplacian with boundary
+    handling ``bc`` (Sec. III-B, Table II): row c of the Laplacian scaled by
+    D at c's position."""
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    if dim not in (2, 3):
+        raise ValueError("2D or 3D grids")
+    L = stencil_matrix(shape, h, bc)
+    X = positions(shape[0], h[0], bc)
+    Y = positions(shape[1], h[1], bc)
+    if dim == 3:
+        Dg = np.broadcast_to(d_coefficient(X[None, None, :], Y[None, :, None]), shape[::-1])
+    else:
+        Dg = d_coefficient(X[None, :], Y[:, None])
+    return sp.csr_matrix(sp.diags(np.ascontiguousarray(Dg).reshape(-1)) @ L)
