@@ -244,6 +244,34 @@ int expeuler_step(expi_op *op, int nonlin, double tau, double *u, double tol, in
                   const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
                   void *stream);
 
+/* ---- allocation-free variant of phi_action ------------------------------- */
+
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc).  The library holds one scratch array of
+ * EXPI_NOALLOC_SCRATCH_BYTES in device memory (a static device variable of
+ * the library's code object, present on every GPU the library runs on until
+ * the process ends) and uses it as phi_action's workspace.
+ *
+ * expi_noalloc_init: set-up, once per (host thread, device), with that device
+ * current: looks up the device address of this device's scratch array and
+ * prepares the calling thread's pinned status slots and timing events (these
+ * are allocations, so they belong here and not in the call).  EXPI_EHIP if a
+ * HIP call fails.
+ *
+ * phi_action_noalloc: phi_action with the scratch array as workspace; same
+ * arguments, results and errors, minus ws/ws_bytes.  It calls no hipMalloc,
+ * hipFree or other allocating routine.  EXPI_EINVAL if expi_noalloc_init has
+ * not run on this thread and device; EXPI_EWORKSPACE if the operator needs
+ * more than EXPI_NOALLOC_SCRATCH_BYTES (expi_workspace_bytes(op, dtype):
+ * about 32 bytes per unknown in FP64, so up to about 2 million unknowns).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (the status record is reset by each call): calls that overlap in
+ * time on one GPU, from any thread or stream, race and must not be made. */
+#define EXPI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int expi_noalloc_init(void);
+int phi_action_noalloc(expi_op *op, int k, double tau, const double *v, double *y, double tol,
+                       int dtype, const expi_params *params, expi_stats *st, void *stream);
+
 /* ---- many problems in one batch ------------------------------------------ */
 
 /* A batch of independent 2D problems y_i = phi_1(tau_i A_i) v_i, A_i the

@@ -13,10 +13,11 @@ import ctypes
 
 from . import autotune, selector
 from ._binding import (COEF_CONST, COEF_FIELD, COEF_SEPARABLE, F32, F64, G_CUBIC, BCS, EXPORTS,
-                       BatchStat, ExpiError, LejaParams, Stats, check, divided_differences,
-                       leja_points, lib)
+                       NOALLOC_SCRATCH_BYTES, BatchStat, ExpiError, LejaParams, Stats, check,
+                       divided_differences, leja_points, lib)
 
-__all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "expeuler_step", "leja_points",
+__all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "phi_action_noalloc", "noalloc_init",
+           "expeuler_step", "leja_points",
            "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32",
            "autotune", "selector", "Batch"]
 
@@ -212,6 +213,29 @@ def phi_action(op: _Op, k: int, tau: float, v, y=None, tol: float = 1e-10, dtype
                           _stream_ptr(stream, op.device))
     check(rc)
     return y, st.as_dict()
+
+
+def noalloc_init(device="cuda:0") -> None:
+    """Set-up of phi_action_noalloc for this thread and device (expi_noalloc_init)."""
+    torch = _torch()
+    with torch.cuda.device(torch.device(device)):
+        check(lib().expi_noalloc_init())
+
+
+def phi_action_noalloc(op: _Op, k: int, tau: float, v, y, tol: float = 1e-10, dtype="f64",
+                       params: LejaParams | None = None, stream=None):
+    """y = phi_k(tau A) v with the library's scratch array as workspace (no
+    device allocation in the call; y must be given); returns the stats dict."""
+    torch = _torch()
+    st = Stats()
+    cp = params.to_c() if params is not None else None
+    with torch.cuda.device(op.device):
+        rc = lib().phi_action_noalloc(op.handle, int(k), float(tau), ctypes.c_void_p(v.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), float(tol), _dtype_code(dtype),
+                                      ctypes.byref(cp) if cp is not None else None,
+                                      ctypes.byref(st), _stream_ptr(stream, op.device))
+    check(rc)
+    return st.as_dict()
 
 
 def expeuler_step(op: _Op, tau: float, u, tol: float = 1e-10, dtype="f64",

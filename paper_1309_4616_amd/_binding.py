@@ -31,7 +31,11 @@ EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "e
            "expi_batch_results", "expi_batch_max_rounds", "expi_batch_graph_rounds",
            "expi_batch_launch_persistent", "expi_batch_capture_persistent",
            "expi_batch_autotune", "expi_batch_get_tiles", "expi_mlp_param_count", "expi_mlp_scratch_floats",
-           "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam")
+           "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam",
+           "expi_noalloc_init", "phi_action_noalloc")
+
+# size of the library's scratch array behind phi_action_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class ExpiError(RuntimeError):
@@ -155,6 +159,11 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(Params), c_void_p, c_size_t, ctypes.POINTER(Stats),
                                 c_void_p]
     L.expeuler_step.restype = c_int
+    L.expi_noalloc_init.argtypes = []
+    L.expi_noalloc_init.restype = c_int
+    L.phi_action_noalloc.argtypes = [c_void_p, c_int, c_double, c_void_p, c_void_p, c_double, c_int,
+                                     ctypes.POINTER(Params), ctypes.POINTER(Stats), c_void_p]
+    L.phi_action_noalloc.restype = c_int
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.expi_batch_create.argtypes = [ctypes.POINTER(c_void_p), c_int, i32p, i32p, dblp, dblp, dblp,
                                     c_int, c_double, c_double, c_int, ctypes.POINTER(Params)]

@@ -881,6 +881,52 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     return fail(EXPI_ENOTCONV, "no convergence within m_max products after all substep doublings");
 }
 
+// ---- allocation-free phi_action ---------------------------------------------
+// The scratch array lives in the library's code object, one copy per GPU.
+// Host code never passes `scratch` itself to a kernel (its host-side name is
+// not a device address): expi_noalloc_init looks up each device's address
+// with hipGetSymbolAddress and every later use goes through that pointer.
+static __device__ __align__(256) unsigned char scratch[EXPI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+int noalloc_init() {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(EXPI_EINVAL, "device index out of range");
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[dev]) {
+            void* ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr || ((uintptr_t)ptr & 255) != 0)
+                return fail(EXPI_EHIP, "scratch array has no 256-byte aligned device address");
+            g_scratch[dev] = static_cast<char*>(ptr);
+        }
+    }
+    // the calling thread's pinned status slots and timing events
+    int rc = ctx_init();
+    if (rc) return rc;
+    return timing_events();
+}
+
+// This thread's set-up for the current device, or an error (no allocation).
+int noalloc_scratch(char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    char* ptr = nullptr;
+    if (dev >= 0 && dev < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ptr = g_scratch[dev];
+    }
+    if (!ptr || tl_ctx.device != dev || !tl_ctx.pinned || !tl_ctx.have_tev)
+        return fail(EXPI_EINVAL, "expi_noalloc_init has not run on this thread for the current device");
+    *out = ptr;
+    return EXPI_OK;
+}
+
 }  // namespace expi
 
 using namespace expi;
@@ -1159,6 +1205,24 @@ int expeuler_step(expi_op* op, int nonlin, double tau, double* u, double tol, in
     if (rc) return rc;
     return run_expeuler(o, nonlin, tau, u, tol, dtype, P, static_cast<char*>(ws), st,
                         static_cast<hipStream_t>(stream));
+}
+
+int expi_noalloc_init(void) { return noalloc_init(); }
+
+int phi_action_noalloc(expi_op* op, int k, double tau, const double* v, double* y, double tol,
+                       int dtype, const expi_params* params, expi_stats* st, void* stream) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
+    const size_t need = layout(*reinterpret_cast<const Op*>(op), dtype).total;
+    if (need > EXPI_NOALLOC_SCRATCH_BYTES)
+        return fail(EXPI_EWORKSPACE, "operator needs " + std::to_string(need) +
+                                         " bytes of workspace, more than the allocation-free scratch array (" +
+                                         std::to_string((size_t)EXPI_NOALLOC_SCRATCH_BYTES) + " bytes)");
+    char* ws = nullptr;
+    int rc = noalloc_scratch(&ws);
+    if (rc) return rc;
+    return phi_action(op, k, tau, v, y, tol, dtype, params, ws, EXPI_NOALLOC_SCRATCH_BYTES, st, stream);
 }
 
 int expi_leja_points(double* out, int count) {

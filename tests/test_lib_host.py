@@ -150,6 +150,24 @@ def test_call_validation_before_any_hip_call(L):
     L.expi_op_destroy(op)
 
 
+def test_noalloc_size_limit_before_any_hip_call(L):
+    """The allocation-free phi_action refuses an operator whose workspace is
+    larger than the library's scratch array, and a bad dtype, before it
+    touches the device."""
+    from paper_1309_4616_amd import _binding
+    rc, op = _stencil(L, dim=3, n=(256, 256, 256))
+    assert rc == 0
+    assert L.expi_workspace_bytes(op, 0) > _binding.NOALLOC_SCRATCH_BYTES
+    st = _binding.Stats()
+    v = ctypes.c_void_p(1 << 20)
+    y = ctypes.c_void_p(1 << 32)
+    assert L.phi_action_noalloc(op, 1, 1e-5, v, y, 1e-10, 0, None, ctypes.byref(st), None) == -3
+    assert b"scratch" in L.expi_last_error()
+    assert L.phi_action_noalloc(op, 1, 1e-5, v, y, 1e-10, 7, None, ctypes.byref(st), None) == -1
+    assert L.phi_action_noalloc(None, 1, 1e-5, v, y, 1e-10, 0, None, ctypes.byref(st), None) == -1
+    L.expi_op_destroy(op)
+
+
 def test_batch_create_validation_and_layout(L):
     """The batch is built on the host (intervals, substeps, divided
     differences, offsets); no GPU is touched until prepare/launch."""
