@@ -50,6 +50,13 @@ points.  The steps, in the order this module performs them:
    ``u_n + tau phi_1(tau A)(A u_n + g(u_n))``; with substeps,
    ``y_0 = u_n``, ``y_{l+1} = y_l + delta phi_1(delta A)(A y_l + g(u_n))``,
    ``u_{n+1} = y_s``.
+9. Complex operators (Sec. II-C allows K = C; the spin system of Sec. III-D
+   solves psi' = -i H psi with H Hermitian, stored in CSR):
+   ``skew_phi_action`` gives ``phi_k(-i tau H) v``, k = 0 or 1, by the same
+   Newton recurrence (real alpha, beta_j applied to H) with the complex
+   divided differences of ``x -> phi_k(-i delta (c + gamma x))``, [a, b] the
+   Gershgorin interval of H, and the substep rules of steps 2 and 6 with
+   A = -i H.
 8. The second-order exponential Runge-Kutta method with c_2 = 1 (one of the
    higher-order methods the paper points to, Sec. II-C; Hochbruck and
    Ostermann's review): the exponential Euler step gives the stage U, then
@@ -95,7 +102,8 @@ def newton_leja(A, r: np.ndarray, d: np.ndarray, xi: np.ndarray, c: float,
     """Steps 4-5 on one vector.  Returns ``(p, m, err, converged)`` where
     ``m`` is the number of products and ``err = (t_{m-1} + t_m)/||p||``."""
     alpha = 1.0 / gamma
-    w = np.array(r, dtype=np.float64, copy=True)
+    # complex when the operator, the vector or the coefficients are (K = C)
+    w = np.array(r, dtype=np.result_type(r, d, A.dtype, np.float64), copy=True)
     p = d[0] * w
     t_prev = abs(d[0]) * np.linalg.norm(w)
     err = math.inf
@@ -259,3 +267,43 @@ def exprk2_step(A, tau: float, u: np.ndarray, tol: float, g=cubic,
     U, st1 = expeuler_step(A, tau, u, tol, g, interval, params, forcing)
     p2, st2 = phi_action(A, 2, tau, g(U) - g(u), tol, interval, params)
     return U + tau * p2, (st1, st2)
+
+
+def skew_phi_action(H, k: int, tau: float, v: np.ndarray, tol: float,
+                    interval=None, params: LejaParams = LejaParams()):
+    """``phi_k(-i tau H) v`` for Hermitian H (step 9), k = 0 or 1.
+    Returns ``(y, Stats)``; y is complex128."""
+    if k not in (0, 1):
+        raise ValueError("k must be 0 or 1")
+    v = np.asarray(v, dtype=np.complex128)
+    a, b = _interval(H, interval)
+    c, gamma = 0.5 * (a + b), 0.25 * (b - a)
+    s = substep_count(tau, a, b, params.l_max)
+    xi = leja.leja_points(params.m_max + 1)
+    st = Stats(interval=(a, b))
+    for attempt in range(params.max_retries + 1):
+        delta = tau / s
+        d = leja.divided_differences_skew(k, delta, c, gamma, xi)
+        st = Stats(interval=(a, b), substeps=s, retries=attempt)
+        ok = True
+        y = v.copy() if k == 0 else np.zeros_like(v)
+        for l in range(s):
+            if k == 0:
+                r = y
+            else:
+                # y(t) = t phi_1(-i t H) v solves y' = -i H y + v
+                r = v if l == 0 else -1j * (H @ y) + v
+                if l > 0:
+                    st.matvecs += 1
+            p, m, err, conv = newton_leja(H, r, d, xi, c, gamma, tol, params.m_max)
+            st.newton_steps += m
+            st.degrees.append(m)
+            st.err_est = max(st.err_est, err)
+            ok &= conv
+            y = p if k == 0 else y + delta * p
+        st.matvecs += st.newton_steps
+        st.converged = ok
+        if ok:
+            return (y if k == 0 else y / tau), st
+        s *= 2
+    return (y if k == 0 else y / tau), st

@@ -113,6 +113,41 @@ def divided_differences(k: int, delta: float, c: float, gamma: float,
         return np.array([float(v) for v in d], dtype=np.float64)
 
 
+def phi_mpc(k: int, z):
+    """phi_k(z) in mpmath arithmetic for complex ``z`` (an mpc)."""
+    z = mpmath.mpc(z)
+    if k == 0:
+        return mpmath.exp(z)
+    if abs(z) < mpmath.mpf("0.5"):
+        term = mpmath.mpf(1) / mpmath.factorial(k)
+        total = term
+        i = 0
+        while abs(term) > mpmath.mpf(10) ** (-(MP_DPS + 5)):
+            i += 1
+            term = term * z / (i + k)
+            total += term
+        return total
+    val = mpmath.expm1(z) / z
+    for j in range(1, k):
+        val = (val - mpmath.mpf(1) / mpmath.factorial(j)) / z
+    return val
+
+
+def divided_differences_skew(k: int, delta: float, c: float, gamma: float,
+                             xi: np.ndarray) -> np.ndarray:
+    """Divided differences of ``f(x) = phi_k(-i delta (c + gamma x))`` at the
+    real nodes ``xi`` (complex128 out; 80 digits).  With H Hermitian and its
+    spectrum in [a, b] = [c - 2 gamma, c + 2 gamma], ``(H - cI)/gamma`` has
+    its spectrum in [-2, 2] and the interpolant evaluated there approximates
+    ``phi_k(-i delta H)``: Sec. II-C's products (alpha A + beta I) x with
+    K = C, where alpha and beta stay real and the coefficients are complex."""
+    with mpmath.workdps(MP_DPS):
+        x = [mpmath.mpf(float(v)) for v in xi]
+        dl, cc, gg = mpmath.mpf(float(delta)), mpmath.mpf(float(c)), mpmath.mpf(float(gamma))
+        d = dd_recurrence([phi_mpc(k, mpmath.mpc(0, -1) * dl * (cc + gg * t)) for t in x], x)
+        return np.array([complex(v) for v in d], dtype=np.complex128)
+
+
 def dd_recurrence(values, nodes):
     """Newton divided differences ``f[x_0..x_j]``, ``j = 0..m-1``, from the
     values ``f(x_i)`` by the textbook in-place recurrence
@@ -142,5 +177,6 @@ def newton_eval(d: np.ndarray, xi: np.ndarray, x) -> np.ndarray:
     return total
 
 
-__all__ = ["leja_points", "phi", "phi_mp", "divided_differences", "dd_recurrence", "newton_eval",
+__all__ = ["leja_points", "phi", "phi_mp", "phi_mpc", "divided_differences",
+           "divided_differences_skew", "dd_recurrence", "newton_eval",
            "MP_DPS", "TIE_RTOL"]

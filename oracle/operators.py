@@ -146,10 +146,14 @@ def gershgorin_interval(A) -> tuple[float, float]:
     ``b = max_i (A_ii + R_i)`` with ``R_i = sum_{j != i} |A_ij|``.
 
     Sec. II-C requires an a-priori bound of the field of values; this is the
-    bound used throughout.
+    bound used throughout.  For a Hermitian A the same bound holds for its
+    real spectrum.
     """
     A = sp.csr_matrix(A)
     d = A.diagonal()
+    if np.iscomplexobj(d):
+        # Hermitian A (K = C): the diagonal is real
+        d = d.real
     absA = abs(A)
     r = np.asarray(absA.sum(axis=1)).reshape(-1) - np.abs(d)
     return float(np.min(d - r)), float(np.max(d + r))

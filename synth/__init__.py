@@ -101,6 +101,16 @@ def diffusivity_amplitudes(count: int, seed: int = 0, lo: float = 0.1,
     return _rng(seed).uniform(lo, hi, size=int(count))
 
 
+def combustion_initial(n_points: int, seed: int = 0, noise: float = 0.0) -> np.ndarray:
+    """Initial state of the combustion model: ``u0 = 1`` at every grid point
+    (the paper leaves it unstated), plus ``noise * U[-1, 1)`` per point when
+    ``noise > 0`` (so that tests see a state that is not constant)."""
+    u = np.ones(int(n_points), dtype=np.float64)
+    if noise > 0:
+        u += noise * uniform_vector(n_points, seed)
+    return u
+
+
 # ---------------------------------------------------------------------------
 # Unstructured matrix: negative graph Laplacian of a random geometric graph
 # ---------------------------------------------------------------------------
@@ -194,6 +204,82 @@ class BatchInstance:
 
     def vector(self) -> np.ndarray:
         return uniform_vector(self.n * self.n, self.seed)
+
+
+# ---------------------------------------------------------------------------
+# Complex Hermitian matrix: a spin system in a spin bath
+# ---------------------------------------------------------------------------
+
+def spin_bath_hamiltonian(n_spins: int, seed: int = 0, n_central: int = 2,
+                          bath_bonds: int = 40, anisotropy: float = 0.5,
+                          field: float = 0.3) -> CsrMatrix:
+    """Hermitian H (complex128 values) of ``n_spins`` spins 1/2 in the S^z
+    basis (basis state index = bit pattern, bit i = spin i up), stored as CSR
+    with int32 indices and sorted columns.  The paper's spin-bath matrix is
+    not given; this one has its shape and sparsity: ``n_central`` central
+    spins coupled to every bath spin, plus ``bath_bonds`` random bath-bath
+    bonds, each bond (i, j) contributing
+
+        J/2 (e^{i theta} S+_i S-_j + e^{-i theta} S-_i S+_j) + J Delta Sz_i Sz_j
+
+    with J ~ U[-1, 1], theta ~ U[0, 2 pi), Delta = ``anisotropy``, plus a
+    field h_i Sz_i, h_i ~ U[-field, field].  A flip term connects two states
+    whose bits i and j differ, so a row holds about 1 + bonds/2 entries (21
+    spins with 38 + 40 bonds: about 40 per row, as in the paper's 2^21
+    matrix with 83.9 million entries).  The values are drawn from the seed;
+    the numbers of the matrix are the Hamiltonian's definition, nothing of the
+    integration method."""
+    rng = _rng(seed)
+    n = 1 << int(n_spins)
+    bonds = [(c, b) for c in range(n_central) for b in range(n_central, n_spins)]
+    bath = list(range(n_central, n_spins))
+    seen = set(bonds)
+    while len(bonds) < n_central * (n_spins - n_central) + bath_bonds and len(bath) >= 2:
+        i, j = sorted(rng.choice(bath, size=2, replace=False).tolist())
+        if (i, j) not in seen:
+            seen.add((i, j))
+            bonds.append((i, j))
+    J = rng.uniform(-1.0, 1.0, size=len(bonds))
+    theta = rng.uniform(0.0, 2.0 * math.pi, size=len(bonds))
+    h = rng.uniform(-field, field, size=n_spins)
+    states = np.arange(n, dtype=np.int64)
+    spin = lambda i: ((states >> i) & 1).astype(np.float64) - 0.5      # S^z eigenvalue
+    diag = np.zeros(n)
+    for i in range(n_spins):
+        diag += h[i] * spin(i)
+    nb = len(bonds)
+    cols = np.full((n, nb + 1), -1, dtype=np.int64)
+    vals = np.zeros((n, nb + 1), dtype=np.complex128)
+    for q, ((i, j), Jq, tq) in enumerate(zip(bonds, J, theta)):
+        si, sj = spin(i), spin(j)
+        diag += Jq * anisotropy * si * sj
+        # <new| S+_i S-_j |old> = 1 when spin i is down and spin j up in |old>
+        mask = (1 << i) | (1 << j)
+        # row r = new state: H[new, old] = J/2 e^{i theta} for the raising of i
+        raised = (si > 0) & (sj < 0)          # new states reached by S+_i S-_j
+        cols[raised, q] = states[raised] ^ mask
+        vals[raised, q] = 0.5 * Jq * np.exp(1j * tq)
+        lowered = (si < 0) & (sj > 0)         # new states reached by S-_i S+_j
+        cols[lowered, q] = states[lowered] ^ mask
+        vals[lowered, q] = 0.5 * Jq * np.exp(-1j * tq)
+    cols[:, nb] = states
+    vals[:, nb] = diag
+    order = np.argsort(np.where(cols < 0, n, cols), axis=1, kind="stable")
+    cols = np.take_along_axis(cols, order, axis=1)
+    vals = np.take_along_axis(vals, order, axis=1)
+    keep = cols >= 0
+    counts = keep.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    return CsrMatrix(n, rowptr.astype(np.int32), cols[keep].astype(np.int32),
+                     vals[keep], {"spins": n_spins, "bonds": bonds, "J": J, "theta": theta,
+                                  "h": h, "anisotropy": anisotropy, "kind": "spin bath"})
+
+
+def complex_uniform_vector(n: int, seed: int = 0) -> np.ndarray:
+    """complex128 values with real and imaginary parts uniform in [-1, 1)."""
+    r = _rng(seed).uniform(-1.0, 1.0, size=(int(n), 2))
+    return (r[:, 0] + 1j * r[:, 1]).astype(np.complex128)
 
 
 def batched_instances(count: int = 256, seed: int = 0, nmin: int = 64,
