@@ -152,12 +152,17 @@ def run_gpu(args, dtype: str):
 
 
 def run_learned(args):
-    """Learned vs plain on held-out steps (the step-selector workload):
-    log `train_steps` plain exponential Euler steps of the same 256^3 problem
-    over trajectories whose diffusivity amplitude is drawn from [0.1, 0.9]
-    (seeded), train the selector network on the GPU with the library's
-    kernels, then run `eval_steps` held-out steps both ways from the same
-    states, at the same tolerance."""
+    """Learned vs plain (the step-selector workload): exponential Euler steps
+    of the same 256^3 problem over trajectories whose diffusivity amplitude
+    is drawn from [0.1, 0.9] (seeded) and whose step size changes from step
+    to step, tau (b - a) log-uniform in [10, 1000] (so the plain method has
+    no degree hint and takes up to 10 substeps).  `train_steps` logged plain
+    steps, each labelled with the substep count that needed the fewest
+    products among those that converge, train the network on the GPU with
+    the library's kernels; `eval_steps` held-out steps then run both ways
+    from the same states at the same tolerance, every fifth one also against
+    a tol 1e-13 reference.  The same network is also evaluated on held-out
+    steps of fixed size tau = 1e-5 (tau (b - a) about 12)."""
     import numpy as np
     import torch
     import paper_1309_4616_amd as E
@@ -169,22 +174,38 @@ def run_learned(args):
     n_train = max(1, args.train_steps // per)
     n_eval = max(1, args.eval_steps // per)
     amps = synth.diffusivity_amplitudes(n_train + n_eval, seed=2024)
+    rng = np.random.default_rng(np.random.SeedSequence(77))
 
     def make_op(amp):
         coef = synth.sine_coefficient(n, float(amp))
         return E.StencilOp((n, n, n), (h, h, h), "neumann0",
                            coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
 
+    def draw_tau(a, b):
+        return float(np.exp(rng.uniform(np.log(10.0), np.log(1000.0)))) / (b - a)
+
     X, Y = [], []
     t0 = time.perf_counter()
     for k in range(n_train):
         op = make_op(amps[k])
+        a, b = op.interval()
+        ws = op.workspace("f64")
         u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=1000 + k), device="cuda:0")
         for _ in range(min(per, args.train_steps)):
-            st = E.expeuler_step(op, args.tau, u, tol=args.tol)
-            X.append(E.selector.features(st, args.tau))
-            Y.append(E.selector.targets(st))
-        del op
+            tau = draw_tau(a, b)
+            L = tau * (b - a)
+
+            def forced(s, u=u, tau=tau, L=L, op=op, ws=ws):
+                try:
+                    return E.expeuler_step(op, tau, u.clone(), tol=args.tol, ws=ws, params=E.LejaParams(
+                        l_max=E.selector.forced_substeps_l_max(L, s), max_retries=0))
+                except E.ExpiError:
+                    return None
+            st = E.expeuler_step(op, tau, u, tol=args.tol, ws=ws)
+            lab, _ = E.selector.best_label(forced, L, st["substeps"], st)
+            X.append(E.selector.features(st, tau))
+            Y.append(lab)
+        del op, ws
     log_s = time.perf_counter() - t0
     X, Y = np.array(X), np.array(Y)
     t0 = time.perf_counter()
@@ -193,42 +214,61 @@ def run_learned(args):
     train_s = time.perf_counter() - t0
     sel = E.selector.pack(net, norms)
     lp = E.LejaParams(selector=sel, selector_hidden=64)
-    res = {"plain": {"mv": 0, "tests": 0, "t": 0.0}, "learned": {"mv": 0, "tests": 0, "t": 0.0}}
-    fallbacks = 0
-    max_diff = 0.0
-    steps = 0
-    for k in range(n_eval):
-        op = make_op(amps[n_train + k])
-        ws = op.workspace("f64")
-        u0 = torch.as_tensor(synth.gaussian_bump_3d(n, seed=5000 + k), device="cuda:0")
-        up, ul = u0.clone(), u0.clone()
-        E.expeuler_step(op, args.tau, u0.clone(), tol=args.tol, ws=ws)   # interval, hints
-        for _ in range(min(per, args.eval_steps)):
-            for key, u, params in (("plain", up, None), ("learned", ul, lp)):
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                st = E.expeuler_step(op, args.tau, u, tol=args.tol, params=params, ws=ws)
-                torch.cuda.synchronize()
-                res[key]["t"] += time.perf_counter() - t1
-                res[key]["mv"] += st["matvecs"]
-                res[key]["tests"] += st["finalized"]
-                if key == "learned":
-                    fallbacks += 1 if st["fallback"] else 0
-            max_diff = max(max_diff, ((ul - up).norm() / up.norm()).item())
-            steps += 1
-        del op
-    out = {
-        "train_steps": len(X), "eval_steps": steps, "hidden": 64,
-        "log_s": log_s, "train_s": train_s, "loss_first_last": [hist[0], hist[-1]],
-        "tol": args.tol,
-        "max_rel_state_diff": max_diff,
-        "fallback_rate": fallbacks / max(steps, 1),
+
+    def evaluate(fixed_tau):
+        res = {"plain": {"mv": 0, "tests": 0, "t": 0.0, "err": 0.0},
+               "learned": {"mv": 0, "tests": 0, "t": 0.0, "err": 0.0}}
+        fallbacks = steps = fewer = 0
+        for k in range(n_eval):
+            op = make_op(amps[n_train + k])
+            a, b = op.interval()
+            ws = op.workspace("f64")
+            u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=5000 + k), device="cuda:0")
+            E.expeuler_step(op, fixed_tau or draw_tau(a, b), u.clone(), tol=args.tol, ws=ws)  # warm-up
+            for i in range(min(per, args.eval_steps)):
+                tau = fixed_tau or draw_tau(a, b)
+                ref = None
+                if i % 5 == 0:
+                    ref = u.clone()
+                    E.expeuler_step(op, tau, ref, tol=1e-13, ws=ws)
+                ul = u.clone()
+                for key, uu, params in (("plain", u, None), ("learned", ul, lp)):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    st = E.expeuler_step(op, tau, uu, tol=args.tol, params=params, ws=ws)
+                    torch.cuda.synchronize()
+                    res[key]["t"] += time.perf_counter() - t1
+                    res[key]["mv"] += st["matvecs"]
+                    res[key]["tests"] += st["finalized"]
+                    if ref is not None:
+                        res[key]["err"] = max(res[key]["err"], ((uu - ref).norm() / ref.norm()).item())
+                    if key == "learned":
+                        fallbacks += 1 if st["fallback"] else 0
+                        fewer += 1 if st["substeps"] < s_plain else 0
+                    else:
+                        s_plain = st["substeps"]
+                steps += 1
+            del op, ws
+        out = {"eval_steps": steps, "fallback_rate": fallbacks / max(steps, 1),
+               "steps_with_fewer_substeps": fewer}
+        for key in ("plain", "learned"):
+            out[key] = {"matvecs_per_step": res[key]["mv"] / steps,
+                        "stop_tests_per_step": res[key]["tests"] / steps,
+                        "ms_per_step": 1e3 * res[key]["t"] / steps,
+                        "max_err_vs_tol_1e-13": res[key]["err"]}
+        out["matvecs_ratio"] = out["learned"]["matvecs_per_step"] / out["plain"]["matvecs_per_step"]
+        out["time_ratio"] = out["learned"]["ms_per_step"] / out["plain"]["ms_per_step"]
+        return out
+
+    variable = evaluate(None)
+    fixed = evaluate(args.tau)
+    return {
+        "train_steps": len(X), "hidden": 64, "log_and_label_s": log_s, "train_s": train_s,
+        "loss_first_last": [hist[0], hist[-1]], "tol": args.tol,
+        "label": "substep count with the fewest products among those that converge",
+        "variable_tau": dict(variable, workload="tau (b - a) log-uniform in [10, 1000] per step"),
+        "fixed_tau": dict(fixed, workload=f"tau = {args.tau:g} (tau (b - a) about 12)"),
     }
-    for key in ("plain", "learned"):
-        out[key] = {"matvecs_per_step": res[key]["mv"] / steps,
-                    "stop_tests_per_step": res[key]["tests"] / steps,
-                    "ms_per_step": 1e3 * res[key]["t"] / steps}
-    return out
 
 
 def run_batched(args):
@@ -369,6 +409,164 @@ def run_csr(args):
     }
 
 
+def _time_launches(fn, reps: int) -> float:
+    """Mean milliseconds per call of fn (launches on torch's current stream),
+    timed with events around `reps` calls after two warm-up calls."""
+    import torch
+    for _ in range(2):
+        fn()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    end.record()
+    end.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def run_paper_tables(args):
+    """The paper's single-kernel experiments on this GPU (context: the
+    paper's numbers are on a Tesla C1060/C2075):
+    - Table I: one 7-point product y = (alpha A + beta I) x at 256^3 and
+      512^3, boundary handling none (interior only) or homogeneous Dirichlet,
+      FP64 and FP32; and the two inhomogeneous Dirichlet data with the data
+      evaluated inside the sweep or by a second kernel;
+    - Table II: the product with c0 D(x, y) times the Laplacian,
+      D = 1/sqrt(1 + x^2 + y^2) computed in the kernel;
+    - Table III: the combustion nonlinearity over a vector, full precision
+      and fast (hardware) exp, FP64 and FP32.
+    Algorithmic traffic: one read and one write per point (16 B FP64, 8 B
+    FP32); Gflop/s in the paper's convention of 10 flops per point."""
+    import torch
+    import paper_1309_4616_amd as E
+    rows = []
+    for n in args.table_sizes:
+        pts = n ** 3
+        h = (1.0 / (n + 1),) * 3
+        for dt, td, bpp in (("f64", torch.float64, 16), ("f32", torch.float32, 8)):
+            x = torch.rand(pts, dtype=td, device="cuda:0")
+            y = torch.empty_like(x)
+            cases = [("I", "none (interior only)", E.StencilOp((n, n, n), h, "interior_only"), None),
+                     ("I", "homogeneous Dirichlet", E.StencilOp((n, n, n), h, "dirichlet0"), None)]
+            for kind in ("z1mz_xy", "sinpiz_expmxy"):
+                for mode in ("in_kernel", "separate"):
+                    op = E.StencilOp((n, n, n), h, "dirichlet0")
+                    op.set_boundary_data(kind, mode)
+                    cases.append(("I", f"Dirichlet data {kind}, {mode}", op, None))
+            cases.append(("II", "D(x,y) Laplacian, D in kernel", E.StencilOp((n, n, n), h, "dirichlet0",
+                                                                             coef=("dlap", 1.0)), None))
+            for table, what, op, _ in cases:
+                ms = _time_launches(lambda: E.apply_op(op, 1.0, 0.5, x, y), args.table_reps)
+                rows.append({"table": table, "n": n, "dtype": dt, "case": what, "ms": ms,
+                             "gbs": bpp * pts / (ms * 1e-3) / 1e9,
+                             "gflops_10_per_point": 10 * pts / (ms * 1e-3) / 1e9})
+            del x, y
+            u = 1.0 + torch.rand(pts, dtype=td, device="cuda:0")
+            g = torch.empty_like(u)
+            for gk in ("combustion", "combustion_fast"):
+                ms = _time_launches(lambda: E.nonlinearity(gk, u, g), args.table_reps)
+                rows.append({"table": "III", "n": n, "dtype": dt, "case": gk, "ms": ms,
+                             "gbs": bpp * pts / (ms * 1e-3) / 1e9})
+            del u, g
+            torch.cuda.empty_cache()
+    return {"note": ("single launches timed with events on the stream, mean of "
+                     f"{args.table_reps} after 2 warm-ups; gbs = one read + one write per point"),
+            "rows": rows}
+
+
+def run_combustion(args):
+    """Table IV's workload: one exponential Euler step of the combustion model
+    u' = Delta u + g(u), g(u) = (2 - u)/4 exp(20 (1 - 1/u)), on the 256^3
+    interior grid with homogeneous Dirichlet boundaries (h = 1/257), u0 = 1,
+    tau = 1e-4, tol = 1e-4 (the paper's settings), FP64 and FP32 storage,
+    full and fast exp; and the second-order exponential Runge-Kutta step of
+    the same problem."""
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+    n = 256
+    op = E.StencilOp((n, n, n), (1.0 / (n + 1),) * 3, "dirichlet0")
+    u0 = torch.as_tensor(synth.combustion_initial(n ** 3), device="cuda:0")
+    out = {}
+    for dt in ("f64", "f32"):
+        for g in ("combustion", "combustion_fast"):
+            u = u0.clone()
+            E.expeuler_step(op, 1e-4, u, tol=1e-4, dtype=dt, g=g)     # warm-up
+            reps = 5
+            t = 0.0
+            for _ in range(reps):
+                u.copy_(u0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = E.expeuler_step(op, 1e-4, u, tol=1e-4, dtype=dt, g=g)
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t0
+            out[f"expeuler_{dt}_{g}"] = {"ms_per_step": 1e3 * t / reps, "matvecs": st["matvecs"],
+                                         "substeps": st["substeps"], "degree": st["degree_last"]}
+    u = u0.clone()
+    E.exprk2_step(op, 1e-4, u, tol=1e-4, g="combustion")
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = E.exprk2_step(op, 1e-4, u, tol=1e-4, g="combustion")
+    torch.cuda.synchronize()
+    out["exprk2_f64_combustion"] = {"ms_per_step": 1e3 * (time.perf_counter() - t0),
+                                    "matvecs": st["matvecs"]}
+    out["paper_table_iv"] = ("40 products per step at tol 1e-4, 1.2 s (FP64) / 210 ms (FP32) on one "
+                             "Tesla C2075; context only")
+    return out
+
+
+def run_spin_bath(args):
+    """Sec. III-D's unstructured complex workload (Table V's shape): psi(t) =
+    e^{-i t H} psi(0) for a Hermitian spin-bath matrix of `spin_spins` spins
+    (2^spins rows, about 40 stored complex entries per row at 21 spins; the
+    paper's Hamiltonian is not given, a synthetic one of the same shape
+    stands in), t = 10, tol 1e-5, FP64, one call of expi_skew_phi_action.
+    Per-product algorithmic bytes: values and columns once (20 B per stored
+    entry), row pointers (4 B per row), w read once, p read and written, w
+    written (64 B per row)."""
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+    t0 = time.perf_counter()
+    g = synth.spin_bath_hamiltonian(args.spin_spins, seed=0)
+    gen_s = time.perf_counter() - t0
+    op = E.CsrComplexOp(g.n, g.rowptr, g.colind, g.val)
+    del g.val
+    psi = torch.as_tensor(synth.complex_uniform_vector(g.n, 0), device="cuda:0")
+    psi /= psi.norm()
+    y = torch.empty_like(psi)
+    ws = op.workspace("f64")
+    params = E.LejaParams(profile=1)
+    E.skew_phi_action(op, 0, args.spin_t, psi, y=y, tol=args.spin_tol, params=params, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = E.skew_phi_action(op, 0, args.spin_t, psi, y=y, tol=args.spin_tol, params=params, ws=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nnz = op.nnz
+    per_product = 20 * nnz + 4 * (g.n + 1) + 64 * g.n
+    avg_us = 1e3 * st["newton_ms"] / max(st["timed_products"], 1)
+    return {
+        "workload": (f"e^(-i t H) psi, H Hermitian spin-bath matrix of {args.spin_spins} spins "
+                     f"(n = 2^{args.spin_spins}, {nnz / g.n:.1f} complex entries per row), "
+                     f"t = {args.spin_t:g}, tol {args.spin_tol:g}, f64"),
+        "ms": 1e3 * wall,
+        "substeps": st["substeps"],
+        "products": st["matvecs"],
+        "interval": [st["interval_a"], st["interval_b"]],
+        "product_avg_us": avg_us,
+        "product_gbs": per_product / (avg_us * 1e-6) / 1e9,
+        "product_frac": per_product / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "norm_drift": abs(y.norm().item() - 1.0),
+        "generate_s": gen_s,
+        "paper_table_v": "21 spins to t = 10 at tol 1e-5: 7.7 s FP64 on one Tesla C2075 (its own Hamiltonian); context only",
+    }
+
+
 def gpu_states(args, dtype: str, steps: int):
     """The first `steps` exponential Euler steps of the benchmark workload
     from its u0 on the GPU (the timed configuration: pair sweeps, the given
@@ -480,6 +678,15 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-csr", action="store_true")
+    ap.add_argument("--no-tables", action="store_true",
+                    help="skip the paper's single-kernel experiments (Tables I-III)")
+    ap.add_argument("--table-sizes", type=int, nargs="+", default=[256, 512])
+    ap.add_argument("--table-reps", type=int, default=10)
+    ap.add_argument("--no-combustion", action="store_true")
+    ap.add_argument("--no-spin", action="store_true")
+    ap.add_argument("--spin-spins", type=int, default=21)
+    ap.add_argument("--spin-t", type=float, default=10.0)
+    ap.add_argument("--spin-tol", type=float, default=1e-5)
     ap.add_argument("--csr-only", action="store_true",
                     help="run only the CSR leg and print its JSON (for profiling)")
     ap.add_argument("--csr-log2n", type=int, default=20)
@@ -541,6 +748,22 @@ def main():
               file=sys.stderr, flush=True)
         csr = run_csr(args)
         print(f"[bench] csr done: {csr['product_avg_us']:.1f} us per product", file=sys.stderr, flush=True)
+    tables = None
+    if not args.no_tables:
+        print("[bench] paper tables I-III: single products and the nonlinearity", file=sys.stderr, flush=True)
+        tables = run_paper_tables(args)
+        print("[bench] tables done", file=sys.stderr, flush=True)
+    comb = None
+    if not args.no_combustion:
+        print("[bench] combustion step (Table IV workload)", file=sys.stderr, flush=True)
+        comb = run_combustion(args)
+        print("[bench] combustion done", file=sys.stderr, flush=True)
+    spin = None
+    if not args.no_spin:
+        print(f"[bench] spin bath: {args.spin_spins} spins, e^(-i t H) psi", file=sys.stderr, flush=True)
+        spin = run_spin_bath(args)
+        print(f"[bench] spin bath done: {spin['ms']:.1f} ms, {spin['products']} products", file=sys.stderr,
+              flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] gpu states of the first {args.cpu_steps} steps (f64, f32)", file=sys.stderr, flush=True)
@@ -645,6 +868,12 @@ def main():
         out["batched"] = batched
     if csr:
         out["csr"] = csr
+    if tables:
+        out["paper_tables"] = tables
+    if comb:
+        out["combustion"] = comb
+    if spin:
+        out["spin_bath"] = spin
     print(json.dumps(out), flush=True)
 
 

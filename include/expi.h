@@ -72,9 +72,30 @@ extern "C" {
 #define EXPI_COEF_CONST     0 /* a = c0                                        */
 #define EXPI_COEF_SEPARABLE 1 /* a = c0 + c1 * tx[i] * ty[j] (* tz[k])          */
 #define EXPI_COEF_FIELD     2 /* a = field[index], float64, same layout as u    */
+#define EXPI_COEF_DLAP      3 /* the operator is c0 * D(x, y) times the
+                                 constant-coefficient stencil Laplacian, with
+                                 D = 1/sqrt(1 + x^2 + y^2) computed in the
+                                 kernel (Sec. III-B, Table II); grid
+                                 positions: index i at (i + 1) h (DIRICHLET0),
+                                 (i + 1/2) h (NEUMANN0), i h (INTERIOR_ONLY)  */
+
+/* Inhomogeneous Dirichlet data of Sec. III-A (the rows of Table I with
+ * boundary values f): the product becomes affine, A_0 u + b_f, where the
+ * stencil reads f at the boundary node instead of 0 (expi_op_set_boundary_data). */
+#define EXPI_BDATA_NONE          0
+#define EXPI_BDATA_Z1MZ_XY       1  /* f = z (1 - z) x y                       */
+#define EXPI_BDATA_SINPIZ_EXPMXY 2  /* f = sin(pi z) exp(-x y)                 */
+#define EXPI_BDATA_IN_KERNEL     0  /* f evaluated inside the stencil sweep    */
+#define EXPI_BDATA_SEPARATE      1  /* a second kernel adds the boundary term  */
 
 /* Pointwise nonlinearity g of u' = A u + g(u). */
-#define EXPI_G_CUBIC 0        /* g(u) = u - u^3                                */
+#define EXPI_G_CUBIC           0  /* g(u) = u - u^3                              */
+#define EXPI_G_COMBUSTION      1  /* g(u) = (2 - u)/4 exp(20 (1 - 1/u)), the
+                                     combustion model of Sec. III-C, eq. (4)-(5),
+                                     IEEE division and the library exp          */
+#define EXPI_G_COMBUSTION_FAST 2  /* the same through the hardware FP32
+                                     reciprocal and base-2 exponential (Table
+                                     III's fast math; relative error ~1e-6)     */
 
 /* ---- types -------------------------------------------------------------- */
 typedef struct expi_op expi_op;   /* opaque operator handle */
@@ -150,6 +171,18 @@ typedef struct {
      * same step size stopped at an odd degree; 1: never; 2: whenever it
      * applies.  Other values: EXPI_EINVAL. */
     int32_t fuse_start;
+    /* Learned step selector, exponential Euler steps: the largest
+     * delta*(b-a) per substep the network's substep count may reach
+     * (0: 500).  A predicted substep count s' with
+     * ceil(tau (b-a) / selector_l_max) <= s' < s (s from l_max) restarts the
+     * step with s' substeps, each run with the predicted degree and its
+     * two-term stop test; if a substep then misses the test within m_max
+     * products, the step is redone by the plain method with s substeps
+     * (counted in stats.fallback). */
+    double  selector_l_max;
+    /* Optional device float[8]: the selector kernel writes the raw features
+     * of its last prediction there (for checking them against the host). */
+    void   *selector_features;
 } expi_params;
 
 /* ---- operators ---------------------------------------------------------- */
@@ -170,10 +203,31 @@ int expi_op_create_stencil(expi_op **op, int dim, const int64_t *n, const double
                            const double *tab_x, const double *tab_y, const double *tab_z,
                            const double *field);
 
+/* Boundary data of a 3D DIRICHLET0 stencil (node grid, boundary nodes at
+ * coordinates 0 and (n_d + 1) h_d): kind EXPI_BDATA_*, mode
+ * EXPI_BDATA_IN_KERNEL (f evaluated by the sweep at boundary-adjacent
+ * points) or EXPI_BDATA_SEPARATE (a second launch over the boundary layer adds
+ * the term; Sec. III-A compares the two).  Afterwards apply_op computes
+ * y = alpha (A_0 x + b_f) + beta x, and expeuler_step / exprk2_step solve
+ * u' = A_0 u + b_f + g(u).  phi_action is unaffected (it uses the linear
+ * part A_0).  EXPI_EINVAL for a CSR operator, 2D, another boundary condition,
+ * EXPI_COEF_DLAP, or an unknown kind/mode.  EXPI_BDATA_NONE switches it off. */
+int expi_op_set_boundary_data(expi_op *op, int kind, int mode);
+
 /* CSR matrix (Sec. III-D): n rows, nnz entries; rowptr int32[n+1],
  * colind int32[nnz] (sorted per row), val float64[nnz]; device, borrowed. */
 int expi_op_create_csr(expi_op **op, int64_t n, int64_t nnz, const int32_t *rowptr,
                        const int32_t *colind, const double *val);
+
+/* Complex Hermitian matrix H in CSR (Sec. II-C allows K = C; Sec. III-D's
+ * spin system is stored this way): val holds complex128 values as nnz
+ * interleaved (re, im) float64 pairs; rowptr, colind as for
+ * expi_op_create_csr.  The operator serves apply_op (x, y complex128 pairs,
+ * EXPI_F64 only; alpha, beta real) and expi_skew_phi_action; phi_action and
+ * the integrator steps refuse it.  H is assumed Hermitian: its Gershgorin
+ * interval uses the real part of the diagonal. */
+int expi_op_create_csr_complex(expi_op **op, int64_t n, int64_t nnz, const int32_t *rowptr,
+                               const int32_t *colind, const double *val);
 
 int expi_op_destroy(expi_op *op);
 
@@ -224,8 +278,10 @@ int apply_op(const expi_op *op, double alpha, double beta, const void *x, void *
              int dtype, void *stream);
 
 /* y = phi_k(tau A) v by Newton interpolation at Leja points (Sec. III-C,
- * Sec. II-C), k = 0 (exponential) or 1 (any substep count) or k >= 2 (one
- * substep only, else EXPI_EUNSUPPORTED).  v, y: float64 device arrays; y must
+ * Sec. II-C), 0 <= k <= 20, any substep count.  Substeps of phi_k, k >= 1,
+ * follow y(t) = t^k phi_k(tA) v, the solution of y' = A y + t^(k-1)/(k-1)! v,
+ * y(0) = 0: each substep after the first takes k extra products for its
+ * start vector (matvecs counts them).  v, y: float64 device arrays; y must
  * not alias v.  tol: relative 2-norm tolerance of the two-term stop test per
  * substep.  dtype: storage of the Newton vectors (EXPI_F64 / EXPI_F32).
  * ws: device workspace of at least expi_workspace_bytes(op, dtype) bytes,
@@ -235,14 +291,50 @@ int phi_action(expi_op *op, int k, double tau, const double *v, double *y, doubl
                int dtype, const expi_params *params, void *ws, size_t ws_bytes,
                expi_stats *st, void *stream);
 
+/* y = phi_k(-i tau H) v for a Hermitian H (complex CSR operator), k = 0
+ * (y = e^{-i tau H} v, the solution of psi' = -i H psi at tau) or 1.  The
+ * Newton recurrence is that of phi_action with A replaced by H: real
+ * products (alpha H + beta_j I) x of complex vectors (eq. (3) with K = C),
+ * real Leja points of [-2, 2] mapped to the Gershgorin interval [a, b] of H,
+ * and complex divided differences of x -> phi_k(-i delta (c + gamma x)).
+ * Substeps as in phi_action (s = ceil(tau (b - a) / l_max)); for k = 1,
+ * y(t) = t phi_1(-i t H) v solves y' = -i H y + v.  v, y: complex128 device
+ * arrays as interleaved (re, im) pairs; FP64 storage; ws: at least
+ * expi_workspace_bytes(op, EXPI_F64) bytes.  Errors as for phi_action
+ * (EXPI_EINVAL for a real operator or k not 0/1). */
+int expi_skew_phi_action(expi_op *op, int k, double tau, const double *v, double *y, double tol,
+                         const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
+                         void *stream);
+
 /* One exponential Euler step (eq. (2)) for u' = A u + g(u), written as
  * u <- u + tau phi_1(tau A) (A u + g(u)), which equals eq. (2) in exact
  * arithmetic and needs one phi_1 action.  u: float64 device array, updated in
  * place only when the step converged (left unchanged on any error).
- * nonlin: EXPI_G_CUBIC.  Other arguments as for phi_action. */
+ * nonlin: EXPI_G_CUBIC, EXPI_G_COMBUSTION or EXPI_G_COMBUSTION_FAST.  Other
+ * arguments as for phi_action. */
 int expeuler_step(expi_op *op, int nonlin, double tau, double *u, double tol, int dtype,
                   const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
                   void *stream);
+
+/* One step of the second-order exponential Runge-Kutta method with c_2 = 1
+ * (a higher-order exponential integrator of the kind Sec. II-C points to):
+ *   U = u + tau phi_1(tau A)(A u + g(u))          (the exponential Euler step)
+ *   u <- U + tau phi_2(tau A)(g(U) - g(u)).
+ * Two Newton loops (phi_1, then phi_2).  ws: at least
+ * expi_exprk2_workspace_bytes(op, dtype) bytes (phi_action's workspace plus
+ * one float64 vector).  u is overwritten by the result only when both
+ * actions converged; on an error in the second one it holds the stage U.
+ * st sums the counts of both loops (degree_last: the phi_2 loop's). */
+size_t expi_exprk2_workspace_bytes(const expi_op *op, int dtype);
+int exprk2_step(expi_op *op, int nonlin, double tau, double *u, double tol, int dtype,
+                const expi_params *params, void *ws, size_t ws_bytes, expi_stats *st,
+                void *stream);
+
+/* g = nonlinearity(u) pointwise over n values (the kernel Table III times):
+ * u, g device arrays of float64 (dtype EXPI_F64) or float32 (EXPI_F32); g
+ * may equal u (in place) but must not overlap it otherwise.  One launch on
+ * `stream`, no synchronisation. */
+int expi_nonlinearity(int nonlin, int64_t n, const void *u, void *g, int dtype, void *stream);
 
 /* ---- allocation-free variant of phi_action ------------------------------- */
 
@@ -399,6 +491,12 @@ int expi_leja_points(double *out, int count);
  * spectrum in [-2, 2]).  count <= 256. */
 int expi_divided_differences(int k, double delta, double c, double gamma, int count,
                              double *out);
+
+/* Complex divided differences f[xi_0..xi_j], j < count, of
+ * f(x) = phi_k(-i delta (c + gamma x)) (real parts into re, imaginary parts
+ * into im): the coefficients expi_skew_phi_action uses.  count <= 256. */
+int expi_divided_differences_skew(int k, double delta, double c, double gamma, int count,
+                                  double *re, double *im);
 
 /* Thread-local message of the last error (never NULL). */
 const char *expi_last_error(void);

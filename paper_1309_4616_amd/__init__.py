@@ -12,12 +12,13 @@ from __future__ import annotations
 import ctypes
 
 from . import autotune, selector
-from ._binding import (COEF_CONST, COEF_FIELD, COEF_SEPARABLE, F32, F64, G_CUBIC, BCS, EXPORTS,
+from ._binding import (BDATA, BDATA_MODES, COEF_CONST, COEF_DLAP, COEF_FIELD, COEF_SEPARABLE, F32, F64,
+                       G_CUBIC, NONLIN, BCS, EXPORTS,
                        NOALLOC_SCRATCH_BYTES, BatchStat, ExpiError, LejaParams, Stats, check,
-                       divided_differences, leja_points, lib)
+                       divided_differences, divided_differences_skew, leja_points, lib)
 
-__all__ = ["StencilOp", "CsrOp", "apply_op", "phi_action", "phi_action_noalloc", "noalloc_init",
-           "expeuler_step", "leja_points",
+__all__ = ["StencilOp", "CsrOp", "CsrComplexOp", "skew_phi_action", "apply_op", "phi_action", "phi_action_noalloc", "noalloc_init",
+           "expeuler_step", "exprk2_step", "nonlinearity", "leja_points",
            "divided_differences", "ExpiError", "LejaParams", "workspace", "F64", "F32",
            "autotune", "selector", "Batch"]
 
@@ -113,7 +114,8 @@ class StencilOp(_Op):
     shape: (nx, ny) or (nx, ny, nz), x fastest; h: spacing per axis.
     bc: 'dirichlet0', 'neumann0' or 'interior_only'.
     coef: None (a = 1), a float (a = c0), a tuple ('separable', c0, c1, tx, ty[, tz])
-    giving a = c0 + c1 tx[i] ty[j] tz[k], or an array of the grid's size.
+    giving a = c0 + c1 tx[i] ty[j] tz[k], ('dlap', c0) for c0 D(x, y) times the
+    Laplacian (D = 1/sqrt(1 + x^2 + y^2), Sec. III-B), or an array of the grid's size.
     """
 
     def __init__(self, shape, h, bc="dirichlet0", coef=None, device="cuda:0"):
@@ -137,6 +139,9 @@ class StencilOp(_Op):
             pass
         elif isinstance(coef, (int, float)):
             c0 = float(coef)
+        elif isinstance(coef, tuple) and coef and coef[0] == "dlap":
+            kind = COEF_DLAP
+            c0 = float(coef[1]) if len(coef) > 1 else 1.0
         elif isinstance(coef, tuple) and coef and coef[0] == "separable":
             kind = COEF_SEPARABLE
             c0, c1 = float(coef[1]), float(coef[2])
@@ -154,6 +159,15 @@ class StencilOp(_Op):
             check(lib().expi_op_create_stencil(ctypes.byref(self._h), dim, n, hh, BCS[bc], kind,
                                                c0, c1, ptr(tabs[0]), ptr(tabs[1]), ptr(tabs[2]),
                                                ptr(field)))
+
+
+    def set_boundary_data(self, kind, mode: str = "in_kernel") -> None:
+        """Inhomogeneous Dirichlet data (3D dirichlet0): kind 'z1mz_xy',
+        'sinpiz_expmxy' or None; mode 'in_kernel' or 'separate'
+        (expi_op_set_boundary_data)."""
+        if kind not in BDATA or mode not in BDATA_MODES:
+            raise ValueError(f"boundary data {kind!r} / mode {mode!r} unknown")
+        check(lib().expi_op_set_boundary_data(self._h, BDATA[kind], BDATA_MODES[mode]))
 
 
 class CsrOp(_Op):
@@ -175,6 +189,48 @@ class CsrOp(_Op):
                                        ctypes.c_void_p(va.data_ptr())))
 
 
+class CsrComplexOp(_Op):
+    """Hermitian CSR matrix with complex128 values (int32 indices); vectors
+    are complex128 tensors (stored as (re, im) float64 pairs)."""
+
+    def __init__(self, n, rowptr, colind, val, device="cuda:0"):
+        super().__init__()
+        torch = _torch()
+        self.device = torch.device(device)
+        rp = torch.as_tensor(rowptr).to(device=self.device, dtype=torch.int32).contiguous()
+        ci = torch.as_tensor(colind).to(device=self.device, dtype=torch.int32).contiguous()
+        va = torch.as_tensor(val).to(device=self.device, dtype=torch.complex128).contiguous()
+        if rp.numel() != n + 1 or ci.numel() != va.numel():
+            raise ValueError("inconsistent CSR array sizes")
+        self._keep += [rp, ci, va]
+        self.nnz = int(va.numel())
+        check(lib().expi_op_create_csr_complex(ctypes.byref(self._h), int(n), self.nnz,
+                                               ctypes.c_void_p(rp.data_ptr()),
+                                               ctypes.c_void_p(ci.data_ptr()),
+                                               ctypes.c_void_p(va.data_ptr())))
+
+
+def skew_phi_action(op: CsrComplexOp, k: int, tau: float, v, y=None, tol: float = 1e-10,
+                    params: LejaParams | None = None, ws=None, stream=None):
+    """y = phi_k(-i tau H) v (k = 0 or 1) for a Hermitian complex CSR operator;
+    v complex128 on the op's device.  Returns (y, stats dict)."""
+    torch = _torch()
+    if v.dtype != torch.complex128:
+        raise ValueError("v must be complex128")
+    if y is None:
+        y = torch.empty_like(v)
+    if ws is None:
+        ws = op.workspace("f64")
+    st = Stats()
+    cp = params.to_c() if params is not None else None
+    check(lib().expi_skew_phi_action(op.handle, int(k), float(tau), ctypes.c_void_p(v.data_ptr()),
+                                     ctypes.c_void_p(y.data_ptr()), float(tol),
+                                     ctypes.byref(cp) if cp is not None else None,
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(st),
+                                     _stream_ptr(stream, op.device)))
+    return y, st.as_dict()
+
+
 def workspace(nbytes: int, device="cuda:0"):
     """Device byte buffer, 256-byte aligned, for phi_action/expeuler_step."""
     torch = _torch()
@@ -187,7 +243,7 @@ def workspace(nbytes: int, device="cuda:0"):
 def apply_op(op: _Op, alpha: float, beta: float, x, y=None, stream=None):
     """y = (alpha A + beta I) x (eq. (3)); x float64 or float32 on the op's device."""
     torch = _torch()
-    code = F32 if x.dtype == torch.float32 else F64
+    code = F32 if x.dtype == torch.float32 else F64     # complex128 is F64 pairs
     if y is None:
         y = torch.empty_like(x)
     check(lib().apply_op(op.handle, float(alpha), float(beta), ctypes.c_void_p(x.data_ptr()),
@@ -238,20 +294,60 @@ def phi_action_noalloc(op: _Op, k: int, tau: float, v, y, tol: float = 1e-10, dt
     return st.as_dict()
 
 
+def _nonlin_code(g) -> int:
+    if g not in NONLIN:
+        raise ValueError(f"nonlinearity must be one of {sorted(NONLIN)}, got {g!r}")
+    return NONLIN[g]
+
+
 def expeuler_step(op: _Op, tau: float, u, tol: float = 1e-10, dtype="f64",
-                  params: LejaParams | None = None, ws=None, stream=None):
-    """One exponential Euler step for u' = A u + u - u^3, in place on u; returns stats."""
+                  params: LejaParams | None = None, ws=None, stream=None, g="cubic"):
+    """One exponential Euler step for u' = A u + g(u), in place on u; g is
+    'cubic' (u - u^3), 'combustion' or 'combustion_fast'; returns stats."""
     code = _dtype_code(dtype)
     if ws is None:
         ws = op.workspace(code)
     st = Stats()
     cp = params.to_c() if params is not None else None
-    rc = lib().expeuler_step(op.handle, G_CUBIC, float(tau), ctypes.c_void_p(u.data_ptr()),
+    rc = lib().expeuler_step(op.handle, _nonlin_code(g), float(tau), ctypes.c_void_p(u.data_ptr()),
                              float(tol), code, ctypes.byref(cp) if cp is not None else None,
                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(st),
                              _stream_ptr(stream, op.device))
     check(rc)
     return st.as_dict()
+
+
+def exprk2_step(op: _Op, tau: float, u, tol: float = 1e-10, dtype="f64",
+                params: LejaParams | None = None, ws=None, stream=None, g="cubic"):
+    """One step of the second-order exponential Runge-Kutta method (exprk2_step),
+    in place on u; returns stats."""
+    code = _dtype_code(dtype)
+    if ws is None:
+        key = ("rk2", code)
+        ws = op._ws.get(key)
+        if ws is None:
+            ws = workspace(int(lib().expi_exprk2_workspace_bytes(op.handle, code)), op.device)
+            op._ws[key] = ws
+    st = Stats()
+    cp = params.to_c() if params is not None else None
+    rc = lib().exprk2_step(op.handle, _nonlin_code(g), float(tau), ctypes.c_void_p(u.data_ptr()),
+                           float(tol), code, ctypes.byref(cp) if cp is not None else None,
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(st),
+                           _stream_ptr(stream, op.device))
+    check(rc)
+    return st.as_dict()
+
+
+def nonlinearity(g: str, u, out=None, stream=None):
+    """out = g(u) pointwise on the device (expi_nonlinearity); u float64 or float32."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(u)
+    code = F32 if u.dtype == torch.float32 else F64
+    check(lib().expi_nonlinearity(_nonlin_code(g), u.numel(), ctypes.c_void_p(u.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), code,
+                                  _stream_ptr(stream, u.device)))
+    return out
 
 
 class Batch:

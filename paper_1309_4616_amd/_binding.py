@@ -18,8 +18,11 @@ ERRORS = {-1: "EINVAL", -2: "EALIAS", -3: "EWORKSPACE", -4: "ENOTCONV",
           -5: "ENONFINITE", -6: "EHIP", -7: "EUNSUPPORTED"}
 F64, F32 = 0, 1
 BCS = {"dirichlet0": 0, "neumann0": 1, "interior_only": 2}
-COEF_CONST, COEF_SEPARABLE, COEF_FIELD = 0, 1, 2
-G_CUBIC = 0
+COEF_CONST, COEF_SEPARABLE, COEF_FIELD, COEF_DLAP = 0, 1, 2, 3
+BDATA = {None: 0, "none": 0, "z1mz_xy": 1, "sinpiz_expmxy": 2}
+BDATA_MODES = {"in_kernel": 0, "separate": 1}
+G_CUBIC, G_COMBUSTION, G_COMBUSTION_FAST = 0, 1, 2
+NONLIN = {"cubic": G_CUBIC, "combustion": G_COMBUSTION, "combustion_fast": G_COMBUSTION_FAST}
 
 # every symbol include/expi.h declares
 EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "expi_op_size",
@@ -32,7 +35,9 @@ EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "e
            "expi_batch_launch_persistent", "expi_batch_capture_persistent",
            "expi_batch_autotune", "expi_batch_get_tiles", "expi_mlp_param_count", "expi_mlp_scratch_floats",
            "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam",
-           "expi_noalloc_init", "phi_action_noalloc")
+           "expi_noalloc_init", "phi_action_noalloc", "exprk2_step",
+           "expi_exprk2_workspace_bytes", "expi_nonlinearity", "expi_op_set_boundary_data",
+           "expi_op_create_csr_complex", "expi_skew_phi_action", "expi_divided_differences_skew")
 
 # size of the library's scratch array behind phi_action_noalloc
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -81,7 +86,8 @@ class Params(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("interval_a", ctypes.c_double),
                 ("interval_b", ctypes.c_double), ("selector", ctypes.c_void_p),
                 ("selector_hidden", ctypes.c_int32), ("no_pairs", ctypes.c_int32),
-                ("fuse_start", ctypes.c_int32)]
+                ("fuse_start", ctypes.c_int32), ("selector_l_max", ctypes.c_double),
+                ("selector_features", ctypes.c_void_p)]
 
 
 @dataclass
@@ -95,6 +101,8 @@ class LejaParams:
     selector_hidden: int = 64
     pairs: bool = True               # fuse consecutive Newton products where supported
     fuse_start: int = 0              # Euler steps: 0 by degree parity, 1 never, 2 always
+    selector_l_max: float = 0.0      # largest delta (b - a) the selector may choose (0: 500)
+    selector_features: object = None  # device float32 tensor of 8: features of the last prediction
 
     def to_c(self) -> Params:
         p = Params()
@@ -104,6 +112,9 @@ class LejaParams:
         p.profile = int(self.profile)
         p.no_pairs = 0 if self.pairs else 1
         p.fuse_start = int(self.fuse_start)
+        p.selector_l_max = float(self.selector_l_max)
+        if self.selector_features is not None:
+            p.selector_features = ctypes.c_void_p(self.selector_features.data_ptr())
         if self.selector is not None:
             p.selector = ctypes.c_void_p(self.selector.data_ptr())
             p.selector_hidden = int(self.selector_hidden)
@@ -159,6 +170,22 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(Params), c_void_p, c_size_t, ctypes.POINTER(Stats),
                                 c_void_p]
     L.expeuler_step.restype = c_int
+    L.exprk2_step.argtypes = L.expeuler_step.argtypes
+    L.exprk2_step.restype = c_int
+    L.expi_exprk2_workspace_bytes.argtypes = [c_void_p, c_int]
+    L.expi_exprk2_workspace_bytes.restype = c_size_t
+    L.expi_nonlinearity.argtypes = [c_int, ctypes.c_int64, c_void_p, c_void_p, c_int, c_void_p]
+    L.expi_nonlinearity.restype = c_int
+    L.expi_op_create_csr_complex.argtypes = L.expi_op_create_csr.argtypes
+    L.expi_op_create_csr_complex.restype = c_int
+    L.expi_skew_phi_action.argtypes = [c_void_p, c_int, c_double, c_void_p, c_void_p, c_double,
+                                       ctypes.POINTER(Params), c_void_p, c_size_t,
+                                       ctypes.POINTER(Stats), c_void_p]
+    L.expi_skew_phi_action.restype = c_int
+    L.expi_divided_differences_skew.argtypes = [c_int, c_double, c_double, c_double, c_int, dblp, dblp]
+    L.expi_divided_differences_skew.restype = c_int
+    L.expi_op_set_boundary_data.argtypes = [c_void_p, c_int, c_int]
+    L.expi_op_set_boundary_data.restype = c_int
     L.expi_noalloc_init.argtypes = []
     L.expi_noalloc_init.restype = c_int
     L.phi_action_noalloc.argtypes = [c_void_p, c_int, c_double, c_void_p, c_void_p, c_double, c_int,
@@ -240,3 +267,14 @@ def divided_differences(k: int, delta: float, c: float, gamma: float, count: int
     check(lib().expi_divided_differences(int(k), float(delta), float(c), float(gamma), int(count),
                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+def divided_differences_skew(k: int, delta: float, c: float, gamma: float, count: int):
+    """Complex divided differences of x -> phi_k(-i delta (c + gamma x))."""
+    import numpy as np
+    re = np.empty(count, dtype=np.float64)
+    im = np.empty(count, dtype=np.float64)
+    P = ctypes.POINTER(ctypes.c_double)
+    check(lib().expi_divided_differences_skew(int(k), float(delta), float(c), float(gamma), int(count),
+                                              re.ctypes.data_as(P), im.ctypes.data_as(P)))
+    return re + 1j * im

@@ -65,7 +65,8 @@ WsLayout layout(const Op& op, int dtype) {
         off += align256(bytes);
         return o;
     };
-    const size_t n = (size_t)op.size;
+    // complex operators: every vector holds (re, im) pairs
+    const size_t n = (size_t)op.size * (op.kind == 2 ? 2 : 1);
     const size_t tw = (dtype == EXPI_F32) ? 4 : 8;
     L.state = take(256);
     L.partials = take(partials_bytes(op));
@@ -182,6 +183,8 @@ struct Params {
     int hidden = 0;
     bool pairs = true;
     int fuse_start = 0;
+    double sel_l_max = 500.0;      // largest delta (b - a) a predicted substep count may give
+    float* sel_features = nullptr;
 };
 
 int read_params(const expi_params* p, Params* out) {
@@ -198,7 +201,11 @@ int read_params(const expi_params* p, Params* out) {
         q.hidden = p->selector_hidden;
         q.pairs = p->no_pairs == 0;
         q.fuse_start = p->fuse_start;
+        if (p->selector_l_max != 0.0) q.sel_l_max = p->selector_l_max;
+        q.sel_features = static_cast<float*>(p->selector_features);
     }
+    if (!(q.sel_l_max > 0) || !std::isfinite(q.sel_l_max))
+        return fail(EXPI_EINVAL, "params.selector_l_max must be positive and finite (or 0)");
     if (q.fuse_start < 0 || q.fuse_start > 2) return fail(EXPI_EINVAL, "params.fuse_start must be 0, 1 or 2");
     if (q.profile < 0 || q.profile > 2) return fail(EXPI_EINVAL, "params.profile must be 0, 1 or 2");
     if (q.selector && (q.hidden < 1 || q.hidden > 256))
@@ -297,6 +304,7 @@ struct LoopOut {
     double rnorm = 0;     // ||r||
     double hist[kHist] = {0, 0, 0, 0, 0};
     int pred_m = 0, pred_s = 0;
+    int restart_s = 0;    // learned mode: restart the step with this many substeps
     int fallback = 0;     // learned mode: the prediction fell short
     int finalized = 0;    // products followed by a norm reduction and stop test
     double fix = 0;       // p holds d_{m+1} w_{m+1} too many (pair stopped at its first product)
@@ -322,6 +330,15 @@ struct Ctx {
     int hidden;
     double ia, ib, tau;
     bool pairs;             // fuse consecutive products into pair sweeps
+    // learned mode: a degree predicted earlier for this step (skip the
+    // probe and the network), and whether the probe's prediction may change
+    // the substep count: a prediction in [s_min, s_cur) ends the loop
+    // (LoopOut::restart_s) so the caller can restart with fewer substeps
+    int fixed_m = 0;
+    bool decide_s = false;
+    int s_cur = 1, s_min = 1;
+    float* features = nullptr;   // device float[8]: features of the prediction
+    std::vector<double> di;      // imaginary parts of d (complex operators; else empty)
 };
 
 // First product reads `src` (storage code tin) and writes w_1 to w0 and p to
@@ -357,6 +374,10 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
     a.beta = -(C.c / C.gamma + C.xi[0]);
     a.d0 = d[0];
     a.d1 = d[1];
+    if (!C.di.empty()) {
+        a.d0i = C.di[0];
+        a.d1i = C.di[1];
+    }
     a.guard = 0;
     int cur = 0;   // w[cur] holds the latest w
 
@@ -433,6 +454,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         a.j = j;
         a.beta = -(C.c / C.gamma + C.xi[j]);
         a.d1 = d[j + 1];
+        if (!C.di.empty()) a.d1i = C.di[j + 1];
         a.guard = 1;
         a.tol = tol_now;
         const bool tm = timing();
@@ -507,20 +529,28 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
     NewtonState last{};
     bool finished = false;
     bool learned_tail = false;
-    if (C.selector && C.m_max >= 6) {
+    bool have_pred = false;
+    int pred = 0;
+    if (C.selector && C.m_max >= 6 && C.fixed_m > 0) {
+        // learned mode with the degree already predicted for this step
+        pred = C.fixed_m;
+        have_pred = true;
+        out->pred_m = pred;
+    } else if (C.selector && C.m_max >= 6) {
         // Learned mode: four products with stop tests give the features; the
-        // network predicts the degree m; products up to m skip the norm
-        // reductions except the last two, whose two-term stop test judges the
-        // prediction.  If it is not met the plain loop below continues.
-        // products up to 3 (at least) with stop tests (t_0..t_4 are recorded
-        // by the tests); pair sweeps where allowed, so that a loop opened by
-        // the start-vector pair runs products 1-2 and 3-4 as pairs
+        // network predicts the substep count and the degree m; products up to
+        // m skip the norm reductions except the last two, whose two-term stop
+        // test judges the prediction.  If it is not met the plain loop below
+        // continues.  Products up to 3 (at least) with stop tests (t_0..t_4
+        // are recorded by the tests); pair sweeps where allowed, so that a
+        // loop opened by the start-vector pair runs products 1-2 and 3-4 as
+        // pairs
         while (j < 4) {
             const int rc = C.pairs ? pair(j, true) : single(j, true);
             if (rc) return rc;
             j += C.pairs ? 2 : 1;
         }
-        HIP_TRY(launch_selector(C.selector, C.hidden, C.st, C.ia, C.ib, C.tau, C.m_max, C.s));
+        HIP_TRY(launch_selector(C.selector, C.hidden, C.st, C.ia, C.ib, C.tau, C.m_max, C.features, C.s));
         int rc = sync_state(&last);
         if (rc) return rc;
         out->pred_m = last.pred_m;
@@ -528,7 +558,22 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         if (last.done) {
             finished = true;
         } else {
-            const int mh = std::min(std::max(last.pred_m, j + 1), C.m_max);
+            pred = last.pred_m;
+            have_pred = true;
+            const int sh = std::min(std::max(last.pred_s, C.s_min), C.s_cur);
+            if (C.decide_s && sh < C.s_cur) {
+                // fewer, longer substeps: the caller restarts the step
+                out->restart_s = sh;
+                out->finalized = finalized;
+                out->m = last.m;
+                return EXPI_OK;
+            }
+        }
+    }
+    if (have_pred) {
+        {
+            int rc;
+            const int mh = std::min(std::max(pred, j + 1), C.m_max);
             // products up to mh - 2 without stop tests (the last of them
             // records t_{mh-2}), then the last two with tests (one pair
             // sweep tests after each of its two products)
@@ -694,6 +739,8 @@ int validate_call(const expi_op* op, double tau, double tol, int dtype, void* ws
     if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
     if (!ws) return fail(EXPI_EWORKSPACE, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(EXPI_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (reinterpret_cast<const Op*>(op)->kind == 2 && dtype != EXPI_F64)
+        return fail(EXPI_EINVAL, "complex operators run in FP64 only");
     const size_t need = layout(*reinterpret_cast<const Op*>(op), dtype).total;
     if (ws_bytes < need)
         return fail(EXPI_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -717,15 +764,11 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
     const WsLayout L = layout(op, dtype);
     const int64_t n = op.size;
     int sub = substep_count(tau, ia, ib, P.l_max);
-    if (k >= 2 && sub > 1)
-        return fail(EXPI_EUNSUPPORTED, "phi_k with k >= 2 needs a single substep (tau (b-a) <= l_max)");
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
           P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pair_supported(op, tw)};
     expi_stats acc{};
     for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
-        if (k >= 2 && sub > 1)
-            return fail(EXPI_EUNSUPPORTED, "phi_k with k >= 2 needs a single substep");
         const double delta = tau / sub;
         C.key = DdKey(k, delta, c, gamma, count);
         C.d = get_dd(op, C.key);
@@ -742,7 +785,46 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
             void* p = p_in_y ? (void*)y : (void*)(ws + L.p);
             const void* src;
             int tin;
-            if (k == 1 && l > 0) {
+            // phi_k, k >= 2, over several substeps: z_l = y(l delta)/tau^k is
+            // kept in y; the substep is sum_{j<k} w_j/j! + phi_k(delta A) w_k
+            // with w_0 = z_l, w_j = delta A w_{j-1} + c_j v,
+            // c_j = s^-j (l/s)^(k-j)/(k-j)!.  At l = 0 every w_j but w_k is
+            // zero and w_k = s^-k v, so the loop runs on v and p is scaled.
+            const bool phik_sub = (k >= 2 && sub > 1);
+            double pscale = (k == 1) ? 1.0 / sub : 1.0;
+            if (phik_sub && l == 0) {
+                src = v;
+                tin = 0;
+                pscale = std::pow((double)sub, -(double)k);
+            } else if (phik_sub) {
+                // w_k lands in w1 (the loop's start vector); w_{k-1} in w0,
+                // which the loop's first product overwrites after reading w1
+                const void* prev = y;
+                int tprev = 0;
+                double fact = 1.0;   // j!
+                for (int jj = 1; jj <= k; ++jj) {
+                    fact *= jj;
+                    void* buf = ((k - jj) % 2 == 0) ? (void*)(ws + L.w1) : (void*)(ws + L.w0);
+                    double kf = 1.0;   // (k - jj)!
+                    for (int q = 2; q <= k - jj; ++q) kf *= q;
+                    SweepArgs a{};
+                    a.x = prev;
+                    a.out = buf;
+                    a.g = v;
+                    a.gmode = G_VEC_SCALED;
+                    a.gscale = std::pow((double)sub, -(double)jj) *
+                               std::pow((double)l / sub, (double)(k - jj)) / kf;
+                    a.sigma = delta;
+                    HIP_TRY(launch_sweep(op, EPI_START, tprev, tw, a, s));
+                    acc.matvecs += 1;
+                    // y <- y + w_j / j! for j < k
+                    if (jj < k) HIP_TRY(launch_update(n, y, y, buf, tw, 1.0 / fact, C.st, 0, s));
+                    prev = buf;
+                    tprev = tw;
+                }
+                src = ws + L.w1;
+                tin = tw;
+            } else if (k == 1 && l > 0) {
                 // r = A y_l + v with y_l = tau * y' (y' = y_l / tau is kept in y)
                 SweepArgs a{};
                 a.x = y;
@@ -765,8 +847,8 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
             C.pairs = P.pairs && pair_supported(op, tw) && (((uintptr_t)p & 15) == 0);
             // the update of this substep, enqueued ahead of the status
             // read-back where it always runs (p_in_y needs one only for a fix)
-            const double* yin = (k == 1 && l > 0) ? y : nullptr;
-            const double scale = (k == 1) ? 1.0 / sub : 1.0;
+            const double* yin = ((k == 1 || phik_sub) && l > 0) ? y : nullptr;
+            const double scale = pscale;
             const std::function<hipError_t()> spec = [&]() {
                 return launch_update_st(n, y, yin, p, tw, scale, C.st, ws + L.w0, ws + L.w1, s);
             };
@@ -780,6 +862,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
             }
             if (!p_in_y) {
                 // k = 1: y' <- y' + p / s (y' = 0 before the first substep);
+                // k >= 2 over substeps: z <- z + p (l > 0) or s^-k p (l = 0);
                 // otherwise e^{delta A} (or phi_k, single substep) applied: y <- p
                 if (!lo.updated)
                     HIP_TRY(launch_update(n, y, yin, p, tw, scale, C.st, 1, s, lo.fix_w, lo.fix));
@@ -794,7 +877,6 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
             return EXPI_OK;
         }
         sub *= 2;
-        if (k >= 2) break;
     }
     if (st) *st = acc;
     return fail(EXPI_ENOTCONV, "no convergence within m_max products after all substep doublings");
@@ -802,7 +884,6 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
 
 static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, int dtype,
                         const Params& P, char* ws, expi_stats* st, hipStream_t s) {
-    (void)nonlin;
     double ia, ib;
     int rc = common_setup(op, tau, tol, dtype, P, ws, s, &ia, &ib);
     if (rc) return rc;
@@ -819,10 +900,34 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     double* yb = reinterpret_cast<double*>(ws + L.y);
     void* p = ws + L.p;
     expi_stats acc{};
+    // learned mode: the probe of the first loop may predict fewer substeps
+    // (at least ceil(tau (b - a) / sel_l_max)); the step then restarts with
+    // them and the predicted degree.  If that fails, the plain method redoes
+    // the step with the original substep count.
+    const int s_plain = sub;
+    const int s_min = std::max(1, substep_count(tau, ia, ib, P.sel_l_max));
+    C.features = P.sel_features;
+    bool learned_sub = false;     // running the predicted substep count
+    int wasted_mv = 0, wasted_newton = 0, wasted_fin = 0, pred_s = 0, pred_m = 0, fallbacks = 0;
+    // products spent on an abandoned probe or a failed prediction count too
+    auto finish = [&](expi_stats& a) {
+        a.matvecs += wasted_mv;
+        a.newton_steps += wasted_newton;
+        a.finalized += wasted_fin;
+        a.fallback += fallbacks;
+        if (pred_s) {
+            a.pred_substeps = pred_s;
+            a.pred_degree = pred_m;
+        }
+    };
     for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
         const double delta = tau / sub;
         C.key = DdKey(1, delta, c, gamma, count);
         C.d = get_dd(op, C.key);
+        C.s_cur = sub;
+        C.s_min = s_min;
+        C.decide_s = C.selector && attempt == 0 && !learned_sub && s_min < sub;
+        C.fixed_m = learned_sub ? pred_m : 0;
         acc = expi_stats{};
         acc.substeps = sub;
         acc.retries = attempt;
@@ -830,6 +935,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
         acc.interval_b = ib;
         HIP_TRY(launch_reset(C.st, s));
         bool ok = true;
+        int restart = 0;
         for (int l = 0; l < sub && ok; ++l) {
             // r = A y_l + g(u), y_0 = u: its own sweep, or (first substep)
             // the first half of the loop's first pair sweep.  The fused form
@@ -837,7 +943,10 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
             // product at the end) when it is even; the degree the last step
             // with this step size stopped at decides.
             const int hint = get_hint(op, C.key);
-            const bool fuse = l == 0 && tw == 0 && C.pairs && C.m_max >= 3 && pair_start_supported(op) &&
+            // (the fused start vector forms u - u^3 only)
+            const bool fuse = l == 0 && tw == 0 && nonlin == EXPI_G_CUBIC && op.bdata == EXPI_BDATA_NONE &&
+                              C.pairs && C.m_max >= 3 &&
+                              pair_start_supported(op) &&
                               (((uintptr_t)u & 15) == 0) &&
                               (P.fuse_start == 2 || (P.fuse_start == 0 && hint >= 3 && hint % 2 == 1));
             acc.matvecs += 1;
@@ -857,11 +966,23 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
                 a.out = ws + L.w1;
                 a.g = u;
                 a.gmode = (l == 0) ? G_CUBIC_SELF : G_CUBIC_OF;
+                a.gkind = nonlin;
+                a.bdata = op.bdata;   // u' = A_0 u + b_f + g(u)
                 a.sigma = 1.0;
                 HIP_TRY(launch_sweep(op, EPI_START, 0, tw, a, s));
                 rc = newton_loop(C, ws + L.w1, tw, p, &lo, false, &spec);
             }
             if (rc) return rc;
+            if (lo.restart_s) {
+                // the probe predicts fewer substeps: its products are spent
+                restart = lo.restart_s;
+                pred_s = lo.restart_s;
+                pred_m = lo.pred_m;
+                wasted_mv = acc.matvecs + lo.m;
+                wasted_newton = lo.m;
+                wasted_fin = lo.finalized;
+                break;
+            }
             stats_add(&acc, lo);
             if (lo.done == 2) return fail(EXPI_ENONFINITE, "a norm became inf/NaN (non-finite input?)");
             if (lo.done != 1) {
@@ -869,6 +990,106 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
                 break;
             }
             if (!lo.updated) HIP_TRY(launch_update(n, yout, yin, p, tw, delta, C.st, 1, s, lo.fix_w, lo.fix));
+        }
+        if (restart) {
+            // not a retry: the step starts again with the predicted count
+            sub = restart;
+            learned_sub = true;
+            --attempt;
+            continue;
+        }
+        acc.converged = ok ? 1 : 0;
+        if (ok) {
+            finish(acc);
+            if (st) *st = acc;
+            return EXPI_OK;
+        }
+        if (learned_sub) {
+            // the predicted substep count failed: the plain method, from u
+            wasted_mv += acc.matvecs;
+            wasted_newton += acc.newton_steps;
+            wasted_fin += acc.finalized;
+            fallbacks += 1;
+            learned_sub = false;
+            C.selector = nullptr;
+            sub = s_plain;
+            --attempt;
+            continue;
+        }
+        sub *= 2;
+    }
+    finish(acc);
+    if (st) *st = acc;
+    return fail(EXPI_ENOTCONV, "no convergence within m_max products after all substep doublings");
+}
+
+// ---- complex operators: phi_k(-i tau H) v ------------------------------------------
+// Hermitian H in complex CSR; the same Newton recurrence on (H - cI)/gamma
+// with the complex divided differences of x -> phi_k(-i delta (c + gamma x))
+// (single products; the loop, stop test and status read-backs are those of
+// phi_action).  k = 0: y_{l+1} = e^{-i delta H} y_l.  k = 1: y(t) = t phi_1(-i t H) v
+// solves y' = -i H y + v; y' = y/tau is kept in y and r = -i tau H y' + v.
+static int run_skew(Op& op, int k, double tau, const double* v, double* y, double tol,
+                    const Params& P, char* ws, expi_stats* st, hipStream_t s) {
+    double ia, ib;
+    int rc = common_setup(op, tau, tol, EXPI_F64, P, ws, s, &ia, &ib);
+    if (rc) return rc;
+    const double c = 0.5 * (ia + ib), gamma = 0.25 * (ib - ia);
+    const int count = P.m_max + 1;
+    const double* xi = leja_points(count);
+    const WsLayout L = layout(op, EXPI_F64);
+    const int64_t nd = op.size * 2;   // doubles per vector
+    int sub = substep_count(tau, ia, ib, P.l_max);
+    Ctx C{&op, 0, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
+          reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
+          P.profile, nullptr, 0, ia, ib, tau, false};
+    expi_stats acc{};
+    for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
+        const double delta = tau / sub;
+        // the key's k is offset so the real and complex coefficients never share a cache slot
+        C.key = DdKey(1000 + k, delta, c, gamma, count);
+        C.d.assign(count, 0.0);
+        C.di.assign(count, 0.0);
+        divided_differences_skew(k, delta, c, gamma, count, C.d.data(), C.di.data());
+        acc = expi_stats{};
+        acc.substeps = sub;
+        acc.retries = attempt;
+        acc.interval_a = ia;
+        acc.interval_b = ib;
+        HIP_TRY(launch_reset(C.st, s));
+        bool ok = true;
+        for (int l = 0; l < sub && ok; ++l) {
+            const bool p_in_y = (sub == 1);
+            void* p = p_in_y ? (void*)y : (void*)(ws + L.p);
+            const void* src = v;
+            if (k == 1 && l > 0) {
+                SweepArgs a{};
+                a.x = y;
+                a.out = ws + L.w1;
+                a.g = v;
+                a.gmode = G_VEC;
+                a.sigma = 0.0;
+                a.sigmai = -tau;
+                HIP_TRY(launch_sweep(op, EPI_START, 0, 0, a, s));
+                acc.matvecs += 1;
+                src = ws + L.w1;
+            } else if (k == 0 && l > 0) {
+                src = y;
+            }
+            LoopOut lo;
+            rc = newton_loop(C, src, 0, p, &lo);
+            if (rc) return rc;
+            stats_add(&acc, lo);
+            if (lo.done == 2) return fail(EXPI_ENONFINITE, "a norm became inf/NaN (non-finite input?)");
+            if (lo.done != 1) {
+                ok = false;
+                break;
+            }
+            if (!p_in_y) {
+                // k = 1: y' <- y' + p/s; k = 0: y <- p (complex vectors as pairs of doubles)
+                const double* yin = (k == 1 && l > 0) ? y : nullptr;
+                HIP_TRY(launch_update(nd, y, yin, p, 0, k == 1 ? 1.0 / sub : 1.0, C.st, 1, s));
+            }
         }
         acc.converged = ok ? 1 : 0;
         if (ok) {
@@ -879,6 +1100,52 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     }
     if (st) *st = acc;
     return fail(EXPI_ENOTCONV, "no convergence within m_max products after all substep doublings");
+}
+
+// ---- second-order exponential Runge-Kutta step ---------------------------------
+// U = u + tau phi_1(tau A)(A u + g(u)); u <- U + tau phi_2(tau A)(g(U) - g(u)).
+// Workspace: phi_action's layout, then u_n (float64).  g(U) - g(u_n) goes to
+// the layout's y slot (unused by run_phi), phi_2 of it into the u_n slot.
+size_t exprk2_bytes(const Op& op, int dtype) {
+    return layout(op, dtype).total + align256((size_t)op.size * 8);
+}
+
+static int run_exprk2(Op& op, int nonlin, double tau, double* u, double tol, int dtype,
+                      const Params& P, char* ws, expi_stats* st, hipStream_t s) {
+    const WsLayout L = layout(op, dtype);
+    const int64_t n = op.size;
+    double* un = reinterpret_cast<double*>(ws + L.total);
+    double* dg = reinterpret_cast<double*>(ws + L.y);
+    HIP_TRY(hipMemcpyAsync(un, u, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    expi_stats s1{}, s2{};
+    int rc = run_expeuler(op, nonlin, tau, u, tol, dtype, P, ws, &s1, s);
+    if (rc) {
+        if (st) *st = s1;
+        return rc;
+    }
+    HIP_TRY(launch_gdiff(nonlin, n, u, un, dg, s));
+    rc = run_phi(op, 2, tau, dg, un, tol, dtype, P, ws, &s2, s);
+    expi_stats acc = s1;
+    acc.substeps = std::max(s1.substeps, s2.substeps);
+    acc.newton_steps += s2.newton_steps;
+    acc.matvecs += s2.matvecs;
+    acc.retries += s2.retries;
+    acc.converged = s1.converged && s2.converged;
+    acc.degree_max = std::max(s1.degree_max, s2.degree_max);
+    acc.degree_last = s2.degree_last;
+    acc.err_est = std::max(s1.err_est, s2.err_est);
+    acc.timed_products += s2.timed_products;
+    acc.newton_ms += s2.newton_ms;
+    acc.finalized += s2.finalized;
+    acc.timed_pairs += s2.timed_pairs;
+    acc.pair_ms += s2.pair_ms;
+    acc.pair_launches += s2.pair_launches;
+    acc.single_launches += s2.single_launches;
+    if (st) *st = acc;
+    if (rc) return rc;
+    // u <- U + tau phi_2(tau A)(g(U) - g(u_n))
+    HIP_TRY(launch_update(n, u, u, un, 0, tau, nullptr, 0, s));
+    return EXPI_OK;
 }
 
 // ---- allocation-free phi_action ---------------------------------------------
@@ -958,7 +1225,7 @@ int expi_op_create_stencil(expi_op** op, int dim, const int64_t* n, const double
             return fail(EXPI_EINVAL, "separable coefficient needs tab_x, tab_y (and tab_z in 3D)");
     } else if (coef_kind == EXPI_COEF_FIELD) {
         if (!field) return fail(EXPI_EINVAL, "field coefficient needs a field pointer");
-    } else if (coef_kind != EXPI_COEF_CONST) {
+    } else if (coef_kind != EXPI_COEF_CONST && coef_kind != EXPI_COEF_DLAP) {
         return fail(EXPI_EINVAL, "unknown coefficient kind");
     }
     Op* o = new Op();
@@ -982,6 +1249,23 @@ int expi_op_create_stencil(expi_op** op, int dim, const int64_t* n, const double
     o->size = total;
     o->tiles = default_tiles(*o);
     *op = reinterpret_cast<expi_op*>(o);
+    return EXPI_OK;
+}
+
+int expi_op_set_boundary_data(expi_op* op, int kind, int mode) {
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    if (kind < EXPI_BDATA_NONE || kind > EXPI_BDATA_SINPIZ_EXPMXY) return fail(EXPI_EINVAL, "unknown boundary data");
+    if (mode != EXPI_BDATA_IN_KERNEL && mode != EXPI_BDATA_SEPARATE)
+        return fail(EXPI_EINVAL, "mode must be EXPI_BDATA_IN_KERNEL or EXPI_BDATA_SEPARATE");
+    if (kind != EXPI_BDATA_NONE) {
+        if (o.kind != 0 || o.dim != 3) return fail(EXPI_EINVAL, "boundary data need a 3D stencil");
+        if (o.bc != EXPI_DIRICHLET0) return fail(EXPI_EINVAL, "boundary data need EXPI_DIRICHLET0");
+        if (o.coef == EXPI_COEF_DLAP) return fail(EXPI_EINVAL, "boundary data are not defined for EXPI_COEF_DLAP");
+    }
+    std::lock_guard<std::mutex> lock(o.mu);
+    o.bdata = kind;
+    o.bdata_mode = mode;
     return EXPI_OK;
 }
 
@@ -1011,6 +1295,16 @@ int expi_op_create_csr(expi_op** op, int64_t n, int64_t nnz, const int32_t* rowp
     o->size = n;
     o->tiles = default_tiles(*o);
     *op = reinterpret_cast<expi_op*>(o);
+    return EXPI_OK;
+}
+
+int expi_op_create_csr_complex(expi_op** op, int64_t n, int64_t nnz, const int32_t* rowptr,
+                               const int32_t* colind, const double* val) {
+    int rc = expi_op_create_csr(op, n, nnz, rowptr, colind, val);
+    if (rc) return rc;
+    Op* o = reinterpret_cast<Op*>(*op);
+    o->kind = 2;
+    o->tiles = default_tiles(*o);
     return EXPI_OK;
 }
 
@@ -1059,7 +1353,7 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
     char* w = static_cast<char*>(ws);
     // candidate tile settings
     std::vector<Tiles> C;
-    if (o.kind == 1) {
+    if (o.kind != 0) {
         for (int v : {4, 8, 16})
             for (int wv : {1, 2, 4, 8}) C.push_back(Tiles{v, wv, 1});
     } else {
@@ -1070,8 +1364,10 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
                 for (int q = 0; q < 4; ++q) C.push_back(Tiles{v, wv, o.dim == 3 ? marches3[q] : marches2[q]});
     }
     // deterministic data in w0 and p; w1 is written by the sweep
-    HIP_TRY(launch_fill(w + L.w0, o.size, tw, 1.0, s));
-    HIP_TRY(launch_fill(w + L.p, o.size, tw, 0.5, s));
+    if (o.kind == 2 && tw != 0) return fail(EXPI_EINVAL, "complex operators run in FP64 only");
+    const int64_t nfill = o.size * (o.kind == 2 ? 2 : 1);
+    HIP_TRY(launch_fill(w + L.w0, nfill, tw, 1.0, s));
+    HIP_TRY(launch_fill(w + L.p, nfill, tw, 0.5, s));
     hipEvent_t e0, e1;   // timing only (no system-scope fence)
     HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
     HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
@@ -1159,13 +1455,15 @@ int apply_op(const expi_op* op, double alpha, double beta, const void* x, void* 
     if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
     if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(EXPI_EINVAL, "alpha, beta must be finite");
     const Op& o = *reinterpret_cast<const Op*>(op);
-    const size_t bytes = (size_t)o.size * (dtype == EXPI_F32 ? 4 : 8);
+    if (o.kind == 2 && dtype != EXPI_F64) return fail(EXPI_EINVAL, "complex operators run in FP64 only");
+    const size_t bytes = (size_t)o.size * (dtype == EXPI_F32 ? 4 : 8) * (o.kind == 2 ? 2 : 1);
     if (overlap(x, bytes, y, bytes)) return fail(EXPI_EALIAS, "y overlaps x");
     SweepArgs a{};
     a.x = x;
     a.out = y;
     a.alpha = alpha;
     a.beta = beta;
+    a.bdata = o.bdata;
     const int t = dtype == EXPI_F32 ? 1 : 0;
     HIP_TRY(launch_sweep(o, EPI_APPLY, t, t, a, static_cast<hipStream_t>(stream)));
     return EXPI_OK;
@@ -1179,6 +1477,7 @@ int phi_action(expi_op* op, int k, double tau, const double* v, double* y, doubl
     if (k < 0 || k > 20) return fail(EXPI_EINVAL, "k must be in [0, 20]");
     if (!v || !y) return fail(EXPI_EINVAL, "v, y must be non-NULL");
     Op& o = *reinterpret_cast<Op*>(op);
+    if (o.kind == 2) return fail(EXPI_EINVAL, "complex operator: use expi_skew_phi_action");
     const size_t bytes = (size_t)o.size * 8;
     if (overlap(v, bytes, y, bytes)) return fail(EXPI_EALIAS, "y overlaps v");
     if (overlap(ws, ws_bytes, v, bytes) || overlap(ws, ws_bytes, y, bytes))
@@ -1196,15 +1495,90 @@ int expeuler_step(expi_op* op, int nonlin, double tau, double* u, double tol, in
     if (st) std::memset(st, 0, sizeof(*st));
     int rc = validate_call(op, tau, tol, dtype, ws, ws_bytes);
     if (rc) return rc;
-    if (nonlin != EXPI_G_CUBIC) return fail(EXPI_EINVAL, "nonlin must be EXPI_G_CUBIC");
+    if (nonlin < EXPI_G_CUBIC || nonlin > EXPI_G_COMBUSTION_FAST)
+        return fail(EXPI_EINVAL, "nonlin must be EXPI_G_CUBIC, EXPI_G_COMBUSTION or EXPI_G_COMBUSTION_FAST");
     if (!u) return fail(EXPI_EINVAL, "u must be non-NULL");
     Op& o = *reinterpret_cast<Op*>(op);
+    if (o.kind == 2) return fail(EXPI_EINVAL, "complex operators have no exponential Euler step here");
     if (overlap(ws, ws_bytes, u, (size_t)o.size * 8)) return fail(EXPI_EALIAS, "workspace overlaps u");
     Params P;
     rc = read_params(params, &P);
     if (rc) return rc;
     return run_expeuler(o, nonlin, tau, u, tol, dtype, P, static_cast<char*>(ws), st,
                         static_cast<hipStream_t>(stream));
+}
+
+size_t expi_exprk2_workspace_bytes(const expi_op* op, int dtype) {
+    if (!op || (dtype != EXPI_F64 && dtype != EXPI_F32)) return 0;
+    return exprk2_bytes(*reinterpret_cast<const Op*>(op), dtype);
+}
+
+int exprk2_step(expi_op* op, int nonlin, double tau, double* u, double tol, int dtype,
+                const expi_params* params, void* ws, size_t ws_bytes, expi_stats* st, void* stream) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    int rc = validate_call(op, tau, tol, dtype, ws, ws_bytes);
+    if (rc) return rc;
+    if (nonlin < EXPI_G_CUBIC || nonlin > EXPI_G_COMBUSTION_FAST)
+        return fail(EXPI_EINVAL, "nonlin must be EXPI_G_CUBIC, EXPI_G_COMBUSTION or EXPI_G_COMBUSTION_FAST");
+    if (!u) return fail(EXPI_EINVAL, "u must be non-NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    if (o.kind == 2) return fail(EXPI_EINVAL, "complex operators have no Runge-Kutta step here");
+    const size_t need = exprk2_bytes(o, dtype);
+    if (ws_bytes < need)
+        return fail(EXPI_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (overlap(ws, ws_bytes, u, (size_t)o.size * 8)) return fail(EXPI_EALIAS, "workspace overlaps u");
+    Params P;
+    rc = read_params(params, &P);
+    if (rc) return rc;
+    return run_exprk2(o, nonlin, tau, u, tol, dtype, P, static_cast<char*>(ws), st,
+                      static_cast<hipStream_t>(stream));
+}
+
+int expi_skew_phi_action(expi_op* op, int k, double tau, const double* v, double* y, double tol,
+                         const expi_params* params, void* ws, size_t ws_bytes, expi_stats* st,
+                         void* stream) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (op && reinterpret_cast<Op*>(op)->kind != 2)
+        return fail(EXPI_EINVAL, "expi_skew_phi_action needs a complex CSR operator");
+    int rc = validate_call(op, tau, tol, EXPI_F64, ws, ws_bytes);
+    if (rc) return rc;
+    if (k != 0 && k != 1) return fail(EXPI_EINVAL, "k must be 0 or 1");
+    if (!v || !y) return fail(EXPI_EINVAL, "v, y must be non-NULL");
+    Op& o = *reinterpret_cast<Op*>(op);
+    const size_t bytes = (size_t)o.size * 16;
+    if (overlap(v, bytes, y, bytes)) return fail(EXPI_EALIAS, "y overlaps v");
+    if (overlap(ws, ws_bytes, v, bytes) || overlap(ws, ws_bytes, y, bytes))
+        return fail(EXPI_EALIAS, "workspace overlaps v or y");
+    Params P;
+    rc = read_params(params, &P);
+    if (rc) return rc;
+    if (P.selector) return fail(EXPI_EINVAL, "no step selector for complex operators");
+    return run_skew(o, k, tau, v, y, tol, P, static_cast<char*>(ws), st, static_cast<hipStream_t>(stream));
+}
+
+int expi_divided_differences_skew(int k, double delta, double c, double gamma, int count, double* re,
+                                  double* im) {
+    if (!re || !im || count < 1 || count > kMaxLeja) return fail(EXPI_EINVAL, "count must be in [1, 256]");
+    if (k < 0 || k > 20) return fail(EXPI_EINVAL, "k must be in [0, 20]");
+    if (!std::isfinite(delta) || !std::isfinite(c) || !std::isfinite(gamma))
+        return fail(EXPI_EINVAL, "delta, c, gamma must be finite");
+    divided_differences_skew(k, delta, c, gamma, count, re, im);
+    return EXPI_OK;
+}
+
+int expi_nonlinearity(int nonlin, int64_t n, const void* u, void* g, int dtype, void* stream) {
+    if (nonlin < EXPI_G_CUBIC || nonlin > EXPI_G_COMBUSTION_FAST)
+        return fail(EXPI_EINVAL, "nonlin must be EXPI_G_CUBIC, EXPI_G_COMBUSTION or EXPI_G_COMBUSTION_FAST");
+    if (dtype != EXPI_F64 && dtype != EXPI_F32) return fail(EXPI_EINVAL, "dtype must be EXPI_F64 or EXPI_F32");
+    if (n < 0) return fail(EXPI_EINVAL, "n must be >= 0");
+    if (n == 0) return EXPI_OK;
+    if (!u || !g) return fail(EXPI_EINVAL, "u, g must be non-NULL");
+    const size_t bytes = (size_t)n * (dtype == EXPI_F32 ? 4 : 8);
+    if (u != g && overlap(u, bytes, g, bytes)) return fail(EXPI_EALIAS, "g overlaps u (other than in place)");
+    if ((((uintptr_t)u | (uintptr_t)g) & 15) != 0)
+        return fail(EXPI_EINVAL, "u and g must be 16-byte aligned");
+    HIP_TRY(launch_nonlin(nonlin, n, u, g, dtype, static_cast<hipStream_t>(stream)));
+    return EXPI_OK;
 }
 
 int expi_noalloc_init(void) { return noalloc_init(); }

@@ -6,6 +6,7 @@
 // (sweep.hip lists them).  Rows are assigned to XCDs in contiguous runs, so
 // with a locality-preserving row order (e.g. Morton order of graph vertices)
 // the gathered vector entries are mostly hits in that XCD's L2.
+#include "nonlin.h"
 #include "sweep_common.h"
 
 namespace expi {
@@ -141,11 +142,12 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
                     TC gv;
                     if (a.gmode == G_VEC) {
                         gv = (TC)a.g[row];
+                    } else if (a.gmode == G_VEC_SCALED) {
+                        gv = (TC)(a.gscale * a.g[row]);
                     } else if (a.gmode == G_CUBIC_OF) {
-                        const TC u = (TC)a.g[row];
-                        gv = u - u * u * u;
+                        gv = g_eval<TC>(a.gkind, (TC)a.g[row]);
                     } else {
-                        gv = wc - wc * wc * wc;
+                        gv = g_eval<TC>(a.gkind, wc);
                     }
                     out[row] = (TOUT)((TC)a.sigma * acc + gv);
                 }
@@ -187,6 +189,7 @@ hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs
         case EPI_START:
             if (tin == 0 && tout == 0) return go<EPI_START, double, double>(g, a, s);
             if (tin == 0 && tout == 1) return go<EPI_START, double, float>(g, a, s);
+            if (tin == 1 && tout == 1) return go<EPI_START, float, float>(g, a, s);
             break;
         case EPI_GERSH:
             return go<EPI_GERSH, double, double>(g, a, s);

@@ -50,8 +50,10 @@ enum Epilogue : int {
     EPI_GERSH = 4,   // per-row Gershgorin bounds, min/max over rows
 };
 
-// Source of g in EPI_START.
-enum GMode : int { G_VEC = 0, G_CUBIC_OF = 1, G_CUBIC_SELF = 2 };
+// Source of g in EPI_START: the vector g (G_VEC), gscale times it
+// (G_VEC_SCALED), or the nonlinearity of kind gkind (EXPI_G_*) of the vector
+// g (G_CUBIC_OF) or of the input x itself (G_CUBIC_SELF).
+enum GMode : int { G_VEC = 0, G_CUBIC_OF = 1, G_CUBIC_SELF = 2, G_VEC_SCALED = 3 };
 
 struct SweepArgs {
     const void* x;        // input vector (stencil source)
@@ -69,13 +71,19 @@ struct SweepArgs {
     const double* val;
     double c0, c1;
     double ih2[3];        // 1/h_d^2
+    double hpos[3];       // h_d (grid positions of EXPI_COEF_DLAP and boundary data)
     double alpha, beta, d0, d1, sigma, tol;
+    double d0i, d1i, sigmai;   // imaginary parts (complex CSR operators)
     int n[3];             // grid sizes (x, y, z); CSR: n[0] = rows
     int nnz;              // CSR stored entries
     int bc;
     int j;                // Newton index of this product
     int guard;            // 1: the sweep does nothing once st->done != 0
     int gmode;
+    int gkind;            // EPI_START: nonlinearity (EXPI_G_*) of G_CUBIC_OF/SELF
+    int bdata;            // EPI_APPLY / EPI_START: add the boundary term of the
+                          // operator's Dirichlet data (EXPI_BDATA_*), 0: none
+    double gscale;        // EPI_START: factor of g under G_VEC_SCALED
     int tiles[3];
     int ntiles;
     int per_xcd;          // tiles per XCD slot
@@ -144,8 +152,9 @@ void set_state_mirror(NewtonState* mirror);
 
 // Step-selector network (mlp.hip): predicted (substeps, degree) from the
 // interval, tau, ||r|| and t_0..t_4 in `st`; written to st->pred_s/pred_m.
+// `features` (device float[8], may be null) receives the raw features.
 hipError_t launch_selector(const float* sel, int hidden, NewtonState* st, double a, double b,
-                           double tau, int m_max, hipStream_t s);
+                           double tau, int m_max, float* features, hipStream_t s);
 
 // Tile setting of an operator's sweeps (chosen by default or by the tuner).
 //   stencil: vec = x points per thread (1 or 2), waves per workgroup,
@@ -167,7 +176,7 @@ struct Geom {
 };
 
 struct Op {
-    int kind;             // 0 stencil, 1 CSR
+    int kind;             // 0 stencil, 1 CSR, 2 complex CSR (val: complex128 pairs)
     int dim;
     int n[3];
     double h[3];
@@ -181,6 +190,8 @@ struct Op {
     const double* val;
     int64_t size;
     Tiles tiles;
+    int bdata = 0;        // EXPI_BDATA_* of a 3D Dirichlet stencil
+    int bdata_mode = 0;   // EXPI_BDATA_IN_KERNEL or EXPI_BDATA_SEPARATE
     std::mutex mu;
     bool have_interval = false;
     double ia = 0, ib = 0;
@@ -213,6 +224,9 @@ hipError_t launch_stencil(const Op& op, const Geom& g, int epi, int tin, int tou
                           const SweepArgs& a, hipStream_t s);
 hipError_t launch_csr(const Geom& g, int epi, int tin, int tout, const SweepArgs& a,
                       hipStream_t s);
+// Complex CSR (csr_complex.hip): complex128 vectors, real alpha/beta,
+// complex d0, d1 (d0i, d1i) and sigma (sigmai).
+hipError_t launch_csr_complex(const Geom& g, int epi, const SweepArgs& a, hipStream_t s);
 hipError_t launch_update(int64_t n, double* out, const double* yin, const void* p, int tp,
                          double scale, const NewtonState* st, int guard, hipStream_t s,
                          const void* wfix = nullptr, double fix = 0.0);
@@ -241,6 +255,14 @@ hipError_t launch_pair_finalize(const double* partials, NewtonState* st, int npa
                                 int guard, double d0, double d1, double d2, double tol, int mode,
                                 int outbuf, hipStream_t s);
 hipError_t launch_fill(void* out, int64_t n, int t, double scale, hipStream_t s);
+// The boundary term of a stencil's Dirichlet data over its boundary layer
+// (boundary.hip): y += scale * b_f, y of storage code t.
+hipError_t launch_boundary(const Op& op, double scale, void* y, int t, hipStream_t s);
+// Pointwise nonlinearity g = kind(u) over n values of dtype (nonlin.hip), and
+// out = kind(U) - kind(u) in float64.
+hipError_t launch_nonlin(int kind, int64_t n, const void* u, void* g, int dtype, hipStream_t s);
+hipError_t launch_gdiff(int kind, int64_t n, const double* U, const double* u, double* out,
+                        hipStream_t s);
 
 // Error reporting (api.hip).
 void set_error(const std::string& msg);

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <complex>
 #include <mutex>
 #include <vector>
 
@@ -133,7 +134,49 @@ ld phi_ld(int k, ld z) {
     return val;
 }
 
+// phi_k(z) for complex z in long double: the power series for |z| < 1,
+// else (e^z - 1)/z and the same recurrence (no cancellation there).
+typedef std::complex<ld> cld;
+cld phi_cld(int k, cld z) {
+    if (k == 0) return std::exp(z);
+    if (std::abs(z) < 1.0L) {
+        ld fact = 1.0L;
+        for (int i = 2; i <= k; ++i) fact *= (ld)i;
+        cld term = 1.0L / fact, sum = term;
+        for (int i = 1; i < 200; ++i) {
+            term *= z / (ld)(i + k);
+            sum += term;
+            if (std::abs(term) <= 1e-22L * std::abs(sum)) break;
+        }
+        return sum;
+    }
+    cld val = (std::exp(z) - 1.0L) / z;
+    ld fact = 1.0L;
+    for (int j = 1; j < k; ++j) {
+        fact *= (ld)j;
+        val = (val - 1.0L / fact) / z;
+    }
+    return val;
+}
+
 }  // namespace
+
+void divided_differences_skew(int k, double delta, double c, double gamma, int count, double* re,
+                              double* im) {
+    const double* xi = leja_points(count);
+    std::vector<cld> d(count);
+    std::vector<ld> x(count);
+    for (int i = 0; i < count; ++i) {
+        x[i] = (ld)xi[i];
+        d[i] = phi_cld(k, cld(0.0L, -(ld)delta * ((ld)c + (ld)gamma * x[i])));
+    }
+    for (int j = 1; j < count; ++j)
+        for (int i = count - 1; i >= j; --i) d[i] = (d[i] - d[i - 1]) / (x[i] - x[i - j]);
+    for (int i = 0; i < count; ++i) {
+        re[i] = (double)d[i].real();
+        im[i] = (double)d[i].imag();
+    }
+}
 
 const double* leja_points(int count) {
     if (count > kMaxLeja) count = kMaxLeja;

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void adam_kernel(int count, float* __restrict_
 // log10(t_k / t_0) for k = 1..4.
 __global__ __launch_bounds__(kMaxHidden) void selector_kernel(const float* __restrict__ sel, int H,
                                                               NewtonState* st, double a, double b,
-                                                              double tau, int m_max) {
+                                                              double tau, int m_max, float* feat) {
     __shared__ float x[kIn], h1[kMaxHidden], h2[kMaxHidden], o[kOut];
     if (threadIdx.x == 0) {
         double f[kIn];
@@ -206,6 +206,8 @@ __global__ __launch_bounds__(kMaxHidden) void selector_kernel(const float* __res
         const double t0 = st->hist[0];
         for (int k = 1; k <= 4; ++k) f[3 + k] = t0 > 0.0 ? log10(st->hist[k] / t0 + 1e-300) : -300.0;
         for (int k = 0; k < kIn; ++k) x[k] = (float)((f[k] - sel[k]) / sel[kIn + k]);
+        if (feat)
+            for (int k = 0; k < kIn; ++k) feat[k] = (float)f[k];
     }
     __syncthreads();
     mlp_forward_one(sel + 2 * kIn + 2 * kOut, H, x, h1, h2, o, nullptr, nullptr);
@@ -222,9 +224,9 @@ __global__ __launch_bounds__(kMaxHidden) void selector_kernel(const float* __res
 }  // namespace
 
 hipError_t launch_selector(const float* sel, int hidden, NewtonState* st, double a, double b,
-                           double tau, int m_max, hipStream_t s) {
+                           double tau, int m_max, float* features, hipStream_t s) {
     hipLaunchKernelGGL(selector_kernel, dim3(1), dim3(kMaxHidden), 0, s, sel, hidden, st, a, b,
-                       tau, m_max);
+                       tau, m_max, features);
     return hipGetLastError();
 }
 

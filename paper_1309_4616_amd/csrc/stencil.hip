@@ -21,7 +21,12 @@
 //    are loads that the workgroup itself or the neighbouring tile brought
 //    into L1/L2;
 //  * tiles are mapped so that each XCD owns a contiguous run of them;
-//  * boundaries are predicated face terms, no ghost cells.
+//  * boundaries are predicated face terms, no ghost cells; inhomogeneous
+//    Dirichlet data (Sec. III-A) are evaluated at the boundary-adjacent
+//    points by instantiations of their own (EPI_APPLY_BD, EPI_START_BD);
+//  * the D-Laplacian of Sec. III-B computes D = 1/sqrt(1 + x^2 + y^2) in the
+//    kernel: once per thread before the march in 3D (D does not depend on
+//    z), once per point and plane in 2D.
 #include "stencil_tile.h"
 
 namespace expi {
@@ -60,6 +65,20 @@ hipError_t go(const Geom& g, const SweepArgs& a, hipStream_t s) {
 
 template <int DIM, int COEF>
 hipError_t dispatch(const Geom& g, int epi, int tin, int tout, const SweepArgs& a, hipStream_t s) {
+    // boundary data of a 3D Dirichlet stencil (not with the D-Laplacian)
+    constexpr bool kBD = (DIM == 3 && COEF != EXPI_COEF_DLAP);
+    if (a.bdata && (epi == EPI_APPLY || epi == EPI_START)) {
+        if constexpr (kBD) {
+            if (epi == EPI_APPLY) {
+                if (tin == 0 && tout == 0) return go<DIM, COEF, EPI_APPLY_BD, double, double>(g, a, s);
+                if (tin == 1 && tout == 1) return go<DIM, COEF, EPI_APPLY_BD, float, float>(g, a, s);
+            } else {
+                if (tin == 0 && tout == 0) return go<DIM, COEF, EPI_START_BD, double, double>(g, a, s);
+                if (tin == 0 && tout == 1) return go<DIM, COEF, EPI_START_BD, double, float>(g, a, s);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     switch (epi) {
         case EPI_APPLY:
             if (tin == 0 && tout == 0) return go<DIM, COEF, EPI_APPLY, double, double>(g, a, s);
@@ -82,6 +101,7 @@ hipError_t dispatch(const Geom& g, int epi, int tin, int tout, const SweepArgs& 
             }
             if (tin == 0 && tout == 0) return go<DIM, COEF, EPI_START, double, double>(g, a, s);
             if (tin == 0 && tout == 1) return go<DIM, COEF, EPI_START, double, float>(g, a, s);
+            if (tin == 1 && tout == 1) return go<DIM, COEF, EPI_START, float, float>(g, a, s);
             break;
         case EPI_GERSH:
             return go<DIM, COEF, EPI_GERSH, double, double>(g, a, s);
@@ -98,12 +118,14 @@ hipError_t launch_stencil(const Op& op, const Geom& g, int epi, int tin, int tou
             case EXPI_COEF_CONST: return dispatch<3, EXPI_COEF_CONST>(g, epi, tin, tout, a, s);
             case EXPI_COEF_SEPARABLE: return dispatch<3, EXPI_COEF_SEPARABLE>(g, epi, tin, tout, a, s);
             case EXPI_COEF_FIELD: return dispatch<3, EXPI_COEF_FIELD>(g, epi, tin, tout, a, s);
+            case EXPI_COEF_DLAP: return dispatch<3, EXPI_COEF_DLAP>(g, epi, tin, tout, a, s);
         }
     } else {
         switch (op.coef) {
             case EXPI_COEF_CONST: return dispatch<2, EXPI_COEF_CONST>(g, epi, tin, tout, a, s);
             case EXPI_COEF_SEPARABLE: return dispatch<2, EXPI_COEF_SEPARABLE>(g, epi, tin, tout, a, s);
             case EXPI_COEF_FIELD: return dispatch<2, EXPI_COEF_FIELD>(g, epi, tin, tout, a, s);
+            case EXPI_COEF_DLAP: return dispatch<2, EXPI_COEF_DLAP>(g, epi, tin, tout, a, s);
         }
     }
     return hipErrorInvalidValue;

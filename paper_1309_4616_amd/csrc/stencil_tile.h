@@ -3,6 +3,7 @@
 // and traversal are described in stencil.hip.
 #pragma once
 
+#include "nonlin.h"
 #include "sweep_common.h"
 
 namespace expi {
@@ -10,8 +11,30 @@ namespace expi {
 // so no load inside the march); chosen by the stencil launcher for
 // G_CUBIC_SELF
 constexpr int EPI_START_SELF = 5;
+// EPI_APPLY / EPI_START that also add the boundary term of the operator's
+// Dirichlet data, f evaluated at the boundary-adjacent points (own
+// instantiations, so the plain sweeps carry none of its code)
+constexpr int EPI_APPLY_BD = 6;
+constexpr int EPI_START_BD = 7;
 
 namespace tile {
+
+// Dirichlet data f at a boundary node (Sec. III-A): kind 1 z(1-z)xy,
+// kind 2 sin(pi z) exp(-xy).
+template <class TC>
+__device__ __forceinline__ TC boundary_value(int kind, TC x, TC y, TC z) {
+    if (kind == EXPI_BDATA_Z1MZ_XY) return z * ((TC)1 - z) * x * y;
+    if constexpr (std::is_same<TC, float>::value)
+        return sinf(3.14159265358979323846f * z) * expf(-x * y);
+    else
+        return sin(3.14159265358979323846 * z) * exp(-x * y);
+}
+
+// D(x, y) = 1/sqrt(1 + x^2 + y^2) of Sec. III-B
+template <class TC>
+__device__ __forceinline__ TC d_coefficient(TC x, TC y) {
+    return (TC)1 / sqrt((TC)1 + x * x + y * y);
+}
 
 template <int V, class T, class TC>
 __device__ __forceinline__ void vld(const T* __restrict__ p, int idx, TC (&o)[V]) {
@@ -76,6 +99,10 @@ template <int DIM, int COEF, int EPI, class TIN, class TOUT, int V>
 __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1, int t2,
                                              double& s0, double& s1, double& s2) {
     using TC = compute_t<TIN, TOUT>;
+    constexpr bool kApply = (EPI == EPI_APPLY || EPI == EPI_APPLY_BD);
+    constexpr bool kStart = (EPI == EPI_START || EPI == EPI_START_BD);
+    constexpr bool kBD = (EPI == EPI_APPLY_BD || EPI == EPI_START_BD) && DIM == 3;
+    constexpr bool kDlap = (COEF == EXPI_COEF_DLAP);
     const TIN* __restrict__ x = static_cast<const TIN*>(a.x);
     TOUT* __restrict__ out = static_cast<TOUT*>(a.out);
     TOUT* __restrict__ p = static_cast<TOUT*>(a.p);
@@ -151,6 +178,18 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                 }
                 zr0 = (TC)Ts[min(max(kb - 1 + lane, 0), ns - 1)];
                 zr1 = (TC)Ts[min(max(kb + 63 + lane, 0), ns - 1)];
+            }
+            // grid positions (D-Laplacian and boundary data): index i at
+            // (i + off) h, off = 1 (Dirichlet nodes), 1/2 (cells), 0
+            const double poff = dir ? 1.0 : (a.bc == EXPI_NEUMANN0 ? 0.5 : 0.0);
+            TC Dv[V];   // 3D: D of the thread's points, constant along the march
+#pragma unroll
+            for (int v = 0; v < V; ++v) Dv[v] = (TC)1;
+            if (kDlap && DIM == 3) {
+                const TC yq = (TC)((jc + poff) * a.hpos[1]);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    Dv[v] = d_coefficient<TC>((TC)((ic + v + poff) * a.hpos[0]), yq);
             }
             auto zv = [&](int k) -> TC {   // k in [kb-1, kb+126], clamped into the grid
                 const int t = min(k, ns - 1) - (kb - 1);
@@ -249,7 +288,7 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                                 const int iv = i + v;
                                 const bool exm = iv > 0, exq = iv < n0 - 1;
                                 Coefs<TC> cf;
-                                if (COEF == EXPI_COEF_CONST) {
+                                if (COEF == EXPI_COEF_CONST || kDlap) {
                                     cf.c = cf.xm = cf.xq = cf.ym = cf.yq = cf.zm = cf.zq = c0;
                                 } else if (COEF == EXPI_COEF_SEPARABLE) {
                                     const TC X_l = (v > 0) ? Xv[v - 1] : Xl;
@@ -291,6 +330,11 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                                     fym = face_weight<TC>(eym, dir, cf.c, cf.ym) * ihy;
                                     fyq = face_weight<TC>(eyq, dir, cf.c, cf.yq) * ihy;
                                 }
+                                // D of the D-Laplacian at this point (2D: varies along the march)
+                                TC Dp = Dv[v];
+                                if (kDlap && DIM == 2)
+                                    Dp = d_coefficient<TC>((TC)((iv + poff) * a.hpos[0]),
+                                                           (TC)((k + poff) * a.hpos[1]));
                                 if (EPI == EPI_GERSH) {
                                     // diagonal = -(sum of the face weights); off-diagonal
                                     // magnitude = weights of faces that have a neighbour
@@ -298,6 +342,10 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                                     TC off = (exm ? fxm : (TC)0) + (exq ? fxq : (TC)0) +
                                              (eym ? fym : (TC)0) + (eyq ? fyq : (TC)0) +
                                              (ezm ? fzm : (TC)0) + (ezq ? fzq : (TC)0);
+                                    if (kDlap) {
+                                        diag *= Dp;
+                                        off *= Dp;
+                                    }
                                     if (zero_row) diag = off = 0;
                                     s0 = fmin(s0, (double)(diag - off));
                                     s1 = fmax(s1, (double)(diag + off));
@@ -316,8 +364,33 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                                         const TC wy1 = eyq ? S[cur].yq[v] : (TC)0;
                                         Aw += fym * (wy0 - w_c) + fyq * (wy1 - w_c);
                                     }
+                                    if constexpr (kBD) {
+                                        // a missing neighbour of a boundary-adjacent point
+                                        // is the boundary node, where the data are f
+                                        if (dir && !(exm && exq && eym && eyq && ezm && ezq)) {
+                                            const TC xp = (TC)((iv + 1) * a.hpos[0]);
+                                            const TC yp = (TC)((j + 1) * a.hpos[1]);
+                                            const TC zp = (TC)((k + 1) * a.hpos[2]);
+                                            const int bk = a.bdata;
+                                            TC bt = 0;
+                                            if (!exm) bt += fxm * boundary_value<TC>(bk, (TC)0, yp, zp);
+                                            if (!exq)
+                                                bt += fxq * boundary_value<TC>(
+                                                                bk, (TC)((n0 + 1) * a.hpos[0]), yp, zp);
+                                            if (!eym) bt += fym * boundary_value<TC>(bk, xp, (TC)0, zp);
+                                            if (!eyq)
+                                                bt += fyq * boundary_value<TC>(
+                                                                bk, xp, (TC)((n1 + 1) * a.hpos[1]), zp);
+                                            if (!ezm) bt += fzm * boundary_value<TC>(bk, xp, yp, (TC)0);
+                                            if (!ezq)
+                                                bt += fzq * boundary_value<TC>(
+                                                                bk, xp, yp, (TC)((ns + 1) * a.hpos[2]));
+                                            Aw += bt;
+                                        }
+                                    }
+                                    if (kDlap) Aw *= Dp;
                                     if (zero_row) Aw = 0;
-                                    if (EPI == EPI_APPLY) {
+                                    if (kApply) {
                                         wo[v] = alpha * Aw + beta * w_c;
                                     } else if (EPI == EPI_NEWTON) {
                                         const TC wn_ = (TC)(TOUT)(alpha * Aw + beta * w_c);
@@ -335,16 +408,17 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
                                         s1 += (double)wn_ * (double)wn_;
                                         s2 += (double)pn_ * (double)pn_;
                                     } else if (EPI == EPI_START_SELF) {
-                                        wo[v] = sigma * Aw + (w_c - w_c * w_c * w_c);
-                                    } else if (EPI == EPI_START) {
+                                        wo[v] = sigma * Aw + g_eval<TC>(a.gkind, w_c);
+                                    } else if (kStart) {
                                         TC gv;
                                         if (a.gmode == G_VEC) {
                                             gv = (TC)a.g[idx + v];
+                                        } else if (a.gmode == G_VEC_SCALED) {
+                                            gv = (TC)(a.gscale * a.g[idx + v]);
                                         } else if (a.gmode == G_CUBIC_OF) {
-                                            const TC u = (TC)a.g[idx + v];
-                                            gv = u - u * u * u;
+                                            gv = g_eval<TC>(a.gkind, (TC)a.g[idx + v]);
                                         } else {
-                                            gv = w_c - w_c * w_c * w_c;
+                                            gv = g_eval<TC>(a.gkind, w_c);
                                         }
                                         wo[v] = sigma * Aw + gv;
                                     }

@@ -20,6 +20,8 @@
 //   EPI_FIRST   w_1 = alpha A w_0 + beta_0 w_0, p = d_0 w_0 + d_1 w_1
 //   EPI_START   r = sigma A x + g, g = v or u - u^3   (substep start vector)
 //   EPI_GERSH   Gershgorin bounds of the rows, min/max over rows
+#include <cmath>
+
 #include "sweep_common.h"
 
 namespace expi {
@@ -186,7 +188,7 @@ Geom make_geom(const Op& op, const Tiles& t) {
     g.vec = t.vec;
     g.waves = t.waves;
     g.march = t.march;
-    if (op.kind == 1) {
+    if (op.kind != 0) {
         const int64_t rows_per = (64 * t.waves) / t.vec;
         g.tiles[0] = (int)((op.nrows + rows_per - 1) / rows_per);
         g.tiles[1] = g.tiles[2] = 1;
@@ -205,14 +207,18 @@ Geom make_geom(const Op& op, const Tiles& t) {
     g.per_xcd = (g.ntiles + kXcd - 1) / kXcd;
     // CSR sweeps loop over row blocks: at most kCsrGrid workgroups, so that
     // the finalize kernel sums few partials
-    if (op.kind == 1 && g.per_xcd > kCsrGrid / kXcd) g.per_xcd = kCsrGrid / kXcd;
+    if (op.kind != 0 && g.per_xcd > kCsrGrid / kXcd) g.per_xcd = kCsrGrid / kXcd;
     g.grid = kXcd * g.per_xcd;
     return g;
 }
 
 Tiles default_tiles(const Op& op) {
     Tiles t;
-    if (op.kind == 1) {
+    if (op.kind == 2) {
+        t.vec = 4;     // lanes per row (complex entries: 16 bytes each)
+        t.waves = 4;
+        t.march = 1;
+    } else if (op.kind == 1) {
         t.vec = 8;     // lanes per row
         t.waves = 4;
         t.march = 1;
@@ -227,7 +233,7 @@ Tiles default_tiles(const Op& op) {
 
 bool tiles_valid(const Op& op, const Tiles& t) {
     if (t.waves < 1 || t.waves > kMaxWaves) return false;
-    if (op.kind == 1) return (t.vec == 4 || t.vec == 8 || t.vec == 16) && t.march == 1;
+    if (op.kind != 0) return (t.vec == 4 || t.vec == 8 || t.vec == 16) && t.march == 1;
     return (t.vec == 1 || t.vec == 2) && t.march >= kMinMarch && t.march <= kMaxMarch &&
            t.march % 4 == 0;
 }
@@ -236,7 +242,7 @@ bool tiles_valid(const Op& op, const Tiles& t) {
 // the partials buffer of the workspace.
 size_t partials_bytes(const Op& op) {
     Tiles t;
-    if (op.kind == 1) {
+    if (op.kind != 0) {
         t.vec = 16;
         t.waves = 1;
         t.march = 1;
@@ -266,17 +272,18 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
     a.per_xcd = g.per_xcd;
     a.march = g.march;
     hipError_t e;
-    if (op.kind == 1) {
+    if (op.kind != 0) {
         a.n[0] = (int)op.nrows;
         a.nnz = (int)op.nnz;
         a.rowptr = op.rowptr;
         a.colind = op.colind;
         a.val = op.val;
-        e = launch_csr(g, epi, tin, tout, a, s);
+        e = (op.kind == 2) ? launch_csr_complex(g, epi, a, s) : launch_csr(g, epi, tin, tout, a, s);
     } else {
         for (int d = 0; d < 3; ++d) {
             a.n[d] = op.n[d];
             a.ih2[d] = 1.0 / (op.h[d] * op.h[d]);
+            a.hpos[d] = op.h[d];
         }
         a.bc = op.bc;
         a.c0 = op.c0;
@@ -285,7 +292,12 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
         a.ty = op.ty;
         a.tz = op.tz;
         a.field = op.field;
+        // boundary data: in the sweep, or afterwards in a launch of their own
+        const bool separate = a.bdata && op.bdata_mode == EXPI_BDATA_SEPARATE;
+        const double bscale = (epi == EPI_APPLY) ? a.alpha : a.sigma;
+        if (separate) a.bdata = 0;
         e = launch_stencil(op, g, epi, tin, tout, a, s);
+        if (e == hipSuccess && separate) e = launch_boundary(op, bscale, a.out, tout, s);
     }
     if (e != hipSuccess) return e;
     if (after_sweep) {
@@ -299,8 +311,9 @@ hipError_t launch_sweep(const Op& op, int epi, int tin, int tout, SweepArgs a, h
     f.partials = a.partials;
     f.st = a.st;
     f.nparts = g.grid;
-    f.d0 = a.d0;
-    f.d1 = a.d1;
+    // the stop test needs |d_j| (complex coefficients: the modulus)
+    f.d0 = std::hypot(a.d0, a.d0i);
+    f.d1 = std::hypot(a.d1, a.d1i);
     f.tol = a.tol;
     f.j = a.j;
     f.guard = a.guard;

@@ -39,6 +39,40 @@ def targets(stats: dict) -> np.ndarray:
     return np.array([math.log2(stats["substeps"]), stats["degree_max"]], dtype=np.float64)
 
 
+def forced_substeps_l_max(length: float, s: int) -> float:
+    """l_max that makes the plain method take exactly s substeps when
+    tau (b - a) = length: ceil(length / l_max) = ceil(s - 1/2) = s."""
+    return length / (s - 0.5)
+
+
+def substep_candidates(length: float, s_plain: int, sel_l_max: float = 500.0) -> list:
+    """Substep counts worth trying for a step of tau (b - a) = length: the
+    plain count and those that make each substep about 150 to sel_l_max
+    long (never more than the plain count)."""
+    c = {s_plain}
+    for L in (sel_l_max, 400.0, 300.0, 200.0, 150.0):
+        if L <= sel_l_max:
+            c.add(max(1, math.ceil(length / L)))
+    return sorted(x for x in c if x <= s_plain)
+
+
+def best_label(run_forced, length: float, s_plain: int, plain_stats: dict,
+               sel_l_max: float = 500.0):
+    """Label of one logged step: the substep count with the fewest products
+    among those that converge (ties to the larger count), and the degree it
+    needed.  run_forced(s) runs the step from the same state with exactly s
+    substeps and no retries and returns its stats dict, or None if it did
+    not converge.  Returns (targets array, {s: matvecs})."""
+    tried = {s_plain: plain_stats}
+    for s in substep_candidates(length, s_plain, sel_l_max):
+        if s not in tried:
+            tried[s] = run_forced(s)
+    ok = {s: st for s, st in tried.items() if st is not None and st["converged"]}
+    best = min(ok, key=lambda s: (ok[s]["matvecs"], -s))
+    return (np.array([math.log2(best), ok[best]["degree_max"]], dtype=np.float64),
+            {s: (st["matvecs"] if st is not None else None) for s, st in tried.items()})
+
+
 class Net:
     """Parameters and Adam state on the device; training by library kernels."""
 

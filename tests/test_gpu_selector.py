@@ -3,7 +3,11 @@
 * forward, backward and Adam kernels against the float64 oracle (oracle.mlp);
 * the learned mode on held-out exponential Euler steps of the 3D
   reaction-diffusion problem: same accuracy as the plain method, with the
-  network's degree prediction replacing most stop tests.
+  network's degree prediction replacing most stop tests;
+* the gain of the learned substep count on steps whose size changes from
+  step to step (tau (b - a) from 20 to 800, so the plain method has no
+  degree hint and often several substeps): fewer products and less time at
+  the same tolerance, with device and host features equal.
 """
 import math
 
@@ -185,3 +189,81 @@ def test_learned_mode_near_l_max_matches_oracle(E):
         # the increment alone: the two differ by at most the oracle's own
         # truncation (the stop test holds it to 1e-10 of ||p||)
         assert np.linalg.norm((got - u0) - (uo - u0)) / np.linalg.norm(uo - u0) <= 1e-9
+
+
+def test_learned_substeps_gain_on_variable_step_sizes(E):
+    """Labels: for each logged step, the substep count with the fewest
+    products among those that converge (selector.best_label).  On held-out
+    steps the learned mode must take at least 20% fewer products and less
+    time than the plain method, both against a tol 1e-13 reference within
+    the error the tolerance allows, and the selector kernel's features must
+    equal the host's."""
+    import torch
+    n = 32
+    tol = 1e-8
+    rng = np.random.default_rng(11)
+    amps = synth.diffusivity_amplitudes(7, seed=12)
+
+    def draw_tau(a, b):
+        return math.exp(rng.uniform(math.log(20.0), math.log(800.0))) / (b - a)
+
+    X, Y = [], []
+    for k, amp in enumerate(amps[:5]):
+        op = rd_op(E, n, amp)
+        a, b = op.interval()
+        u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=300 + k), device="cuda:0")
+        for _ in range(12):
+            tau = draw_tau(a, b)
+            L = tau * (b - a)
+
+            def forced(s, u=u, tau=tau, L=L, op=op):
+                try:
+                    return E.expeuler_step(op, tau, u.clone(), tol=tol, params=E.LejaParams(
+                        l_max=E.selector.forced_substeps_l_max(L, s), max_retries=0))
+                except E.ExpiError:
+                    return None
+            st = E.expeuler_step(op, tau, u, tol=tol)
+            lab, _ = E.selector.best_label(forced, L, st["substeps"], st)
+            X.append(E.selector.features(st, tau))
+            Y.append(lab)
+    net, norms, hist = E.selector.train(np.array(X), np.array(Y), hidden=64, epochs=2000, lr=3e-3,
+                                        kappa=1.5, seed=0)
+    sel = E.selector.pack(net, norms)
+    feat = torch.zeros(8, dtype=torch.float32, device="cuda:0")
+    lp = E.LejaParams(selector=sel, selector_hidden=64, selector_features=feat)
+    mv = {"plain": 0, "learned": 0}
+    ms = {"plain": 0.0, "learned": 0.0}
+    import time
+    for k, amp in enumerate(amps[5:]):
+        op = rd_op(E, n, amp)
+        a, b = op.interval()
+        u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=700 + k), device="cuda:0")
+        for step in range(10):
+            tau = draw_tau(a, b)
+            ref = u.clone()
+            E.expeuler_step(op, tau, ref, tol=1e-13)
+            ul = u.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sp = E.expeuler_step(op, tau, u, tol=tol)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sl = E.expeuler_step(op, tau, ul, tol=tol, params=lp)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            mv["plain"] += sp["matvecs"]
+            mv["learned"] += sl["matvecs"]
+            ms["plain"] += 1e3 * (t1 - t0)
+            ms["learned"] += 1e3 * (t2 - t1)
+            ep = ((u - ref).norm() / ref.norm()).item()
+            el = ((ul - ref).norm() / ref.norm()).item()
+            assert ep <= 5e-8 and el <= 5e-8, (step, ep, el)
+            assert sl["pred_degree"] > 0
+            # the features the selector kernel computed (from the probe at
+            # the plain substep count) are the host's, to float32 rounding
+            hf = E.selector.features(sp, tau)
+            assert np.allclose(feat.cpu().numpy(), hf, rtol=1e-5, atol=1e-6)
+    print(f"variable steps: products plain {mv['plain']} learned {mv['learned']}; "
+          f"ms plain {ms['plain']:.1f} learned {ms['learned']:.1f}")
+    assert mv["learned"] <= 0.8 * mv["plain"]
+    assert ms["learned"] < ms["plain"]

@@ -67,6 +67,29 @@ def test_divided_differences_match_oracle(L, k, length):
     assert np.allclose(d_lib[lead], d_or[lead], rtol=1e-9, atol=0)
 
 
+@pytest.mark.parametrize("k", [0, 1])
+@pytest.mark.parametrize("length", [3.0, 40.0, 100.0])
+def test_skew_divided_differences_match_oracle(L, k, length):
+    """The complex coefficients of phi_k(-i delta H) (long double in the
+    library, 80-digit mpmath in the oracle) define the same interpolant."""
+    from paper_1309_4616_amd import _binding
+    c, gamma = 7.0, length / 4
+    xi = oleja.leja_points(101)
+    lib_d = _binding.divided_differences_skew(k, 1.0, c, gamma, 101)
+    ora_d = oleja.divided_differences_skew(k, 1.0, c, gamma, xi)
+    xs = np.linspace(-2, 2, 801)
+
+    def newton(d):
+        p = np.zeros(xs.shape, dtype=np.complex128)
+        w = np.ones(xs.shape)
+        for j in range(len(d)):
+            p += d[j] * w
+            w = w * (xs - xi[j])
+        return p
+    pl, po = newton(lib_d), newton(ora_d)
+    assert np.max(np.abs(pl - po)) <= 1e-13 * max(1.0, np.max(np.abs(po)))
+
+
 def _stencil(L, dim=2, n=(8, 8, 8), h=(0.1, 0.1, 0.1), bc=0, kind=0, tabs=(None, None, None), field=None):
     op = ctypes.c_void_p()
     nn = (ctypes.c_int64 * 3)(*n)
@@ -136,7 +159,20 @@ def test_call_validation_before_any_hip_call(L):
     x = ctypes.c_void_p(ctypes.addressof(v))
     assert L.apply_op(op, 1.0, 0.0, x, x, 0, None) == -2
     assert L.apply_op(op, float("inf"), 0.0, x, yp, 0, None) == -1
-    assert L.expeuler_step(op, 1, 1e-3, yp, 1e-10, 0, None, ws, need, ctypes.byref(st), None) == -1
+    assert L.expeuler_step(op, 7, 1e-3, yp, 1e-10, 0, None, ws, need, ctypes.byref(st), None) == -1
+    assert b"nonlin" in L.expi_last_error()
+    # the second-order step needs one more float64 vector of workspace
+    need2 = L.expi_exprk2_workspace_bytes(op, 0)
+    assert need2 >= need + 16 * 16 * 8
+    assert L.exprk2_step(op, 0, 1e-3, yp, 1e-10, 0, None, ws, need, ctypes.byref(st), None) == -3
+    assert L.exprk2_step(op, 3, 1e-3, yp, 1e-10, 0, None, ws, need, ctypes.byref(st), None) == -1
+    assert L.exprk2_step(op, 0, -1.0, yp, 1e-10, 0, None, ws, need, ctypes.byref(st), None) == -1
+    # the pointwise nonlinearity kernel
+    assert L.expi_nonlinearity(5, 16, vp, yp, 0, None) == -1
+    assert L.expi_nonlinearity(1, 16, vp, yp, 2, None) == -1
+    assert L.expi_nonlinearity(1, -1, vp, yp, 0, None) == -1
+    assert L.expi_nonlinearity(1, 0, None, None, 0, None) == 0
+    assert L.expi_nonlinearity(1, 16, vp, ctypes.c_void_p(ctypes.addressof(v) + 8), 0, None) == -2
     nc = ctypes.c_int()
     assert L.expi_op_autotune(op, 0, 0, ws, need, None, None, None, 0, ctypes.byref(nc)) == -1
     assert L.expi_op_autotune(op, 0, 5, ws, need - 1, None, None, None, 0, ctypes.byref(nc)) == -3
