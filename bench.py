@@ -536,6 +536,9 @@ def run_spin_bath(args):
     gen_s = time.perf_counter() - t0
     op = E.CsrComplexOp(g.n, g.rowptr, g.colind, g.val)
     del g.val
+    # lanes per row and waves per workgroup from the library's autotuner
+    from paper_1309_4616_amd import autotune
+    tuned = autotune.tune(op, "f64", reps=3, use_cache=False)
     psi = torch.as_tensor(synth.complex_uniform_vector(g.n, 0), device="cuda:0")
     psi /= psi.norm()
     y = torch.empty_like(psi)
@@ -562,6 +565,8 @@ def run_spin_bath(args):
         "product_gbs": per_product / (avg_us * 1e-6) / 1e9,
         "product_frac": per_product / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
         "norm_drift": abs(y.norm().item() - 1.0),
+        "tiles": {"lanes_per_row_waves": tuned["tiles"][:2], "chosen_by": "expi_op_autotune",
+                  "candidates_us": tuned["candidates"]},
         "generate_s": gen_s,
         "paper_table_v": "21 spins to t = 10 at tol 1e-5: 7.7 s FP64 on one Tesla C2075 (its own Hamiltonian); context only",
     }

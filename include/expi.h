@@ -422,10 +422,13 @@ int expi_batch_prepare(expi_batch *b, void *ws, size_t ws_bytes, void *stream);
 int expi_batch_launch(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
                       void *stream);
 /* Build a HIP graph (owned by the batch) of the state reset and `rounds`
- * rounds as kernel nodes, for v, y and ws as given; rounds = 0 (or more
- * than expi_batch_max_rounds) takes expi_batch_max_rounds, enough for every
- * instance; rounds after the last instance finished return at once.  With
- * fewer rounds, unfinished instances report EXPI_ENOTCONV.  Replay with
+ * rounds as kernel nodes, for v, y and ws as given; rounds more than
+ * expi_batch_max_rounds take expi_batch_max_rounds, enough for every
+ * instance.  rounds = 0: the rounds the last expi_batch_launch needed plus
+ * 1/8 and 8 more (the same inputs need exactly as many), or
+ * expi_batch_max_rounds if there was none.  Rounds after the last instance
+ * finished return at once.  With too few rounds, unfinished instances
+ * report EXPI_ENOTCONV (expi_batch_results).  Replay with
  * expi_batch_replay (asynchronous, one graph launch on `stream`).  The
  * graph holds no copies or fills.  `stream` of capture is unused. */
 int expi_batch_capture(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,

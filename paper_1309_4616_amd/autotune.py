@@ -31,12 +31,14 @@ def device_tag(device) -> str:
 
 def op_key(op, dtype: str) -> str:
     """Cache key: what determines the best tile setting."""
-    from . import CsrOp, StencilOp
+    from . import CsrComplexOp, CsrOp, StencilOp
     if isinstance(op, StencilOp):
-        kind = {0: "const", 1: "separable", 2: "field"}[op.coef_kind]
+        kind = {0: "const", 1: "separable", 2: "field", 3: "dlap"}[op.coef_kind]
         body = f"stencil{len(op.shape)}d-{'x'.join(map(str, op.shape))}-{op.bc}-{kind}"
     elif isinstance(op, CsrOp):
         body = f"csr-n{op.size}-nnz{op.nnz}"
+    elif isinstance(op, CsrComplexOp):
+        body = f"csr-complex-n{op.size}-nnz{op.nnz}"
     else:
         raise TypeError("not an operator")
     return f"{body}-{dtype}-{device_tag(op.device)}"

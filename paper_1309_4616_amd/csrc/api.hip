@@ -928,6 +928,11 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
         C.s_min = s_min;
         C.decide_s = C.selector && attempt == 0 && !learned_sub && s_min < sub;
         C.fixed_m = learned_sub ? pred_m : 0;
+        // substeps longer than l_max (only the learned count makes them):
+        // the stop test's tolerance scales by l_max / (delta (b - a)), since
+        // the two-term estimate of the remainder is looser on long substeps
+        const double len = delta * (ib - ia);
+        C.tol = (learned_sub && len > P.l_max) ? tol * (P.l_max / len) : tol;
         acc = expi_stats{};
         acc.substeps = sub;
         acc.retries = attempt;
@@ -1353,7 +1358,10 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
     char* w = static_cast<char*>(ws);
     // candidate tile settings
     std::vector<Tiles> C;
-    if (o.kind != 0) {
+    if (o.kind == 2) {
+        for (int v : {1, 2, 4, 8, 16})
+            for (int wv : {1, 2, 4, 8}) C.push_back(Tiles{v, wv, 1});
+    } else if (o.kind != 0) {
         for (int v : {4, 8, 16})
             for (int wv : {1, 2, 4, 8}) C.push_back(Tiles{v, wv, 1});
     } else {

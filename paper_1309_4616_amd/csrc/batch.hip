@@ -482,6 +482,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 }  // namespace
 
 struct Batch {
+    int last_rounds = 0;   // rounds the last eager solve needed (0: none yet)
     int count, dtype, bc, m_max, waves, march;
     double c0, tol;
     std::vector<BatchInfo> info;
@@ -682,6 +683,7 @@ int run_rounds(Batch& b, char* ws, const double* v, double* y, hipStream_t s) {
             pending.pop_front();
             BHIP(hipEventSynchronize(b.ev[slot]));
             if (b.pinned[slot].finished >= (unsigned)b.count) {
+                b.last_rounds = (int)b.pinned[slot].rounds;
                 done = true;
                 break;
             }
@@ -971,7 +973,12 @@ int expi_batch_capture(expi_batch* bp, const double* v, double* y, void* ws, siz
     int rc = check_run_args(b, v, y, ws, ws_bytes);
     if (rc) return rc;
     if (rounds < 0) return bfail(EXPI_EINVAL, "rounds must be >= 0");
-    if (rounds == 0 || rounds > b->max_rounds) rounds = b->max_rounds;
+    if (rounds == 0) {
+        // the rounds the last eager solve needed, with a margin of 1/8 + 8
+        // (the same inputs need exactly as many); else the bound
+        rounds = b->last_rounds > 0 ? b->last_rounds + b->last_rounds / 8 + 8 : b->max_rounds;
+    }
+    if (rounds > b->max_rounds) rounds = b->max_rounds;
     (void)stream;
     drop_graph(b);
     return build_round_graph(*b, static_cast<char*>(ws), v, y, rounds);

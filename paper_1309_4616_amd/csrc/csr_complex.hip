@@ -8,8 +8,11 @@
 // of the Hermitian H), and only the divided differences d_j are complex;
 // the start vector of a phi_1 substep is r = (-i tau) H y + v.
 //
-// `G` lanes share a row (4 by default: the paper found four threads per
-// row best for its spin system with about 40 entries per row); each lane
+// `G` lanes share a row (1, 2, 4, 8 or 16; 4 by default: the paper found
+// four threads per row best for its spin system with about 40 entries per
+// row; with one lane per row the lanes of a wave hold consecutive rows,
+// whose k-th entries of a spin system flip the same spins, so their gathers
+// land in the same lines); each lane
 // walks the row with stride G, so the G lanes read G consecutive 16-byte
 // values per instruction, the partial sums meet by cross-lane butterflies
 // and the row's first lane applies the epilogue.  Rows are taken in
@@ -72,13 +75,29 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_complex_sweep(SweepArgs a)
             }
             continue;
         }
+        // four entries per lane and pass, their loads issued together
+        // (indices clamped to the row's last entry, contributions past the
+        // row's end masked), so that each lane has four gathers in flight
         cplx acc = {0.0, 0.0};
-        for (int e = e0 + sub; e < e1; e += G) {
-            const int c = a.colind[e];
-            if ((unsigned)c < nrows) {
-                const cplx v = val[e], xc = x[c];
-                acc.x = fma(v.x, xc.x, fma(-v.y, xc.y, acc.x));
-                acc.y = fma(v.x, xc.y, fma(v.y, xc.x, acc.y));
+        for (int e = e0 + sub; e < e1; e += 4 * G) {
+            int c[4];
+            cplx v[4], xc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int eq = min(e + q * G, e1 - 1);
+                c[q] = a.colind[eq];
+                v[q] = val[eq];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = (e + q * G < e1) && ((unsigned)c[q] < nrows);
+                xc[q] = x[ok ? c[q] : row];
+                if (!ok) v[q] = cplx{0.0, 0.0};
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc.x = fma(v[q].x, xc[q].x, fma(-v[q].y, xc[q].y, acc.x));
+                acc.y = fma(v[q].x, xc[q].y, fma(v[q].y, xc[q].x, acc.y));
             }
         }
 #pragma unroll
@@ -119,6 +138,8 @@ template <int EPI>
 hipError_t go(const Geom& g, const SweepArgs& a, hipStream_t s) {
     const dim3 grid(g.grid), block(64 * g.waves);
     switch (g.vec) {  // lanes per row
+        case 1: hipLaunchKernelGGL((csr_complex_sweep<EPI, 1>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((csr_complex_sweep<EPI, 2>), grid, block, 0, s, a); break;
         case 8: hipLaunchKernelGGL((csr_complex_sweep<EPI, 8>), grid, block, 0, s, a); break;
         case 16: hipLaunchKernelGGL((csr_complex_sweep<EPI, 16>), grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL((csr_complex_sweep<EPI, 4>), grid, block, 0, s, a); break;

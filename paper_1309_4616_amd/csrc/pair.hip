@@ -99,44 +99,70 @@ __device__ __forceinline__ PlaneW<TC> plane_weights(const RowW<TC>& r, const ZPl
 // neighbour: 0 under Dirichlet, the point's own value otherwise), the y and
 // z neighbour values (anything finite where the neighbour is missing: its
 // weight is 0) and the weights.
+// The face weights of the lane's two points on one plane of its row: the
+// x faces left of point 0, between the points and right of point 1, and per
+// point the y and z faces and the diagonal.  Both products of a pair sweep
+// use the same plane's weights (the second one two iterations later), so
+// the FP32 sweep keeps them in registers between the two.
+template <class TC>
+struct PointW {
+    TC wxl, wxc, wxr;
+    TC wym[2], wyq[2], wzm[2], wzq[2], d[2];
+};
+
+template <int COEF, class TC>
+__device__ __forceinline__ PointW<TC> point_weights(const PlaneW<TC>& w, TC c0ihx, const TC (&xd)[5]) {
+    // xd: X of the two points, face values left, between, right
+    PointW<TC> q;
+    TC X[2] = {1, 1};
+    if (COEF == EXPI_COEF_SEPARABLE) {
+        X[0] = xd[0];
+        X[1] = xd[1];
+        q.wxl = c0ihx + w.sx * xd[2];
+        q.wxc = c0ihx + w.sx * xd[3];
+        q.wxr = c0ihx + w.sx * xd[4];
+    } else {
+        q.wxl = q.wxc = q.wxr = c0ihx;
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        if (COEF == EXPI_COEF_SEPARABLE) {
+            q.wym[v] = w.aym + w.bym * X[v];
+            q.wyq[v] = w.ayq + w.byq * X[v];
+            q.wzm[v] = w.azm + w.bzm * X[v];
+            q.wzq[v] = w.azq + w.bzq * X[v];
+            q.d[v] = w.ad + w.bd * X[v];
+        } else {
+            q.wym[v] = w.aym;
+            q.wyq[v] = w.ayq;
+            q.wzm[v] = w.azm;
+            q.wzq[v] = w.azq;
+            q.d[v] = w.ad;
+        }
+    }
+    return q;
+}
+
+template <class TC>
+__device__ __forceinline__ void aw_pair_w(const TC (&wc)[2], TC wl, TC wr, const TC (&ym)[2],
+                                          const TC (&yq)[2], const TC (&zm)[2], const TC (&zq)[2],
+                                          const PointW<TC>& q, TC (&aw)[2]) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        const TC left = v == 0 ? wl : wc[0];
+        const TC right = v == 1 ? wr : wc[1];
+        const TC fl = v == 0 ? q.wxl : q.wxc;
+        const TC fr = v == 1 ? q.wxr : q.wxc;
+        aw[v] = fl * (left - wc[v]) + fr * (right - wc[v]) + q.wym[v] * ym[v] + q.wyq[v] * yq[v] +
+                q.wzm[v] * zm[v] + q.wzq[v] * zq[v] - q.d[v] * wc[v];
+    }
+}
+
 template <int COEF, class TC>
 __device__ __forceinline__ void aw_pair(const TC (&wc)[2], TC wl, TC wr, const TC (&ym)[2],
                                         const TC (&yq)[2], const TC (&zm)[2], const TC (&zq)[2],
                                         const PlaneW<TC>& w, TC c0ihx, const TC (&xd)[5], TC (&aw)[2]) {
-    // xd: X of the two points, face values left, between, right
-    TC wxl, wxc, wxr, X[2] = {1, 1};
-    if (COEF == EXPI_COEF_SEPARABLE) {
-        X[0] = xd[0];
-        X[1] = xd[1];
-        wxl = c0ihx + w.sx * xd[2];
-        wxc = c0ihx + w.sx * xd[3];
-        wxr = c0ihx + w.sx * xd[4];
-    } else {
-        wxl = wxc = wxr = c0ihx;
-    }
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        TC wym, wyq, wzm, wzq, d;
-        if (COEF == EXPI_COEF_SEPARABLE) {
-            wym = w.aym + w.bym * X[v];
-            wyq = w.ayq + w.byq * X[v];
-            wzm = w.azm + w.bzm * X[v];
-            wzq = w.azq + w.bzq * X[v];
-            d = w.ad + w.bd * X[v];
-        } else {
-            wym = w.aym;
-            wyq = w.ayq;
-            wzm = w.azm;
-            wzq = w.azq;
-            d = w.ad;
-        }
-        const TC left = v == 0 ? wl : wc[0];
-        const TC right = v == 1 ? wr : wc[1];
-        const TC fl = v == 0 ? wxl : wxc;
-        const TC fr = v == 1 ? wxr : wxc;
-        aw[v] = fl * (left - wc[v]) + fr * (right - wc[v]) + wym * ym[v] + wyq * yq[v] +
-                wzm * zm[v] + wzq * zq[v] - d * wc[v];
-    }
+    aw_pair_w<TC>(wc, wl, wr, ym, yq, zm, zq, point_weights<COEF, TC>(w, c0ihx, xd), aw);
 }
 
 template <class T, class TC>
@@ -419,6 +445,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         // k, k-1, k-2 (values from the rings' zero fill before the first)
         constexpr bool kOwnW1 = sizeof(TW) == 4;
         TC Q0[2] = {0, 0}, Q1[2] = {0, 0}, Q2[2] = {0, 0};
+        // FP32: the point weights of plane k+1 (step 3) wait two iterations
+        // for step 2 on the same plane; slot (plane - kst) mod 2
+        constexpr bool kKeepW = sizeof(TW) == 4;
+        PointW<TC> PWq[2];
         L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
         // ring slot of a plane: (plane - kst) mod 3.  The march is unrolled
@@ -471,6 +501,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         // a point of the outer layer has a zero row under interior_only
         const bool yedge = !(eym && eyq);
         for (int k0 = kst; k0 <= ke; k0 += 6) {
+            // FP32: the lane's squares of a block of six planes are summed in
+            // FP32 and added to the FP64 sums once per block (at most twelve
+            // terms per FP32 sum); FP64 adds each square
+            float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
                 const int k = k0 + s;
@@ -515,18 +549,20 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         const TC er = vb[ry * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
                         TC left, right;
                         neighbours(wc, ezero ? (TC)0 : el, ezero ? (TC)0 : er, left, right);
-                        const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, kp, n2, dir, c0ihz, c1ihx);
                         TC aw[2];
-                        aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
+                        if constexpr (kKeepW) {
+                            aw_pair_w<TC>(wc, left, right, ym, yq, zm, zq, PWq[(s + 1) & 1], aw);
+                        } else {
+                            const PlaneW<TC> pw =
+                                plane_weights<COEF, TC>(rw, ztab, kb - 2, kp, n2, dir, c0ihz, c1ihx);
+                            aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
+                        }
                         if (ionly) {
                             const bool edge = yedge || kp == 0 || kp == n2 - 1;
                             if (edge || lb) aw[0] = 0;
                             if (edge || rb) aw[1] = 0;
                         }
                         const TC* pp = P[(s + 1) & 1];        // p (FIRST: r) of plane k-1
-                        // FP32: the lane's two squares are summed in FP32 and
-                        // added to the FP64 sums once (one rounding to FP32 per
-                        // pair of terms); FP64 adds each square
                         constexpr bool kPairSq = sizeof(TW) == 4;
                         TC q0 = 0, q1 = 0, q2 = 0, q3 = 0;
 #pragma unroll
@@ -552,11 +588,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                                 s3 += (double)p2 * (double)p2;
                             }
                         }
-                        if (kPairSq && xin) {
-                            s0 += (double)q0;
-                            if (!START) s1 += (double)q1;
-                            s2 += (double)q2;
-                            s3 += (double)q3;
+                        if (kPairSq) {
+                            b0 += (float)q0;
+                            if (!START) b1 += (float)q1;
+                            b2 += (float)q2;
+                            b3 += (float)q3;
                         }
                     }
                     // the stores, on every path (dropped where there is no
@@ -589,8 +625,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     TC left, right;
                     neighbours(wc, ezero ? (TC)0 : el, ezero ? (TC)0 : er, left, right);
                     const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, q, n2, dir, c0ihz, c1ihx);
+                    const PointW<TC> qw = point_weights<COEF, TC>(pw, c0ihx, xd);
+                    if constexpr (kKeepW) PWq[(s + 1) & 1] = qw;   // plane k+1, read at k+2
                     TC aw[2];
-                    aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
+                    aw_pair_w<TC>(wc, left, right, ym, yq, zm, zq, qw, aw);
                     if (ionly) {
                         const bool edge = yedge || q == 0 || q == n2 - 1;
                         if (edge || lb) aw[0] = 0;
@@ -614,6 +652,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     }
                 }
                 __syncthreads();
+            }
+            if (sizeof(TW) == 4 && xin) {
+                s0 += (double)b0;
+                if (!START) s1 += (double)b1;
+                s2 += (double)b2;
+                s3 += (double)b3;
             }
         }
     }

@@ -233,6 +233,8 @@ Tiles default_tiles(const Op& op) {
 
 bool tiles_valid(const Op& op, const Tiles& t) {
     if (t.waves < 1 || t.waves > kMaxWaves) return false;
+    if (op.kind == 2)
+        return (t.vec == 1 || t.vec == 2 || t.vec == 4 || t.vec == 8 || t.vec == 16) && t.march == 1;
     if (op.kind != 0) return (t.vec == 4 || t.vec == 8 || t.vec == 16) && t.march == 1;
     return (t.vec == 1 || t.vec == 2) && t.march >= kMinMarch && t.march <= kMaxMarch &&
            t.march % 4 == 0;
