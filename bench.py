@@ -448,6 +448,14 @@ def run_paper_tables(args):
         for dt, td, bpp in (("f64", torch.float64, 16), ("f32", torch.float32, 8)):
             x = torch.rand(pts, dtype=td, device="cuda:0")
             y = torch.empty_like(x)
+            # tile setting for this size and dtype from the library's autotuner
+            # (it times the fused Newton sweep, the same traversal); every case
+            # of the size uses it
+            from paper_1309_4616_amd import autotune
+            probe = E.StencilOp((n, n, n), h, "dirichlet0")
+            tiles = autotune.tune(probe, dt, reps=3, use_cache=False)["tiles"]
+            del probe
+            torch.cuda.empty_cache()
             cases = [("I", "none (interior only)", E.StencilOp((n, n, n), h, "interior_only"), None),
                      ("I", "homogeneous Dirichlet", E.StencilOp((n, n, n), h, "dirichlet0"), None)]
             for kind in ("z1mz_xy", "sinpiz_expmxy"):
@@ -458,8 +466,9 @@ def run_paper_tables(args):
             cases.append(("II", "D(x,y) Laplacian, D in kernel", E.StencilOp((n, n, n), h, "dirichlet0",
                                                                              coef=("dlap", 1.0)), None))
             for table, what, op, _ in cases:
+                op.set_tiles(*tiles)
                 ms = _time_launches(lambda: E.apply_op(op, 1.0, 0.5, x, y), args.table_reps)
-                rows.append({"table": table, "n": n, "dtype": dt, "case": what, "ms": ms,
+                rows.append({"table": table, "n": n, "dtype": dt, "case": what, "ms": ms, "tiles": tiles,
                              "gbs": bpp * pts / (ms * 1e-3) / 1e9,
                              "gflops_10_per_point": 10 * pts / (ms * 1e-3) / 1e9})
             del x, y

@@ -425,7 +425,7 @@ int expi_batch_launch(expi_batch *b, const double *v, double *y, void *ws, size_
  * rounds as kernel nodes, for v, y and ws as given; rounds more than
  * expi_batch_max_rounds take expi_batch_max_rounds, enough for every
  * instance.  rounds = 0: the rounds the last expi_batch_launch needed plus
- * 1/8 and 8 more (the same inputs need exactly as many), or
+ * 1/64 and 8 more (the same inputs need exactly as many), or
  * expi_batch_max_rounds if there was none.  Rounds after the last instance
  * finished return at once.  With too few rounds, unfinished instances
  * report EXPI_ENOTCONV (expi_batch_results).  Replay with

@@ -974,9 +974,9 @@ int expi_batch_capture(expi_batch* bp, const double* v, double* y, void* ws, siz
     if (rc) return rc;
     if (rounds < 0) return bfail(EXPI_EINVAL, "rounds must be >= 0");
     if (rounds == 0) {
-        // the rounds the last eager solve needed, with a margin of 1/8 + 8
+        // the rounds the last eager solve needed, with a margin of 1/64 + 8
         // (the same inputs need exactly as many); else the bound
-        rounds = b->last_rounds > 0 ? b->last_rounds + b->last_rounds / 8 + 8 : b->max_rounds;
+        rounds = b->last_rounds > 0 ? b->last_rounds + b->last_rounds / 64 + 8 : b->max_rounds;
     }
     if (rounds > b->max_rounds) rounds = b->max_rounds;
     (void)stream;
