@@ -442,7 +442,7 @@ class Batch:
         return int(lib().expi_batch_graph_rounds(self._h))
 
     def launch_persistent(self, v, y, stream=None):
-        """The single persistent-kernel launch (switched off: raises)."""
+        """All rounds in one persistent (cooperative) kernel launch."""
         check(lib().expi_batch_launch_persistent(*self._run_args(v, y),
                                                  _stream_ptr(stream, self.device)))
 

@@ -25,8 +25,12 @@
 // (no copies or fills inside) and replayed.  A round in which no instance is
 // left returns at once.
 //
-// A single persistent kernel that runs all rounds with grid barriers is kept
-// below but switched off (see expi_batch_launch_persistent).
+// The alternative is one persistent kernel that runs every round, with an
+// atomic tile counter and grid barriers between the tiles and the stop
+// tests (expi_batch_launch_persistent; a cooperative launch, so that every
+// workgroup is resident).  Every loop in it ends: the rounds are bounded,
+// each barrier wait has a time limit, and a workgroup that takes more tile
+// passes than the batch has tiles aborts the launch.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -45,7 +49,6 @@ namespace {
 enum Phase : int { PH_START = 0, PH_FIRST = 1, PH_NEWTON = 2, PH_UPDATE = 3, PH_DONE = 4, PH_FAILED = 5 };
 
 constexpr int kMaxBatch = 4096;
-constexpr int kBatchLaunchEnabled = 0;   // see expi_batch_launch
 
 struct alignas(16) BatchInfo {   // static per instance
     long long off;               // offset of the instance's vectors, in elements
@@ -83,10 +86,14 @@ struct BatchArgs {
     void* w0;
     void* w1;
     void* p;
-    int count, m_max, march, max_rounds, bc;
+    int count, m_max, march, max_rounds, bc, total_tiles;
     double c0, tol;
     long long deadline_ticks;   // longest wait at a barrier, GPU wall-clock ticks
 };
+
+// s_waitcnt operand that waits for vector memory operations only:
+// vmcnt 0, expcnt 7 (no wait), lgkmcnt 15 (no wait).
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 // Grid barrier with a time limit; returns false once any workgroup has
 // aborted.  Arrival releases the workgroup's writes; waiting polls the
@@ -95,6 +102,11 @@ struct BatchArgs {
 // follows.  A waiter past the deadline (GPU wall clock) sets the abort flag,
 // which every other waiter sees, so no wave can wait forever.
 __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
+    // every wave waits for its own stores (s_waitcnt vmcnt(0)) before the
+    // workgroup barrier: the workgroup barrier alone does not wait for them,
+    // and the release below (L2 write-back, then the arrival) must cover the
+    // stores of every wave, not only those of thread 0's
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     if (threadIdx.x == 0) {
         BatchCtrl* c = B.ctrl;
@@ -230,6 +242,10 @@ __device__ void finalize_instance(const BatchArgs& B, int inst) {
     const BatchInfo& I = B.info[inst];
     BatchState* S = &B.state[inst];
     const int phase = S->phase;
+    // every wave has loaded the phase before thread 0 stores the next one: a
+    // wave that loaded it afterwards would take the other branch and pair
+    // the workgroup's later barriers wrongly
+    __syncthreads();
     if (phase == PH_FIRST || phase == PH_NEWTON) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
@@ -414,7 +430,7 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
     if (threadIdx.x == 0 && !active_phase(B.state[inst].phase)) atomicAdd(&B.ctrl->finished, 1u);
 }
 
-// ---- persistent kernel (switched off) -----------------------------------------
+// ---- persistent kernel --------------------------------------------------------
 
 template <class TW>
 __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
@@ -429,7 +445,16 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
         if (nact == 0) break;
         // (B) the round's tiles
         unsigned* ctr = &B.ctrl->tile_ctr[round & 1];
+        // each pass takes a distinct counter value, so a workgroup makes at
+        // most total + 1 passes; more means the workgroup's waves disagree,
+        // and the launch aborts instead of looping
+        int passes = 0;
         while (true) {
+            if (++passes > B.total_tiles + 1) {
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&B.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
             if (threadIdx.x == 0) s_tile = (int)atomicAdd(ctr, 1u);
             __syncthreads();
             const int t = s_tile;
@@ -572,6 +597,7 @@ BatchArgs make_args(const Batch& b, char* ws, const double* v, double* y) {
     a.m_max = b.m_max;
     a.march = b.march;
     a.max_rounds = b.max_rounds;
+    a.total_tiles = b.total_tiles;
     a.bc = b.bc;
     a.c0 = b.c0;
     a.tol = b.tol;
@@ -924,16 +950,6 @@ int expi_batch_prepare(expi_batch* bp, void* ws, size_t ws_bytes, void* stream) 
     return EXPI_OK;
 }
 
-// The persistent launch is switched off: on the GPU it did not finish (the
-// host waited past its test's time limit on both runs, the second with
-// cooperative launches and time-bounded barrier waits), and the cause has
-// not been shown yet.  The round kernels replace it.
-static int batch_disabled() {
-    return bfail(EXPI_EUNSUPPORTED,
-                 "the persistent batched kernel is switched off until the cause of its "
-                 "unfinished GPU runs is found; use expi_batch_launch");
-}
-
 static int check_run_args(Batch* b, const double* v, double* y, void* ws, size_t ws_bytes) {
     if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
     if (ws != b->prepared_ws) return bfail(EXPI_EINVAL, "call expi_batch_prepare with this workspace first");
@@ -1055,8 +1071,6 @@ int expi_batch_get_tiles(const expi_batch* bp, int* waves, int* march) {
 int expi_batch_launch_persistent(expi_batch* bp, const double* v, double* y, void* ws,
                                  size_t ws_bytes, void* stream) {
     Batch* b = reinterpret_cast<Batch*>(bp);
-    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
-    if (kBatchLaunchEnabled == 0) return batch_disabled();
     int rc = check_run_args(b, v, y, ws, ws_bytes);
     if (rc) return rc;
     return enqueue(*b, static_cast<char*>(ws), v, y, static_cast<hipStream_t>(stream));
@@ -1065,8 +1079,6 @@ int expi_batch_launch_persistent(expi_batch* bp, const double* v, double* y, voi
 int expi_batch_capture_persistent(expi_batch* bp, const double* v, double* y, void* ws,
                                   size_t ws_bytes, void* stream) {
     Batch* b = reinterpret_cast<Batch*>(bp);
-    if (!b || !v || !y || !ws) return bfail(EXPI_EINVAL, "NULL argument");
-    if (kBatchLaunchEnabled == 0) return batch_disabled();
     int rc = check_run_args(b, v, y, ws, ws_bytes);
     if (rc) return rc;
     (void)stream;
@@ -1100,7 +1112,9 @@ int expi_batch_results(expi_batch* bp, void* ws, void* stream, expi_batch_stat* 
         }
         if (st[i].phase != PH_DONE) worst = (st[i].status == 2) ? EXPI_ENONFINITE : EXPI_ENOTCONV;
     }
-    if (ctrl.abort) return bfail(EXPI_EHIP, "batched kernel aborted: workgroups were not all resident");
+    if (ctrl.abort)
+        return bfail(EXPI_EHIP, "persistent batched kernel aborted: a barrier wait passed its time limit "
+                                "or a workgroup took more tile passes than the batch has tiles");
     if (worst == EXPI_ENOTCONV)
         return bfail(worst, "some instances did not converge within m_max or did not finish in the rounds run");
     if (worst == EXPI_ENONFINITE) return bfail(worst, "some instances became non-finite");

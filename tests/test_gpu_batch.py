@@ -216,8 +216,8 @@ def test_batch_rejects_bad_arguments(E):
         b.launch(v[:-1], v[1:])
     with pytest.raises(RuntimeError, match="aligned"):
         b.launch(v[1:], y[:-1])
-    with pytest.raises(RuntimeError, match="switched off"):
-        b.launch_persistent(v[:-1], y[:-1])
+    with pytest.raises(RuntimeError, match="overlaps"):
+        b.launch_persistent(v[:-1], v[1:])
 
 
 def test_batch_autotune_picks_a_candidate_and_caches(E, tmp_path):

@@ -247,8 +247,8 @@ def test_batch_create_validation_and_layout(L):
     assert L.expi_batch_launch(b, dummy, ctypes.c_void_p(1 << 40), dummy, ws_bytes, None) == -1
     assert b"prepare" in L.expi_last_error()
     assert L.expi_batch_capture(b, dummy, ctypes.c_void_p(1 << 40), dummy, ws_bytes, 0, None) == -1
-    # the persistent launch is switched off and says so before any HIP call
-    assert L.expi_batch_launch_persistent(b, dummy, ctypes.c_void_p(512), dummy, ws_bytes, None) == -7
-    assert b"switched off" in L.expi_last_error()
-    assert L.expi_batch_capture_persistent(b, dummy, ctypes.c_void_p(512), dummy, ws_bytes, None) == -7
+    # so does the persistent launch
+    assert L.expi_batch_launch_persistent(b, dummy, ctypes.c_void_p(1 << 40), dummy, ws_bytes, None) == -1
+    assert b"prepare" in L.expi_last_error()
+    assert L.expi_batch_capture_persistent(b, dummy, ctypes.c_void_p(1 << 40), dummy, ws_bytes, None) == -1
     L.expi_batch_destroy(b)
