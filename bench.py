@@ -276,7 +276,8 @@ def run_batched(args):
     side lengths log-uniform in [64, 1024] and tau uniform in [1e-5, 1e-3]
     (seeded), FP32 storage of the Newton vectors with float64 divided
     differences, norms, stop test and y; solved eagerly (host-enqueued rounds)
-    and as one replay of the captured round graph.  Errors per instance are
+    as one replay of the captured round graph, and in one persistent kernel
+    launch (directly and as a replayed graph).  Errors per instance are
     against the float64 sine-mode closed form of phi_1(tau A) v."""
     import numpy as np
     import torch
@@ -319,6 +320,27 @@ def run_batched(args):
     graph = (time.perf_counter() - t0) / args.batch_reps
     same = bool(torch.equal(y, y_eager))
     s_graph, r_graph = b.results()
+    # all rounds in one persistent (cooperative) launch, then as a replayed
+    # graph of that launch
+    y.zero_()
+    b.launch_persistent(v, y)           # warm-up
+    s_pers, r_pers = b.results()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        b.launch_persistent(v, y)
+    torch.cuda.synchronize()
+    persistent = (time.perf_counter() - t0) / args.batch_reps
+    pers_diff = float((y - y_eager).abs().max())
+    b.capture_persistent(v, y)
+    b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        b.replay()
+    torch.cuda.synchronize()
+    pers_graph = (time.perf_counter() - t0) / args.batch_reps
+    b.results()
     yy = y.cpu().numpy()
     errs = []
     for i, it in enumerate(inst):
@@ -327,7 +349,7 @@ def run_batched(args):
         errs.append(float(np.linalg.norm(yy[o:o + n2] - want) / np.linalg.norm(want)))
     pts = int((ns * ns).sum())
     prods = sum(int(st["newton_steps"]) * it.n * it.n for st, it in zip(stats, inst))
-    best = min(eager, graph)
+    best = min(eager, graph, persistent, pers_graph)
     return {
         "workload": (f"{args.batch_count} independent 2D 5-point Dirichlet problems, sides "
                      f"log-uniform in [64, 1024], tau uniform in [1e-5, 1e-3], seed 0"),
@@ -339,6 +361,10 @@ def run_batched(args):
         "eager_ms": 1e3 * eager,
         "graph_replay_ms": 1e3 * graph,
         "graph_rounds": b.graph_rounds,
+        "persistent_ms": 1e3 * persistent,
+        "persistent_graph_replay_ms": 1e3 * pers_graph,
+        "persistent_rounds": r_pers,
+        "persistent_max_abs_diff_vs_eager": pers_diff,
         "tiles": {"waves_march": tuned["tiles"], "chosen_by": "expi_batch_autotune",
                   "candidates_ms": tuned["candidates"]},
         "graph_capture_s": t_capture,
@@ -752,10 +778,12 @@ def main():
         print(f"[bench] learned done", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batched:
-        print(f"[bench] batched: {args.batch_count} problems, eager and graph", file=sys.stderr, flush=True)
+        print(f"[bench] batched: {args.batch_count} problems, eager, graph and persistent",
+              file=sys.stderr, flush=True)
         batched = run_batched(args)
         print(f"[bench] batched done: eager {batched['eager_ms']:.1f} ms, graph "
-              f"{batched['graph_replay_ms']:.1f} ms", file=sys.stderr, flush=True)
+              f"{batched['graph_replay_ms']:.1f} ms, persistent {batched['persistent_ms']:.1f} ms "
+              f"(graph {batched['persistent_graph_replay_ms']:.1f} ms)", file=sys.stderr, flush=True)
     csr = None
     if not args.no_csr:
         print("[bench] csr: random geometric graph Laplacian, n = 2^%d" % args.csr_log2n,

@@ -451,13 +451,12 @@ int expi_batch_graph_rounds(const expi_batch *b);
  * some instance was still unfinished. */
 int expi_batch_results(expi_batch *b, void *ws, void *stream, expi_batch_stat *out, int *rounds);
 /* All rounds in ONE persistent kernel (Sec. III-C's method per instance, as
- * expi_batch_launch): an atomic tile counter, grid barriers between the
- * tiles of a round and its stop tests, a cooperative launch so that every
- * workgroup is resident; directly or as a cooperative graph node (replays
- * run the whole solve).  Needs expi_batch_prepare with this workspace.
- * Every wait is bounded: a barrier wait past 2 s or a workgroup whose waves
- * disagree aborts the launch, and expi_batch_results then returns
- * EXPI_EHIP. */
+ * expi_batch_launch): the tiles of a round in grid-stride order, grid
+ * barriers between them and the round's stop tests, a cooperative launch
+ * so that every workgroup is resident; directly or as a cooperative graph
+ * node (replays run the whole solve).  Needs expi_batch_prepare with this workspace.
+ * Every wait is bounded: a grid barrier wait past 2 s aborts the launch,
+ * and expi_batch_results then returns EXPI_EHIP. */
 int expi_batch_launch_persistent(expi_batch *b, const double *v, double *y, void *ws,
                                  size_t ws_bytes, void *stream);
 int expi_batch_capture_persistent(expi_batch *b, const double *v, double *y, void *ws,

@@ -509,3 +509,25 @@ def test_batch_graph_replays_are_identical(E):
         assert r_rep == r_eager
         assert torch.equal(y[mask], y_eager[mask]), rep
         assert [s["newton_steps"] for s in s_rep] == [s["newton_steps"] for s in s_eager]
+
+
+def test_batch_persistent_equals_rounds(E):
+    """The persistent launch and the eager rounds run the same tiles and
+    combine each instance's partials in the same order."""
+    import torch
+    nx, ny, hx, hy, tau = batch_case(seed=5, count=24)
+    b = E.Batch(nx, ny, hx, hy, tau, tol=1e-9, dtype="f64")
+    v = T(synth.uniform_vector(b.total_length, 8))
+    y0 = torch.zeros_like(v)
+    y1 = torch.zeros_like(v)
+    b.prepare()
+    b.launch(v, y0)
+    s0, r0 = b.results()
+    b.launch_persistent(v, y1)
+    s1, r1 = b.results()
+    assert r1 == r0
+    assert [s["newton_steps"] for s in s1] == [s["newton_steps"] for s in s0]
+    mask = torch.zeros(b.total_length, dtype=torch.bool, device=v.device)
+    for i in range(b.count):
+        mask[int(b.offsets[i]):int(b.offsets[i]) + int(nx[i] * ny[i])] = True
+    assert torch.equal(y1[mask], y0[mask])
