@@ -309,8 +309,9 @@ def run_batched(args):
     eager = (time.perf_counter() - t0) / args.batch_reps
     y_eager = y.clone()
     t0 = time.perf_counter()
-    b.capture(v, y)                     # rounds = the bound every instance fits in
+    b.capture(v, y)                     # the rounds the eager solve needed, plus a margin
     t_capture = time.perf_counter() - t0
+    graph_rounds = b.graph_rounds
     b.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -360,7 +361,7 @@ def run_batched(args):
         "total_points": pts,
         "eager_ms": 1e3 * eager,
         "graph_replay_ms": 1e3 * graph,
-        "graph_rounds": b.graph_rounds,
+        "graph_rounds": graph_rounds,
         "persistent_ms": 1e3 * persistent,
         "persistent_graph_replay_ms": 1e3 * pers_graph,
         "persistent_rounds": r_pers,
