@@ -218,9 +218,13 @@ def run_learned(args):
     def evaluate(fixed_tau):
         res = {"plain": {"mv": 0, "tests": 0, "t": 0.0, "err": 0.0},
                "learned": {"mv": 0, "tests": 0, "t": 0.0, "err": 0.0}}
-        fallbacks = steps = fewer = 0
+        fallbacks = steps = fewer = consulted = 0
         for k in range(n_eval):
-            op = make_op(amps[n_train + k])
+            # one operator object per method: each keeps its own degree
+            # hints (keyed by the substep length), as a run of that method
+            # alone would; the reference at tol 1e-13 has its own too
+            ops = {key: make_op(amps[n_train + k]) for key in ("plain", "learned", "ref")}
+            op = ops["plain"]
             a, b = op.interval()
             ws = op.workspace("f64")
             u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=5000 + k), device="cuda:0")
@@ -230,12 +234,12 @@ def run_learned(args):
                 ref = None
                 if i % 5 == 0:
                     ref = u.clone()
-                    E.expeuler_step(op, tau, ref, tol=1e-13, ws=ws)
+                    E.expeuler_step(ops["ref"], tau, ref, tol=1e-13, ws=ws)
                 ul = u.clone()
                 for key, uu, params in (("plain", u, None), ("learned", ul, lp)):
                     torch.cuda.synchronize()
                     t1 = time.perf_counter()
-                    st = E.expeuler_step(op, tau, uu, tol=args.tol, params=params, ws=ws)
+                    st = E.expeuler_step(ops[key], tau, uu, tol=args.tol, params=params, ws=ws)
                     torch.cuda.synchronize()
                     res[key]["t"] += time.perf_counter() - t1
                     res[key]["mv"] += st["matvecs"]
@@ -243,14 +247,15 @@ def run_learned(args):
                     if ref is not None:
                         res[key]["err"] = max(res[key]["err"], ((uu - ref).norm() / ref.norm()).item())
                     if key == "learned":
+                        consulted += 1 if st["pred_degree"] > 0 else 0
                         fallbacks += 1 if st["fallback"] else 0
                         fewer += 1 if st["substeps"] < s_plain else 0
                     else:
                         s_plain = st["substeps"]
                 steps += 1
-            del op, ws
+            del op, ops, ws
         out = {"eval_steps": steps, "fallback_rate": fallbacks / max(steps, 1),
-               "steps_with_fewer_substeps": fewer}
+               "steps_with_fewer_substeps": fewer, "steps_network_consulted": consulted}
         for key in ("plain", "learned"):
             out[key] = {"matvecs_per_step": res[key]["mv"] / steps,
                         "stop_tests_per_step": res[key]["tests"] / steps,

@@ -536,7 +536,10 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         pred = C.fixed_m;
         have_pred = true;
         out->pred_m = pred;
-    } else if (C.selector && C.m_max >= 6) {
+    } else if (C.selector && C.m_max >= 6 && (C.decide_s || get_hint(*C.op, C.key) < 2)) {
+        // (the network is consulted where it can change something: where a
+        // shorter substep count is allowed, or where the plain loop has no
+        // degree from an earlier loop with the same substep length)
         // Learned mode: four products with stop tests give the features; the
         // network predicts the substep count and the degree m; products up to
         // m skip the norm reductions except the last two, whose two-term stop

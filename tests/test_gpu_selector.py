@@ -115,16 +115,17 @@ def test_learned_selector_on_held_out_steps(E):
     sel = E.selector.pack(net, norms)
     pred = E.selector.predict(net, norms, X)
     assert np.mean(np.abs(pred[:, 1] - Y[:, 1])) < 1.5      # fits the degrees it saw
-    # held-out trajectories: plain vs learned from the same states
+    # held-out trajectories: plain vs learned from the same states, each step
+    # on fresh operator objects, so that neither method has a degree from an
+    # earlier step (the learned mode consults the network only then)
     plain_mv = learned_mv = plain_fin = learned_fin = 0
     for k, amp in enumerate(amps[6:]):
-        op = rd_op(E, n, amp)
         u0 = torch.as_tensor(synth.gaussian_bump_3d(n, seed=500 + k), device="cuda:0")
         up, ul = u0.clone(), u0.clone()
         params = E.LejaParams(selector=sel, selector_hidden=64)
         for step in range(10):
-            sp = E.expeuler_step(op, tau, up, tol=tol)
-            sl = E.expeuler_step(op, tau, ul, tol=tol, params=params)
+            sp = E.expeuler_step(rd_op(E, n, amp), tau, up, tol=tol)
+            sl = E.expeuler_step(rd_op(E, n, amp), tau, ul, tol=tol, params=params)
             plain_mv += sp["matvecs"]
             learned_mv += sl["matvecs"]
             plain_fin += sp["finalized"]
@@ -173,8 +174,8 @@ def test_learned_mode_near_l_max_matches_oracle(E):
     X, Y, _ = log_plain(E, n, [0.3, 0.5, 0.7], 4, tau, 1e-10, seed0=40)
     net, norms, _ = E.selector.train(X, Y, hidden=32, epochs=800, lr=3e-3, seed=2)
     sel = E.selector.pack(net, norms)
-    op = rd_op(E, n, 0.5)
     for seed in (41, 42):
+        op = rd_op(E, n, 0.5)          # no degree from an earlier step
         u0 = synth.gaussian_bump_3d(n, seed=seed)
         u = torch.as_tensor(u0, device="cuda:0")
         st = E.expeuler_step(op, tau, u, tol=1e-10,
@@ -235,20 +236,21 @@ def test_learned_substeps_gain_on_variable_step_sizes(E):
     ms = {"plain": 0.0, "learned": 0.0}
     import time
     for k, amp in enumerate(amps[5:]):
-        op = rd_op(E, n, amp)
+        # one operator object per method (each keeps its own degree hints)
+        op, op_l, op_r = rd_op(E, n, amp), rd_op(E, n, amp), rd_op(E, n, amp)
         a, b = op.interval()
         u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=700 + k), device="cuda:0")
         for step in range(10):
             tau = draw_tau(a, b)
             ref = u.clone()
-            E.expeuler_step(op, tau, ref, tol=1e-13)
+            E.expeuler_step(op_r, tau, ref, tol=1e-13)
             ul = u.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sp = E.expeuler_step(op, tau, u, tol=tol)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            sl = E.expeuler_step(op, tau, ul, tol=tol, params=lp)
+            sl = E.expeuler_step(op_l, tau, ul, tol=tol, params=lp)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             mv["plain"] += sp["matvecs"]
@@ -267,3 +269,31 @@ def test_learned_substeps_gain_on_variable_step_sizes(E):
           f"ms plain {ms['plain']:.1f} learned {ms['learned']:.1f}")
     assert mv["learned"] <= 0.8 * mv["plain"]
     assert ms["learned"] < ms["plain"]
+
+
+def test_learned_mode_follows_plain_loop_once_a_degree_is_known(E):
+    """With one substep allowed (tau (b - a) well below l_max) and a degree
+    known from an earlier step of the same substep length, the network could
+    change nothing: the learned mode runs the plain loop with that degree,
+    launch for launch, and its result equals the plain method's bitwise."""
+    import torch
+    n = 24
+    tau = 1e-5 * (256 / n) ** 2
+    X, Y, _ = log_plain(E, n, [0.3, 0.6], 4, tau, 1e-8, seed0=60)
+    net, norms, _ = E.selector.train(X, Y, hidden=32, epochs=300, lr=3e-3, seed=3)
+    params = E.LejaParams(selector=E.selector.pack(net, norms), selector_hidden=32)
+    op_p, op_l = rd_op(E, n, 0.5), rd_op(E, n, 0.5)
+    u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=61), device="cuda:0")
+    # a fresh operator has no degree: the network decides
+    st = E.expeuler_step(rd_op(E, n, 0.5), tau, u.clone(), tol=1e-8, params=params)
+    assert st["pred_degree"] > 0
+    # one plain step on each operator gives both the same degree
+    for op in (op_p, op_l):
+        E.expeuler_step(op, tau, u.clone(), tol=1e-8)
+    for step in range(3):
+        ul = u.clone()
+        sp = E.expeuler_step(op_p, tau, u, tol=1e-8)
+        sl = E.expeuler_step(op_l, tau, ul, tol=1e-8, params=params)
+        assert sl["pred_degree"] == 0
+        assert sl["matvecs"] == sp["matvecs"] and sl["degree_last"] == sp["degree_last"]
+        assert torch.equal(ul, u), step
