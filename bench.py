@@ -209,7 +209,7 @@ def run_learned(args):
     log_s = time.perf_counter() - t0
     X, Y = np.array(X), np.array(Y)
     t0 = time.perf_counter()
-    net, norms, hist = E.selector.train(X, Y, hidden=64, epochs=2000, lr=3e-3, kappa=1.5, seed=0)
+    net, norms, hist = E.selector.train(X, Y, hidden=64, epochs=2000, lr=3e-3, kappa=args.sel_kappa, seed=0)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     sel = E.selector.pack(net, norms)
@@ -722,6 +722,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--eval-steps", type=int, default=200)
+    ap.add_argument("--sel-kappa", type=float, default=1.5,
+                    help="weight of under-prediction in the selector's training loss")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-csr", action="store_true")
     ap.add_argument("--no-tables", action="store_true",
