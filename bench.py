@@ -83,12 +83,15 @@ def counter_traffic(kernel_sub: str):
     return None
 
 
-def run_gpu(args, dtype: str):
+def run_gpu(args, dtype: str, n: int = None, tau: float = None, steps: int = None, warmup: int = None):
     import torch
     import paper_1309_4616_amd as E
     import synth
 
-    n = args.n
+    n = n or args.n
+    tau = tau or args.tau
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
     h = 1.0 / n
     coef = synth.sine_coefficient(n, 0.5)
     op = E.StencilOp((n, n, n), (h, h, h), "neumann0",
@@ -100,16 +103,16 @@ def run_gpu(args, dtype: str):
     # per step instead of two per launch
     params = E.LejaParams(profile=2, pairs=not args.no_pairs)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        E.expeuler_step(op, args.tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
+    for _ in range(warmup):
+        E.expeuler_step(op, tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
     torch.cuda.synchronize()
     matvecs = newton = timed = pairs = 0
     pair_launches = single_launches = loops = fused = 0
     newton_ms = pair_ms = 0.0
     degrees = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = E.expeuler_step(op, args.tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
+    for _ in range(steps):
+        st = E.expeuler_step(op, tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
         matvecs += st["matvecs"]
         newton += st["newton_steps"]
         timed += st["timed_products"]
@@ -132,16 +135,16 @@ def run_gpu(args, dtype: str):
     pair_us = 1e3 * pair_ms / max(pairs, 1)
     return {
         "wall_s": wall,
-        "value": pts * args.steps / wall,
-        "ms_per_step": 1e3 * wall / args.steps,
-        "matvecs_per_step": matvecs / args.steps,
-        "newton_per_step": newton / args.steps,
+        "value": pts * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "matvecs_per_step": matvecs / steps,
+        "newton_per_step": newton / steps,
         "degrees": sorted(set(degrees)),
         "point_products_per_s": pts * matvecs / wall,
         "step_gbs": bytes_total / wall / 1e9,
-        "pairs_per_step": pair_launches / args.steps,
-        "singles_per_step": single_launches / args.steps,
-        "fused_starts_per_step": fused / args.steps,
+        "pairs_per_step": pair_launches / steps,
+        "singles_per_step": single_launches / steps,
+        "fused_starts_per_step": fused / steps,
         "timed_launches": pairs + singles,
         "pair_avg_us": pair_us if pairs else None,
         "pair_gbs": per_launch / (pair_us * 1e-6) / 1e9 if pairs else None,
@@ -719,6 +722,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-512", action="store_true", help="skip the FP32 512^3 leg")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--eval-steps", type=int, default=200)
@@ -778,6 +782,14 @@ def main():
     if not args.no_fp32:
         r32 = run_gpu(args, "f32")
         print(f"[bench] f32 done: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    r32_512 = None
+    if not args.no_fp32 and not args.no_512:
+        # FP32 storage beyond the 256 MB MALL: 512^3 (w, p 0.5 GB each), tau
+        # scaled by (256/512)^2 to keep tau (b - a) and the degree of 256^3;
+        # rows of 512 points take single products (the pair sweep holds rows
+        # of at most 256)
+        r32_512 = run_gpu(args, "f32", n=512, tau=args.tau * (args.n / 512.0) ** 2, steps=3, warmup=1)
+        print(f"[bench] f32 512^3 done: {r32_512['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     learned = None
     if not args.no_learned:
         print(f"[bench] learned selector: log {args.train_steps} plain steps, train, "
@@ -911,6 +923,19 @@ def main():
             "pair_gbs": r32["pair_gbs"],
             "note": "w, p stored in float32; divided differences, norms, stop test and u in float64",
             "err_vs_oracle": cpu["errors"]["f32"] if cpu else None,
+        }
+    if r32_512:
+        out["fp32_storage_512"] = {
+            "workload": (f"the 3D workload at 512^3, tau {args.tau * (args.n / 512.0) ** 2:g} "
+                         f"(tau (b - a) as at {args.n}^3), 3 steps, FP32 w and p"),
+            "value": r32_512["value"],
+            "ms_per_step": r32_512["ms_per_step"],
+            "matvecs_per_step": r32_512["matvecs_per_step"],
+            "single_avg_us": r32_512["single_avg_us"],
+            "single_gbs": r32_512["single_gbs"],
+            "single_frac": (r32_512["single_gbs"] / HBM_PEAK_GBS) if r32_512["single_gbs"] else None,
+            "note": ("working set 3 x 0.54 GB, beyond the MALL; single fused Newton products "
+                     "(16 B per point: read w, p; write w', p)"),
         }
     if learned:
         out["learned_vs_plain"] = learned
