@@ -597,6 +597,8 @@ def run_spin_bath(args):
     nnz = op.nnz
     per_product = 20 * nnz + 4 * (g.n + 1) + 64 * g.n
     avg_us = 1e3 * st["newton_ms"] / max(st["timed_products"], 1)
+    lanes = tuned["tiles"][0]
+    traffic = counter_traffic(f"csr_complex_sweep<1, {lanes}>") if args.spin_spins == 21 else None
     return {
         "workload": (f"e^(-i t H) psi, H Hermitian spin-bath matrix of {args.spin_spins} spins "
                      f"(n = 2^{args.spin_spins}, {nnz / g.n:.1f} complex entries per row), "
@@ -608,6 +610,9 @@ def run_spin_bath(args):
         "product_avg_us": avg_us,
         "product_gbs": per_product / (avg_us * 1e-6) / 1e9,
         "product_frac": per_product / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_product": per_product,
+        "counted_bytes_per_product": traffic["bytes"] if traffic else None,
+        "counted_bytes_source": traffic["profile"] if traffic else None,
         "norm_drift": abs(y.norm().item() - 1.0),
         "tiles": {"lanes_per_row_waves": tuned["tiles"][:2], "chosen_by": "expi_op_autotune",
                   "candidates_us": tuned["candidates"]},
