@@ -28,6 +28,8 @@
 //    chunks that share halo rows run on the same L2 at the same time.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "sweep_common.h"
 
 namespace expi {
@@ -500,7 +502,11 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         __syncthreads();   // x and row data, the first two ring planes
         // a point of the outer layer has a zero row under interior_only
         const bool yedge = !(eym && eyq);
-        for (int k0 = kst; k0 <= ke; k0 += 6) {
+        // one block of six planes from k0 (k0 - kst a multiple of 6); in
+        // FP32, whole blocks while six planes remain, then the last, shorter
+        // one
+        auto block = [&](const int k0, auto full) {
+            constexpr bool kFull = decltype(full)::value;
             // FP32: the lane's squares of a block of six planes are summed in
             // FP32 and added to the FP64 sums once per block (at most twelve
             // terms per FP32 sum); FP64 adds each square
@@ -509,8 +515,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             for (int s = 0; s < 6; ++s) {
                 const int k = k0 + s;
                 // the last output plane ke-1 is done at k = ke; the rest of
-                // the last block has nothing to do
-                if (k > ke) break;
+                // the last block has nothing to do (only the last block of a
+                // segment tests this: a test in every block would make the
+                // compiler copy the queues at each possible exit)
+                if constexpr (!kFull) {
+                    if (k > ke) break;
+                }
                 // (1) w_j of plane k+2 into the ring (and the wave's own
                 // registers), then load plane k+4
                 {
@@ -659,7 +669,16 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 s2 += (double)b2;
                 s3 += (double)b3;
             }
+        };
+        int k0 = kst;
+        if constexpr (sizeof(TW) == 4) {
+            for (; k0 + 5 <= ke; k0 += 6) block(k0, std::true_type{});
         }
+        // (FP64 keeps the test in every block: whole blocks there need more
+        // scalar registers than it has, and the spills cost more than the
+        // copies they save)
+        for (; k0 <= ke; k0 += 6) block(k0, std::false_type{});
+
     }
     if (a.guard && __builtin_amdgcn_readfirstlane(done_v) != 0) return;   // a workgroup without a unit
     if (FIRST) {
