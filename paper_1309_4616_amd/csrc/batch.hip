@@ -49,6 +49,7 @@ namespace {
 enum Phase : int { PH_START = 0, PH_FIRST = 1, PH_NEWTON = 2, PH_UPDATE = 3, PH_DONE = 4, PH_FAILED = 5 };
 
 constexpr int kMaxBatch = 4096;
+constexpr int kPersistWaves = 16;   // waves per workgroup of the persistent kernel
 
 struct alignas(16) BatchInfo {   // static per instance
     long long off;               // offset of the instance's vectors, in elements
@@ -165,10 +166,13 @@ __device__ __forceinline__ bool in_set(int set, int phase, int l) {
     return set == SET_ALL || (set == SET_HOT) == hot;
 }
 
+// One tile of an instance: `march` rows of 64 V points, taken by one wave
+// (lt = tile index within the instance).  The wave reduces its norm sums
+// across its lanes and lane 0 writes them as the tile's partials; no
+// workgroup barrier, so the waves of a workgroup work independently.
 template <class TW, int V, int SET>
 __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchState& S, int phase,
                          int lt, double* red_partial) {
-    const int waves = blockDim.x >> 6;
     const int t0 = lt % I.tiles0, t1 = lt / I.tiles0;
     SweepArgs a{};
     a.n[0] = I.nx;
@@ -190,16 +194,15 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
         a.g = B.v + I.off;
         a.gmode = G_VEC;
         a.sigma = I.tau;
-        tile::stencil_tile<2, EXPI_COEF_CONST, EPI_START, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
+        tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_START, double, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
         return;
     }
     if (SET != SET_HOT && phase == PH_UPDATE) {
         // y' <- (l == 0 ? 0 : y') + p / s over the tile's points
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        const int rows = waves * B.march;
+        const int lane = threadIdx.x & 63;
         double* y = B.y + I.off;
         for (int r = 0; r < B.march; ++r) {
-            const int j = t1 * rows + wv * B.march + r;
+            const int j = t1 * B.march + r;
             if (j >= I.ny) break;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -223,24 +226,25 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
         if (S.l == 0) {
             if constexpr (SET != SET_HOT) {
                 a.x = B.v + I.off;
-                tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, double, TW, V>(a, t0, t1, 0, s0, s1, s2);
+                tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_FIRST, double, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
             }
         } else {
             if constexpr (SET != SET_AUX) {
                 a.x = w1;
-                tile::stencil_tile<2, EXPI_COEF_CONST, EPI_FIRST, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+                tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_FIRST, TW, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
             }
         }
     } else {
         if constexpr (SET != SET_AUX) {
             a.x = (j & 1) ? w0 : w1;     // w_j lives in w[(j-1) & 1]
             a.out = (j & 1) ? w1 : w0;
-            tile::stencil_tile<2, EXPI_COEF_CONST, EPI_NEWTON, TW, TW, V>(a, t0, t1, 0, s0, s1, s2);
+            tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_NEWTON, TW, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
         }
     }
-    __shared__ double red[kMaxWaves][3];
-    block_combine<EPI_NEWTON>(s0, s1, s2, red);
-    if (threadIdx.x == 0) {
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if ((threadIdx.x & 63) == 0) {
         red_partial[0] = s0;
         red_partial[1] = s1;
         red_partial[2] = s2;
@@ -249,7 +253,7 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
 
 // Combine an instance's tile partials in index order and advance its state.
 __device__ void finalize_instance(const BatchArgs& B, int inst) {
-    __shared__ double red[kMaxWaves][3];
+    __shared__ double red[kPersistWaves][3];   // a round kernel's or the persistent kernel's waves
     const BatchInfo& I = B.info[inst];
     BatchState* S = &B.state[inst];
     const int phase = S->phase;
@@ -402,12 +406,13 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B
     total = __builtin_amdgcn_readfirstlane(total);
     if (nact == 0) return;
     if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->hot_rounds += 1;
-    // Grid-stride order over the XCD-major logical index: in each pass the
-    // workgroups together take G consecutive tiles and every XCD a
-    // contiguous block of them, so tiles that share halo rows and DRAM pages
-    // run at the same time on the same L2.
-    const int G = gridDim.x;
-    const int L = xcd_tile(G / kXcd);
+    // Grid-stride order over the XCD-major logical wave index: in each pass
+    // the waves together take G consecutive tiles and every XCD a contiguous
+    // block of them, so tiles that share halo rows and DRAM pages run at the
+    // same time on the same L2.  Each wave goes through its tiles alone.
+    const int nw = blockDim.x >> 6;
+    const int G = gridDim.x * nw;
+    const int L = xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6);
     if (L >= total) return;
     int q = __builtin_amdgcn_readfirstlane(find_instance(s_pref, nact, L));
     int inst = __builtin_amdgcn_readfirstlane(s_ids[q]);
@@ -444,10 +449,10 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
 // ---- persistent kernel --------------------------------------------------------
 
 template <class TW>
-__global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
+__global__ __launch_bounds__(kPersistWaves * 64) void batch_kernel(BatchArgs B) {
     __shared__ int s_pref[kMaxBatch + 1];
     __shared__ int s_ids[kMaxBatch];
-    __shared__ int s_wave[kMaxWaves + 1];
+    __shared__ int s_wave[kPersistWaves + 1];
     __shared__ int s_ok;
     for (int round = 0; round < B.max_rounds; ++round) {
         // (A) active instances and the prefix sums of their tile counts
@@ -455,11 +460,12 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_kernel(BatchArgs B) {
         active_list(B, SET_ALL, s_pref, s_ids, s_wave, nact, total);
         if (nact == 0) break;
         // (B) the round's tiles in grid-stride order over the XCD-major
-        // workgroup index, as in the round kernels: no counter to contend
-        // on, and each wave computes its tile indices itself
-        const int G = gridDim.x;
+        // wave index, as in the round kernels: each wave computes its tile
+        // indices itself and goes through its tiles alone
+        const int nw = blockDim.x >> 6;
+        const int G = gridDim.x * nw;
         int q = -1, inst = 0, base = 0, next = 0;
-        for (int t = xcd_tile(G / kXcd); t < total; t += G) {
+        for (int t = xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6); t < total; t += G) {
             if (q < 0 || t >= next) {
                 q = __builtin_amdgcn_readfirstlane(find_instance(s_pref, nact, t));
                 inst = __builtin_amdgcn_readfirstlane(s_ids[q]);
@@ -547,8 +553,7 @@ void layout_tiles(Batch& b) {
     b.total_tiles = 0;
     for (auto& I : b.info) {
         I.tiles0 = (I.nx + 64 * I.vec - 1) / (64 * I.vec);
-        const int rows = b.waves * b.march;
-        const int tiles1 = (I.ny + rows - 1) / rows;
+        const int tiles1 = (I.ny + b.march - 1) / b.march;   // one wave per tile
         I.ntiles = I.tiles0 * tiles1;
         I.part_off = part;
         part += I.ntiles;
@@ -566,7 +571,7 @@ void layout_tiles(Batch& b) {
     b.off_state = take(sizeof(BatchState) * b.count);
     b.off_dd = take(sizeof(double) * b.dd.size());
     b.off_xi = take(sizeof(double) * b.xi.size());
-    // partial slots sized for the smallest accepted tiles (waves 1, march 4)
+    // partial slots sized for the smallest accepted tiles (march 4)
     size_t maxpart = 0;
     for (const auto& I : b.info) {
         const int t0 = (I.nx + 63) / 64;
@@ -620,13 +625,14 @@ int occupancy_grid(Batch& b) {
     BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     if (b.dtype == EXPI_F32)
-        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<float>, 64 * b.waves, 0));
+        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<float>, 64 * kPersistWaves, 0));
     else
-        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<double>, 64 * b.waves, 0));
+        BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<double>, 64 * kPersistWaves, 0));
     if (per < 1) return bfail(EXPI_EHIP, "batched kernel cannot be resident");
-    // two workgroups per CU where they fit: more make every grid barrier
-    // slower (its cost grows with the workgroups that arrive)
-    b.grid = std::max(kXcd, (std::min(per, 2) * cus / kXcd) * kXcd);
+    // one workgroup of 16 waves per CU: the waves take tiles independently,
+    // and few workgroups keep every grid barrier cheap (its cost grows with
+    // the workgroups that arrive)
+    b.grid = std::max(kXcd, (cus / kXcd) * kXcd);
     // tiles kernels of a round: as many workgroups as fit on the device at
     // once (occupancy of the hot kernel), a multiple of the XCD count, no
     // more than the batch has tiles
@@ -634,7 +640,8 @@ int occupancy_grid(Batch& b) {
     BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_hot, tiles_kernel(b, SET_HOT), 64 * b.waves,
                                                       tiles_lds_bytes(b.count)));
     if (per_hot < 1) return bfail(EXPI_EHIP, "batched tiles kernel cannot be resident");
-    const int want = std::min(per_hot * cus, ((b.total_tiles + kXcd - 1) / kXcd) * kXcd);
+    const int wgs = (b.total_tiles + b.waves - 1) / b.waves;   // a tile per wave
+    const int want = std::min(per_hot * cus, ((wgs + kXcd - 1) / kXcd) * kXcd);
     b.round_grid = std::max(kXcd, (want / kXcd) * kXcd);
     // a barrier wait longer than two seconds means something is wrong
     b.deadline_ticks = 2ll * 1000ll * (long long)(khz > 0 ? khz : 100000);
@@ -652,7 +659,7 @@ int enqueue(Batch& b, char* ws, const double* v, double* y, hipStream_t s) {
                        a.state, a.ctrl, b.count);
     BHIP(hipGetLastError());
     void* params[] = {&a};
-    BHIP(hipLaunchCooperativeKernel(kernel_ptr(b), dim3(b.grid), dim3(64 * b.waves), params, 0, s));
+    BHIP(hipLaunchCooperativeKernel(kernel_ptr(b), dim3(b.grid), dim3(64 * kPersistWaves), params, 0, s));
     return EXPI_OK;
 }
 
@@ -786,7 +793,7 @@ int build_graph(Batch& b, char* ws, const double* v, double* y) {
     hipKernelNodeParams k1{};
     k1.func = const_cast<void*>(kernel_ptr(b));
     k1.gridDim = dim3(b.grid);
-    k1.blockDim = dim3(64 * b.waves);
+    k1.blockDim = dim3(64 * kPersistWaves);
     k1.kernelParams = p1;
     hipKernelNodeAttrValue coop{};
     coop.cooperative = 1;

@@ -93,11 +93,13 @@ struct Side {
 };
 
 // The work of one tile (t0, t1, t2) of operator `a`, accumulating the
-// reduction values of its points into s0..s2.  Called by every thread of the
-// workgroup (the x neighbours are exchanged by cross-lane shuffles).
+// reduction values of its points into s0..s2.  The tile has nw waves, of
+// which the calling wave is wv (a workgroup's waves by default; the batched
+// solver passes single-wave tiles); every lane of the wave calls it (the x
+// neighbours are exchanged by cross-lane shuffles).  No workgroup barrier.
 template <int DIM, int COEF, int EPI, class TIN, class TOUT, int V>
-__device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1, int t2,
-                                             double& s0, double& s1, double& s2) {
+__device__ __forceinline__ void stencil_tile_w(const SweepArgs& a, int t0, int t1, int t2, int wv, int nw,
+                                               double& s0, double& s1, double& s2) {
     using TC = compute_t<TIN, TOUT>;
     constexpr bool kApply = (EPI == EPI_APPLY || EPI == EPI_APPLY_BD);
     constexpr bool kStart = (EPI == EPI_START || EPI == EPI_START_BD);
@@ -110,8 +112,7 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
     constexpr bool kW = (EPI != EPI_GERSH);          // reads the vector
     constexpr bool kP = (EPI == EPI_NEWTON);         // reads p
     constexpr bool kF = (COEF == EXPI_COEF_FIELD);   // reads the coefficient field
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     {
         const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
         const int ns = (DIM == 3) ? n2 : n1;          // marched axis
@@ -433,6 +434,13 @@ __device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1,
             }
         }
     }
+}
+
+template <int DIM, int COEF, int EPI, class TIN, class TOUT, int V>
+__device__ __forceinline__ void stencil_tile(const SweepArgs& a, int t0, int t1, int t2,
+                                             double& s0, double& s1, double& s2) {
+    stencil_tile_w<DIM, COEF, EPI, TIN, TOUT, V>(a, t0, t1, t2, (int)(threadIdx.x >> 6), (int)(blockDim.x >> 6),
+                                                 s0, s1, s2);
 }
 
 }  // namespace tile
