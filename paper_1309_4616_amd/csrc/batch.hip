@@ -50,6 +50,7 @@ enum Phase : int { PH_START = 0, PH_FIRST = 1, PH_NEWTON = 2, PH_UPDATE = 3, PH_
 
 constexpr int kMaxBatch = 4096;
 constexpr int kPersistWaves = 16;   // waves per workgroup of the persistent kernel
+constexpr int kMaxGrid = 2048;      // workgroups of the persistent kernel at most
 
 struct alignas(16) BatchInfo {   // static per instance
     long long off;               // offset of the instance's vectors, in elements
@@ -73,7 +74,6 @@ struct alignas(64) BatchCtrl {
     unsigned finished;           // instances done or failed (round kernels)
     unsigned hot_rounds;         // rounds with Newton products on stored vectors
     unsigned pad[8];
-    unsigned xcd_count[8][16];   // grid barrier: arrivals per XCD, one line each
 };
 
 struct BatchArgs {
@@ -83,6 +83,7 @@ struct BatchArgs {
     const double* dd;
     const double* xi;
     double* partials;
+    unsigned* bar_flag;           // grid barrier: one arrival flag per workgroup
     const double* v;
     double* y;
     void* w0;
@@ -98,15 +99,18 @@ struct BatchArgs {
 constexpr int kWaitVmcnt0 = 0x0F70;
 
 // Grid barrier with a time limit; returns false once any workgroup has
-// aborted.  Two levels: the workgroups of one XCD (blockIdx mod 8) arrive
-// at that XCD's counter, the last of them at the global counter, and the
-// last of those opens the next generation (measured on the MI355X: 14 us
-// for 512 workgroups, against 22 us with one counter, whose arrivals
-// serialize).  Arrival releases the workgroup's writes; waiting polls the
-// generation with relaxed loads (an acquire per poll would invalidate
+// aborted.  Every workgroup publishes its arrival in a flag of its own (the
+// generation it waits for); one wave of workgroup 0 polls all flags, 64 at a
+// time, and opens the next generation.  Arrivals go to distinct words, so
+// nothing serializes on one counter (measured on the MI355X at 256
+// workgroups: 5.8 us per barrier, against 7.6 us for per-XCD counters and
+// 11.2 us for one counter).  Arrival releases the workgroup's writes;
+// waiting polls with relaxed loads (an acquire per poll would invalidate
 // caches for every waiter on every poll) and one acquire fence follows.  A
 // waiter past the deadline (GPU wall clock) sets the abort flag, which every
-// other waiter sees, so no wave can wait forever.
+// other waiter sees, so no wave can wait forever.  Generations only grow
+// (each launch starts two past the last), so flags left by an earlier
+// launch never match.
 __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
     // every wave waits for its own stores (s_waitcnt vmcnt(0)) before the
     // workgroup barrier: the workgroup barrier alone does not wait for them,
@@ -114,35 +118,49 @@ __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
     // stores of every wave, not only those of thread 0's
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        BatchCtrl* c = B.ctrl;
-        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned* xc = &c->xcd_count[blockIdx.x % kXcd][0];
-        const unsigned per_xcd = gridDim.x / kXcd;
-        bool last = false;
-        if (__hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == per_xcd - 1) {
-            __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
-                   (unsigned)kXcd - 1;
-        }
-        int ok = 1;
-        if (last) {
-            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const long long t_end = wall_clock64() + B.deadline_ticks;
-            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    break;
+    BatchCtrl* c = B.ctrl;
+    const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&B.bar_flag[blockIdx.x], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t_end = wall_clock64() + B.deadline_ticks;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) {
+            int ok = 1;
+            for (int b0 = 0; b0 < (int)gridDim.x && ok; b0 += 64) {
+                const int b = b0 + (int)threadIdx.x;
+                while (true) {
+                    const bool in = b >= (int)gridDim.x ||
+                                    __hip_atomic_load(&B.bar_flag[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                                        gen + 1u;
+                    if (__all(in)) break;
+                    if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                        wall_clock64() > t_end) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                if (wall_clock64() > t_end) {
-                    __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
             }
+            if (threadIdx.x == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (ok) __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                else __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *s_ok = ok;
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        int ok = 1;
+        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() > t_end) {
+                __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
@@ -498,8 +516,7 @@ __global__ void batch_reset_kernel(BatchState* st, BatchCtrl* ctrl, int count) {
     }
     if (i == 0) {
         ctrl->bar_count = 0;
-        ctrl->bar_gen = 0;
-        for (int x = 0; x < 8; ++x) ctrl->xcd_count[x][0] = 0;
+        ctrl->bar_gen += 2;   // past every flag an earlier launch left (zeroed at prepare)
         ctrl->abort = 0;
         ctrl->rounds = 0;
         ctrl->finished = 0;
@@ -520,7 +537,7 @@ struct Batch {
     std::vector<double> xi;       // m_max + 1
     long long total_len = 0;
     int total_tiles = 0, max_rounds = 0;
-    size_t off_ctrl, off_info, off_state, off_dd, off_xi, off_part, off_w0, off_w1, off_p, ws_total;
+    size_t off_ctrl, off_bar, off_info, off_state, off_dd, off_xi, off_part, off_w0, off_w1, off_p, ws_total;
     void* prepared_ws = nullptr;
     int grid = 0;                 // persistent kernel
     int round_grid = 0;           // tiles kernel of a round
@@ -567,6 +584,7 @@ void layout_tiles(Batch& b) {
         return o;
     };
     b.off_ctrl = take(sizeof(BatchCtrl));
+    b.off_bar = take(sizeof(unsigned) * kMaxGrid);
     b.off_info = take(sizeof(BatchInfo) * b.count);
     b.off_state = take(sizeof(BatchState) * b.count);
     b.off_dd = take(sizeof(double) * b.dd.size());
@@ -592,6 +610,7 @@ BatchArgs make_args(const Batch& b, char* ws, const double* v, double* y) {
     a.dd = reinterpret_cast<const double*>(ws + b.off_dd);
     a.xi = reinterpret_cast<const double*>(ws + b.off_xi);
     a.partials = reinterpret_cast<double*>(ws + b.off_part);
+    a.bar_flag = reinterpret_cast<unsigned*>(ws + b.off_bar);
     a.v = v;
     a.y = y;
     a.w0 = ws + b.off_w0;
@@ -632,7 +651,7 @@ int occupancy_grid(Batch& b) {
     // one workgroup of 16 waves per CU: the waves take tiles independently,
     // and few workgroups keep every grid barrier cheap (its cost grows with
     // the workgroups that arrive)
-    b.grid = std::max(kXcd, (cus / kXcd) * kXcd);
+    b.grid = std::min(kMaxGrid, std::max(kXcd, (cus / kXcd) * kXcd));
     // tiles kernels of a round: as many workgroups as fit on the device at
     // once (occupancy of the hot kernel), a multiple of the XCD count, no
     // more than the batch has tiles
@@ -949,6 +968,9 @@ int expi_batch_prepare(expi_batch* bp, void* ws, size_t ws_bytes, void* stream) 
                         hipMemcpyHostToDevice, s));
     BHIP(hipMemcpyAsync(w + b->off_xi, b->xi.data(), sizeof(double) * b->xi.size(),
                         hipMemcpyHostToDevice, s));
+    // the grid barrier's generation and flags start at zero once; launches
+    // then only move them forward
+    BHIP(hipMemsetAsync(w + b->off_ctrl, 0, b->off_info - b->off_ctrl, s));
     BHIP(hipStreamSynchronize(s));
     int rc = occupancy_grid(*b);
     if (rc) return rc;
