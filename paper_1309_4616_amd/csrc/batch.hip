@@ -70,7 +70,8 @@ struct alignas(16) BatchState {  // advanced by the finalize step
 
 struct alignas(64) BatchCtrl {
     unsigned bar_count, bar_gen, abort, rounds;
-    unsigned pad0[2];
+    unsigned aux_next;           // round kernels: some instance's next step is an auxiliary one
+    unsigned pad0;
     unsigned finished;           // instances done or failed (round kernels)
     unsigned hot_rounds;         // rounds with Newton products on stored vectors
     unsigned pad[8];
@@ -413,9 +414,16 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B
     int* s_ids = s_dyn + B.count + 1;     // count
     int* s_wave = s_ids + B.count;        // kMaxWaves + 1
     if (B.ctrl->finished >= (unsigned)B.count) return;
+    // the auxiliary kernel of a round without auxiliary steps returns at
+    // once (the flag is set by the previous round's stop tests and cleared
+    // by the hot kernel that follows; kernel boundaries order the three)
+    if (SET == SET_AUX && B.ctrl->aux_next == 0) return;
     // a round counts when some instance is unfinished at its start (the
     // count changes only in the finalize kernel that ends the round)
-    if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->rounds += 1;
+    if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) {
+        B.ctrl->rounds += 1;
+        B.ctrl->aux_next = 0;
+    }
     int nact, total;
     active_list(B, SET, s_pref, s_ids, s_wave, nact, total);
     // values read from LDS are the same in every lane; saying so keeps the
@@ -461,7 +469,12 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
     const int inst = blockIdx.x;
     if (inst >= B.count || !active_phase(B.state[inst].phase)) return;
     finalize_instance(B, inst);
-    if (threadIdx.x == 0 && !active_phase(B.state[inst].phase)) atomicAdd(&B.ctrl->finished, 1u);
+    if (threadIdx.x == 0) {
+        const BatchState& S = B.state[inst];
+        if (!active_phase(S.phase)) atomicAdd(&B.ctrl->finished, 1u);
+        if (S.phase == PH_START || S.phase == PH_UPDATE || (S.phase == PH_FIRST && S.l == 0))
+            B.ctrl->aux_next = 1;
+    }
 }
 
 // ---- persistent kernel --------------------------------------------------------
@@ -521,6 +534,7 @@ __global__ void batch_reset_kernel(BatchState* st, BatchCtrl* ctrl, int count) {
         ctrl->rounds = 0;
         ctrl->finished = 0;
         ctrl->hot_rounds = 0;
+        ctrl->aux_next = 1;   // the first products read the float64 input
     }
 }
 
