@@ -120,13 +120,16 @@ __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     BatchCtrl* c = B.ctrl;
-    const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x == 0)
-        __hip_atomic_store(&B.bar_flag[blockIdx.x], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const long long t_end = wall_clock64() + B.deadline_ticks;
-    if (blockIdx.x == 0) {
-        if (threadIdx.x < 64) {
-            int ok = 1;
+    // wave 0 of each workgroup arrives and waits; the other waves wait at
+    // the workgroup barrier below
+    if (threadIdx.x < 64) {
+        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&B.bar_flag[blockIdx.x], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const long long t_end = wall_clock64() + B.deadline_ticks;
+        int ok = 1;
+        if (blockIdx.x == 0) {
+            // every workgroup's flag, 64 at a time
             for (int b0 = 0; b0 < (int)gridDim.x && ok; b0 += 64) {
                 const int b = b0 + (int)threadIdx.x;
                 while (true) {
@@ -148,24 +151,23 @@ __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
                 else __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 *s_ok = ok;
             }
-        }
-    } else if (threadIdx.x == 0) {
-        int ok = 1;
-        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-            if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = 0;
-                break;
+        } else if (threadIdx.x == 0) {
+            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() > t_end) {
+                    __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
-            if (wall_clock64() > t_end) {
-                __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+            *s_ok = ok;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-        *s_ok = ok;
     }
     __syncthreads();
     return *s_ok != 0;
