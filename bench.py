@@ -83,6 +83,33 @@ def counter_traffic(kernel_sub: str):
     return None
 
 
+def copy_ceiling():
+    """A plain device copy (torch's copy kernel: one read and one write of
+    every byte) at two sizes: 2 GiB per array, far beyond the 256 MB MALL,
+    and 134 MB (one 256^3 float64 vector).  Bytes moved (read + written)
+    per second, HIP events around 10 copies after 2 warm-ups: a measured
+    ceiling for streaming kernels beside the 8 TB/s peak."""
+    import torch
+    out = {}
+    for label, n in (("2GiB", 1 << 28), ("256^3_f64", 256 ** 3)):
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[label] = {"bytes_moved": 16 * n, "us": 1e3 * ms, "gbs": 16 * n / (ms * 1e-3) / 1e9}
+        del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_gpu(args, dtype: str, n: int = None, tau: float = None, steps: int = None, warmup: int = None):
     import torch
     import paper_1309_4616_amd as E
@@ -780,6 +807,9 @@ def main():
         print("[bench] csr only", file=sys.stderr, flush=True)
         print(json.dumps({"csr": run_csr(args)}), flush=True)
         return
+    ceiling = copy_ceiling()
+    print(f"[bench] device copy: {ceiling['2GiB']['gbs']:.0f} GB/s at 2 GiB, "
+          f"{ceiling['256^3_f64']['gbs']:.0f} GB/s at 134 MB", file=sys.stderr, flush=True)
     print(f"[bench] f64: {args.warmup} warmup + {args.steps} timed steps at {args.n}^3", file=sys.stderr, flush=True)
     r64 = run_gpu(args, "f64")
     print(f"[bench] f64 done: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -863,6 +893,8 @@ def main():
             "launches_per_step": r64["pairs_per_step"],
             "single_product": {"avg_launch_us": r64["single_avg_us"], "achieved_gbs": r64["single_gbs"],
                                "launches_per_step": r64["singles_per_step"]},
+            "measured_copy_gbs": {k: v["gbs"] for k, v in ceiling.items()},
+            "frac_of_copy_2GiB": r64["pair_gbs"] / ceiling["2GiB"]["gbs"],
         }
     else:
         traffic = counter_traffic("stencil_sweep<3, 1, 1, double, double, 2>") if n == 256 else None
