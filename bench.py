@@ -125,10 +125,13 @@ def run_gpu(args, dtype: str, n: int = None, tau: float = None, steps: int = Non
                      coef=("separable", coef.c0, coef.c1, coef.tx, coef.ty, coef.tz))
     u = torch.as_tensor(synth.gaussian_bump_3d(n, seed=0), device="cuda:0")
     ws = op.workspace(dtype)
-    # profile=2: HIP events around the first Newton launch of each loop
-    # only (a pair sweep unless --no-pairs), so that timing costs two events
-    # per step instead of two per launch
-    params = E.LejaParams(profile=2, pairs=not args.no_pairs)
+    # every fourth timed step runs with HIP events around each of its Newton
+    # launches (profile=1); the others without (events around every launch
+    # of every step would cost about 4% of the step).  The launch average is
+    # over all Newton launches of those steps: single launches vary by +-15%
+    # within a step, the first after a loop's opening among the slowest.
+    params = E.LejaParams(profile=0, pairs=not args.no_pairs)
+    params_timed = E.LejaParams(profile=1, pairs=not args.no_pairs)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         E.expeuler_step(op, tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
@@ -138,8 +141,9 @@ def run_gpu(args, dtype: str, n: int = None, tau: float = None, steps: int = Non
     newton_ms = pair_ms = 0.0
     degrees = []
     t0 = time.perf_counter()
-    for _ in range(steps):
-        st = E.expeuler_step(op, tau, u, tol=args.tol, dtype=dtype, params=params, ws=ws)
+    for i in range(steps):
+        st = E.expeuler_step(op, tau, u, tol=args.tol, dtype=dtype, params=params_timed if i % 4 == 0 else params,
+                             ws=ws)
         matvecs += st["matvecs"]
         newton += st["newton_steps"]
         timed += st["timed_products"]
@@ -807,9 +811,11 @@ def main():
         print("[bench] csr only", file=sys.stderr, flush=True)
         print(json.dumps({"csr": run_csr(args)}), flush=True)
         return
-    ceiling = copy_ceiling()
-    print(f"[bench] device copy: {ceiling['2GiB']['gbs']:.0f} GB/s at 2 GiB, "
-          f"{ceiling['256^3_f64']['gbs']:.0f} GB/s at 134 MB", file=sys.stderr, flush=True)
+    # (not in counter runs: their only copies are the 512 MiB calibration)
+    ceiling = None if args.copy_probe else copy_ceiling()
+    if ceiling:
+        print(f"[bench] device copy: {ceiling['2GiB']['gbs']:.0f} GB/s at 2 GiB, "
+              f"{ceiling['256^3_f64']['gbs']:.0f} GB/s at 134 MB", file=sys.stderr, flush=True)
     print(f"[bench] f64: {args.warmup} warmup + {args.steps} timed steps at {args.n}^3", file=sys.stderr, flush=True)
     r64 = run_gpu(args, "f64")
     print(f"[bench] f64 done: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -893,8 +899,8 @@ def main():
             "launches_per_step": r64["pairs_per_step"],
             "single_product": {"avg_launch_us": r64["single_avg_us"], "achieved_gbs": r64["single_gbs"],
                                "launches_per_step": r64["singles_per_step"]},
-            "measured_copy_gbs": {k: v["gbs"] for k, v in ceiling.items()},
-            "frac_of_copy_2GiB": r64["pair_gbs"] / ceiling["2GiB"]["gbs"],
+            "measured_copy_gbs": {k: v["gbs"] for k, v in ceiling.items()} if ceiling else None,
+            "frac_of_copy_2GiB": r64["pair_gbs"] / ceiling["2GiB"]["gbs"] if ceiling else None,
         }
     else:
         traffic = counter_traffic("stencil_sweep<3, 1, 1, double, double, 2>") if n == 256 else None

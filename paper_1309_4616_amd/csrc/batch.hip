@@ -273,7 +273,8 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
 }
 
 // Combine an instance's tile partials in index order and advance its state.
-__device__ void finalize_instance(const BatchArgs& B, int inst) {
+// Returns the new phase in thread 0 (-1 in the other threads).
+__device__ int finalize_instance(const BatchArgs& B, int inst) {
     __shared__ double red[kPersistWaves][3];   // a round kernel's or the persistent kernel's waves
     const BatchInfo& I = B.info[inst];
     BatchState* S = &B.state[inst];
@@ -282,6 +283,7 @@ __device__ void finalize_instance(const BatchArgs& B, int inst) {
     // wave that loaded it afterwards would take the other branch and pair
     // the workgroup's later barriers wrongly
     __syncthreads();
+    int next = -1;
     if (phase == PH_FIRST || phase == PH_NEWTON) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
@@ -302,32 +304,37 @@ __device__ void finalize_instance(const BatchArgs& B, int inst) {
             S->newton += 1;
             S->t_prev = t;
             if (!isfinite(wn) || !isfinite(pn) || !isfinite(tprev)) {
-                S->phase = PH_FAILED;
+                next = PH_FAILED;
                 S->status = 2;
             } else if (m >= 2 && num <= B.tol * pn) {
                 S->degree_last = m;
                 S->degree_max = max(S->degree_max, m);
                 S->err_max = fmax(S->err_max, err);
-                S->phase = PH_UPDATE;
+                next = PH_UPDATE;
             } else if (m >= B.m_max) {
-                S->phase = PH_FAILED;
+                next = PH_FAILED;
                 S->status = 1;
                 S->err_max = fmax(S->err_max, err);
             } else {
-                S->phase = PH_NEWTON;
+                next = PH_NEWTON;
                 S->j = m;
             }
+            S->phase = next;
         }
     } else if (threadIdx.x == 0) {
+        next = phase;
         if (phase == PH_START) {
-            S->phase = PH_FIRST;
+            next = PH_FIRST;
         } else if (phase == PH_UPDATE) {
-            S->l += 1;
+            const int l = S->l + 1;
+            S->l = l;
             S->j = 0;
-            S->phase = (S->l < I.s) ? PH_START : PH_DONE;
+            next = (l < I.s) ? PH_START : PH_DONE;
         }
+        S->phase = next;
     }
     __syncthreads();
+    return next;
 }
 
 // Exclusive prefix sum over the workgroup (blockDim a multiple of 64);
@@ -470,12 +477,11 @@ size_t tiles_lds_bytes(int count) { return sizeof(int) * (2 * (size_t)count + kM
 __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
     const int inst = blockIdx.x;
     if (inst >= B.count || !active_phase(B.state[inst].phase)) return;
-    finalize_instance(B, inst);
+    const int next = finalize_instance(B, inst);
     if (threadIdx.x == 0) {
-        const BatchState& S = B.state[inst];
-        if (!active_phase(S.phase)) atomicAdd(&B.ctrl->finished, 1u);
-        if (S.phase == PH_START || S.phase == PH_UPDATE || (S.phase == PH_FIRST && S.l == 0))
-            B.ctrl->aux_next = 1;
+        if (!active_phase(next)) atomicAdd(&B.ctrl->finished, 1u);
+        // (a first product made here follows a start vector: l >= 1, hot)
+        if (next == PH_START || next == PH_UPDATE) B.ctrl->aux_next = 1;
     }
 }
 
