@@ -826,9 +826,7 @@ def main():
     r32_512 = None
     if not args.no_fp32 and not args.no_512:
         # FP32 storage beyond the 256 MB MALL: 512^3 (w, p 0.5 GB each), tau
-        # scaled by (256/512)^2 to keep tau (b - a) and the degree of 256^3;
-        # rows of 512 points take single products (the pair sweep holds rows
-        # of at most 256)
+        # scaled by (256/512)^2 to keep tau (b - a) and the degree of 256^3
         r32_512 = run_gpu(args, "f32", n=512, tau=args.tau * (args.n / 512.0) ** 2, steps=3, warmup=1)
         print(f"[bench] f32 512^3 done: {r32_512['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     learned = None
@@ -974,11 +972,15 @@ def main():
             "value": r32_512["value"],
             "ms_per_step": r32_512["ms_per_step"],
             "matvecs_per_step": r32_512["matvecs_per_step"],
+            "pairs_per_step": r32_512["pairs_per_step"],
+            "pair_avg_us": r32_512["pair_avg_us"],
+            "pair_gbs": r32_512["pair_gbs"],
+            "pair_frac": (r32_512["pair_gbs"] / HBM_PEAK_GBS) if r32_512["pair_gbs"] else None,
             "single_avg_us": r32_512["single_avg_us"],
             "single_gbs": r32_512["single_gbs"],
-            "single_frac": (r32_512["single_gbs"] / HBM_PEAK_GBS) if r32_512["single_gbs"] else None,
-            "note": ("working set 3 x 0.54 GB, beyond the MALL; single fused Newton products "
-                     "(16 B per point: read w, p; write w', p)"),
+            "note": ("working set 3 x 0.54 GB, beyond the MALL; pair sweeps with four waves per "
+                     "row and two output rows per workgroup (16 B per point and launch: read w, p; "
+                     "write w'', p)"),
         }
     if learned:
         out["learned_vs_plain"] = learned

@@ -14,9 +14,10 @@
 //
 // Layout and traversal:
 //  * a workgroup is 16 waves; a wave owns 128 consecutive x points of one row
-//    (2 per lane), so a row of n0 <= 256 points takes NX = 1 or 2 waves and
-//    the workgroup holds 16/NX rows: R = 16/NX - 2 output rows and one halo
-//    row on each side;
+//    (2 per lane), so a row of n0 <= 512 points takes NX = 1, 2 or 4 waves
+//    and the workgroup holds 16/NX rows: R = 16/NX - 2 output rows and one
+//    halo row on each side (R = 2 for rows longer than 256 points: the
+//    first product is then computed on twice the output rows);
 //  * every wave marches along z computing w_{j+1} of its row one plane ahead;
 //    the plane goes into a three-plane LDS ring, one barrier per plane, and
 //    the inner waves then compute w_{j+2} of the plane behind from their own
@@ -27,7 +28,6 @@
 //    split into equal contiguous chunks numbered XCD-major, so that the
 //    chunks that share halo rows run on the same L2 at the same time.
 #include <algorithm>
-
 #include <type_traits>
 
 #include "sweep_common.h"
@@ -38,8 +38,8 @@ namespace {
 constexpr int kPairWaves = 16;
 constexpr int kPairLds = kPairWaves * 128;   // points of one plane of the w_{j+1} ring
 constexpr int kZSeg = 248;                   // planes per marched segment at most
-constexpr int kWRingLds = 2560;              // points of one plane of the w_j ring:
-                                             // (16/NX + 2) rows of 128 NX points
+constexpr int kWRingLds = 3072;              // points of one plane of the w_j ring:
+                                             // (16/NX + 2) rows of 128 NX points, NX <= 4
 
 // Face weights.  With a(x, y, z) = c0 + c1 X(x) Y(y) Z(z) the weight of the
 // face between cells c and c' (the mean of a_c and a_c') is
@@ -718,13 +718,13 @@ hipError_t go(const PairGeom& g, int coef, int bc, const PairArgs& a, hipStream_
 }  // namespace
 
 // Pair sweeps need a 3D stencil with a constant or separable coefficient,
-// rows of at most 256 points (even, for the two-point vector accesses),
+// rows of at most 512 points (even, for the two-point vector accesses),
 // fewer than 2^28 points, and 16-byte aligned vectors.
 bool pair_supported(const Op& op, int tw) {
     (void)tw;
     // the stores address a vector with 32-bit byte offsets: below 2^31
     // bytes in FP64 (2^28 points)
-    return op.kind == 0 && op.dim == 3 && op.n[0] % 2 == 0 && op.n[0] <= 256 &&
+    return op.kind == 0 && op.dim == 3 && op.n[0] % 2 == 0 && op.n[0] <= 512 &&
            (op.coef == EXPI_COEF_CONST || op.coef == EXPI_COEF_SEPARABLE) &&
            op.size * 8 < ((int64_t)1 << 31) - 64;
 }
@@ -735,7 +735,9 @@ bool pair_start_supported(const Op& op) { return pair_supported(op, 0); }
 
 PairGeom pair_geom(const Op& op, int cus) {
     PairGeom g{};
-    g.nxw = (op.n[0] + 127) / 128;
+    // waves per row: 1, 2 or 4 (a divisor of the 16 waves; with 4, waves past
+    // a shorter row's end are masked)
+    g.nxw = op.n[0] <= 128 ? 1 : (op.n[0] <= 256 ? 2 : 4);
     g.rows = kPairWaves / g.nxw - 2;
     g.nrt = (op.n[1] + g.rows - 1) / g.rows;
     const long long units = (long long)g.nrt * op.n[2];

@@ -70,6 +70,8 @@ SHAPES = [
     (2, 3, 4),        # tiny
     (200, 1, 3),      # a single row
     (96, 15, 1),      # a single plane
+    (512, 7, 6),      # four waves per row, 2-row tiles, ragged rows
+    (300, 5, 8),      # four waves per row, the last one beyond the row end
 ]
 
 
@@ -181,7 +183,7 @@ def test_pair_fp32_constant_coefficient(E):
     assert st2["timed_pairs"] >= 1
 
 
-@pytest.mark.parametrize("shape", [(256, 12, 9), (128, 30, 5), (64, 7, 17)])
+@pytest.mark.parametrize("shape", [(256, 12, 9), (128, 30, 5), (64, 7, 17), (512, 5, 9)])
 def test_pair_equals_single_products_elementwise(E, shape):
     """Pair sweeps and single products give the same result to rounding at
     every point (a tighter check than the oracle bar: it would show a stale
@@ -304,3 +306,18 @@ def test_update_enqueued_ahead_of_status_with_wrong_hints(E):
         yo, so = I.phi_action(A, 1, tau3, v, 1e-10)
         assert st["substeps"] == 3
         assert relerr(N(y), yo) <= TOL_F64, (name, relerr(N(y), yo))
+
+
+def test_pair_fp32_rows_of_512(E):
+    """FP32 storage on rows of 512 points (four waves per row, two output
+    rows per workgroup): pair sweeps are taken and agree with the oracle
+    to the FP32 bar."""
+    shape = (512, 6, 8)
+    op, A = make(E, shape, "neumann0", "separable")
+    v = synth.uniform_vector(int(np.prod(shape)), 9)
+    a, b = O.gershgorin_interval(A)
+    tau = 10.0 / (b - a)
+    y, st = E.phi_action(op, 1, tau, T(v), tol=1e-10, dtype="f32", params=E.LejaParams(profile=True))
+    yo, _ = I.phi_action(A, 1, tau, v, 1e-10)
+    assert relerr(N(y), yo) <= 5e-6
+    assert st["timed_pairs"] >= 1
