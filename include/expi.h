@@ -245,12 +245,22 @@ int64_t expi_op_size(const expi_op *op);
 int expi_op_set_tiles(expi_op *op, int vec, int waves, int march);
 int expi_op_get_tiles(const expi_op *op, int *vec, int *waves, int *march);
 
+/* Pair sweeps (two consecutive Newton products per pass on 3D stencils
+ * with a constant or separable coefficient, rows of at most 512 points):
+ * use = 1 (the default) takes them wherever they apply, 0 runs single
+ * products.  EXPI_EINVAL for other values. */
+int expi_op_set_pairs(expi_op *op, int use);
+int expi_op_get_pairs(const expi_op *op, int *use);
+
 /* Autotuner: times the fused Newton product (the hot loop's sweep, each
  * product doing full work) under every candidate tile setting on this
  * operator and storage dtype, `reps` launches each after one warm-up, with
  * HIP events on `stream`, and keeps the fastest as the operator's setting.
  * Candidates: stencils vec {2,1} x waves {1,2,4,8} x march {8,16,32,64}
- * (3D) or {4,8,16,32} (2D); CSR lanes {4,8,16} x waves {1,2,4,8}.  The
+ * (3D) or {4,8,16,32} (2D); CSR lanes {4,8,16} x waves {1,2,4,8}.  Where
+ * a pair sweep applies, it is timed last (listed as (0, 0, 2), time per
+ * launch of two products) and the operator's pair setting becomes 1 if it
+ * takes less per product than the best single product, else 0.  The
  * workspace (expi_workspace_bytes(op, dtype)) supplies the vectors and is
  * overwritten.  If cand/us are given, the first max_cand tried settings
  * (vec, waves, march triples) and their mean microseconds per launch are

@@ -91,6 +91,16 @@ class _Op:
         check(lib().expi_op_get_tiles(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(m)))
         return v.value, w.value, m.value
 
+    def set_pairs(self, use: bool) -> None:
+        """Pair sweeps where they apply (the default), or single products
+        (see expi_op_set_pairs)."""
+        check(lib().expi_op_set_pairs(self._h, 1 if use else 0))
+
+    def pairs(self) -> bool:
+        u = ctypes.c_int()
+        check(lib().expi_op_get_pairs(self._h, ctypes.byref(u)))
+        return bool(u.value)
+
     def interval(self, stream=None):
         a, b = ctypes.c_double(), ctypes.c_double()
         ws = self.workspace("f64")

@@ -26,7 +26,7 @@ NONLIN = {"cubic": G_CUBIC, "combustion": G_COMBUSTION, "combustion_fast": G_COM
 
 # every symbol include/expi.h declares
 EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "expi_op_size",
-           "expi_op_set_tiles", "expi_op_get_tiles", "expi_op_autotune", "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
+           "expi_op_set_tiles", "expi_op_get_tiles", "expi_op_set_pairs", "expi_op_get_pairs", "expi_op_autotune", "expi_workspace_bytes", "expi_op_interval", "apply_op", "phi_action",
            "expeuler_step", "expi_leja_points", "expi_divided_differences", "expi_last_error",
            "expi_batch_create", "expi_batch_destroy", "expi_batch_set_tiles",
            "expi_batch_total_length", "expi_batch_offsets", "expi_batch_workspace_bytes",
@@ -153,6 +153,10 @@ def lib() -> ctypes.CDLL:
     ip = ctypes.POINTER(c_int)
     L.expi_op_get_tiles.argtypes = [c_void_p, ip, ip, ip]
     L.expi_op_get_tiles.restype = c_int
+    L.expi_op_set_pairs.argtypes = [c_void_p, c_int]
+    L.expi_op_set_pairs.restype = c_int
+    L.expi_op_get_pairs.argtypes = [c_void_p, ip]
+    L.expi_op_get_pairs.restype = c_int
     L.expi_op_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p,
                                    ip, ctypes.POINTER(ctypes.c_float), c_int, ip]
     L.expi_op_autotune.restype = c_int

@@ -1,8 +1,9 @@
 """Tile-shape autotuner with a JSON cache.
 
 `tune(op, dtype)` asks the library (expi_op_autotune) to time the fused
-Newton product under every candidate tile setting on this operator, keeps the
-fastest on the operator, and records it in a JSON cache keyed by operator
+Newton product under every candidate tile setting on this operator, and,
+where pair sweeps apply, a pair sweep against two single products; it keeps
+the fastest on the operator and records it in a JSON cache keyed by operator
 shape, boundary handling, coefficient kind, storage dtype and GPU, so later
 processes reuse the choice without timing again (`load(op, dtype)`).
 
@@ -66,21 +67,30 @@ def load(op, dtype: str = "f64", path: str | None = None) -> bool:
     entry = _read(path).get(op_key(op, dtype))
     if not entry:
         return False
-    op.set_tiles(*entry["tiles"])
+    _apply(op, entry)
     return True
+
+
+def _apply(op, entry: dict) -> None:
+    op.set_tiles(*entry["tiles"])
+    if "pairs" in entry and hasattr(op, "set_pairs"):
+        op.set_pairs(bool(entry["pairs"]))
 
 
 def tune(op, dtype: str = "f64", reps: int = 10, path: str | None = None,
          use_cache: bool = True, stream=None) -> dict:
     """Time every candidate, keep the fastest on `op`, record it; returns
-    {'tiles': (vec, waves, march), 'us': best time, 'candidates': [...]}."""
+    {'tiles': (vec, waves, march), 'us': best time, 'pairs': whether pair
+    sweeps are kept (None where they do not apply), 'candidates': [...]}
+    (the pair sweep is the candidate (0, 0, 2), its time per launch of two
+    products)."""
     import torch
     from . import _dtype_code, _stream_ptr
     path = path or cache_path()
     key = op_key(op, dtype)
     data = _read(path) if use_cache else {}
     if use_cache and key in data:
-        op.set_tiles(*data[key]["tiles"])
+        _apply(op, data[key])
         return data[key]
     code = _dtype_code(dtype)
     ws = op.workspace(code)
@@ -94,7 +104,10 @@ def tune(op, dtype: str = "f64", reps: int = 10, path: str | None = None,
     rows = [((cand[3 * i], cand[3 * i + 1], cand[3 * i + 2]), float(us[i]))
             for i in range(min(nc.value, maxc))]
     best = op.tiles()
-    entry = {"tiles": list(best), "us": min(t for _, t in rows) if rows else None,
+    singles = [t for c, t in rows if c[0] != 0]
+    paired = any(c[0] == 0 for c, _ in rows)
+    entry = {"tiles": list(best), "us": min(singles) if singles else None,
+             "pairs": (op.pairs() if paired else None),
              "candidates": [[list(c), t] for c, t in rows]}
     if use_cache:
         data = _read(path)

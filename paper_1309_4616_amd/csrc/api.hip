@@ -769,7 +769,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
     int sub = substep_count(tau, ia, ib, P.l_max);
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pair_supported(op, tw)};
+          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pairs_enabled(op, tw)};
     expi_stats acc{};
     for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
         const double delta = tau / sub;
@@ -847,7 +847,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
                 tin = 0;
             }
             LoopOut lo;
-            C.pairs = P.pairs && pair_supported(op, tw) && (((uintptr_t)p & 15) == 0);
+            C.pairs = P.pairs && pairs_enabled(op, tw) && (((uintptr_t)p & 15) == 0);
             // the update of this substep, enqueued ahead of the status
             // read-back where it always runs (p_in_y needs one only for a fix)
             const double* yin = ((k == 1 || phik_sub) && l > 0) ? y : nullptr;
@@ -899,7 +899,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     int sub = substep_count(tau, ia, ib, P.l_max);
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pair_supported(op, tw)};
+          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pairs_enabled(op, tw)};
     double* yb = reinterpret_cast<double*>(ws + L.y);
     void* p = ws + L.p;
     expi_stats acc{};
@@ -1338,6 +1338,21 @@ int expi_op_set_tiles(expi_op* op, int vec, int waves, int march) {
     return EXPI_OK;
 }
 
+int expi_op_set_pairs(expi_op* op, int use) {
+    if (!op) return fail(EXPI_EINVAL, "op is NULL");
+    if (use != 0 && use != 1) return fail(EXPI_EINVAL, "use must be 0 or 1");
+    Op& o = *reinterpret_cast<Op*>(op);
+    std::lock_guard<std::mutex> lock(o.mu);
+    o.use_pairs = use;
+    return EXPI_OK;
+}
+
+int expi_op_get_pairs(const expi_op* op, int* use) {
+    if (!op || !use) return fail(EXPI_EINVAL, "op and use must be non-NULL");
+    *use = reinterpret_cast<const Op*>(op)->use_pairs;
+    return EXPI_OK;
+}
+
 int expi_op_get_tiles(const expi_op* op, int* vec, int* waves, int* march) {
     if (!op || !vec || !waves || !march) return fail(EXPI_EINVAL, "NULL argument");
     const Op& o = *reinterpret_cast<const Op*>(op);
@@ -1423,11 +1438,51 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
             best = t;
         }
     }
+    // the dominant kernel's form: where a pair sweep can run, it is timed
+    // against two single products at the best tiles (the same data, every
+    // product doing full work) and kept if it takes less per product.  It is
+    // listed as the candidate (0, 0, 2), its time per launch (two products).
+    int use_pairs = o.use_pairs;
+    if (err == hipSuccess && pair_supported(o, tw) && best_us < 1e30f) {
+        PairArgs b{};
+        b.x = w + L.w0;
+        b.out = w + L.w1;
+        b.p = w + L.p;
+        b.partials = reinterpret_cast<double*>(w + L.partials);
+        b.st = reinterpret_cast<NewtonState*>(w + L.state);
+        b.alpha = 1e-6;
+        b.beta1 = -0.5;
+        b.beta2 = -0.5;
+        b.d1 = 1e-3;
+        b.d2 = 1e-3;
+        b.tol = 1e-300;
+        b.j = 1;
+        b.guard = 0;
+        err = launch_pair(o, tw, b, s, nullptr, false);   // warm up
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_pair(o, tw, b, s, nullptr, false);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess) {
+            const float per = 1e3f * ms / reps;
+            if (nc < max_cand && cand && us) {
+                cand[3 * nc] = 0;
+                cand[3 * nc + 1] = 0;
+                cand[3 * nc + 2] = 2;
+                us[nc] = per;
+            }
+            ++nc;
+            use_pairs = (0.5f * per < best_us) ? 1 : 0;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> lock(o.mu);
         o.tiles = (err == hipSuccess) ? best : keep;
+        if (err == hipSuccess) o.use_pairs = use_pairs;
     }
     *n_cand = nc;
     if (err != hipSuccess) {

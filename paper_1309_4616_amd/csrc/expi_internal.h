@@ -192,6 +192,7 @@ struct Op {
     Tiles tiles;
     int bdata = 0;        // EXPI_BDATA_* of a 3D Dirichlet stencil
     int bdata_mode = 0;   // EXPI_BDATA_IN_KERNEL or EXPI_BDATA_SEPARATE
+    int use_pairs = 1;    // pair sweeps where supported (the autotuner may turn them off)
     std::mutex mu;
     bool have_interval = false;
     double ia = 0, ib = 0;
@@ -242,6 +243,8 @@ hipError_t launch_reset(NewtonState* st, hipStream_t s);
 // Pair sweeps: two Newton products in one pass (pair.hip), then a finalize
 // kernel that applies the stop test after each of them.
 bool pair_supported(const Op& op, int tw);
+// pair sweeps are supported and the operator's setting allows them
+inline bool pairs_enabled(const Op& op, int tw) { return op.use_pairs != 0 && pair_supported(op, tw); }
 bool pair_start_supported(const Op& op);
 PairGeom pair_geom(const Op& op, int cus);
 // `mode` (PairMode): PAIR_FIRST starts the loop from r = w_0 (products 0

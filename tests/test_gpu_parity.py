@@ -417,21 +417,32 @@ def test_autotune_stencil_and_csr(E, tmp_path):
     v = synth.uniform_vector(A.shape[0], 3)
     y0, _ = E.phi_action(op, 1, 2e-3, T(v), tol=1e-10)
     entry = E.autotune.tune(op, "f64", reps=3, path=cache)
-    assert len(entry["candidates"]) == 32
+    # 32 single-product settings, then the pair sweep (0, 0, 2)
+    assert len(entry["candidates"]) == 33
+    singles = [t for c, t in entry["candidates"] if c[0] != 0]
+    pair_us = [t for c, t in entry["candidates"] if c == [0, 0, 2]]
+    assert len(singles) == 32 and len(pair_us) == 1
     assert tuple(entry["tiles"]) == op.tiles()
-    assert entry["us"] == min(t for _, t in entry["candidates"])
+    assert entry["us"] == min(singles)
+    assert entry["pairs"] == (0.5 * pair_us[0] < min(singles)) == op.pairs()
     y1, _ = E.phi_action(op, 1, 2e-3, T(v), tol=1e-10)
-    assert relerr(N(y1), N(y0)) <= 1e-13
+    assert relerr(N(y1), N(y0)) <= 1e-12
     yo, _ = I.phi_action(A, 1, 2e-3, v, 1e-10)
     assert relerr(N(y1), yo) <= TOL_F64
     # a fresh operator picks the cached setting without timing
     op2, _ = stencil_pair(E, shape, h, "neumann0", "separable")
+    op2.set_pairs(not op.pairs())
     assert E.autotune.load(op2, "f64", path=cache)
-    assert op2.tiles() == op.tiles()
+    assert op2.tiles() == op.tiles() and op2.pairs() == op.pairs()
+    # single products on request, the same result to rounding
+    op2.set_pairs(False)
+    y2, st2 = E.phi_action(op2, 1, 2e-3, T(v), tol=1e-10, params=E.LejaParams(profile=True))
+    assert st2["timed_pairs"] == 0
+    assert relerr(N(y2), N(y0)) <= 1e-12
     # CSR lanes per row
     cop, CA, g = csr_pair(E, 20011, seed=3)
     centry = E.autotune.tune(cop, "f64", reps=3, path=cache)
-    assert len(centry["candidates"]) == 12
+    assert len(centry["candidates"]) == 12 and centry["pairs"] is None
     x = synth.uniform_vector(g.n, 4)
     y = E.apply_op(cop, -0.5, 2.0, T(x))
     assert np.max(np.abs(N(y) - O.apply_op(CA, -0.5, 2.0, x))) <= 1e-13 * np.abs(N(y)).max()

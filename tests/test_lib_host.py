@@ -183,6 +183,11 @@ def test_call_validation_before_any_hip_call(L):
     v_, w_, m_ = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     assert L.expi_op_get_tiles(op, ctypes.byref(v_), ctypes.byref(w_), ctypes.byref(m_)) == 0
     assert (v_.value, w_.value, m_.value) == (1, 2, 16)
+    use = ctypes.c_int()
+    assert L.expi_op_get_pairs(op, ctypes.byref(use)) == 0 and use.value == 1
+    assert L.expi_op_set_pairs(op, 2) == -1
+    assert L.expi_op_set_pairs(op, 0) == 0
+    assert L.expi_op_get_pairs(op, ctypes.byref(use)) == 0 and use.value == 0
     L.expi_op_destroy(op)
 
 
