@@ -151,3 +151,26 @@ def test_pair_sweep_multi_segment_march(E):
         assert st["timed_pairs"] >= 1
         assert relerr(N(y), yo) <= TOL_F64, (bc, relerr(N(y), yo))
         assert relerr(N(y), N(ys)) <= 1e-12
+
+
+def test_expeuler_512_fp32_pairs_equal_singles(E):
+    """The 3D workload at 512^3 with FP32 storage (the bench leg beyond the
+    MALL, tau scaled to keep tau (b - a) of 256^3): pair sweeps on rows of 512
+    points (four waves per row, two output rows per workgroup) against
+    single products, element by element, to FP32 rounding; no oracle at this
+    size (its operator would need about 60 GB of host memory)."""
+    import torch
+    n = 512
+    op, _ = rd_op(E, n)
+    u0 = torch.as_tensor(synth.gaussian_bump_3d(n, seed=0), device="cuda:0")
+    tau = 1e-5 * (256 / n) ** 2
+    up, us = u0.clone(), u0.clone()
+    print("512^3 FP32 Euler step, pairs then singles", flush=True)
+    sp = E.expeuler_step(op, tau, up, tol=1e-8, dtype="f32", params=E.LejaParams(profile=True))
+    ss = E.expeuler_step(op, tau, us, tol=1e-8, dtype="f32", params=E.LejaParams(pairs=False, profile=True))
+    assert sp["timed_pairs"] >= 1 and ss["timed_pairs"] == 0
+    assert abs(sp["degree_last"] - ss["degree_last"]) <= 1
+    d = ((up - us).norm() / (us - u0).norm()).item()
+    assert d <= 1e-5, d
+    del op, u0, up, us
+    torch.cuda.empty_cache()
