@@ -464,6 +464,8 @@ def run_csr(args):
     per_product = 12 * g.nnz + 4 * (g.n + 1) + 32 * g.n
     avg_us = 1e3 * ms / max(timed, 1)
     gbs = per_product / (avg_us * 1e-6) / 1e9
+    lanes = op.tiles()[0]
+    traffic = counter_traffic(f"csr_sweep<1, double, double, {lanes}>") if args.csr_log2n == 20 else None
     return {
         "workload": (f"phi_1(tau A) v, A = negative graph Laplacian of a random geometric graph, "
                      f"n = 2^{args.csr_log2n}, {g.nnz / g.n:.1f} stored entries per row, "
@@ -477,6 +479,9 @@ def run_csr(args):
         "product_gbs": gbs,
         "product_frac": gbs / HBM_PEAK_GBS,
         "algorithmic_bytes_per_product": per_product,
+        "counted_bytes_per_product": traffic["bytes"] if traffic else None,
+        "counted_bytes_source": traffic["profile"] if traffic else None,
+        "lanes_per_row": lanes,
         "nnz": int(g.nnz),
     }
 
