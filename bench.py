@@ -762,7 +762,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # (about 30 ms of steps: the first tens of steps after start-up run
+    # about 10% slower while the GPU clocks come up)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--tau", type=float, default=1e-5)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -971,6 +973,7 @@ def main():
             "single_gbs": r32["single_gbs"],
             "single_frac": (r32["single_gbs"] / HBM_PEAK_GBS) if r32["single_gbs"] else None,
             "pairs_per_step": r32["pairs_per_step"],
+            "fused_starts_per_step": r32["fused_starts_per_step"],
             "step_hbm_gbs": r32["step_gbs"],
             "pair_avg_us": r32["pair_avg_us"],
             "pair_gbs": r32["pair_gbs"],

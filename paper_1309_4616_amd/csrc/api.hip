@@ -952,7 +952,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
             // with this step size stopped at decides.
             const int hint = get_hint(op, C.key);
             // (the fused start vector forms u - u^3 only)
-            const bool fuse = l == 0 && tw == 0 && nonlin == EXPI_G_CUBIC && op.bdata == EXPI_BDATA_NONE &&
+            const bool fuse = l == 0 && nonlin == EXPI_G_CUBIC && op.bdata == EXPI_BDATA_NONE &&
                               C.pairs && C.m_max >= 3 &&
                               pair_start_supported(op) &&
                               (((uintptr_t)u & 15) == 0) &&

@@ -249,7 +249,7 @@ bool pair_start_supported(const Op& op);
 PairGeom pair_geom(const Op& op, int cus);
 // `mode` (PairMode): PAIR_FIRST starts the loop from r = w_0 (products 0
 // and 1; the finalize records t_0, t_1 and ||r|| before its stop test at
-// m = 2); PAIR_START (FP64 storage only) forms r itself and takes product 0
+// m = 2); PAIR_START forms r itself (in FP64 from the FP64 u) and takes product 0
 // (the finalize records t_0, t_1 and ||r||, and cannot stop at m = 1).
 hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s,
                        hipEvent_t after_sweep = nullptr, bool finalize = true,

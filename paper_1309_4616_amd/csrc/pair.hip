@@ -145,6 +145,24 @@ __device__ __forceinline__ PointW<TC> point_weights(const PlaneW<TC>& w, TC c0ih
     return q;
 }
 
+// The same weights in another arithmetic type.
+template <class TO, class TI>
+__device__ __forceinline__ PointW<TO> point_weights_as(const PointW<TI>& q) {
+    PointW<TO> r;
+    r.wxl = (TO)q.wxl;
+    r.wxc = (TO)q.wxc;
+    r.wxr = (TO)q.wxr;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        r.wym[v] = (TO)q.wym[v];
+        r.wyq[v] = (TO)q.wyq[v];
+        r.wzm[v] = (TO)q.wzm[v];
+        r.wzq[v] = (TO)q.wzq[v];
+        r.d[v] = (TO)q.d[v];
+    }
+    return r;
+}
+
 template <class TC>
 __device__ __forceinline__ void aw_pair_w(const TC (&wc)[2], TC wl, TC wr, const TC (&ym)[2],
                                           const TC (&yq)[2], const TC (&zm)[2], const TC (&zq)[2],
@@ -264,7 +282,13 @@ template <int COEF, int BC, class TW, int MODE>
 __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     using TC = compute_t<TW, TW>;
     constexpr bool FIRST = MODE == PAIR_FIRST, START = MODE == PAIR_START;
-    typedef TC TC2 __attribute__((ext_vector_type(2)));
+    // TX: the arithmetic of the first half (w_j, its ring and queues, step
+    // 3).  TC except for PAIR_START with FP32 storage: u is read in FP64 and
+    // r = sigma A u + u - u^3 is formed in FP64 (A u cancels: formed in FP32
+    // from a rounded u it would lose most of its digits), then rounded to
+    // FP32 for the ring and product 0, which runs in FP32 like the other
+    // FP32 pairs
+    using TX = typename std::conditional<START && sizeof(TW) == 4, double, TC>::type;
     // the status flag (the loop has stopped: do nothing) is looked at only
     // at the first barrier, so its load overlaps the first plane loads
     // (a.st is always a valid state record).  A buffer load: a scalar load
@@ -273,12 +297,12 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         __builtin_amdgcn_make_buffer_rsrc(a.st, 0, (int)sizeof(NewtonState), 0x00020000);
     const int done_v = (int)__builtin_amdgcn_raw_buffer_load_b32(st_r, (int)offsetof(NewtonState, done), 0, 0);
     __shared__ TC ring[3 * kPairLds];     // w_{j+1}: rows y0-1 .. y0+R of three planes
-    __shared__ TC wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
+    __shared__ TX wring[3 * kWRingLds];   // w_j: rows y0-2 .. y0+R+1 of three planes
     // z data of the planes of the current segment: read where used through
     // LDS (a vector load there would make the in-order memory counter wait
     // for every prefetch issued before it)
-    __shared__ ZPlane<TC> ztab[kZSeg + 8];
-    const TW* __restrict__ x = static_cast<const TW*>(a.x);
+    __shared__ ZPlane<TX> ztab[kZSeg + 8];
+    const TX* __restrict__ x = static_cast<const TX*>(a.x);
     TW* __restrict__ out = static_cast<TW*>(a.out);
     TW* __restrict__ pv = static_cast<TW*>(a.p);
     // w_{j+2} and p are written through buffer resources (range-checked
@@ -302,9 +326,10 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     // arguments stay in scalar registers; products formed here would hold
     // vector registers for the whole sweep)
     const TC alpha = (TC)a.alpha, beta1 = (TC)a.beta1, beta2 = (TC)a.beta2;
-    const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2, sigma = (TC)a.sigma;
-    const TC c0ihx = (TC)a.c0ih[0], c0ihz = (TC)a.c0ih[2];
-    const TC c1ihx = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[0] : (TC)0;
+    const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2;
+    const TX c0ihx = (TX)a.c0ih[0], c0ihz = (TX)a.c0ih[2];
+    const TX c1ihx = COEF == EXPI_COEF_SEPARABLE ? (TX)a.c1ih[0] : (TX)0;
+    const TX sigmax = (TX)a.sigma;
     // Row ends.  The x neighbour of a point at a row end is 0 under
     // Dirichlet and the point's own value otherwise (no flux), so that one
     // formula serves all points.  The first lane of a row has no left
@@ -315,16 +340,16 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
     // x data of the lane, in registers for the whole sweep: table values of
     // its points, face values left of point 0, between the points and right
     // of point 1 (own value where the row ends)
-    TC xd[5] = {1, 1, 1, 1, 1};
+    TX xd[5] = {1, 1, 1, 1, 1};
     if (COEF == EXPI_COEF_SEPARABLE) {
         // four loads issued together (clamped, none behind a branch)
-        const TC X0 = (TC)a.tx[ic], X1 = (TC)a.tx[ic + 1];
-        const TC Xm = (TC)a.tx[max(ic - 1, 0)], Xq = (TC)a.tx[min(ic + 2, n0 - 1)];
+        const TX X0 = (TX)a.tx[ic], X1 = (TX)a.tx[ic + 1];
+        const TX Xm = (TX)a.tx[max(ic - 1, 0)], Xq = (TX)a.tx[min(ic + 2, n0 - 1)];
         xd[0] = X0;
         xd[1] = X1;
-        xd[2] = lb ? X0 : (TC)0.5 * (Xm + X0);
-        xd[3] = (TC)0.5 * (X0 + X1);
-        xd[4] = rb ? X1 : (TC)0.5 * (X1 + Xq);
+        xd[2] = lb ? X0 : (TX)0.5 * (Xm + X0);
+        xd[3] = (TX)0.5 * (X0 + X1);
+        xd[4] = rb ? X1 : (TX)0.5 * (X1 + Xq);
     }
     // (after the loads above are on their way) every ring entry holds a
     // finite value before it is read; the barrier keeps a slow wave's fill
@@ -338,12 +363,14 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
 
     // the neighbours of the lane's pair from the adjacent lanes; el, er are
     // the values lanes 0 and 63 take in
-    auto neighbours = [&](const TC (&wc)[2], TC el, TC er, TC& left, TC& right) {
-        TC srcr = wc[0];
-        if (partial && !xin) srcr = dir ? (TC)0 : wc[1];   // past the row end: the last point
+    // (in TC for the second product, in TX for the first)
+    auto neighbours = [&](const auto (&wc)[2], auto el, auto er, auto& left, auto& right) {
+        using T = decltype(el);
+        T srcr = wc[0];
+        if (partial && !xin) srcr = dir ? (T)0 : wc[1];   // past the row end: the last point
         left = dpp_shift<kDppWaveShr1>(el, wc[1]);
         right = dpp_shift<kDppWaveShl1>(er, srcr);
-        if (partial && xin && rb) right = dir ? (TC)0 : wc[1];
+        if (partial && xin && rb) right = dir ? (T)0 : wc[1];
     };
 
     const long long units = (long long)a.nrt * n2;
@@ -376,36 +403,36 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             for (int t = threadIdx.x; t < zlen; t += blockDim.x) {
                 const int q = kb - 2 + t;
                 const bool ezm = q > 0, ezq = q < n2 - 1;
-                const TC dm = (ezm || dir) ? (TC)1 : (TC)0, dq = (ezq || dir) ? (TC)1 : (TC)0;
+                const TX dm = (ezm || dir) ? (TX)1 : (TX)0, dq = (ezq || dir) ? (TX)1 : (TX)0;
                 // three loads issued together (clamped, none behind a branch)
-                const TC zc = (TC)a.tz[min(max(q, 0), n2 - 1)];
-                const TC zm = (TC)a.tz[min(max(q - 1, 0), n2 - 1)];
-                const TC zq = (TC)a.tz[min(max(q + 1, 0), n2 - 1)];
-                const TC zfm = ezm ? (TC)0.5 * (zm + zc) : zc;
-                const TC zfq = ezq ? (TC)0.5 * (zq + zc) : zc;
-                ZPlane<TC> z;
+                const TX zc = (TX)a.tz[min(max(q, 0), n2 - 1)];
+                const TX zm = (TX)a.tz[min(max(q - 1, 0), n2 - 1)];
+                const TX zq = (TX)a.tz[min(max(q + 1, 0), n2 - 1)];
+                const TX zfm = ezm ? (TX)0.5 * (zm + zc) : zc;
+                const TX zfq = ezq ? (TX)0.5 * (zq + zc) : zc;
+                ZPlane<TX> z;
                 z.zc = zc;
-                z.zfm = ezm ? zfm : (TC)0;
-                z.zfq = ezq ? zfq : (TC)0;
+                z.zfm = ezm ? zfm : (TX)0;
+                z.zfq = ezq ? zfq : (TX)0;
                 z.zd = dm * zfm + dq * zfq;
                 ztab[t] = z;
             }
         }
         // y data of the row: the same in every lane, moved to scalar
         // registers for the march
-        RowW<TC> rw;
+        RowW<TX> rw;
         {
-            const TC c0ihy = (TC)a.c0ih[1];
-            const TC c1ihy = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[1] : (TC)0;
-            const TC c1ihz = COEF == EXPI_COEF_SEPARABLE ? (TC)a.c1ih[2] : (TC)0;
-            const TC em = eym ? (TC)1 : (TC)0, eq = eyq ? (TC)1 : (TC)0;
-            const TC dm = (eym || dir) ? (TC)1 : (TC)0, dq = (eyq || dir) ? (TC)1 : (TC)0;
-            TC Y = 1, yfm = 1, yfq = 1;
+            const TX c0ihy = (TX)a.c0ih[1];
+            const TX c1ihy = COEF == EXPI_COEF_SEPARABLE ? (TX)a.c1ih[1] : (TX)0;
+            const TX c1ihz = COEF == EXPI_COEF_SEPARABLE ? (TX)a.c1ih[2] : (TX)0;
+            const TX em = eym ? (TX)1 : (TX)0, eq = eyq ? (TX)1 : (TX)0;
+            const TX dm = (eym || dir) ? (TX)1 : (TX)0, dq = (eyq || dir) ? (TX)1 : (TX)0;
+            TX Y = 1, yfm = 1, yfq = 1;
             if (COEF == EXPI_COEF_SEPARABLE) {
-                Y = (TC)a.ty[yc];
-                const TC Ym = (TC)a.ty[max(yc - 1, 0)], Yq = (TC)a.ty[min(yc + 1, n1 - 1)];
-                yfm = eym ? (TC)0.5 * (Ym + Y) : Y;
-                yfq = eyq ? (TC)0.5 * (Yq + Y) : Y;
+                Y = (TX)a.ty[yc];
+                const TX Ym = (TX)a.ty[max(yc - 1, 0)], Yq = (TX)a.ty[min(yc + 1, n1 - 1)];
+                yfm = eym ? (TX)0.5 * (Ym + Y) : Y;
+                yfq = eyq ? (TX)0.5 * (Yq + Y) : Y;
             }
             rw.y = Y;
             rw.gym = em * (c1ihy * yfm);
@@ -441,15 +468,16 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         // on every path (clamped addresses, range-checked stores), so the
         // in-order memory counter waits only for the load that is needed.
         const int kst = kb - 2;
-        TC L[2][2], P[2][2];
-        TC Wm[2], Wc[2], Wq[2];   // the wave's own row of w_j: planes k, k+1, k+2
+        TX L[2][2], P[2][2];
+        TX Wm[2], Wc[2], Wq[2];   // the wave's own row of w_j: planes k, k+1, k+2
         // FP32 (registers to spare): the own row of w_{j+1} too, planes
         // k, k-1, k-2 (values from the rings' zero fill before the first)
-        constexpr bool kOwnW1 = sizeof(TW) == 4;
+        // (not with the FP64 first half of a mixed start: registers)
+        constexpr bool kOwnW1 = sizeof(TW) == 4 && std::is_same<TX, TC>::value;
         TC Q0[2] = {0, 0}, Q1[2] = {0, 0}, Q2[2] = {0, 0};
         // FP32: the point weights of plane k+1 (step 3) wait two iterations
         // for step 2 on the same plane; slot (plane - kst) mod 2
-        constexpr bool kKeepW = sizeof(TW) == 4;
+        constexpr bool kKeepW = sizeof(TW) == 4 && std::is_same<TX, TC>::value;
         PointW<TC> PWq[2];
         L[0][0] = L[0][1] = L[1][0] = L[1][1] = 0;
         P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0;
@@ -461,14 +489,19 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
         auto slot_of = [&](int c) { return c % 3; };   // c >= 0
         auto wslot_c = [&](int c) { return &wring[slot_of(c) * kWRingLds]; };
         auto vslot_c = [&](int c) { return &ring[slot_of(c) * kPairLds]; };
-        auto put = [&](TC* base, int row, const TC (&v)[2]) {
-            TC2 t;
+        // (rings of TC or TX values)
+        auto put = [&](auto* base, int row, const auto (&v)[2]) {
+            using T = typename std::remove_pointer<decltype(base)>::type;
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            T2 t;
             t.x = v[0];
             t.y = v[1];
-            *reinterpret_cast<TC2*>(base + row * RW + i) = t;
+            *reinterpret_cast<T2*>(base + row * RW + i) = t;
         };
-        auto get = [&](const TC* base, int row, TC (&v)[2]) {
-            const TC2 t = *reinterpret_cast<const TC2*>(base + row * RW + i);
+        auto get = [&](const auto* base, int row, auto (&v)[2]) {
+            using T = typename std::remove_const<typename std::remove_pointer<decltype(base)>::type>::type;
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            const T2 t = *reinterpret_cast<const T2*>(base + row * RW + i);
             v[0] = t.x;
             v[1] = t.y;
         };
@@ -477,7 +510,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
             // (rows outside the grid load a clamped row: finite values that
             // no nonzero weight uses; the inner rows load their own row a
             // second time where the outer rows load their extra row)
-            TC h0[2], h1[2], e0[2], e1[2];
+            TX h0[2], h1[2], e0[2], e1[2];
             ld2(x, at(kst), h0);
             ld2(x, at(kst + 1), h1);
             ld2(x, at(kst + 2), L[0]);
@@ -524,7 +557,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 // (1) w_j of plane k+2 into the ring (and the wave's own
                 // registers), then load plane k+4
                 {
-                    TC* wb = wslot_c(s + 2);
+                    TX* wb = wslot_c(s + 2);
                     Wq[0] = L[s & 1][0];
                     Wq[1] = L[s & 1][1];
                     put(wb, rr, L[s & 1]);
@@ -563,16 +596,17 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                         if constexpr (kKeepW) {
                             aw_pair_w<TC>(wc, left, right, ym, yq, zm, zq, PWq[(s + 1) & 1], aw);
                         } else {
-                            const PlaneW<TC> pw =
-                                plane_weights<COEF, TC>(rw, ztab, kb - 2, kp, n2, dir, c0ihz, c1ihx);
-                            aw_pair<COEF, TC>(wc, left, right, ym, yq, zm, zq, pw, c0ihx, xd, aw);
+                            // (formed in TX, the type of the row and z data)
+                            const PointW<TC> pw = point_weights_as<TC>(point_weights<COEF, TX>(
+                                plane_weights<COEF, TX>(rw, ztab, kb - 2, kp, n2, dir, c0ihz, c1ihx), c0ihx, xd));
+                            aw_pair_w<TC>(wc, left, right, ym, yq, zm, zq, pw, aw);
                         }
                         if (ionly) {
                             const bool edge = yedge || kp == 0 || kp == n2 - 1;
                             if (edge || lb) aw[0] = 0;
                             if (edge || rb) aw[1] = 0;
                         }
-                        const TC* pp = P[(s + 1) & 1];        // p (FIRST: r) of plane k-1
+                        const TX* pp = P[(s + 1) & 1];        // p (FIRST: r) of plane k-1
                         constexpr bool kPairSq = sizeof(TW) == 4;
                         TC q0 = 0, q1 = 0, q2 = 0, q3 = 0;
 #pragma unroll
@@ -585,7 +619,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                             wo[v] = w2;
                             po[v] = p2;
                             // FIRST: ||r||^2 in place of ||p_1||^2
-                            const TC n1 = FIRST ? pp[v] : p1;
+                            const TC n1 = FIRST ? (TC)pp[v] : p1;
                             if constexpr (kPairSq) {
                                 q0 += wc[v] * wc[v];
                                 if (!START) q1 += n1 * n1;
@@ -614,7 +648,9 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     // into the slot just read: p (FIRST: r) of plane k+1,
                     // used two iterations on; the outer rows load their
                     // extra row of w_j, plane k+4
-                    const TW* psrc = (FIRST || START || hal) ? x : static_cast<const TW*>(pv);
+                    const TX* psrc;
+                    if constexpr (START) psrc = x;
+                    else psrc = (FIRST || hal) ? x : static_cast<const TW*>(pv);
                     // (p outside the output planes: a neighbouring output
                     // plane's p instead, a cache hit)
                     ld2(psrc, hal ? at(min(k + 4, ke + 1)) + hoff : at(min(max(k + 1, kb), ke - 1)),
@@ -624,21 +660,22 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                 // grid are never used with a nonzero weight)
                 {
                     const int q = k + 1;
-                    const TC* wb = wslot_c(s + 1);
+                    const TX* wb = wslot_c(s + 1);
                     // own row from registers: planes k, k+1, k+2
-                    const TC wc[2] = {Wc[0], Wc[1]}, zm[2] = {Wm[0], Wm[1]}, zq[2] = {Wq[0], Wq[1]};
-                    TC ym[2], yq[2];
+                    const TX wc[2] = {Wc[0], Wc[1]}, zm[2] = {Wm[0], Wm[1]}, zq[2] = {Wq[0], Wq[1]};
+                    TX ym[2], yq[2];
                     get(wb, rr - 1, ym);
                     get(wb, rr + 1, yq);
-                    const TC el = wb[rr * RW + (ic > 0 ? ic - 1 : ic)];
-                    const TC er = wb[rr * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
-                    TC left, right;
-                    neighbours(wc, ezero ? (TC)0 : el, ezero ? (TC)0 : er, left, right);
-                    const PlaneW<TC> pw = plane_weights<COEF, TC>(rw, ztab, kb - 2, q, n2, dir, c0ihz, c1ihx);
-                    const PointW<TC> qw = point_weights<COEF, TC>(pw, c0ihx, xd);
-                    if constexpr (kKeepW) PWq[(s + 1) & 1] = qw;   // plane k+1, read at k+2
-                    TC aw[2];
-                    aw_pair_w<TC>(wc, left, right, ym, yq, zm, zq, qw, aw);
+                    const TX el = wb[rr * RW + (ic > 0 ? ic - 1 : ic)];
+                    const TX er = wb[rr * RW + (ic + 2 < n0 ? ic + 2 : ic + 1)];
+                    TX left, right;
+                    neighbours(wc, ezero ? (TX)0 : el, ezero ? (TX)0 : er, left, right);
+                    const PlaneW<TX> pw = plane_weights<COEF, TX>(rw, ztab, kb - 2, q, n2, dir, c0ihz, c1ihx);
+                    const PointW<TX> qw = point_weights<COEF, TX>(pw, c0ihx, xd);
+                    // plane k+1, read at k+2 (in TC)
+                    if constexpr (kKeepW) PWq[(s + 1) & 1] = point_weights_as<TC>(qw);
+                    TX aw[2];
+                    aw_pair_w<TX>(wc, left, right, ym, yq, zm, zq, qw, aw);
                     if (ionly) {
                         const bool edge = yedge || q == 0 || q == n2 - 1;
                         if (edge || lb) aw[0] = 0;
@@ -647,7 +684,7 @@ __global__ __launch_bounds__(kPairWaves * 64) void pair_sweep(PairArgs a) {
                     TC r[2];
 #pragma unroll
                     for (int v = 0; v < 2; ++v)
-                        r[v] = START ? (TC)(TW)(sigma * aw[v] + (wc[v] - wc[v] * wc[v] * wc[v]))
+                        r[v] = START ? (TC)(TW)(sigmax * aw[v] + (wc[v] - wc[v] * wc[v] * wc[v]))
                                      : (TC)(TW)(alpha * aw[v] + beta1 * wc[v]);
                     put(vslot_c(s + 1), ry, r);
 #pragma unroll
@@ -729,8 +766,8 @@ bool pair_supported(const Op& op, int tw) {
            op.size * 8 < ((int64_t)1 << 31) - 64;
 }
 
-// The start vector fused into the first pair sweep (PAIR_START): FP64
-// storage.
+// The start vector fused into the first pair sweep (PAIR_START): u is read
+// and r formed in FP64 with either storage type.
 bool pair_start_supported(const Op& op) { return pair_supported(op, 0); }
 
 PairGeom pair_geom(const Op& op, int cus) {
@@ -765,7 +802,7 @@ int device_cus() {
 
 hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep,
                        bool finalize, int mode) {
-    if (mode == PAIR_START && (tw != 0 || !pair_start_supported(op))) return hipErrorInvalidValue;
+    if (mode == PAIR_START && !pair_start_supported(op)) return hipErrorInvalidValue;
     const PairGeom g = pair_geom(op, device_cus());
     for (int d = 0; d < 3; ++d) {
         a.n[d] = op.n[d];
@@ -785,7 +822,8 @@ hipError_t launch_pair(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent
     a.chunk = g.chunk;
     a.per_xcd = g.per_xcd;
     hipError_t e;
-    if (mode == PAIR_START) e = go<double, PAIR_START>(g, op.coef, op.bc, a, s);
+    if (mode == PAIR_START)
+        e = tw == 1 ? go<float, PAIR_START>(g, op.coef, op.bc, a, s) : go<double, PAIR_START>(g, op.coef, op.bc, a, s);
     else if (mode == PAIR_FIRST)
         e = tw == 1 ? go<float, PAIR_FIRST>(g, op.coef, op.bc, a, s) : go<double, PAIR_FIRST>(g, op.coef, op.bc, a, s);
     else

@@ -228,7 +228,8 @@ def test_first_pair_and_its_fallbacks(E):
 
 
 @pytest.mark.parametrize("bc,kind", [("neumann0", "separable"), ("neumann0", "const"),
-                                     ("dirichlet0", "const"), ("interior_only", "separable")])
+                                     ("dirichlet0", "const"), ("dirichlet0", "separable"),
+                                     ("interior_only", "separable")])
 def test_start_vector_fused_into_first_pair(E, bc, kind):
     """Euler steps whose start vector r = A u + u - u^3 is formed inside the
     first pair sweep (fuse_start = 2) agree with the oracle and, point by
@@ -257,6 +258,36 @@ def test_start_vector_fused_into_first_pair(E, bc, kind):
         assert np.max(np.abs(got[1][0] - got[2][0])) <= 1e-12 * np.max(np.abs(uo))
         degrees.add(got[2][1]["degree_last"] % 2)
     assert degrees == {0, 1}
+
+
+@pytest.mark.parametrize("bc,kind", [("neumann0", "separable"), ("dirichlet0", "const"),
+                                     ("dirichlet0", "separable"), ("interior_only", "const")])
+def test_start_vector_fused_into_first_pair_fp32(E, bc, kind):
+    """FP32 storage: the fused start pair reads u in FP64 and forms r in FP64
+    (as the separate start sweep does), rounds it to FP32 and runs product 0
+    in FP32.  Fused and separate agree with the oracle to the FP32 bar of
+    phi_1 (and so with each other to twice it); the fused run fuses."""
+    shape = (256, 10, 7)
+    op, A = make(E, shape, bc, kind)
+    n = int(np.prod(shape))
+    u0 = 0.5 + 0.1 * synth.uniform_vector(n, 13)
+    a, b = O.gershgorin_interval(A)
+    for q in (9.0, 21.0, 230.0):
+        tau = q / (b - a)
+        uo, so = I.expeuler_step(A, tau, u0, 1e-10)
+        got = {}
+        for fs in (1, 2):
+            u = T(u0)
+            print(f"fused start fp32 {bc} {kind} q={q} fuse_start={fs}", flush=True)
+            st = E.expeuler_step(op, tau, u, tol=1e-10, dtype="f32", params=E.LejaParams(fuse_start=fs))
+            assert st["converged"] == 1
+            # the FP32 bar of phi_1 (w, p rounded to FP32 at every product;
+            # up to 3 substeps of degree up to 60 here)
+            assert relerr(N(u), uo) <= 5e-6, (q, fs, relerr(N(u), uo))
+            assert st["fused_starts"] == (1 if fs == 2 else 0)
+            got[fs] = N(u)
+        # each within the bar of the oracle, so within twice it of each other
+        assert relerr(got[2], got[1]) <= 1e-5, (q, relerr(got[2], got[1]))
 
 
 def test_fused_start_by_degree_parity(E):
