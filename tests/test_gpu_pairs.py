@@ -352,3 +352,24 @@ def test_pair_fp32_rows_of_512(E):
     yo, _ = I.phi_action(A, 1, tau, v, 1e-10)
     assert relerr(N(y), yo) <= 5e-6
     assert st["timed_pairs"] >= 1
+
+
+def test_fused_start_fp32_rows_of_512(E):
+    """The FP32 fused start on rows of 512 points (four waves per row, the
+    FP64 w_j ring at its largest), against the separate start and the
+    oracle."""
+    shape = (512, 6, 8)
+    op, A = make(E, shape, "neumann0", "separable")
+    n = int(np.prod(shape))
+    u0 = 0.5 + 0.1 * synth.uniform_vector(n, 14)
+    a, b = O.gershgorin_interval(A)
+    tau = 15.0 / (b - a)
+    uo, _ = I.expeuler_step(A, tau, u0, 1e-10)
+    got = {}
+    for fs in (1, 2):
+        u = T(u0)
+        st = E.expeuler_step(op, tau, u, tol=1e-10, dtype="f32", params=E.LejaParams(fuse_start=fs))
+        assert st["fused_starts"] == (1 if fs == 2 else 0)
+        assert relerr(N(u), uo) <= 5e-6
+        got[fs] = N(u)
+    assert relerr(got[2], got[1]) <= 1e-5
