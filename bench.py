@@ -449,6 +449,9 @@ def run_csr(args):
     y = torch.empty_like(v)
     params = E.LejaParams(profile=True)
     ws = op.workspace("f64")
+    # lanes per row and waves per workgroup from the library's autotuner
+    from paper_1309_4616_amd import autotune
+    tuned = autotune.tune(op, "f64", reps=5, use_cache=False)
     E.phi_action(op, 1, tau, v, y=y, tol=1e-10, params=params, ws=ws)
     torch.cuda.synchronize()
     reps = args.csr_reps
@@ -482,6 +485,8 @@ def run_csr(args):
         "counted_bytes_per_product": traffic["bytes"] if traffic else None,
         "counted_bytes_source": traffic["profile"] if traffic else None,
         "lanes_per_row": lanes,
+        "tiles": {"lanes_per_row_waves": tuned["tiles"][:2], "chosen_by": "expi_op_autotune",
+                  "candidates_us": tuned["candidates"]},
         "nnz": int(g.nnz),
     }
 
