@@ -159,14 +159,16 @@ typedef struct {
     int32_t selector_hidden;
     /* 1: never fuse two Newton products into one sweep.  By default, on 3D
      * stencils with a constant or separable coefficient and rows of at most
-     * 256 points, consecutive products run as pair sweeps that keep w_{j+1}
+     * 512 points, consecutive products run as pair sweeps that keep w_{j+1}
      * on chip (same arithmetic, half the vector traffic) and test the stop
-     * rule after each of the two. */
+     * rule after each of the two (unless the operator's pair setting,
+     * expi_op_set_pairs, is 0). */
     int32_t no_pairs;
     /* Exponential Euler steps: the start-vector sweep r = A u + u - u^3 of
      * the first substep can run as the first half of a pair sweep whose
-     * second half is Newton product 0 (FP64 storage, pair sweeps on, u
-     * 16-byte aligned); a stop at degree m then takes ceil((m+1)/2) sweeps
+     * second half is Newton product 0 (pair sweeps on, u 16-byte aligned;
+     * with FP32 storage r is still formed in FP64, from the FP64 u, and
+     * rounded to FP32); a stop at degree m then takes ceil((m+1)/2) sweeps
      * instead of 1 + ceil(m/2).  0: fuse when the previous step with the
      * same step size stopped at an odd degree; 1: never; 2: whenever it
      * applies.  Other values: EXPI_EINVAL. */
