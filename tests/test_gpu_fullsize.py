@@ -174,3 +174,35 @@ def test_expeuler_512_fp32_pairs_equal_singles(E):
     assert d <= 1e-5, d
     del op, u0, up, us
     torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_pair_sweep_at_its_size_limit(E):
+    """Pair sweeps address a vector with 32-bit byte offsets, so they take
+    grids of FP64 vectors below 2^31 bytes.  A grid just below the limit
+    (512 x 512 x 1022 points, 2.14 GB per vector) runs pair sweeps and gives
+    the single products' result to rounding; one at the limit (512 x 512 x
+    1024, 2^31 bytes) runs single products only and still converges."""
+    import torch
+    gen = torch.Generator(device="cuda:0")
+    for nz, pairs_expected in ((1022, True), (1024, False)):
+        shape = (512, 512, nz)
+        h = (1.0 / 512, 1.0 / 512, 1.0 / nz)
+        op = E.StencilOp(shape, h, "neumann0", coef=1.0)
+        n = 512 * 512 * nz
+        gen.manual_seed(5)
+        v = torch.rand(n, generator=gen, device="cuda:0", dtype=torch.float64) - 0.5
+        a, b = op.interval()
+        tau = 6.0 / (b - a)
+        print(f"size limit: {shape}, {8 * n} bytes per vector", flush=True)
+        yp, sp = E.phi_action(op, 1, tau, v, tol=1e-12, params=E.LejaParams(profile=True))
+        assert (sp["timed_pairs"] >= 1) == pairs_expected
+        if pairs_expected:
+            ys, ss = E.phi_action(op, 1, tau, v, tol=1e-12, params=E.LejaParams(pairs=False, profile=True))
+            assert ss["timed_pairs"] == 0 and ss["degree_last"] == sp["degree_last"]
+            d = ((yp - ys).abs().max() / ys.abs().max()).item()
+            assert d <= 1e-12, d
+            del ys
+        assert sp["converged"] == 1
+        del op, v, yp
+        torch.cuda.empty_cache()
