@@ -13,6 +13,11 @@ oracle step by step.
 Also: the pair sweep's multi-segment march (a workgroup whose chunk of
 (row tile, plane) units is longer than one segment of planes), forced by a
 grid with 65536 planes, against the oracle.
+
+And: the start vector fused into the first pair sweep against the separate
+start sweep on the 256^3 step; the batched workload (256 uneven 2D problems)
+against the sine-mode closed form, with the persistent launch equal to the
+rounds bit for bit.
 """
 import numpy as np
 import pytest
@@ -206,3 +211,71 @@ def test_pair_sweep_at_its_size_limit(E):
         assert sp["converged"] == 1
         del op, v, yp
         torch.cuda.empty_cache()
+
+
+def test_expeuler_256_fused_start_equals_separate(E):
+    """At full size (256^3, the benchmark's operator and state), the start
+    vector fused into the first pair sweep gives the separate start sweep's
+    step to rounding, in FP64 and with FP32 storage (the configuration the
+    benchmark times fuses whenever the previous step stopped at an odd
+    degree)."""
+    import torch
+    n = 256
+    op, _ = rd_op(E, n)
+    u0 = torch.as_tensor(synth.gaussian_bump_3d(n, seed=0), device="cuda:0")
+    for dtype, bar in (("f64", 1e-12), ("f32", 1e-5)):
+        res = {}
+        for fs in (1, 2):
+            u = u0.clone()
+            print(f"256^3 {dtype} fuse_start={fs}", flush=True)
+            st = E.expeuler_step(op, 1e-5, u, tol=1e-8, dtype=dtype, params=E.LejaParams(fuse_start=fs))
+            assert st["fused_starts"] == (1 if fs == 2 else 0)
+            res[fs] = u - u0
+        d = ((res[2] - res[1]).norm() / res[1].norm()).item()
+        assert d <= bar, (dtype, d)
+    del op, u0, res
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_batched_256_problems_against_sine_modes(E):
+    """The batched workload at full size (256 uneven 2D Dirichlet problems,
+    sides 64..1024, FP32 storage, tol 1e-8): every instance against the FP64
+    sine-mode closed form within the FP32 bar, the persistent launch
+    bitwise equal to the rounds."""
+    import torch
+    inst = synth.batched_instances(256, seed=0)
+    ns = np.array([it.n for it in inst])
+    taus = np.array([it.tau for it in inst])
+    h = 1.0 / (ns + 1.0)
+    b = E.Batch(ns, ns, h, h, taus, bc="dirichlet0", tol=1e-8, dtype="f32")
+    v_host = np.zeros(b.total_length)
+    for i, it in enumerate(inst):
+        o = int(b.offsets[i])
+        v_host[o:o + it.n * it.n] = synth.uniform_vector(it.n * it.n, it.seed)
+    v = torch.as_tensor(v_host, device="cuda:0")
+    y = torch.zeros_like(v)
+    b.prepare()
+    print("batched 256: rounds", flush=True)
+    b.launch(v, y)
+    stats, rounds = b.results()
+    yy = y.cpu().numpy()
+    worst = 0.0
+    for i, it in enumerate(inst):
+        o, n2 = int(b.offsets[i]), it.n * it.n
+        want = O.dirichlet_box_phi(1, (it.n, it.n), (h[i], h[i]), it.tau, v_host[o:o + n2])
+        e = relerr(yy[o:o + n2], want)
+        worst = max(worst, e)
+        assert e <= 5e-6, (i, it.n, e)
+        assert stats[i]["status"] == 0
+    print(f"batched 256: {rounds} rounds, worst error {worst:.2e}", flush=True)
+    y2 = torch.zeros_like(v)
+    print("batched 256: persistent", flush=True)
+    b.launch_persistent(v, y2)
+    _, r2 = b.results()
+    assert r2 == rounds
+    mask = torch.zeros(b.total_length, dtype=torch.bool, device=v.device)
+    for i, it in enumerate(inst):
+        mask[int(b.offsets[i]):int(b.offsets[i]) + it.n * it.n] = True
+    assert torch.equal(y2[mask], y[mask])
