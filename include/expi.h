@@ -392,11 +392,18 @@ int phi_action_noalloc(expi_op *op, int k, double tau, const double *v, double *
  * test and y stay float64.
  *
  * The work runs in rounds; in each round every unfinished instance takes one
- * step (start vector, one Newton product, or the substep update).  A round
- * is two kernels (the tiles of all unfinished instances, then one stop test
- * per instance); nothing inside waits on memory.  At most
- * expi_batch_max_rounds rounds are needed.  No retries: an instance that
- * misses the stop test within m_max products reports EXPI_ENOTCONV. */
+ * step (start vector, Newton products, or the substep update).  A round is
+ * three kernels (the tiles of the instances whose step is a start vector,
+ * an update or a product that reads the float64 input; the tiles of the
+ * other products; then one stop test per instance); nothing inside waits
+ * on memory.  By default a step after the first product forms two Newton
+ * products in one pass (expi_batch_set_pairs): w_{j+1} stays in registers,
+ * so w_j and p are read and w_{j+2} and p written once for both, and the
+ * stop test is applied after each of the two as single products would
+ * apply it (a stop after the first leaves the second product's term in p,
+ * and the update subtracts it); newton_steps then counts both products.  At
+ * most expi_batch_max_rounds rounds are needed.  No retries: an instance
+ * that misses the stop test within m_max products reports EXPI_ENOTCONV. */
 typedef struct expi_batch expi_batch;
 typedef struct {
     int32_t status;         /* 0, EXPI_ENOTCONV or EXPI_ENONFINITE            */
@@ -456,6 +463,13 @@ int expi_batch_replay(expi_batch *b, void *stream);
 int expi_batch_autotune(expi_batch *b, const double *v, double *y, void *ws, size_t ws_bytes,
                         int reps, void *stream, int *cand, float *ms, int max_cand, int *n_cand);
 int expi_batch_get_tiles(const expi_batch *b, int *waves, int *march);
+/* Newton products two per round (on = 1, the default) or one per round
+ * (on = 0); the same interpolant up to rounding and the stop decisions
+ * rounding can move.  EXPI_EINVAL for other values or after
+ * expi_batch_capture (the captured graph holds the setting); applies to the
+ * next solve, persistent or in rounds. */
+int expi_batch_set_pairs(expi_batch *b, int on);
+int expi_batch_get_pairs(const expi_batch *b, int *on);
 /* Rounds of the captured graph (0 if none). */
 int expi_batch_graph_rounds(const expi_batch *b);
 /* Read per-instance results back (synchronises); returns EXPI_OK if every

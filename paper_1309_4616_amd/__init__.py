@@ -415,6 +415,16 @@ class Batch:
         check(lib().expi_batch_get_tiles(self._h, ctypes.byref(w), ctypes.byref(m)))
         return (w.value, m.value)
 
+    @property
+    def pairs(self) -> bool:
+        """Newton products two per round (the default) or one."""
+        on = ctypes.c_int()
+        check(lib().expi_batch_get_pairs(self._h, ctypes.byref(on)))
+        return bool(on.value)
+
+    def set_pairs(self, on: bool) -> None:
+        check(lib().expi_batch_set_pairs(self._h, int(bool(on))))
+
     def set_tiles(self, waves: int, march: int) -> None:
         check(lib().expi_batch_set_tiles(self._h, int(waves), int(march)))
         nb = int(lib().expi_batch_workspace_bytes(self._h))

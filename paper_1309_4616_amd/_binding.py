@@ -33,7 +33,7 @@ EXPORTS = ("expi_op_create_stencil", "expi_op_create_csr", "expi_op_destroy", "e
            "expi_batch_prepare", "expi_batch_launch", "expi_batch_capture", "expi_batch_replay",
            "expi_batch_results", "expi_batch_max_rounds", "expi_batch_graph_rounds",
            "expi_batch_launch_persistent", "expi_batch_capture_persistent",
-           "expi_batch_autotune", "expi_batch_get_tiles", "expi_mlp_param_count", "expi_mlp_scratch_floats",
+           "expi_batch_autotune", "expi_batch_get_tiles", "expi_batch_set_pairs", "expi_batch_get_pairs", "expi_mlp_param_count", "expi_mlp_scratch_floats",
            "expi_mlp_forward", "expi_mlp_backward", "expi_mlp_adam",
            "expi_noalloc_init", "phi_action_noalloc", "exprk2_step",
            "expi_exprk2_workspace_bytes", "expi_nonlinearity", "expi_op_set_boundary_data",
@@ -223,6 +223,10 @@ def lib() -> ctypes.CDLL:
     L.expi_batch_autotune.restype = c_int
     L.expi_batch_get_tiles.argtypes = [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.expi_batch_get_tiles.restype = c_int
+    L.expi_batch_set_pairs.argtypes = [c_void_p, c_int]
+    L.expi_batch_set_pairs.restype = c_int
+    L.expi_batch_get_pairs.argtypes = [c_void_p, ctypes.POINTER(c_int)]
+    L.expi_batch_get_pairs.restype = c_int
     for name in ("expi_batch_max_rounds", "expi_batch_graph_rounds"):
         getattr(L, name).argtypes = [c_void_p]
         getattr(L, name).restype = c_int

@@ -10,16 +10,19 @@
 // differences ahead of time; they do not depend on the data.
 //
 // The work runs in rounds.  In each round every unfinished instance takes
-// one step of its own sequence (start vector, a product, or the update).  A
-// round is two ordinary kernels:
-//  * the tiles kernel: every workgroup builds the same list of unfinished
-//    instances and the prefix sums of their tile counts from the states in
-//    memory, then works through a contiguous share of the round's tiles
-//    (load balance across uneven sizes; shares are contiguous per XCD so a
-//    tile's neighbours mostly sit in the same L2);
+// one step of its own sequence (start vector, the first product, two more
+// Newton products, or the update; one product per step when pairs are off).
+// A round is three ordinary kernels:
+//  * two tiles kernels, one for the hot steps (the pairs of products) and
+//    one for the rest: every workgroup builds the same list of unfinished
+//    instances whose step is in its kernel's set and the prefix sums of
+//    their tile counts from the states in memory, then works through a
+//    contiguous share of the round's tiles (load balance across uneven
+//    sizes; shares are contiguous per XCD so a tile's neighbours mostly sit
+//    in the same L2);
 //  * the finalize kernel: one workgroup per instance combines that
-//    instance's tile partials in a fixed order, applies the stop test and
-//    advances its state.
+//    instance's tile partials in a fixed order, applies the stop test (after
+//    each product of a pair) and advances its state.
 // The kernel boundaries order the rounds; nothing waits on memory, so the
 // rounds can be enqueued eagerly or recorded as kernel nodes of a HIP graph
 // (no copies or fills inside) and replayed.  A round in which no instance is
@@ -46,7 +49,10 @@ namespace expi {
 
 namespace {
 
-enum Phase : int { PH_START = 0, PH_FIRST = 1, PH_NEWTON = 2, PH_UPDATE = 3, PH_DONE = 4, PH_FAILED = 5 };
+// PH_PAIR: two Newton products in one step (w_{j+1} kept in registers)
+enum Phase : int {
+    PH_START = 0, PH_FIRST = 1, PH_NEWTON = 2, PH_UPDATE = 3, PH_DONE = 4, PH_FAILED = 5, PH_PAIR = 6
+};
 
 constexpr int kMaxBatch = 4096;
 constexpr int kPersistWaves = 16;   // waves per workgroup of the persistent kernel
@@ -64,8 +70,10 @@ struct alignas(16) BatchInfo {   // static per instance
 
 struct alignas(16) BatchState {  // advanced by the finalize step
     int phase, l, j, newton;
-    int degree_max, degree_last, status, pad;
+    int degree_max, degree_last, status;
+    int wb;                      // which of w0 / w1 holds the newest Newton vector
     double t_prev, err_max;
+    double fix;                  // d_{m+1} when a pair stopped at its first product, else 0
 };
 
 struct alignas(64) BatchCtrl {
@@ -91,6 +99,7 @@ struct BatchArgs {
     void* w1;
     void* p;
     int count, m_max, march, max_rounds, bc;
+    int pairs;                    // Newton products two per step where the degree bound allows
     double c0, tol;
     long long deadline_ticks;   // longest wait at a barrier, GPU wall-clock ticks
 };
@@ -173,18 +182,201 @@ __device__ bool grid_barrier(const BatchArgs& B, int* s_ok) {
     return *s_ok != 0;
 }
 
-// Which steps a tiles kernel takes: all of them (persistent kernel), the
-// products on Newton vectors of the storage type (first product of a later
-// substep, Newton products), or the rest (start vector, update, first
-// product of the first substep, which reads the float64 input).  Keeping the
-// hot products in a kernel of their own keeps its register count, and so its
-// occupancy, that of the plain sweep.
-enum PhaseSet : int { SET_ALL = 0, SET_HOT = 1, SET_AUX = 2 };
+// Which steps a tiles kernel takes: all of them (persistent kernel); with
+// one product per round, the products on Newton vectors of the storage type
+// (first product of a later substep, Newton products: SET_HOT) and the rest
+// (start vector, update, first product of the first substep, which reads
+// the float64 input: SET_AUX); with two products per round, the pairs
+// (SET_PAIR) and everything else (SET_REST).  Keeping the hot products in a
+// kernel of their own keeps its register count, and so its occupancy, that
+// of its own sweep.
+enum PhaseSet : int { SET_ALL = 0, SET_HOT = 1, SET_AUX = 2, SET_PAIR = 3, SET_REST = 4 };
 
 __device__ __forceinline__ bool in_set(int set, int phase, int l) {
     if (phase == PH_DONE || phase == PH_FAILED) return false;
+    if (set == SET_ALL) return true;
+    if (set == SET_PAIR) return phase == PH_PAIR;
+    if (set == SET_REST) return phase != PH_PAIR;
     const bool hot = phase == PH_NEWTON || (phase == PH_FIRST && l > 0);
-    return set == SET_ALL || (set == SET_HOT) == hot;
+    return (set == SET_HOT) == hot;
+}
+
+// Steps whose code a kernel of each set holds.
+template <int SET>
+struct SetCode {
+    static constexpr bool aux = SET == SET_ALL || SET == SET_AUX || SET == SET_REST;
+    static constexpr bool single = SET == SET_ALL || SET == SET_HOT || SET == SET_REST;
+    static constexpr bool pair = SET == SET_ALL || SET == SET_PAIR;
+};
+
+// Two consecutive Newton products on one tile (two steps of the Newton
+// recurrence of Sec. III-C): w_{j+1} = alpha A w_j + beta_j w_j, then
+// w_{j+2} = alpha A w_{j+1} + beta_{j+1} w_{j+1}, with
+// p += d_{j+1} w_{j+1} + d_{j+2} w_{j+2}.  w_{j+1} stays in registers: the
+// wave forms it on its strip of 64 V points and on the point just beyond
+// each end of the strip (lane 0 the left one, lane 63 the right one, from
+// one more column of w_j and one point beyond that), on the tile's rows and
+// on the row above and below them; then w_{j+2} and p on the tile.  Each
+// point takes the single product's operations in the same order, with
+// values rounded to the storage type where the single products store them,
+// so the tile's sums are those of two single products.  Per point w_j and p
+// are read once and w_{j+2} and p written once, for two products.  Partials:
+// ||w_{j+1}||^2, ||p_{j+1}||^2, ||w_{j+2}||^2, ||p_{j+2}||^2 over the tile.
+template <class TW, int V>
+__device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchState& S, int t0, int t1,
+                          double* red_partial) {
+    using TC = TW;
+    const int lane = threadIdx.x & 63;
+    const int n0 = I.nx, n1 = I.ny;
+    const int i0 = t0 * 64 * V;
+    const int i = i0 + lane * V;
+    const int kb = t1 * B.march, ke = min(kb + B.march, n1);
+    const bool active = i < n0;
+    const int ic = active ? i : (n0 - V);
+    // the point beyond the strip at which this lane forms w_{j+1} (lanes 0
+    // and 63; the others repeat a point of their own), and the w_j point
+    // beyond that one
+    const int xe = (lane == 0) ? i0 - 1 : (lane == 63 ? i0 + 64 * V : ic);
+    const int xf = (lane == 0) ? i0 - 2 : (lane == 63 ? i0 + 64 * V + 1 : ic);
+    const int xec = min(max(xe, 0), n0 - 1), xfc = min(max(xf, 0), n0 - 1);
+    const bool dir = (B.bc == EXPI_DIRICHLET0);
+    const TC ihx = (TC)I.ihx, ihy = (TC)I.ihy, c0 = (TC)B.c0;
+    const TC alpha = (TC)I.alpha;
+    const int j = S.j;
+    const TC beta1 = (TC)(-(I.cg + B.xi[j])), beta2 = (TC)(-(I.cg + B.xi[j + 1]));
+    const TC d1 = (TC)B.dd[I.dd_off + j + 1], d2 = (TC)B.dd[I.dd_off + j + 2];
+    const TW* __restrict__ w = static_cast<const TW*>(S.wb ? B.w1 : B.w0) + I.off;
+    TW* __restrict__ out = static_cast<TW*>(S.wb ? B.w0 : B.w1) + I.off;
+    TW* __restrict__ pp = static_cast<TW*>(B.p) + I.off;
+    // every load is from a row clamped into the grid; values of rows and
+    // columns that do not exist are masked by the existence flags
+    auto row = [&](int k) { return n0 * min(max(k, 0), n1 - 1); };
+    // one point of alpha A w + beta w, as the single product forms it
+    auto prod = [&](TC wl, TC wr, TC wm, TC wq, TC wc, bool exm, bool exq, bool ezm, bool ezq,
+                    TC beta) -> TC {
+        const TC fxm = face_weight<TC>(exm, dir, c0, c0) * ihx;
+        const TC fxq = face_weight<TC>(exq, dir, c0, c0) * ihx;
+        const TC fzm = face_weight<TC>(ezm, dir, c0, c0) * ihy;
+        const TC fzq = face_weight<TC>(ezq, dir, c0, c0) * ihy;
+        const TC l = exm ? wl : (TC)0, r = exq ? wr : (TC)0;
+        const TC m = ezm ? wm : (TC)0, q = ezq ? wq : (TC)0;
+        const TC Aw = fxm * (l - wc) + fxq * (r - wc) + fzm * (m - wc) + fzq * (q - wc);
+        return (TC)(TW)(alpha * Aw + beta * wc);
+    };
+    // w_{j+1} on row q of the strip (u) and at the lane's point beyond it
+    // (ue), from w_j rows q-1, q, q+1 (wm, wc, wq; em, ec, eq at column xe)
+    // and the far point ef of row q
+    auto form_u = [&](const TC (&wm)[V], const TC (&wc)[V], const TC (&wq)[V], TC em, TC ec, TC eq, TC ef,
+                      int q, TC (&u)[V], TC& ue) {
+        const bool ezm = q > 0, ezq = q < n1 - 1;
+        TC left = __shfl_up(wc[V - 1], 1, 64);
+        TC right = __shfl_down(wc[0], 1, 64);
+        if (lane == 0) left = ec;
+        if (lane == 63) right = ec;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int iv = i + v;
+            const TC wl = (v > 0) ? wc[v - 1] : left;
+            const TC wr = (v < V - 1) ? wc[v + 1] : right;
+            u[v] = prod(wl, wr, wm[v], wq[v], wc[v], iv > 0, iv < n0 - 1, ezm, ezq, beta1);
+        }
+        const TC el = (lane == 63) ? wc[V - 1] : ef;
+        const TC er = (lane == 63) ? ef : wc[0];
+        ue = prod(el, er, em, eq, ec, xe > 0, xe < n0 - 1, ezm, ezq, beta1);
+    };
+    // w_j rows k .. k+3 (W0..W3, column xe: E0..E3), far points of rows k+1,
+    // k+2 (F1, F2); w_{j+1} rows k-1 .. k (U0, U1; Ue0, Ue1); p rows k, k+1
+    TC W0[V], W1[V], W2[V], W3[V], U0[V], U1[V], P0[V], P1[V];
+    TC E0, E1, E2, E3, F1, F2, Ue1;
+    {
+        TC Wa[V], Wb[V];
+        tile::vld<V>(w, row(kb - 2) + ic, Wa);
+        tile::vld<V>(w, row(kb - 1) + ic, Wb);
+        tile::vld<V>(w, row(kb) + ic, W0);
+        tile::vld<V>(w, row(kb + 1) + ic, W1);
+        tile::vld<V>(w, row(kb + 2) + ic, W2);
+        tile::vld<V>(w, row(kb + 3) + ic, W3);
+        const TC Ea = (TC)w[row(kb - 2) + xec], Eb = (TC)w[row(kb - 1) + xec];
+        E0 = (TC)w[row(kb) + xec];
+        E1 = (TC)w[row(kb + 1) + xec];
+        E2 = (TC)w[row(kb + 2) + xec];
+        E3 = (TC)w[row(kb + 3) + xec];
+        const TC Fa = (TC)w[row(kb - 1) + xfc], Fb = (TC)w[row(kb) + xfc];
+        F1 = (TC)w[row(kb + 1) + xfc];
+        F2 = (TC)w[row(kb + 2) + xfc];
+        tile::vld<V>(pp, row(kb) + ic, P0);
+        tile::vld<V>(pp, row(kb + 1) + ic, P1);
+        TC Ue0;   // (w_{j+2} needs w_{j+1} beyond the strip on its own row only)
+        form_u(Wa, Wb, W0, Ea, Eb, E0, Fa, kb - 1, U0, Ue0);
+        form_u(Wb, W0, W1, Eb, E0, E1, Fb, kb, U1, Ue1);
+    }
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k = kb; k < ke; ++k) {
+        // loads two rows ahead of their first use
+        TC Wn[V], Pn[V];
+        tile::vld<V>(w, row(k + 4) + ic, Wn);
+        const TC En = (TC)w[row(k + 4) + xec];
+        const TC Fn = (TC)w[row(k + 3) + xfc];
+        tile::vld<V>(pp, row(k + 2) + ic, Pn);
+        // w_{j+1} on row k+1
+        TC U2[V], Ue2;
+        form_u(W0, W1, W2, E0, E1, E2, F1, k + 1, U2, Ue2);
+        // w_{j+2} and p on row k
+        {
+            const bool ezm = k > 0, ezq = k < n1 - 1;
+            TC left = __shfl_up(U1[V - 1], 1, 64);
+            TC right = __shfl_down(U1[0], 1, 64);
+            if (lane == 0) left = Ue1;
+            if (lane == 63) right = Ue1;
+            TC wo[V], po[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int iv = i + v;
+                const TC wl = (v > 0) ? U1[v - 1] : left;
+                const TC wr = (v < V - 1) ? U1[v + 1] : right;
+                const TC u2 = prod(wl, wr, U0[v], U2[v], U1[v], iv > 0, iv < n0 - 1, ezm, ezq, beta2);
+                const TC p1 = (TC)(TW)(P0[v] + d1 * U1[v]);
+                const TC p2 = (TC)(TW)(p1 + d2 * u2);
+                wo[v] = u2;
+                po[v] = p2;
+                if (active) {
+                    s[0] += (double)U1[v] * (double)U1[v];
+                    s[1] += (double)p1 * (double)p1;
+                    s[2] += (double)u2 * (double)u2;
+                    s[3] += (double)p2 * (double)p2;
+                }
+            }
+            if (active) {
+                tile::vst<V>(out, n0 * k + i, wo);
+                tile::vst<V>(pp, n0 * k + i, po);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            W0[v] = W1[v];
+            W1[v] = W2[v];
+            W2[v] = W3[v];
+            W3[v] = Wn[v];
+            U0[v] = U1[v];
+            U1[v] = U2[v];
+            P0[v] = P1[v];
+            P1[v] = Pn[v];
+        }
+        E0 = E1;
+        E1 = E2;
+        E2 = E3;
+        E3 = En;
+        F1 = F2;
+        F2 = Fn;
+        Ue1 = Ue2;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red_partial[q] = s[q];
+    }
 }
 
 // One tile of an instance: `march` rows of 64 V points, taken by one wave
@@ -209,7 +401,7 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
     TW* w1 = static_cast<TW*>(B.w1) + I.off;
     TW* pp = static_cast<TW*>(B.p) + I.off;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (SET != SET_HOT && phase == PH_START) {
+    if (SetCode<SET>::aux && phase == PH_START) {
         a.x = B.y + I.off;
         a.out = w1;
         a.g = B.v + I.off;
@@ -218,10 +410,12 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
         tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_START, double, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
         return;
     }
-    if (SET != SET_HOT && phase == PH_UPDATE) {
-        // y' <- (l == 0 ? 0 : y') + p / s over the tile's points
+    if (SetCode<SET>::aux && phase == PH_UPDATE) {
+        // y' <- (l == 0 ? 0 : y') + p / s over the tile's points; after a pair
+        // that stopped at its first product, p - d_{m+1} w_{m+1}
         const int lane = threadIdx.x & 63;
         double* y = B.y + I.off;
+        const TW* wx = S.wb ? w1 : w0;
         for (int r = 0; r < B.march; ++r) {
             const int j = t1 * B.march + r;
             if (j >= I.ny) break;
@@ -230,10 +424,15 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
                 const int i = t0 * 64 * V + lane * V + v;
                 if (i < I.nx) {
                     const int idx = i + I.nx * j;
-                    y[idx] = (S.l == 0 ? 0.0 : y[idx]) + I.inv_s * (double)pp[idx];
+                    const double pv = (S.fix != 0.0) ? (double)pp[idx] - S.fix * (double)wx[idx] : (double)pp[idx];
+                    y[idx] = (S.l == 0 ? 0.0 : y[idx]) + I.inv_s * pv;
                 }
             }
         }
+        return;
+    }
+    if (phase == PH_PAIR) {
+        if constexpr (SetCode<SET>::pair) pair_tile<TW, V>(B, I, S, t0, t1, red_partial);
         return;
     }
     const int j = (phase == PH_FIRST) ? 0 : S.j;
@@ -245,20 +444,20 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
     if (phase == PH_FIRST) {
         a.out = w0;
         if (S.l == 0) {
-            if constexpr (SET != SET_HOT) {
+            if constexpr (SetCode<SET>::aux) {
                 a.x = B.v + I.off;
                 tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_FIRST, double, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
             }
         } else {
-            if constexpr (SET != SET_AUX) {
+            if constexpr (SetCode<SET>::single) {
                 a.x = w1;
                 tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_FIRST, TW, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
             }
         }
     } else {
-        if constexpr (SET != SET_AUX) {
-            a.x = (j & 1) ? w0 : w1;     // w_j lives in w[(j-1) & 1]
-            a.out = (j & 1) ? w1 : w0;
+        if constexpr (SetCode<SET>::single) {
+            a.x = S.wb ? w1 : w0;
+            a.out = S.wb ? w0 : w1;
             tile::stencil_tile_w<2, EXPI_COEF_CONST, EPI_NEWTON, TW, TW, V>(a, t0, t1, 0, 0, 1, s0, s1, s2);
         }
     }
@@ -270,6 +469,32 @@ __device__ void run_tile(const BatchArgs& B, const BatchInfo& I, const BatchStat
         red_partial[1] = s1;
         red_partial[2] = s2;
     }
+}
+
+// Four per-thread sums combined over the workgroup in a fixed order (the
+// order block_combine takes for three); the result is valid in thread 0.
+__device__ void block_sum4(double (&v)[4], double (*red)[4]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) red[wv][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 4; ++q) {
+            double acc = red[0][q];
+            for (int w = 1; w < nw; ++w) acc += red[w][q];
+            v[q] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// The step after Newton products that reached degree m without a stop: the
+// next product, two of them when the degree bound leaves room for both.
+__device__ __forceinline__ int next_products(const BatchArgs& B, int m) {
+    return (B.pairs && m + 2 <= B.m_max) ? PH_PAIR : PH_NEWTON;
 }
 
 // Combine an instance's tile partials in index order and advance its state.
@@ -316,8 +541,57 @@ __device__ int finalize_instance(const BatchArgs& B, int inst) {
                 S->status = 1;
                 S->err_max = fmax(S->err_max, err);
             } else {
-                next = PH_NEWTON;
+                next = next_products(B, m);
                 S->j = m;
+            }
+            // w_1 went to w0, a later product to the buffer it did not read
+            S->wb = (phase == PH_FIRST) ? 0 : (S->wb ^ 1);
+            S->phase = next;
+        }
+    } else if (phase == PH_PAIR) {
+        // the two-term test after each product of the pair, as two single
+        // steps would apply it: at m = j+1 (a stop there leaves the second
+        // product's term in p, which the update takes back out), else at
+        // m = j+2
+        __shared__ double red4[kPersistWaves][4];
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = threadIdx.x; t < I.ntiles; t += blockDim.x) {
+            const double* q = B.partials + 4 * (size_t)(I.part_off + t);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] += q[k];
+        }
+        block_sum4(v, red4);
+        if (threadIdx.x == 0) {
+            const int j = S->j;
+            const double w1n = sqrt(v[0]), p1n = sqrt(v[1]), w2n = sqrt(v[2]), p2n = sqrt(v[3]);
+            const double d2 = B.dd[I.dd_off + j + 2];
+            const double t1 = fabs(B.dd[I.dd_off + j + 1]) * w1n, t2 = fabs(d2) * w2n;
+            const double tprev = S->t_prev;
+            auto rel = [](double num, double pn) { return (pn > 0.0) ? num / pn : (num == 0.0 ? 0.0 : INFINITY); };
+            S->newton += 2;
+            S->wb ^= 1;
+            if (!isfinite(w1n) || !isfinite(p1n) || !isfinite(w2n) || !isfinite(p2n) || !isfinite(tprev)) {
+                next = PH_FAILED;
+                S->status = 2;
+            } else if (tprev + t1 <= B.tol * p1n) {   // m = j+1 >= 2
+                S->degree_last = j + 1;
+                S->degree_max = max(S->degree_max, j + 1);
+                S->err_max = fmax(S->err_max, rel(tprev + t1, p1n));
+                S->fix = d2;
+                next = PH_UPDATE;
+            } else if (t1 + t2 <= B.tol * p2n) {
+                S->degree_last = j + 2;
+                S->degree_max = max(S->degree_max, j + 2);
+                S->err_max = fmax(S->err_max, rel(t1 + t2, p2n));
+                next = PH_UPDATE;
+            } else if (j + 2 >= B.m_max) {
+                next = PH_FAILED;
+                S->status = 1;
+                S->err_max = fmax(S->err_max, rel(t1 + t2, p2n));
+            } else {
+                S->t_prev = t2;
+                S->j = j + 2;
+                next = next_products(B, j + 2);
             }
             S->phase = next;
         }
@@ -329,6 +603,7 @@ __device__ int finalize_instance(const BatchArgs& B, int inst) {
             const int l = S->l + 1;
             S->l = l;
             S->j = 0;
+            S->fix = 0.0;
             next = (l < I.s) ? PH_START : PH_DONE;
         }
         S->phase = next;
@@ -426,10 +701,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B
     // the auxiliary kernel of a round without auxiliary steps returns at
     // once (the flag is set by the previous round's stop tests and cleared
     // by the hot kernel that follows; kernel boundaries order the three)
-    if (SET == SET_AUX && B.ctrl->aux_next == 0) return;
+    constexpr bool kHot = (SET == SET_HOT || SET == SET_PAIR);
+    if (!kHot && B.ctrl->aux_next == 0) return;
     // a round counts when some instance is unfinished at its start (the
     // count changes only in the finalize kernel that ends the round)
-    if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (kHot && blockIdx.x == 0 && threadIdx.x == 0) {
         B.ctrl->rounds += 1;
         B.ctrl->aux_next = 0;
     }
@@ -440,7 +716,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B
     nact = __builtin_amdgcn_readfirstlane(nact);
     total = __builtin_amdgcn_readfirstlane(total);
     if (nact == 0) return;
-    if (SET == SET_HOT && blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->hot_rounds += 1;
+    if (kHot && blockIdx.x == 0 && threadIdx.x == 0) B.ctrl->hot_rounds += 1;
     // Grid-stride order over the XCD-major logical wave index: in each pass
     // the waves together take G consecutive tiles and every XCD a contiguous
     // block of them, so tiles that share halo rows and DRAM pages run at the
@@ -480,8 +756,12 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs B) {
     const int next = finalize_instance(B, inst);
     if (threadIdx.x == 0) {
         if (!active_phase(next)) atomicAdd(&B.ctrl->finished, 1u);
-        // (a first product made here follows a start vector: l >= 1, hot)
-        if (next == PH_START || next == PH_UPDATE) B.ctrl->aux_next = 1;
+        // (a first product made here follows a start vector: l >= 1, hot
+        // with one product per round; with two, every step but a pair is
+        // auxiliary)
+        if (next == PH_START || next == PH_UPDATE ||
+            (B.pairs && active_phase(next) && next != PH_PAIR))
+            B.ctrl->aux_next = 1;
     }
 }
 
@@ -553,6 +833,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct Batch {
     int last_rounds = 0;   // rounds the last eager solve needed (0: none yet)
     int count, dtype, bc, m_max, waves, march;
+    int pairs = 1;                // Newton products two per round (expi_batch_set_pairs)
     double c0, tol;
     std::vector<BatchInfo> info;
     std::vector<double> dd;       // count x (m_max + 1)
@@ -643,18 +924,27 @@ BatchArgs make_args(const Batch& b, char* ws, const double* v, double* y) {
     a.march = b.march;
     a.max_rounds = b.max_rounds;
     a.bc = b.bc;
+    a.pairs = b.pairs;
     a.c0 = b.c0;
     a.tol = b.tol;
     a.deadline_ticks = b.deadline_ticks;
     return a;
 }
 
-const void* tiles_kernel(const Batch& b, int set) {
-    if (b.dtype == EXPI_F32)
-        return set == SET_HOT ? reinterpret_cast<const void*>(batch_tiles_kernel<float, SET_HOT>)
-                              : reinterpret_cast<const void*>(batch_tiles_kernel<float, SET_AUX>);
-    return set == SET_HOT ? reinterpret_cast<const void*>(batch_tiles_kernel<double, SET_HOT>)
-                          : reinterpret_cast<const void*>(batch_tiles_kernel<double, SET_AUX>);
+// The kernel of a round's hot steps (hot = true) or of the others, for the
+// batch's storage type and products per round.
+template <class TW>
+const void* tiles_kernel_t(bool pairs, bool hot) {
+    if (pairs)
+        return hot ? reinterpret_cast<const void*>(batch_tiles_kernel<TW, SET_PAIR>)
+                   : reinterpret_cast<const void*>(batch_tiles_kernel<TW, SET_REST>);
+    return hot ? reinterpret_cast<const void*>(batch_tiles_kernel<TW, SET_HOT>)
+               : reinterpret_cast<const void*>(batch_tiles_kernel<TW, SET_AUX>);
+}
+
+const void* tiles_kernel(const Batch& b, bool hot) {
+    return b.dtype == EXPI_F32 ? tiles_kernel_t<float>(b.pairs != 0, hot)
+                               : tiles_kernel_t<double>(b.pairs != 0, hot);
 }
 
 // The persistent kernel needs every workgroup resident at once.  The grid
@@ -678,7 +968,7 @@ int occupancy_grid(Batch& b) {
     // once (occupancy of the hot kernel), a multiple of the XCD count, no
     // more than the batch has tiles
     int per_hot = 0;
-    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_hot, tiles_kernel(b, SET_HOT), 64 * b.waves,
+    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_hot, tiles_kernel(b, true), 64 * b.waves,
                                                       tiles_lds_bytes(b.count)));
     if (per_hot < 1) return bfail(EXPI_EHIP, "batched tiles kernel cannot be resident");
     const int wgs = (b.total_tiles + b.waves - 1) / b.waves;   // a tile per wave
@@ -709,13 +999,11 @@ constexpr int kRoundChunk = 8;   // rounds enqueued between status read-backs
 // One round: the auxiliary steps, the hot products, then the stop tests.
 hipError_t enqueue_round(const Batch& b, const BatchArgs& a, hipStream_t s) {
     const size_t lds = tiles_lds_bytes(b.count);
-    if (b.dtype == EXPI_F32) {
-        hipLaunchKernelGGL((batch_tiles_kernel<float, SET_AUX>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
-        hipLaunchKernelGGL((batch_tiles_kernel<float, SET_HOT>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
-    } else {
-        hipLaunchKernelGGL((batch_tiles_kernel<double, SET_AUX>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
-        hipLaunchKernelGGL((batch_tiles_kernel<double, SET_HOT>), dim3(b.round_grid), dim3(64 * b.waves), lds, s, a);
-    }
+    void* args[] = {const_cast<BatchArgs*>(&a)};
+    hipError_t e = hipLaunchKernel(tiles_kernel(b, false), dim3(b.round_grid), dim3(64 * b.waves), args, lds, s);
+    if (e == hipSuccess)
+        e = hipLaunchKernel(tiles_kernel(b, true), dim3(b.round_grid), dim3(64 * b.waves), args, lds, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(b.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -785,13 +1073,13 @@ int build_round_graph(Batch& b, char* ws, const double* v, double* y, int rounds
     hipError_t e = hipGraphAddKernelNode(&prev, g, nullptr, 0, &k0);
     void* pa[] = {&a};
     hipKernelNodeParams kx{};
-    kx.func = const_cast<void*>(tiles_kernel(b, SET_AUX));
+    kx.func = const_cast<void*>(tiles_kernel(b, false));
     kx.gridDim = dim3(b.round_grid);
     kx.blockDim = dim3(64 * b.waves);
     kx.sharedMemBytes = (unsigned)tiles_lds_bytes(b.count);
     kx.kernelParams = pa;
     hipKernelNodeParams kt = kx;
-    kt.func = const_cast<void*>(tiles_kernel(b, SET_HOT));
+    kt.func = const_cast<void*>(tiles_kernel(b, true));
     hipKernelNodeParams kf{};
     kf.func = reinterpret_cast<void*>(batch_finalize_kernel);
     kf.gridDim = dim3(b.count);
@@ -1108,6 +1396,22 @@ int expi_batch_autotune(expi_batch* bp, const double* v, double* y, void* ws, si
     int rc = expi_batch_set_tiles(bp, best_w, best_m);
     if (rc == EXPI_OK) rc = expi_batch_prepare(bp, ws, ws_bytes, stream);
     return rc;
+}
+
+int expi_batch_set_pairs(expi_batch* bp, int on) {
+    Batch* b = reinterpret_cast<Batch*>(bp);
+    if (!b) return bfail(EXPI_EINVAL, "batch is NULL");
+    if (on != 0 && on != 1) return bfail(EXPI_EINVAL, "on must be 0 or 1");
+    if (b->graph_exec) return bfail(EXPI_EINVAL, "the product setting cannot change after a graph was captured");
+    b->pairs = on;
+    return EXPI_OK;
+}
+
+int expi_batch_get_pairs(const expi_batch* bp, int* on) {
+    const Batch* b = reinterpret_cast<const Batch*>(bp);
+    if (!b || !on) return bfail(EXPI_EINVAL, "NULL argument");
+    *on = b->pairs;
+    return EXPI_OK;
 }
 
 int expi_batch_get_tiles(const expi_batch* bp, int* waves, int* march) {

@@ -2,7 +2,8 @@
 
 Each instance is compared with the oracle on its own: the Leja oracle
 (phi_action on the assembled matrix, same interval) at small sizes, the
-sine-mode closed form at larger ones.  The captured graph is replayed with
+sine-mode closed form at larger ones.  The solver forms two Newton products
+per round by default; one per round is compared too.  The captured graph is replayed with
 eager work in between and every replay is compared with the eager run.
 """
 import numpy as np
@@ -88,12 +89,53 @@ def test_batch_matches_leja_oracle_per_instance(E, dtype, bc):
         assert relerr(got, yo) <= bar, (i, relerr(got, yo))
         assert stats[i]["status"] == 0 and stats[i]["substeps"] == sto.substeps
         if dtype == "f64":
-            # the stop test sees the same norms up to summation order
+            # the stop test sees the same norms up to summation order; a pair
+            # of products that stops after its first one has formed one more
             assert abs(stats[i]["degree_last"] - sto.degrees[-1]) <= 1
-            assert abs(stats[i]["newton_steps"] - sum(sto.degrees)) <= sto.substeps
-    # each round advances every unfinished instance by one step
+            assert -sto.substeps <= stats[i]["newton_steps"] - sum(sto.degrees) <= 2 * sto.substeps
+    # each round advances every unfinished instance by one step of at most
+    # two products
+    assert b.pairs
     longest = max(s["newton_steps"] + 2 * s["substeps"] for s in stats)
-    assert max(s["newton_steps"] for s in stats) <= rounds <= min(longest, b.max_rounds)
+    assert max((s["newton_steps"] + 1) // 2 for s in stats) <= rounds <= min(longest, b.max_rounds)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_pairs_against_single_products(E, dtype):
+    """Two products per round against one per round on the same batch: the
+    same degrees up to one (the stop test sees the same norms up to the
+    order of the sums), products formed at most one more per substep,
+    fewer rounds, and each against the Leja oracle."""
+    import torch
+    nx, ny, hx, hy, tau = batch_case(seed=9, count=14)
+    nx[2], ny[2] = 1024, 3      # rows longer than a tile, few of them
+    nx[3], ny[3] = 2, 200       # two columns: both edge points of the strip
+    hx, hy = 1.0 / (nx + 1.0), 1.0 / (ny + 1.0)
+    tol = 1e-10 if dtype == "f64" else 1e-7
+    bar = TOL_F64 if dtype == "f64" else TOL_F32
+    res = {}
+    for pairs in (False, True):
+        b = E.Batch(nx, ny, hx, hy, tau, tol=tol, dtype=dtype)
+        b.set_pairs(pairs)
+        assert b.pairs == pairs
+        v_all = synth.uniform_vector(b.total_length, 21)
+        y = torch.zeros(b.total_length, dtype=torch.float64, device="cuda:0")
+        b.prepare()
+        print(f"batch pairs={pairs} {dtype}", flush=True)
+        b.launch(T(v_all), y)
+        stats, rounds = b.results()
+        res[pairs] = (N(y), stats, rounds)
+    want = leja_oracle(nx, ny, hx, hy, tau, v_all, b.offsets, "dirichlet0", tol)
+    (y1, st1, r1), (y2, st2, r2) = res[False], res[True]
+    assert r2 < r1
+    for i, (yo, sto) in enumerate(want):
+        sl = slice(int(b.offsets[i]), int(b.offsets[i]) + int(nx[i] * ny[i]))
+        assert relerr(y1[sl], yo) <= bar, (i, relerr(y1[sl], yo))
+        assert relerr(y2[sl], yo) <= bar, (i, relerr(y2[sl], yo))
+        assert abs(st2[i]["degree_last"] - st1[i]["degree_last"]) <= 1
+        assert st1[i]["substeps"] == st2[i]["substeps"]
+        extra = st2[i]["newton_steps"] - st1[i]["newton_steps"]
+        assert -st1[i]["substeps"] <= extra <= 2 * st1[i]["substeps"], (i, extra)
 
 
 def test_batch_coef_and_tiles(E):

@@ -241,6 +241,14 @@ def test_batch_create_validation_and_layout(L):
     assert L.expi_batch_set_tiles(b, 2, 6) == -1
     assert L.expi_batch_set_tiles(b, 2, 16) == 0
     assert L.expi_batch_workspace_bytes(b) == ws_bytes
+    on = ctypes.c_int(-1)
+    assert L.expi_batch_get_pairs(b, ctypes.byref(on)) == 0 and on.value == 1   # two products per round by default
+    assert L.expi_batch_set_pairs(b, 2) == -1
+    assert L.expi_batch_set_pairs(None, 0) == -1
+    assert L.expi_batch_get_pairs(b, None) == -1
+    assert L.expi_batch_set_pairs(b, 0) == 0
+    assert L.expi_batch_get_pairs(b, ctypes.byref(on)) == 0 and on.value == 0
+    assert L.expi_batch_set_pairs(b, 1) == 0
     # substeps from the closed-form interval: s_i = ceil(tau_i 4 (2/h_i^2) / 100)
     s_want = np.maximum(np.ceil(tau * 8.0 / h**2 / 100.0), 1).astype(int)
     assert L.expi_batch_max_rounds(b) == int(s_want.max()) * (100 + 2) + 2
