@@ -209,23 +209,68 @@ struct SetCode {
     static constexpr bool pair = SET == SET_ALL || SET == SET_PAIR;
 };
 
+// Buffer loads and stores of V values of the storage type: the row offset
+// goes in a scalar register, the lane's column offset in a vector register
+// that stays the same along the march (no per-load address arithmetic).
+template <class TW, int V>
+struct Pack {
+    TW v[V];
+};
+
+template <class TW, int V>
+__device__ __forceinline__ void bld(__amdgpu_buffer_rsrc_t r, int voff, int soff, TW (&o)[V]) {
+    constexpr int N = (int)sizeof(TW) * V;
+    Pack<TW, V> p;
+    if constexpr (N == 4)
+        p = __builtin_bit_cast(Pack<TW, V>, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else if constexpr (N == 8)
+        p = __builtin_bit_cast(Pack<TW, V>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        p = __builtin_bit_cast(Pack<TW, V>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = p.v[v];
+}
+
+template <class TW, int V>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, int voff, int soff, const TW (&o)[V]) {
+    constexpr int N = (int)sizeof(TW) * V;
+    Pack<TW, V> p;
+#pragma unroll
+    for (int v = 0; v < V; ++v) p.v[v] = o[v];
+    typedef unsigned U2 __attribute__((ext_vector_type(2)));
+    typedef unsigned U4 __attribute__((ext_vector_type(4)));
+    if constexpr (N == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, p), r, voff, soff, 0);
+    else if constexpr (N == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, p), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, p), r, voff, soff, 0);
+}
+
 // Two consecutive Newton products on one tile (two steps of the Newton
 // recurrence of Sec. III-C): w_{j+1} = alpha A w_j + beta_j w_j, then
 // w_{j+2} = alpha A w_{j+1} + beta_{j+1} w_{j+1}, with
 // p += d_{j+1} w_{j+1} + d_{j+2} w_{j+2}.  w_{j+1} stays in registers: the
 // wave forms it on its strip of 64 V points and on the point just beyond
-// each end of the strip (lane 0 the left one, lane 63 the right one, from
-// one more column of w_j and one point beyond that), on the tile's rows and
-// on the row above and below them; then w_{j+2} and p on the tile.  Each
-// point takes the single product's operations in the same order, with
-// values rounded to the storage type where the single products store them,
-// so the tile's sums are those of two single products.  Per point w_j and p
-// are read once and w_{j+2} and p written once, for two products.  Partials:
-// ||w_{j+1}||^2, ||p_{j+1}||^2, ||w_{j+2}||^2, ||p_{j+2}||^2 over the tile.
+// each end of the strip (lane 0 the left one, lane 63 the right one), on
+// the tile's rows and on the row above and below them; then w_{j+2} and p
+// on the tile.  Per point w_j and p are read once and w_{j+2} and p written
+// once, for two products.  Partials: ||w_{j+1}||^2, ||p_{j+1}||^2,
+// ||w_{j+2}||^2, ||p_{j+2}||^2 over the tile, summed in the order of the
+// single product's sweep.
+//
+// A point's product is written as alpha A w + beta w =
+// sum over faces of (alpha f) w_nb + (beta - alpha sum f) w_c, with face
+// weights f = coef/h^2 (0 for a face towards a neighbour that does not
+// exist, except that under homogeneous Dirichlet conditions such a face
+// still takes its share of the diagonal): one multiply and four fused
+// multiply-adds per point; the x weights are fixed per lane and the y ones
+// per row.
 template <class TW, int V>
 __device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchState& S, int t0, int t1,
                           double* red_partial) {
     using TC = TW;
+    constexpr int sz = (int)sizeof(TW);
     const int lane = threadIdx.x & 63;
     const int n0 = I.nx, n1 = I.ny;
     const int i0 = t0 * 64 * V;
@@ -233,98 +278,120 @@ __device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchSta
     const int kb = t1 * B.march, ke = min(kb + B.march, n1);
     const bool active = i < n0;
     const int ic = active ? i : (n0 - V);
-    // the point beyond the strip at which this lane forms w_{j+1} (lanes 0
-    // and 63; the others repeat a point of their own), and the w_j point
-    // beyond that one
+    // the point beyond the strip at which lane 0 (63) forms w_{j+1}, and the
+    // w_j point beyond that one, which lane 1 (62) loads in the same load
+    // and hands over
     const int xe = (lane == 0) ? i0 - 1 : (lane == 63 ? i0 + 64 * V : ic);
-    const int xf = (lane == 0) ? i0 - 2 : (lane == 63 ? i0 + 64 * V + 1 : ic);
-    const int xec = min(max(xe, 0), n0 - 1), xfc = min(max(xf, 0), n0 - 1);
+    const int xg = (lane == 1) ? i0 - 2 : (lane == 62 ? i0 + 64 * V + 1 : xe);
+    const int gsrc = (lane == 0) ? 1 : (lane == 63 ? 62 : lane);
+    const int nbytes = n0 * n1 * sz;
+    const TW* w = static_cast<const TW*>(S.wb ? B.w1 : B.w0) + I.off;
+    TW* out = static_cast<TW*>(S.wb ? B.w0 : B.w1) + I.off;
+    TW* pp = static_cast<TW*>(B.p) + I.off;
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(const_cast<TW*>(w), 0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(out, 0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(pp, 0, nbytes, 0x00020000);
+    const int vo = ic * sz;                                  // the lane's points
+    const int vg = min(max(xg, 0), n0 - 1) * sz;             // its point beyond the strip
+    // every load is from a row clamped into the grid; values of rows and
+    // columns that do not exist get weight 0
+    auto roff = [&](int k) { return n0 * min(max(k, 0), n1 - 1) * sz; };
+    auto g_load = [&](int k) -> TC {
+        TC t[1];
+        bld<TW, 1>(rw, vg, roff(k), t);
+        return t[0];
+    };
     const bool dir = (B.bc == EXPI_DIRICHLET0);
-    const TC ihx = (TC)I.ihx, ihy = (TC)I.ihy, c0 = (TC)B.c0;
     const TC alpha = (TC)I.alpha;
     const int j = S.j;
     const TC beta1 = (TC)(-(I.cg + B.xi[j])), beta2 = (TC)(-(I.cg + B.xi[j + 1]));
     const TC d1 = (TC)B.dd[I.dd_off + j + 1], d2 = (TC)B.dd[I.dd_off + j + 2];
-    const TW* __restrict__ w = static_cast<const TW*>(S.wb ? B.w1 : B.w0) + I.off;
-    TW* __restrict__ out = static_cast<TW*>(S.wb ? B.w0 : B.w1) + I.off;
-    TW* __restrict__ pp = static_cast<TW*>(B.p) + I.off;
-    // every load is from a row clamped into the grid; values of rows and
-    // columns that do not exist are masked by the existence flags
-    auto row = [&](int k) { return n0 * min(max(k, 0), n1 - 1); };
-    // one point of alpha A w + beta w, as the single product forms it
-    auto prod = [&](TC wl, TC wr, TC wm, TC wq, TC wc, bool exm, bool exq, bool ezm, bool ezq,
-                    TC beta) -> TC {
-        const TC fxm = face_weight<TC>(exm, dir, c0, c0) * ihx;
-        const TC fxq = face_weight<TC>(exq, dir, c0, c0) * ihx;
-        const TC fzm = face_weight<TC>(ezm, dir, c0, c0) * ihy;
-        const TC fzq = face_weight<TC>(ezq, dir, c0, c0) * ihy;
-        const TC l = exm ? wl : (TC)0, r = exq ? wr : (TC)0;
-        const TC m = ezm ? wm : (TC)0, q = ezq ? wq : (TC)0;
-        const TC Aw = fxm * (l - wc) + fxq * (r - wc) + fzm * (m - wc) + fzq * (q - wc);
-        return (TC)(TW)(alpha * Aw + beta * wc);
+    const TC fx = (TC)(B.c0 * I.ihx), fy = (TC)(B.c0 * I.ihy);
+    // x weights: alpha f of the two x faces of each of the lane's points and
+    // of its point beyond the strip, and alpha times the x part of the
+    // diagonal
+    TC axm[V + 1], axq[V + 1], adx[V + 1];
+#pragma unroll
+    for (int v = 0; v <= V; ++v) {
+        const int x = (v < V) ? i + v : xe;
+        const bool em = x > 0, eq = x < n0 - 1;
+        axm[v] = em ? alpha * fx : (TC)0;
+        axq[v] = eq ? alpha * fx : (TC)0;
+        adx[v] = alpha * (((em || dir) ? fx : (TC)0) + ((eq || dir) ? fx : (TC)0));
+    }
+    // y weights of row q: alpha f of its two faces and the diagonal
+    // coefficient beta - alpha sum f without the x part
+    auto yw = [&](int q, TC beta, TC& aym, TC& ayq, TC& cdy) {
+        const bool em = q > 0, eq = q < n1 - 1;
+        aym = em ? alpha * fy : (TC)0;
+        ayq = eq ? alpha * fy : (TC)0;
+        cdy = beta - alpha * (((em || dir) ? fy : (TC)0) + ((eq || dir) ? fy : (TC)0));
+    };
+    auto prod = [&](int v, TC wl, TC wr, TC wm, TC wq, TC wc, TC aym, TC ayq, TC cdy) -> TC {
+        return axm[v] * wl + axq[v] * wr + aym * wm + ayq * wq + (cdy - adx[v]) * wc;
     };
     // w_{j+1} on row q of the strip (u) and at the lane's point beyond it
-    // (ue), from w_j rows q-1, q, q+1 (wm, wc, wq; em, ec, eq at column xe)
-    // and the far point ef of row q
-    auto form_u = [&](const TC (&wm)[V], const TC (&wc)[V], const TC (&wq)[V], TC em, TC ec, TC eq, TC ef,
-                      int q, TC (&u)[V], TC& ue) {
-        const bool ezm = q > 0, ezq = q < n1 - 1;
+    // (ue), from w_j rows q-1, q, q+1 (wm, wc, wq), the beyond-strip values
+    // of those rows (gm, gc, gq) and the farther point of row q (in gc of
+    // the neighbouring lane)
+    auto form_u = [&](const TC (&wm)[V], const TC (&wc)[V], const TC (&wq)[V], TC gm, TC gc, TC gq, int q,
+                      TC (&u)[V], TC& ue) {
+        TC aym, ayq, cdy;
+        yw(q, beta1, aym, ayq, cdy);
         TC left = __shfl_up(wc[V - 1], 1, 64);
         TC right = __shfl_down(wc[0], 1, 64);
-        if (lane == 0) left = ec;
-        if (lane == 63) right = ec;
+        const TC far = __shfl(gc, gsrc, 64);
+        if (lane == 0) left = gc;
+        if (lane == 63) right = gc;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const int iv = i + v;
             const TC wl = (v > 0) ? wc[v - 1] : left;
             const TC wr = (v < V - 1) ? wc[v + 1] : right;
-            u[v] = prod(wl, wr, wm[v], wq[v], wc[v], iv > 0, iv < n0 - 1, ezm, ezq, beta1);
+            u[v] = (TC)(TW)prod(v, wl, wr, wm[v], wq[v], wc[v], aym, ayq, cdy);
         }
-        const TC el = (lane == 63) ? wc[V - 1] : ef;
-        const TC er = (lane == 63) ? ef : wc[0];
-        ue = prod(el, er, em, eq, ec, xe > 0, xe < n0 - 1, ezm, ezq, beta1);
+        const TC el = (lane == 63) ? wc[V - 1] : far;
+        const TC er = (lane == 63) ? far : wc[0];
+        ue = (TC)(TW)prod(V, el, er, gm, gq, gc, aym, ayq, cdy);
     };
-    // w_j rows k .. k+3 (W0..W3, column xe: E0..E3), far points of rows k+1,
-    // k+2 (F1, F2); w_{j+1} rows k-1 .. k (U0, U1; Ue0, Ue1); p rows k, k+1
+    // w_j rows k .. k+3 (W0..W3) and their beyond-strip values (G0..G3);
+    // w_{j+1} rows k-1, k (U0, U1) and row k beyond the strip (Ue1); p rows
+    // k, k+1
     TC W0[V], W1[V], W2[V], W3[V], U0[V], U1[V], P0[V], P1[V];
-    TC E0, E1, E2, E3, F1, F2, Ue1;
+    TC G0, G1, G2, G3, Ue1;
     {
         TC Wa[V], Wb[V];
-        tile::vld<V>(w, row(kb - 2) + ic, Wa);
-        tile::vld<V>(w, row(kb - 1) + ic, Wb);
-        tile::vld<V>(w, row(kb) + ic, W0);
-        tile::vld<V>(w, row(kb + 1) + ic, W1);
-        tile::vld<V>(w, row(kb + 2) + ic, W2);
-        tile::vld<V>(w, row(kb + 3) + ic, W3);
-        const TC Ea = (TC)w[row(kb - 2) + xec], Eb = (TC)w[row(kb - 1) + xec];
-        E0 = (TC)w[row(kb) + xec];
-        E1 = (TC)w[row(kb + 1) + xec];
-        E2 = (TC)w[row(kb + 2) + xec];
-        E3 = (TC)w[row(kb + 3) + xec];
-        const TC Fa = (TC)w[row(kb - 1) + xfc], Fb = (TC)w[row(kb) + xfc];
-        F1 = (TC)w[row(kb + 1) + xfc];
-        F2 = (TC)w[row(kb + 2) + xfc];
-        tile::vld<V>(pp, row(kb) + ic, P0);
-        tile::vld<V>(pp, row(kb + 1) + ic, P1);
+        bld<TW, V>(rw, vo, roff(kb - 2), Wa);
+        bld<TW, V>(rw, vo, roff(kb - 1), Wb);
+        bld<TW, V>(rw, vo, roff(kb), W0);
+        bld<TW, V>(rw, vo, roff(kb + 1), W1);
+        bld<TW, V>(rw, vo, roff(kb + 2), W2);
+        bld<TW, V>(rw, vo, roff(kb + 3), W3);
+        const TC Ga = g_load(kb - 2), Gb = g_load(kb - 1);
+        G0 = g_load(kb);
+        G1 = g_load(kb + 1);
+        G2 = g_load(kb + 2);
+        G3 = g_load(kb + 3);
+        bld<TW, V>(rp, vo, roff(kb), P0);
+        bld<TW, V>(rp, vo, roff(kb + 1), P1);
         TC Ue0;   // (w_{j+2} needs w_{j+1} beyond the strip on its own row only)
-        form_u(Wa, Wb, W0, Ea, Eb, E0, Fa, kb - 1, U0, Ue0);
-        form_u(Wb, W0, W1, Eb, E0, E1, Fb, kb, U1, Ue1);
+        form_u(Wa, Wb, W0, Ga, Gb, G0, kb - 1, U0, Ue0);
+        form_u(Wb, W0, W1, Gb, G0, G1, kb, U1, Ue1);
     }
     double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int k = kb; k < ke; ++k) {
         // loads two rows ahead of their first use
         TC Wn[V], Pn[V];
-        tile::vld<V>(w, row(k + 4) + ic, Wn);
-        const TC En = (TC)w[row(k + 4) + xec];
-        const TC Fn = (TC)w[row(k + 3) + xfc];
-        tile::vld<V>(pp, row(k + 2) + ic, Pn);
+        bld<TW, V>(rw, vo, roff(k + 4), Wn);
+        const TC Gn = g_load(k + 4);
+        bld<TW, V>(rp, vo, roff(k + 2), Pn);
         // w_{j+1} on row k+1
         TC U2[V], Ue2;
-        form_u(W0, W1, W2, E0, E1, E2, F1, k + 1, U2, Ue2);
+        form_u(W0, W1, W2, G0, G1, G2, k + 1, U2, Ue2);
         // w_{j+2} and p on row k
         {
-            const bool ezm = k > 0, ezq = k < n1 - 1;
+            TC aym, ayq, cdy;
+            yw(k, beta2, aym, ayq, cdy);
             TC left = __shfl_up(U1[V - 1], 1, 64);
             TC right = __shfl_down(U1[0], 1, 64);
             if (lane == 0) left = Ue1;
@@ -332,10 +399,9 @@ __device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchSta
             TC wo[V], po[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int iv = i + v;
                 const TC wl = (v > 0) ? U1[v - 1] : left;
                 const TC wr = (v < V - 1) ? U1[v + 1] : right;
-                const TC u2 = prod(wl, wr, U0[v], U2[v], U1[v], iv > 0, iv < n0 - 1, ezm, ezq, beta2);
+                const TC u2 = (TC)(TW)prod(v, wl, wr, U0[v], U2[v], U1[v], aym, ayq, cdy);
                 const TC p1 = (TC)(TW)(P0[v] + d1 * U1[v]);
                 const TC p2 = (TC)(TW)(p1 + d2 * u2);
                 wo[v] = u2;
@@ -347,10 +413,10 @@ __device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchSta
                     s[3] += (double)p2 * (double)p2;
                 }
             }
-            if (active) {
-                tile::vst<V>(out, n0 * k + i, wo);
-                tile::vst<V>(pp, n0 * k + i, po);
-            }
+            // lanes past the row end store past the buffer (dropped)
+            const int vs = active ? vo : nbytes;
+            bst<TW, V>(ro, vs, roff(k), wo);
+            bst<TW, V>(rp, vs, roff(k), po);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -363,12 +429,10 @@ __device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchSta
             P0[v] = P1[v];
             P1[v] = Pn[v];
         }
-        E0 = E1;
-        E1 = E2;
-        E2 = E3;
-        E3 = En;
-        F1 = F2;
-        F2 = Fn;
+        G0 = G1;
+        G1 = G2;
+        G2 = G3;
+        G3 = Gn;
         Ue1 = Ue2;
     }
 #pragma unroll
@@ -723,7 +787,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void batch_tiles_kernel(BatchArgs B
     // same time on the same L2.  Each wave goes through its tiles alone.
     const int nw = blockDim.x >> 6;
     const int G = gridDim.x * nw;
-    const int L = xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6);
+    // (the same in every lane of a wave: saying so keeps the tile indices,
+    // rows and row offsets in scalar registers)
+    const int L = __builtin_amdgcn_readfirstlane(xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6));
     if (L >= total) return;
     int q = __builtin_amdgcn_readfirstlane(find_instance(s_pref, nact, L));
     int inst = __builtin_amdgcn_readfirstlane(s_ids[q]);
@@ -784,7 +850,8 @@ __global__ __launch_bounds__(kPersistWaves * 64) void batch_kernel(BatchArgs B) 
         const int nw = blockDim.x >> 6;
         const int G = gridDim.x * nw;
         int q = -1, inst = 0, base = 0, next = 0;
-        for (int t = xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6); t < total; t += G) {
+        const int t_first = __builtin_amdgcn_readfirstlane(xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6));
+        for (int t = t_first; t < total; t += G) {
             if (q < 0 || t >= next) {
                 q = __builtin_amdgcn_readfirstlane(find_instance(s_pref, nact, t));
                 inst = __builtin_amdgcn_readfirstlane(s_ids[q]);
