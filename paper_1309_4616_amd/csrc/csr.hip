@@ -29,58 +29,96 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
     // grid-stride over row blocks in XCD-major order: in each pass the
     // workgroups of one XCD take a contiguous run of rows (the gathered
     // entries of neighbouring rows then meet in that XCD's L2), and the grid
-    // stays small enough for a short finalize
-    // each pass loads the next pass's row pointers ahead of its own entries
-    // (clamped to a row that exists, unconditionally), so that they are not
-    // a memory round trip of their own at the head of every pass
+    // stays small enough for a short finalize.
+    // Software pipeline: a pass finds its own entries (column indices and
+    // values) and the next pass's row pointers already in registers; it
+    // issues its gathers first and then the loads of the next pass's
+    // entries and of the row pointers of the pass after that, so waiting
+    // for the gathers (the memory counter retires in order) never waits for
+    // those streaming loads, and they are in flight while the pass
+    // computes.  Row indices are clamped into the matrix (unconditional
+    // loads).
     const int nrow = a.n[0];
+    const unsigned nrows = (unsigned)nrow;
+    // an empty matrix may come without entry arrays: its entry loads then
+    // read the first row pointers instead (valid memory, values unused), so
+    // that no load sits in a branch (the compiler would then wait for every
+    // load in flight where the branches meet)
+    const bool any = a.nnz > 0;
+    const int* __restrict__ ci = any ? a.colind : a.rowptr;
+    const double* __restrict__ va = any ? a.val : reinterpret_cast<const double*>(a.rowptr);
+    constexpr bool kStaged = (EPI != EPI_GERSH);
+    constexpr int kStage = 2048 / G;   // 32 entries per row of the wave
+    constexpr int kQ = kStage / 64;
+    const int lane = threadIdx.x & 63;
     int L = xcd_tile(a.per_xcd);
-    int pa = 0, pb = 0;
-    if (nrow > 0) {
-        const int r = min(L * rows_per + g, nrow - 1);
-        pa = a.rowptr[r];
-        pb = a.rowptr[r + 1];
+    auto rp_load = [&](int Lx, int& pa_, int& pb_) {
+        const int r = min(min(Lx, a.ntiles - 1) * rows_per + g, nrow - 1);
+        pa_ = a.rowptr[r];
+        pb_ = a.rowptr[r + 1];
+    };
+    // the wave's rows own the contiguous entries [wb, we): every lane takes
+    // consecutive ones, so each index, value and gather instruction covers
+    // 64 consecutive entries (clamped to the last one: no branch)
+    auto ent_load = [&](int pa_, int pb_, int (&col_)[kQ], TC (&vv_)[kQ]) {
+        const int wb_ = __shfl(max(pa_, 0), 0), we_ = __shfl(min(pb_, a.nnz), 63);
+        const int lastw = max(we_ - 1, 0);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int e = min(wb_ + lane + 64 * q, lastw);
+            col_[q] = ci[e];
+            vv_[q] = (TC)va[e];
+        }
+    };
+    int pa = 0, pb = 0, pa1 = 0, pb1 = 0;
+    int col[kQ];
+    TC vv[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        col[q] = 0;
+        vv[q] = 0;
+    }
+    if (nrow > 0 && L < a.ntiles) {
+        rp_load(L, pa, pb);
+        rp_load(L + (int)gridDim.x, pa1, pb1);
+        if (kStaged) ent_load(pa, pb, col, vv);
     }
     for (; L < a.ntiles; L += gridDim.x) {
     const int row = L * rows_per + g;
     // row range clamped to [0, nnz) and column indices checked against n, so
     // a malformed matrix cannot send a load out of bounds
     const int e0 = max(pa, 0), e1 = min(pb, a.nnz);
-    {
-        const int rn = min(min(L + (int)gridDim.x, a.ntiles - 1) * rows_per + g, nrow - 1);
-        pa = a.rowptr[rn];
-        pb = a.rowptr[rn + 1];
-    }
-    const unsigned nrows = (unsigned)nrow;
-    // Products of the wave's rows (contiguous entries [wb, we)), staged in
-    // LDS: every lane of the wave takes consecutive entries, so each index,
-    // value and gather instruction covers 64 consecutive entries; the G
-    // lanes of a row then sum its products from LDS.  Entries past the
-    // first kStage of the wave are taken directly by the row's lanes.
-    TC acc = 0;
+    // the row's own entry of x (and of p) for the epilogue, loaded ahead of
+    // the gathers (it does not depend on them)
+    TC wc_row = 0, p_row = 0;
     if (EPI != EPI_GERSH) {
-        constexpr int kStage = 2048 / G;   // 32 entries per row of the wave
+        const int rc = min(row, nrow - 1);
+        wc_row = (TC)x[rc];
+        if (EPI == EPI_NEWTON) p_row = (TC)p[rc];
+    }
+    // Products of the wave's rows, staged in LDS; the G lanes of a row then
+    // sum its products from there.  Entries past the first kStage of the
+    // wave are taken directly by the row's lanes.
+    TC acc = 0;
+    int pa2 = 0, pb2 = 0;
+    if (kStaged) {
         __shared__ TC stage[kMaxWaves][kStage];
         TC* st = stage[threadIdx.x >> 6];
-        const int lane = threadIdx.x & 63;
         const int wb = __shfl(e0, 0), we = __shfl(e1, 63);
-        const int lastw = max(we - 1, 0);
-        const bool any = a.nnz > 0;   // an empty matrix may come without arrays
-        constexpr int kQ = kStage / 64;
-        int col[kQ];
-        TC vv[kQ], xv[kQ];
+        TC xv[kQ];
+        bool ok[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-            const int e = min(wb + lane + 64 * q, lastw);   // clamped: no branch
-            col[q] = any ? a.colind[e] : 0;
-            vv[q] = any ? (TC)a.val[e] : (TC)0;
+            ok[q] = (wb + lane + 64 * q < we) && ((unsigned)col[q] < nrows);
+            xv[q] = (TC)x[ok[q] ? col[q] : 0];
         }
+        // streaming loads for the passes ahead, issued after the gathers
+        int coln[kQ];
+        TC vvn[kQ];
+        ent_load(pa1, pb1, coln, vvn);
+        rp_load(L + 2 * (int)gridDim.x, pa2, pb2);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const bool ok = (wb + lane + 64 * q < we) && ((unsigned)col[q] < nrows);
-            xv[q] = (TC)x[ok ? col[q] : 0];
-            st[lane + 64 * q] = ok ? vv[q] * xv[q] : (TC)0;
-        }
+        for (int q = 0; q < kQ; ++q) st[lane + 64 * q] = ok[q] ? vv[q] * xv[q] : (TC)0;
         // the same wave reads what it wrote: LDS operations of a wave
         // complete in order; the fences keep the compiler from moving them
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -98,8 +136,42 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            col[q] = coln[q];
+            vv[q] = vvn[q];
+        }
+    } else {
+        rp_load(L + 2 * (int)gridDim.x, pa2, pb2);
     }
-    if (row < nrow) {
+    pa = pa1;
+    pb = pb1;
+    pa1 = pa2;
+    pb1 = pb2;
+    if (EPI == EPI_NEWTON || EPI == EPI_FIRST) {
+        // The Newton epilogues without a branch around their stores (the
+        // compiler would otherwise wait, at the head of the next pass, for
+        // every load in flight, the streaming ones included): after the
+        // butterfly every lane of the row's group holds the row's sum, and
+        // all of them store the same values; rows past the matrix (last
+        // pass) store into the unused fourth word of this workgroup's
+        // partials.  The norms count the first lane of each row.
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+        const bool own = row < nrow;
+        const TC wc = wc_row;
+        const TC alpha = (TC)a.alpha, beta = (TC)a.beta;
+        const TOUT wn = (TOUT)(alpha * acc + beta * wc);
+        const TOUT pn = (EPI == EPI_NEWTON) ? (TOUT)(p_row + (TC)a.d1 * (TC)wn)
+                                            : (TOUT)((TC)a.d0 * wc + (TC)a.d1 * (TC)wn);
+        TOUT* spare = reinterpret_cast<TOUT*>(a.partials + 4 * (size_t)blockIdx.x + 3);
+        *(own ? out + row : spare) = wn;
+        *(own ? p + row : spare) = pn;
+        const bool first = own && sub == 0;
+        if (EPI == EPI_FIRST) s0 += first ? (double)wc * (double)wc : 0.0;
+        s1 += first ? (double)wn * (double)wn : 0.0;
+        s2 += first ? (double)pn * (double)pn : 0.0;
+    } else if (row < nrow) {
         if (EPI == EPI_GERSH) {
             double dg = 0.0, off = 0.0;
             for (int e = e0 + sub; e < e1; e += G) {
@@ -119,25 +191,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) void csr_sweep(SweepArgs a) {
 #pragma unroll
             for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
             if (sub == 0) {
-                const TC wc = (TC)x[row];
+                const TC wc = wc_row;
                 const TC alpha = (TC)a.alpha, beta = (TC)a.beta;
                 if (EPI == EPI_APPLY) {
                     out[row] = (TOUT)(alpha * acc + beta * wc);
-                } else if (EPI == EPI_NEWTON) {
-                    const TOUT wn = (TOUT)(alpha * acc + beta * wc);
-                    const TOUT pn = (TOUT)((TC)p[row] + (TC)a.d1 * (TC)wn);
-                    out[row] = wn;
-                    p[row] = pn;
-                    s1 += (double)wn * (double)wn;
-                    s2 += (double)pn * (double)pn;
-                } else if (EPI == EPI_FIRST) {
-                    const TOUT wn = (TOUT)(alpha * acc + beta * wc);
-                    const TOUT pn = (TOUT)((TC)a.d0 * wc + (TC)a.d1 * (TC)wn);
-                    out[row] = wn;
-                    p[row] = pn;
-                    s0 += (double)wc * (double)wc;
-                    s1 += (double)wn * (double)wn;
-                    s2 += (double)pn * (double)pn;
                 } else if (EPI == EPI_START) {
                     TC gv;
                     if (a.gmode == G_VEC) {
