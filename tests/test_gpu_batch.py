@@ -138,6 +138,42 @@ def test_batch_pairs_against_single_products(E, dtype):
         assert -st1[i]["substeps"] <= extra <= 2 * st1[i]["substeps"], (i, extra)
 
 
+def test_batch_degree_bound_with_pairs(E):
+    """m_max = 12 with two products per round: pairs while j + 2 <= m_max,
+    then one single product to m = 12.  Instances whose degree (oracle, same
+    tol) is at most 11 converge and match the oracle; those needing 14 or
+    more report EXPI_ENOTCONV after exactly m_max products; the same with
+    one product per round."""
+    import torch
+    nx, ny, hx, hy, tau = batch_case(seed=9, count=14)
+    res = {}
+    for pairs in (True, False):
+        b = E.Batch(nx, ny, hx, hy, tau, tol=1e-10, dtype="f64", params=E.LejaParams(m_max=12))
+        b.set_pairs(pairs)
+        v_all = synth.uniform_vector(b.total_length, 21)
+        y = torch.zeros(b.total_length, dtype=torch.float64, device="cuda:0")
+        b.prepare()
+        print(f"batch m_max 12 pairs={pairs}", flush=True)
+        b.launch(T(v_all), y)
+        stats, _ = b.results(check_status=False)
+        res[pairs] = (N(y), stats)
+    want = leja_oracle(nx, ny, hx, hy, tau, v_all, b.offsets, "dirichlet0", 1e-10)
+    n_ok = n_fail = 0
+    for pairs, (yy, stats) in res.items():
+        for i, (yo, sto) in enumerate(want):
+            st = stats[i]
+            if sto.substeps == 1 and sto.degrees[0] <= 11:
+                sl = slice(int(b.offsets[i]), int(b.offsets[i]) + int(nx[i] * ny[i]))
+                assert st["status"] == 0 and st["degree_max"] <= 12, (pairs, i, st)
+                assert relerr(yy[sl], yo) <= TOL_F64, (pairs, i, relerr(yy[sl], yo))
+                n_ok += 1
+            elif min(sto.degrees) >= 14:
+                assert st["status"] == -4, (pairs, i, st)       # EXPI_ENOTCONV
+                assert st["newton_steps"] == 12, (pairs, i, st)  # the first substep stops at m_max
+                n_fail += 1
+    assert n_ok >= 4 and n_fail >= 16
+
+
 def test_batch_coef_and_tiles(E):
     """A non-unit coefficient and several tile settings give the oracle's result."""
     nx, ny, hx, hy, tau = batch_case(seed=5, count=7)
