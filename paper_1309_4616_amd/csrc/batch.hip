@@ -231,6 +231,12 @@ __device__ __forceinline__ void bld(__amdgpu_buffer_rsrc_t r, int voff, int soff
     for (int v = 0; v < V; ++v) o[v] = p.v[v];
 }
 
+//
+// Stores are at most 8 bytes wide: the compiler has been seen to write the
+// data registers of a 16-byte buffer store in the very next instruction,
+// without the wait state such a store needs before its data registers are
+// overwritten, and the store then wrote the new value for some lanes (FP64
+// pair tiles, the first double of the lane's two).
 template <class TW, int V>
 __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, int voff, int soff, const TW (&o)[V]) {
     constexpr int N = (int)sizeof(TW) * V;
@@ -238,13 +244,18 @@ __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, int voff, int soff
 #pragma unroll
     for (int v = 0; v < V; ++v) p.v[v] = o[v];
     typedef unsigned U2 __attribute__((ext_vector_type(2)));
-    typedef unsigned U4 __attribute__((ext_vector_type(4)));
-    if constexpr (N == 4)
+    if constexpr (N == 4) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, p), r, voff, soff, 0);
-    else if constexpr (N == 8)
+    } else if constexpr (N == 8) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, p), r, voff, soff, 0);
-    else
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, p), r, voff, soff, 0);
+    } else {
+        static_assert(N == 16, "two 8-byte halves");
+        Pack<TW, 1> lo, hi;
+        lo.v[0] = o[0];
+        hi.v[0] = o[1];
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, lo), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, hi), r, voff + 8, soff, 0);
+    }
 }
 
 // Two consecutive Newton products on one tile (two steps of the Newton

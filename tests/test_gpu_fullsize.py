@@ -239,17 +239,21 @@ def test_expeuler_256_fused_start_equals_separate(E):
 
 @pytest.mark.slow
 @pytest.mark.timeout(600)
-def test_batched_256_problems_against_sine_modes(E):
+# FP64 bar: the stop test bounds each substep's error by about tol, and the
+# largest instances take up to 85 substeps
+@pytest.mark.parametrize("dtype,tol,bar", [("f32", 1e-8, 5e-6), ("f64", 1e-10, 1e-8)])
+def test_batched_256_problems_against_sine_modes(E, dtype, tol, bar):
     """The batched workload at full size (256 uneven 2D Dirichlet problems,
-    sides 64..1024, FP32 storage, tol 1e-8): every instance against the FP64
-    sine-mode closed form within the FP32 bar, the persistent launch
-    bitwise equal to the rounds."""
+    sides 64..1024; FP32 storage at tol 1e-8, and FP64 at tol 1e-10): every
+    instance against the FP64 sine-mode closed form, the persistent launch
+    bitwise equal to the rounds.  At this size the waves take many tiles
+    each, one after another."""
     import torch
     inst = synth.batched_instances(256, seed=0)
     ns = np.array([it.n for it in inst])
     taus = np.array([it.tau for it in inst])
     h = 1.0 / (ns + 1.0)
-    b = E.Batch(ns, ns, h, h, taus, bc="dirichlet0", tol=1e-8, dtype="f32")
+    b = E.Batch(ns, ns, h, h, taus, bc="dirichlet0", tol=tol, dtype=dtype)
     v_host = np.zeros(b.total_length)
     for i, it in enumerate(inst):
         o = int(b.offsets[i])
@@ -257,7 +261,7 @@ def test_batched_256_problems_against_sine_modes(E):
     v = torch.as_tensor(v_host, device="cuda:0")
     y = torch.zeros_like(v)
     b.prepare()
-    print("batched 256: rounds", flush=True)
+    print(f"batched 256 {dtype}: rounds", flush=True)
     b.launch(v, y)
     stats, rounds = b.results()
     yy = y.cpu().numpy()
@@ -267,7 +271,7 @@ def test_batched_256_problems_against_sine_modes(E):
         want = O.dirichlet_box_phi(1, (it.n, it.n), (h[i], h[i]), it.tau, v_host[o:o + n2])
         e = relerr(yy[o:o + n2], want)
         worst = max(worst, e)
-        assert e <= 5e-6, (i, it.n, e)
+        assert e <= bar, (i, it.n, e)
         assert stats[i]["status"] == 0
     print(f"batched 256: {rounds} rounds, worst error {worst:.2e}", flush=True)
     y2 = torch.zeros_like(v)
