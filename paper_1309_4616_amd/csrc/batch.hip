@@ -364,87 +364,81 @@ __device__ void pair_tile(const BatchArgs& B, const BatchInfo& I, const BatchSta
         const TC er = (lane == 63) ? far : wc[0];
         ue = (TC)(TW)prod(V, el, er, gm, gq, gc, aym, ayq, cdy);
     };
-    // w_j rows k .. k+3 (W0..W3) and their beyond-strip values (G0..G3);
-    // w_{j+1} rows k-1, k (U0, U1) and row k beyond the strip (Ue1); p rows
-    // k, k+1
-    TC W0[V], W1[V], W2[V], W3[V], U0[V], U1[V], P0[V], P1[V];
-    TC G0, G1, G2, G3, Ue1;
+    // Register queues, indexed by row modulo 4 (the march is unrolled four
+    // rows per block, so every queue rotates by renaming and no value is
+    // copied: a copy of a register that a load is still filling would make
+    // the wave wait for that load).  Step k (output row k) finds w_j of rows
+    // k .. k+2 and their beyond-strip values, loaded a step or more ahead,
+    // and issues the loads of w_j row k+3 (used next step) and of p row k+2
+    // (used two steps on); w_{j+1} rows k-1, k sit in U, row k+1 is formed
+    // into the slot of row k-3.
+    TC W[4][V], P[4][V], U[4][V], G[4], Ue[2];
     {
-        TC Wa[V], Wb[V];
-        bld<TW, V>(rw, vo, roff(kb - 2), Wa);
-        bld<TW, V>(rw, vo, roff(kb - 1), Wb);
-        bld<TW, V>(rw, vo, roff(kb), W0);
-        bld<TW, V>(rw, vo, roff(kb + 1), W1);
-        bld<TW, V>(rw, vo, roff(kb + 2), W2);
-        bld<TW, V>(rw, vo, roff(kb + 3), W3);
-        const TC Ga = g_load(kb - 2), Gb = g_load(kb - 1);
-        G0 = g_load(kb);
-        G1 = g_load(kb + 1);
-        G2 = g_load(kb + 2);
-        G3 = g_load(kb + 3);
-        bld<TW, V>(rp, vo, roff(kb), P0);
-        bld<TW, V>(rp, vo, roff(kb + 1), P1);
-        TC Ue0;   // (w_{j+2} needs w_{j+1} beyond the strip on its own row only)
-        form_u(Wa, Wb, W0, Ga, Gb, G0, kb - 1, U0, Ue0);
-        form_u(Wb, W0, W1, Gb, G0, G1, kb, U1, Ue1);
+        // rows kb-2 .. kb+1 of w_j (slots 2, 3, 0, 1), p rows kb, kb+1
+        bld<TW, V>(rw, vo, roff(kb - 2), W[2]);
+        bld<TW, V>(rw, vo, roff(kb - 1), W[3]);
+        bld<TW, V>(rw, vo, roff(kb), W[0]);
+        bld<TW, V>(rw, vo, roff(kb + 1), W[1]);
+        G[2] = g_load(kb - 2);
+        G[3] = g_load(kb - 1);
+        G[0] = g_load(kb);
+        G[1] = g_load(kb + 1);
+        bld<TW, V>(rp, vo, roff(kb), P[0]);
+        bld<TW, V>(rp, vo, roff(kb + 1), P[1]);
+        TC ue_m;   // (w_{j+2} needs w_{j+1} beyond the strip on its own row only)
+        form_u(W[2], W[3], W[0], G[2], G[3], G[0], kb - 1, U[3], ue_m);
+        // row kb+2 into the slot of row kb-2, which is no longer needed
+        bld<TW, V>(rw, vo, roff(kb + 2), W[2]);
+        G[2] = g_load(kb + 2);
+        form_u(W[3], W[0], W[1], G[3], G[0], G[1], kb, U[0], Ue[0]);
     }
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int k = kb; k < ke; ++k) {
-        // loads two rows ahead of their first use
-        TC Wn[V], Pn[V];
-        bld<TW, V>(rw, vo, roff(k + 4), Wn);
-        const TC Gn = g_load(k + 4);
-        bld<TW, V>(rp, vo, roff(k + 2), Pn);
-        // w_{j+1} on row k+1
-        TC U2[V], Ue2;
-        form_u(W0, W1, W2, G0, G1, G2, k + 1, U2, Ue2);
-        // w_{j+2} and p on row k
-        {
+    for (int k0 = kb; k0 < ke; k0 += 4) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int k = k0 + st;
+            const bool valid = k < ke;   // all four steps run; only valid ones count and store
+            // loads ahead: w_j row k+3 (next step), p row k+2 (two steps on)
+            bld<TW, V>(rw, vo, roff(k + 3), W[(st + 3) & 3]);
+            G[(st + 3) & 3] = g_load(k + 3);
+            bld<TW, V>(rp, vo, roff(k + 2), P[(st + 2) & 3]);
+            // w_{j+1} on row k+1, from w_j rows k, k+1, k+2
+            form_u(W[st & 3], W[(st + 1) & 3], W[(st + 2) & 3], G[st & 3], G[(st + 1) & 3], G[(st + 2) & 3],
+                   k + 1, U[(st + 1) & 3], Ue[(st + 1) & 1]);
+            // w_{j+2} and p on row k, from w_{j+1} rows k-1, k, k+1
+            const TC* um = U[(st + 3) & 3];
+            const TC* uc = U[st & 3];
+            const TC* uq = U[(st + 1) & 3];
+            const TC* pk = P[st & 3];
             TC aym, ayq, cdy;
             yw(k, beta2, aym, ayq, cdy);
-            TC left = __shfl_up(U1[V - 1], 1, 64);
-            TC right = __shfl_down(U1[0], 1, 64);
-            if (lane == 0) left = Ue1;
-            if (lane == 63) right = Ue1;
+            TC left = __shfl_up(uc[V - 1], 1, 64);
+            TC right = __shfl_down(uc[0], 1, 64);
+            if (lane == 0) left = Ue[st & 1];
+            if (lane == 63) right = Ue[st & 1];
             TC wo[V], po[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const TC wl = (v > 0) ? U1[v - 1] : left;
-                const TC wr = (v < V - 1) ? U1[v + 1] : right;
-                const TC u2 = (TC)(TW)prod(v, wl, wr, U0[v], U2[v], U1[v], aym, ayq, cdy);
-                const TC p1 = (TC)(TW)(P0[v] + d1 * U1[v]);
+                const TC wl = (v > 0) ? uc[v - 1] : left;
+                const TC wr = (v < V - 1) ? uc[v + 1] : right;
+                const TC u2 = (TC)(TW)prod(v, wl, wr, um[v], uq[v], uc[v], aym, ayq, cdy);
+                const TC p1 = (TC)(TW)(pk[v] + d1 * uc[v]);
                 const TC p2 = (TC)(TW)(p1 + d2 * u2);
                 wo[v] = u2;
                 po[v] = p2;
-                if (active) {
-                    s[0] += (double)U1[v] * (double)U1[v];
+                if (active && valid) {
+                    s[0] += (double)uc[v] * (double)uc[v];
                     s[1] += (double)p1 * (double)p1;
                     s[2] += (double)u2 * (double)u2;
                     s[3] += (double)p2 * (double)p2;
                 }
             }
-            // lanes past the row end store past the buffer (dropped)
-            const int vs = active ? vo : nbytes;
+            // lanes past the row end, and steps past the tile, store past
+            // the buffer (dropped)
+            const int vs = (active && valid) ? vo : nbytes;
             bst<TW, V>(ro, vs, roff(k), wo);
             bst<TW, V>(rp, vs, roff(k), po);
         }
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            W0[v] = W1[v];
-            W1[v] = W2[v];
-            W2[v] = W3[v];
-            W3[v] = Wn[v];
-            U0[v] = U1[v];
-            U1[v] = U2[v];
-            P0[v] = P1[v];
-            P1[v] = Pn[v];
-        }
-        G0 = G1;
-        G1 = G2;
-        G2 = G3;
-        G3 = Gn;
-        Ue1 = Ue2;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
