@@ -28,7 +28,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
-HIP_SOURCES = ["stencil.hip", "pair.hip", "csr.hip", "csr_complex.hip", "sweep.hip", "batch.hip", "mlp.hip", "nonlin.hip", "boundary.hip", "api.hip"]
+HIP_SOURCES = ["stencil.hip", "pair.hip", "pair2d.hip", "csr.hip", "csr_complex.hip", "sweep.hip", "batch.hip", "mlp.hip", "nonlin.hip", "boundary.hip", "api.hip"]
 CXX_SOURCES = ["leja.cpp"]
 
 

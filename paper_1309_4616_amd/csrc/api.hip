@@ -33,9 +33,27 @@
 
 namespace expi {
 
+// pair2d.hip: the pair sweep of 2D constant-coefficient stencils (same
+// arguments, partials and finalize as the 3D one)
+bool pair2d_supported(const Op& op, int tw);
+hipError_t launch_pair2d(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep, bool finalize,
+                         int mode, int cus);
+int device_cus();
+
 namespace {
 
 thread_local std::string tl_error = "no error";
+
+// A pair sweep exists for the operator (3D or 2D stencil kernel).
+bool pair_any_supported(const Op& op, int tw) { return pair_supported(op, tw) || pair2d_supported(op, tw); }
+// ... and the operator's setting allows it
+bool pairs_on(const Op& op, int tw) { return op.use_pairs != 0 && pair_any_supported(op, tw); }
+// The pair sweep of the operator's dimension.
+hipError_t launch_pair_op(const Op& op, int tw, const PairArgs& a, hipStream_t s, hipEvent_t after_sweep = nullptr,
+                          bool finalize = true, int mode = PAIR_NEWTON) {
+    if (op.dim == 2) return launch_pair2d(op, tw, a, s, after_sweep, finalize, mode, device_cus());
+    return launch_pair(op, tw, a, s, after_sweep, finalize, mode);
+}
 
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
@@ -437,7 +455,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.tol = C.tol;
         b.j = 0;
         b.guard = 0;
-        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, nullptr, true, PAIR_FIRST));
+        HIP_TRY(launch_pair_op(*C.op, C.tw, b, C.s, nullptr, true, PAIR_FIRST));
         log.push_back({0, 2, w[0], false});
         finalized = 2;
         j = 2;
@@ -485,7 +503,7 @@ int newton_loop(Ctx& C, const void* src, int tin, void* p, LoopOut* out, bool st
         b.outbuf = cur ^ 1;
         const bool tm = timing();
         if (tm) HIP_TRY(hipEventRecord(tl_ctx.tev[2 * j], C.s));
-        HIP_TRY(launch_pair(*C.op, C.tw, b, C.s, tm ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
+        HIP_TRY(launch_pair_op(*C.op, C.tw, b, C.s, tm ? tl_ctx.tev[2 * j + 1] : nullptr, fin));
         log.push_back({j, 2, w[cur ^ 1], tm});
         cur ^= 1;
         if (fin) finalized += 2;
@@ -769,7 +787,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
     int sub = substep_count(tau, ia, ib, P.l_max);
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pairs_enabled(op, tw)};
+          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pairs_on(op, tw)};
     expi_stats acc{};
     for (int attempt = 0; attempt <= P.max_retries; ++attempt) {
         const double delta = tau / sub;
@@ -847,7 +865,7 @@ static int run_phi(Op& op, int k, double tau, const double* v, double* y, double
                 tin = 0;
             }
             LoopOut lo;
-            C.pairs = P.pairs && pairs_enabled(op, tw) && (((uintptr_t)p & 15) == 0);
+            C.pairs = P.pairs && pairs_on(op, tw) && (((uintptr_t)p & 15) == 0);
             // the update of this substep, enqueued ahead of the status
             // read-back where it always runs (p_in_y needs one only for a fix)
             const double* yin = ((k == 1 || phik_sub) && l > 0) ? y : nullptr;
@@ -899,7 +917,7 @@ static int run_expeuler(Op& op, int nonlin, double tau, double* u, double tol, i
     int sub = substep_count(tau, ia, ib, P.l_max);
     Ctx C{&op, tw, ws, L, reinterpret_cast<NewtonState*>(ws + L.state),
           reinterpret_cast<double*>(ws + L.partials), s, xi, {}, c, gamma, tol, P.m_max, {},
-          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pairs_enabled(op, tw)};
+          P.profile, P.selector, P.hidden, ia, ib, tau, P.pairs && pairs_on(op, tw)};
     double* yb = reinterpret_cast<double*>(ws + L.y);
     void* p = ws + L.p;
     expi_stats acc{};
@@ -1443,7 +1461,7 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
     // product doing full work) and kept if it takes less per product.  It is
     // listed as the candidate (0, 0, 2), its time per launch (two products).
     int use_pairs = o.use_pairs;
-    if (err == hipSuccess && pair_supported(o, tw) && best_us < 1e30f) {
+    if (err == hipSuccess && pair_any_supported(o, tw) && best_us < 1e30f) {
         PairArgs b{};
         b.x = w + L.w0;
         b.out = w + L.w1;
@@ -1458,9 +1476,9 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
         b.tol = 1e-300;
         b.j = 1;
         b.guard = 0;
-        err = launch_pair(o, tw, b, s, nullptr, false);   // warm up
+        err = launch_pair_op(o, tw, b, s, nullptr, false);   // warm up
         if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_pair(o, tw, b, s, nullptr, false);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_pair_op(o, tw, b, s, nullptr, false);
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
