@@ -533,6 +533,53 @@ def _time_launches(fn, reps: int) -> float:
     return start.elapsed_time(end) / reps
 
 
+def run_plain_2d(args):
+    """The plain-method workload: phi_1(tau A) v for the 5-point Laplacian
+    with homogeneous Dirichlet conditions on the 128 x 128 interior grid of
+    the unit square (h = 1/129), v uniform in [-1, 1] (seeded), tau = 1e-4,
+    tolerance 1e-10, FP64.  Wall time per call (inputs resident, the call's
+    own status read-backs included) with 2D pair sweeps (the default) and
+    with single products, and the average kernel time per launch from the
+    library's profiling events."""
+    import torch
+    import paper_1309_4616_amd as E
+    import synth
+
+    n, tau, tol, reps = 128, 1e-4, 1e-10, args.plain_reps
+    h = 1.0 / (n + 1)
+    op = E.StencilOp((n, n), (h, h), "dirichlet0", coef=1.0)
+    v = torch.as_tensor(synth.uniform_vector(n * n, 0), device="cuda:0")
+    y = torch.empty_like(v)
+    ws = op.workspace("f64")
+    out = {"workload": "phi_1(tau A) v, 2D 5-point Dirichlet Laplacian, 128^2, h = 1/129, tau 1e-4, "
+                       "tol 1e-10, FP64"}
+    for key, pairs in (("pairs", True), ("singles", False)):
+        params = E.LejaParams(pairs=pairs)
+        for _ in range(10):
+            E.phi_action(op, 1, tau, v, y=y, tol=tol, ws=ws, params=params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, st = E.phi_action(op, 1, tau, v, y=y, tol=tol, ws=ws, params=params)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        _, sp = E.phi_action(op, 1, tau, v, y=y, tol=tol, ws=ws, params=E.LejaParams(pairs=pairs, profile=True))
+        rec = {"ms_per_call": ms, "degree": st["degree_last"], "substeps": st["substeps"],
+               "matvecs": st["matvecs"], "pair_launches": st["pair_launches"],
+               "single_launches": st["single_launches"]}
+        if sp["timed_pairs"]:
+            rec["pair_avg_us"] = 1e3 * sp["pair_ms"] / sp["timed_pairs"]
+            # read w_j and p, write w_{j+2} and p: 32 B per point and launch
+            rec["pair_gbs"] = 32.0 * n * n / (rec["pair_avg_us"] * 1e3)
+        if sp["timed_products"]:
+            rec["single_avg_us"] = 1e3 * sp["newton_ms"] / sp["timed_products"]
+        out[key] = rec
+    out["speedup_pairs"] = out["singles"]["ms_per_call"] / out["pairs"]["ms_per_call"]
+    out["note"] = ("128 KiB per vector: every launch is latency bound (a few microseconds); pairs halve "
+                   "the launches and the stop tests")
+    return out
+
+
 def run_paper_tables(args):
     """The paper's single-kernel experiments on this GPU (context: the
     paper's numbers are on a Tesla C1060/C2075):
@@ -815,6 +862,8 @@ def main():
     ap.add_argument("--table-reps", type=int, default=10)
     ap.add_argument("--no-combustion", action="store_true")
     ap.add_argument("--no-spin", action="store_true")
+    ap.add_argument("--no-plain-2d", action="store_true")
+    ap.add_argument("--plain-reps", type=int, default=200)
     ap.add_argument("--spin-spins", type=int, default=21)
     ap.add_argument("--spin-t", type=float, default=10.0)
     ap.add_argument("--spin-tol", type=float, default=1e-5)
@@ -908,6 +957,12 @@ def main():
         spin = run_spin_bath(args)
         print(f"[bench] spin bath done: {spin['ms']:.1f} ms, {spin['products']} products", file=sys.stderr,
               flush=True)
+    plain2d = None
+    if not args.no_plain_2d:
+        print("[bench] plain method: phi_1 on the 128^2 Dirichlet Laplacian", file=sys.stderr, flush=True)
+        plain2d = run_plain_2d(args)
+        print(f"[bench] plain 2D done: {plain2d['pairs']['ms_per_call']:.3f} ms per call with pairs, "
+              f"{plain2d['singles']['ms_per_call']:.3f} ms with singles", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] gpu states of the first {args.cpu_steps} steps (f64, f32)", file=sys.stderr, flush=True)
@@ -1039,6 +1094,8 @@ def main():
         out["combustion"] = comb
     if spin:
         out["spin_bath"] = spin
+    if plain2d:
+        out["plain_2d"] = plain2d
     print(json.dumps(out), flush=True)
 
 
