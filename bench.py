@@ -533,6 +533,15 @@ def _time_launches(fn, reps: int) -> float:
     return start.elapsed_time(end) / reps
 
 
+def tuned_2d(E, op):
+    """Autotune a 2D operator (single-product tiles, and the pair sweep's
+    tile height against single products); returns what it chose."""
+    from paper_1309_4616_amd import autotune
+    res = autotune.tune(op, "f64", reps=5, use_cache=False)
+    return {"tiles": list(op.tiles()), "single_us": res["us"], "pair_setting": op.pair_setting(),
+            "pair_us_by_rows": {str(c[1]): round(t, 2) for c, t in res["candidates"] if c[0] == 0}}
+
+
 def run_plain_2d(args):
     """The plain-method workload: phi_1(tau A) v for the 5-point Laplacian
     with homogeneous Dirichlet conditions on the 128 x 128 interior grid of
@@ -540,7 +549,9 @@ def run_plain_2d(args):
     tolerance 1e-10, FP64.  Wall time per call (inputs resident, the call's
     own status read-backs included) with 2D pair sweeps (the default) and
     with single products, and the average kernel time per launch from the
-    library's profiling events."""
+    library's profiling events; the operator is autotuned first (tiles, and
+    the pair sweep's tile height).  Then the same at 8192^2, where the
+    sweeps are bound by HBM."""
     import torch
     import paper_1309_4616_amd as E
     import synth
@@ -552,7 +563,8 @@ def run_plain_2d(args):
     y = torch.empty_like(v)
     ws = op.workspace("f64")
     out = {"workload": "phi_1(tau A) v, 2D 5-point Dirichlet Laplacian, 128^2, h = 1/129, tau 1e-4, "
-                       "tol 1e-10, FP64"}
+                       "tol 1e-10, FP64",
+           "autotune": tuned_2d(E, op)}
     for key, pairs in (("pairs", True), ("singles", False)):
         params = E.LejaParams(pairs=pairs)
         for _ in range(10):
@@ -577,6 +589,46 @@ def run_plain_2d(args):
     out["speedup_pairs"] = out["singles"]["ms_per_call"] / out["pairs"]["ms_per_call"]
     out["note"] = ("128 KiB per vector: every launch is latency bound (a few microseconds); pairs halve "
                    "the launches and the stop tests")
+    del op, v, y, ws
+    # the same operator on a grid whose sweeps are bound by HBM: 8192^2 (537 MB
+    # per FP64 vector, as a 256^3 one), tau (b - a) = 30, tol 1e-8
+    n = args.plain_large_n
+    h = 1.0 / (n + 1)
+    op = E.StencilOp((n, n), (h, h), "dirichlet0", coef=1.0)
+    a, b = op.interval()
+    tau = 30.0 / (b - a)
+    v = torch.as_tensor(synth.uniform_vector(n * n, 1), device="cuda:0")
+    y = torch.empty_like(v)
+    ws = op.workspace("f64")
+    large = {"workload": f"phi_1(tau A) v, 2D 5-point Dirichlet Laplacian, {n}^2, tau (b - a) = 30, tol 1e-8, "
+                         "FP64",
+             "autotune": tuned_2d(E, op)}
+    for key, pairs in (("pairs", True), ("singles", False)):
+        params = E.LejaParams(pairs=pairs)
+        E.phi_action(op, 1, tau, v, y=y, tol=1e-8, ws=ws, params=params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            _, st = E.phi_action(op, 1, tau, v, y=y, tol=1e-8, ws=ws, params=params)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 3
+        _, sp = E.phi_action(op, 1, tau, v, y=y, tol=1e-8, ws=ws, params=E.LejaParams(pairs=pairs, profile=True))
+        rec = {"ms_per_call": ms, "degree": st["degree_last"], "pair_launches": st["pair_launches"],
+               "single_launches": st["single_launches"]}
+        if sp["timed_pairs"]:
+            us = 1e3 * sp["pair_ms"] / sp["timed_pairs"]
+            rec.update(pair_avg_us=us, pair_gbs=32.0 * n * n / (us * 1e3),
+                       pair_frac=32.0 * n * n / (us * 1e3) / HBM_PEAK_GBS)
+        else:
+            us = 1e3 * sp["newton_ms"] / sp["timed_products"]
+            rec.update(single_avg_us=us, single_gbs=32.0 * n * n / (us * 1e3),
+                       single_frac=32.0 * n * n / (us * 1e3) / HBM_PEAK_GBS)
+        large[key] = rec
+    large["speedup_pairs"] = large["singles"]["ms_per_call"] / large["pairs"]["ms_per_call"]
+    large["note"] = "32 B per point and launch for both: a pair sweep reads w_j, p and writes w_{j+2}, p"
+    out["large"] = large
+    del op, v, y, ws
+    torch.cuda.empty_cache()
     return out
 
 
@@ -864,6 +916,7 @@ def main():
     ap.add_argument("--no-spin", action="store_true")
     ap.add_argument("--no-plain-2d", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=200)
+    ap.add_argument("--plain-large-n", type=int, default=8192)
     ap.add_argument("--spin-spins", type=int, default=21)
     ap.add_argument("--spin-t", type=float, default=10.0)
     ap.add_argument("--spin-tol", type=float, default=1e-5)
@@ -962,7 +1015,9 @@ def main():
         print("[bench] plain method: phi_1 on the 128^2 Dirichlet Laplacian", file=sys.stderr, flush=True)
         plain2d = run_plain_2d(args)
         print(f"[bench] plain 2D done: {plain2d['pairs']['ms_per_call']:.3f} ms per call with pairs, "
-              f"{plain2d['singles']['ms_per_call']:.3f} ms with singles", file=sys.stderr, flush=True)
+              f"{plain2d['singles']['ms_per_call']:.3f} ms with singles; {args.plain_large_n}^2: "
+              f"{plain2d['large']['pairs']['ms_per_call']:.2f} / {plain2d['large']['singles']['ms_per_call']:.2f} ms",
+              file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] gpu states of the first {args.cpu_steps} steps (f64, f32)", file=sys.stderr, flush=True)

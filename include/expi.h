@@ -159,10 +159,11 @@ typedef struct {
     int32_t selector_hidden;
     /* 1: never fuse two Newton products into one sweep.  By default, on 3D
      * stencils with a constant or separable coefficient and rows of at most
-     * 512 points, consecutive products run as pair sweeps that keep w_{j+1}
-     * on chip (same arithmetic, half the vector traffic) and test the stop
-     * rule after each of the two (unless the operator's pair setting,
-     * expi_op_set_pairs, is 0). */
+     * 512 points, and on 2D stencils with a constant coefficient and
+     * homogeneous Dirichlet or Neumann conditions, consecutive products run
+     * as pair sweeps that keep w_{j+1} on chip (same arithmetic, half the
+     * vector traffic) and test the stop rule after each of the two (unless
+     * the operator's pair setting, expi_op_set_pairs, is 0). */
     int32_t no_pairs;
     /* Exponential Euler steps: the start-vector sweep r = A u + u - u^3 of
      * the first substep can run as the first half of a pair sweep whose
@@ -247,10 +248,16 @@ int64_t expi_op_size(const expi_op *op);
 int expi_op_set_tiles(expi_op *op, int vec, int waves, int march);
 int expi_op_get_tiles(const expi_op *op, int *vec, int *waves, int *march);
 
-/* Pair sweeps (two consecutive Newton products per pass on 3D stencils
- * with a constant or separable coefficient, rows of at most 512 points):
- * use = 1 (the default) takes them wherever they apply, 0 runs single
- * products.  EXPI_EINVAL for other values. */
+/* Pair sweeps (two consecutive Newton products per pass, Sec. III-C's
+ * Newton recurrence taken two steps at a time; on 3D stencils with a
+ * constant or separable coefficient and rows of at most 512 points, and on
+ * 2D stencils with a constant coefficient and homogeneous Dirichlet or
+ * Neumann conditions): use = 1 (the default) takes them wherever they
+ * apply, 0 runs single products.  On a 2D operator with pair sweeps,
+ * use = 4..64 (a multiple of 4) takes them with tiles of that many grid
+ * rows (with 1 the height follows the grid size: 16 rows, fewer where the
+ * grid has too few tiles for the device).  EXPI_EINVAL for other values.
+ * expi_op_get_pairs returns the stored value (0, 1 or a row count). */
 int expi_op_set_pairs(expi_op *op, int use);
 int expi_op_get_pairs(const expi_op *op, int *use);
 
@@ -262,7 +269,11 @@ int expi_op_get_pairs(const expi_op *op, int *use);
  * (3D) or {4,8,16,32} (2D); CSR lanes {4,8,16} x waves {1,2,4,8}.  Where
  * a pair sweep applies, it is timed last (listed as (0, 0, 2), time per
  * launch of two products) and the operator's pair setting becomes 1 if it
- * takes less per product than the best single product, else 0.  The
+ * takes less per product than the best single product, else 0.  A 2D pair
+ * sweep is timed at tile heights 4, 8, 16 and, where the grid has the
+ * rows, 32 and 64 (listed as (0, rows, 2)); the pair setting becomes the
+ * fastest height if that one takes less per product than the best single
+ * product, else 0.  The
  * workspace (expi_workspace_bytes(op, dtype)) supplies the vectors and is
  * overwritten.  If cand/us are given, the first max_cand tried settings
  * (vec, waves, march triples) and their mean microseconds per launch are

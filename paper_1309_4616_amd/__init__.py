@@ -91,15 +91,22 @@ class _Op:
         check(lib().expi_op_get_tiles(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(m)))
         return v.value, w.value, m.value
 
-    def set_pairs(self, use: bool) -> None:
+    def set_pairs(self, use) -> None:
         """Pair sweeps where they apply (the default), or single products
-        (see expi_op_set_pairs)."""
-        check(lib().expi_op_set_pairs(self._h, 1 if use else 0))
+        (see expi_op_set_pairs); on a 2D operator an int 4..64 (a multiple
+        of 4) also sets the rows per tile of its pair sweep."""
+        u = use if (isinstance(use, int) and not isinstance(use, bool) and use > 1) else (1 if use else 0)
+        check(lib().expi_op_set_pairs(self._h, u))
 
     def pairs(self) -> bool:
+        return bool(self.pair_setting())
+
+    def pair_setting(self) -> int:
+        """The stored pair setting: 0 off, 1 on, or the 2D pair sweep's rows
+        per tile."""
         u = ctypes.c_int()
         check(lib().expi_op_get_pairs(self._h, ctypes.byref(u)))
-        return bool(u.value)
+        return int(u.value)
 
     def interval(self, stream=None):
         a, b = ctypes.c_double(), ctypes.c_double()

@@ -74,7 +74,8 @@ def load(op, dtype: str = "f64", path: str | None = None) -> bool:
 def _apply(op, entry: dict) -> None:
     op.set_tiles(*entry["tiles"])
     if "pairs" in entry and hasattr(op, "set_pairs"):
-        op.set_pairs(bool(entry["pairs"]))
+        rows = entry.get("pair_rows")
+        op.set_pairs(int(rows) if (entry["pairs"] and rows) else bool(entry["pairs"]))
 
 
 def tune(op, dtype: str = "f64", reps: int = 10, path: str | None = None,
@@ -83,7 +84,8 @@ def tune(op, dtype: str = "f64", reps: int = 10, path: str | None = None,
     {'tiles': (vec, waves, march), 'us': best time, 'pairs': whether pair
     sweeps are kept (None where they do not apply), 'candidates': [...]}
     (the pair sweep is the candidate (0, 0, 2), its time per launch of two
-    products)."""
+    products; a 2D pair sweep is timed at several tile heights, (0, rows, 2),
+    and 'pair_rows' records the one kept)."""
     import torch
     from . import _dtype_code, _stream_ptr
     path = path or cache_path()
@@ -109,6 +111,8 @@ def tune(op, dtype: str = "f64", reps: int = 10, path: str | None = None,
     entry = {"tiles": list(best), "us": min(singles) if singles else None,
              "pairs": (op.pairs() if paired else None),
              "candidates": [[list(c), t] for c, t in rows]}
+    if paired and op.pair_setting() > 1:
+        entry["pair_rows"] = op.pair_setting()   # the 2D pair sweep's tile height
     if use_cache:
         data = _read(path)
         data[key] = entry

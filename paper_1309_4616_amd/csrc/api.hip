@@ -36,8 +36,9 @@ namespace expi {
 // pair2d.hip: the pair sweep of 2D constant-coefficient stencils (same
 // arguments, partials and finalize as the 3D one)
 bool pair2d_supported(const Op& op, int tw);
+bool pair2d_rows_valid(int rows);
 hipError_t launch_pair2d(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep, bool finalize,
-                         int mode, int cus);
+                         int mode, int cus, int rows);
 int device_cus();
 
 namespace {
@@ -48,10 +49,14 @@ thread_local std::string tl_error = "no error";
 bool pair_any_supported(const Op& op, int tw) { return pair_supported(op, tw) || pair2d_supported(op, tw); }
 // ... and the operator's setting allows it
 bool pairs_on(const Op& op, int tw) { return op.use_pairs != 0 && pair_any_supported(op, tw); }
-// The pair sweep of the operator's dimension.
+// The pair sweep of the operator's dimension.  A 2D operator's use_pairs
+// above 1 is the rows per tile of its pair sweep (expi_op_set_pairs).
 hipError_t launch_pair_op(const Op& op, int tw, const PairArgs& a, hipStream_t s, hipEvent_t after_sweep = nullptr,
-                          bool finalize = true, int mode = PAIR_NEWTON) {
-    if (op.dim == 2) return launch_pair2d(op, tw, a, s, after_sweep, finalize, mode, device_cus());
+                          bool finalize = true, int mode = PAIR_NEWTON, int rows = -1) {
+    if (op.dim == 2) {
+        if (rows < 0) rows = op.use_pairs > 1 ? op.use_pairs : 0;
+        return launch_pair2d(op, tw, a, s, after_sweep, finalize, mode, device_cus(), rows);
+    }
     return launch_pair(op, tw, a, s, after_sweep, finalize, mode);
 }
 
@@ -1358,8 +1363,10 @@ int expi_op_set_tiles(expi_op* op, int vec, int waves, int march) {
 
 int expi_op_set_pairs(expi_op* op, int use) {
     if (!op) return fail(EXPI_EINVAL, "op is NULL");
-    if (use != 0 && use != 1) return fail(EXPI_EINVAL, "use must be 0 or 1");
     Op& o = *reinterpret_cast<Op*>(op);
+    if (use != 0 && use != 1 && !(pair2d_supported(o, 0) && pair2d_rows_valid(use)))
+        return fail(EXPI_EINVAL, "use must be 0 or 1 (or, on a 2D operator with pair sweeps, a row count "
+                                 "4..64, a multiple of 4)");
     std::lock_guard<std::mutex> lock(o.mu);
     o.use_pairs = use;
     return EXPI_OK;
@@ -1460,6 +1467,8 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
     // against two single products at the best tiles (the same data, every
     // product doing full work) and kept if it takes less per product.  It is
     // listed as the candidate (0, 0, 2), its time per launch (two products).
+    // A 2D pair sweep is timed at several tile heights (candidates
+    // (0, rows, 2)) and kept with the fastest: use_pairs then holds its rows.
     int use_pairs = o.use_pairs;
     if (err == hipSuccess && pair_any_supported(o, tw) && best_us < 1e30f) {
         PairArgs b{};
@@ -1476,24 +1485,38 @@ int expi_op_autotune(expi_op* op, int dtype, int reps, void* ws, size_t ws_bytes
         b.tol = 1e-300;
         b.j = 1;
         b.guard = 0;
-        err = launch_pair_op(o, tw, b, s, nullptr, false);   // warm up
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_pair_op(o, tw, b, s, nullptr, false);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err == hipSuccess) {
+        std::vector<int> heights{0};
+        if (o.dim == 2) {
+            heights.clear();
+            for (int r = 4; r <= 64; r *= 2)
+                if (r <= 16 || r / 2 < o.n[1]) heights.push_back(r);
+        }
+        float best_pair = 1e30f;
+        int best_rows = 1;
+        for (int rows : heights) {
+            err = launch_pair_op(o, tw, b, s, nullptr, false, PAIR_NEWTON, rows);   // warm up
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && err == hipSuccess; ++r)
+                err = launch_pair_op(o, tw, b, s, nullptr, false, PAIR_NEWTON, rows);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) break;
             const float per = 1e3f * ms / reps;
             if (nc < max_cand && cand && us) {
                 cand[3 * nc] = 0;
-                cand[3 * nc + 1] = 0;
+                cand[3 * nc + 1] = rows;
                 cand[3 * nc + 2] = 2;
                 us[nc] = per;
             }
             ++nc;
-            use_pairs = (0.5f * per < best_us) ? 1 : 0;
+            if (per < best_pair) {
+                best_pair = per;
+                best_rows = rows ? rows : 1;
+            }
         }
+        if (err == hipSuccess) use_pairs = (0.5f * best_pair < best_us) ? best_rows : 0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

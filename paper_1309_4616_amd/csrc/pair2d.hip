@@ -19,7 +19,8 @@ namespace expi {
 namespace {
 
 constexpr int kP2Waves = 4;     // waves per workgroup
-constexpr int kP2March = 16;    // rows per tile at most (a multiple of 4)
+constexpr int kP2March = 16;    // rows per tile by default (a multiple of 4)
+constexpr int kP2MaxMarch = 64; // rows per tile at most
 constexpr int kP2MaxGrid = 512; // workgroups at most (partials: 8 doubles each)
 
 template <class TW, int V>
@@ -248,6 +249,9 @@ hipError_t go2(int vec, int grid, int tiles0, int ntiles, int march, const PairA
 
 }  // namespace
 
+// Rows per tile a caller may ask for: a multiple of 4 up to kP2MaxMarch.
+bool pair2d_rows_valid(int rows) { return rows >= 4 && rows <= kP2MaxMarch && rows % 4 == 0; }
+
 bool pair2d_supported(const Op& op, int tw) {
     (void)tw;
     // buffer offsets are 32-bit byte offsets: below 2^31 bytes in FP64
@@ -255,9 +259,12 @@ bool pair2d_supported(const Op& op, int tw) {
            (op.bc == EXPI_DIRICHLET0 || op.bc == EXPI_NEUMANN0) && op.size * 8 < ((int64_t)1 << 31) - 64;
 }
 
+// rows: rows per tile (pair2d_rows_valid), or 0 for 16, fewer where the
+// grid has too few tiles of 16 rows.
 hipError_t launch_pair2d(const Op& op, int tw, PairArgs a, hipStream_t s, hipEvent_t after_sweep, bool finalize,
-                         int mode, int cus) {
+                         int mode, int cus, int rows) {
     if (mode != PAIR_NEWTON && mode != PAIR_FIRST) return hipErrorInvalidValue;
+    if (rows != 0 && !pair2d_rows_valid(rows)) return hipErrorInvalidValue;
     for (int d = 0; d < 2; ++d) {
         a.n[d] = op.n[d];
         a.ih2[d] = 1.0 / (op.h[d] * op.h[d]);
@@ -272,8 +279,8 @@ hipError_t launch_pair2d(const Op& op, int tw, PairArgs a, hipStream_t s, hipEve
     // rows per tile: 16, or fewer (a multiple of 4) where the grid has too
     // few tiles of 16 rows for a wave on every SIMD
     const int slots = 4 * std::max(cus, kXcd);
-    int march = kP2March;
-    while (march > 4 && (long long)tiles0 * ((op.n[1] + march - 1) / march) < slots) march /= 2;
+    int march = rows ? rows : kP2March;
+    while (!rows && march > 4 && (long long)tiles0 * ((op.n[1] + march - 1) / march) < slots) march /= 2;
     const int ntiles = tiles0 * ((op.n[1] + march - 1) / march);
     // enough workgroups for every tile a wave of its own, up to four per CU,
     // a multiple of the XCD count

@@ -135,3 +135,51 @@ def test_pair2d_stops_after_either_product(E):
         assert sp["degree_last"] == ss["degree_last"]
         parities.add(sp["degree_last"] % 2)
     assert parities == {0, 1}
+
+
+@pytest.mark.parametrize("rows", [4, 8, 16, 32, 64])
+def test_pair2d_every_tile_height(E, rows):
+    """The operator's pair setting fixes the tile height: every allowed
+    height gives the oracle's result (tiles ragged against the grid's rows
+    and taller than it)."""
+    for shape, bc in (((300, 70), "dirichlet0"), ((129, 33), "neumann0"), ((64, 5), "dirichlet0")):
+        op, A = make(E, shape, bc)
+        op.set_pairs(rows)
+        assert op.pair_setting() == rows
+        n = int(np.prod(shape))
+        v = synth.uniform_vector(n, 21)
+        a, b = O.gershgorin_interval(A)
+        tau = 8.0 / (b - a)
+        print(f"pair2d rows={rows} {shape} {bc}", flush=True)
+        yp, sp = E.phi_action(op, 1, tau, T(v), tol=1e-10, params=E.LejaParams(profile=True))
+        yo, _ = I.phi_action(A, 1, tau, v, 1e-10)
+        assert relerr(N(yp), yo) <= TOL_F64, relerr(N(yp), yo)
+        assert sp["timed_pairs"] >= 1
+
+
+def test_pair2d_autotuned_height(E, tmp_path):
+    """The autotuner times the 2D pair sweep at several tile heights, keeps
+    the fastest (or single products), a fresh operator takes the cached
+    choice, and the result still matches the oracle."""
+    from paper_1309_4616_amd import autotune
+    cache = str(tmp_path / "tiles.json")
+    shape = (512, 300)
+    op, A = make(E, shape, "dirichlet0")
+    print("pair2d autotune", flush=True)
+    res = autotune.tune(op, "f64", reps=3, path=cache)
+    heights = sorted(c[1] for c, _ in res["candidates"] if c[0] == 0)
+    assert heights == [4, 8, 16, 32, 64]
+    setting = op.pair_setting()
+    assert setting in (0, 4, 8, 16, 32, 64)
+    if setting:
+        best = min((t, c[1]) for c, t in res["candidates"] if c[0] == 0)[1]
+        assert setting == best and res["pair_rows"] == best
+    op2, _ = make(E, shape, "dirichlet0")
+    assert autotune.load(op2, "f64", path=cache)
+    assert op2.pair_setting() == setting and op2.tiles() == op.tiles()
+    v = synth.uniform_vector(512 * 300, 4)
+    a, b = O.gershgorin_interval(A)
+    tau = 8.0 / (b - a)
+    yp, _ = E.phi_action(op, 1, tau, T(v), tol=1e-10)
+    yo, _ = I.phi_action(A, 1, tau, v, 1e-10)
+    assert relerr(N(yp), yo) <= TOL_F64

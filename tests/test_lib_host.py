@@ -191,6 +191,27 @@ def test_call_validation_before_any_hip_call(L):
     L.expi_op_destroy(op)
 
 
+def test_pair_rows_setting(L):
+    """A 2D constant-coefficient operator with pair sweeps also takes a tile
+    height for them (a multiple of 4 up to 64); other operators take only
+    0 or 1."""
+    use = ctypes.c_int()
+    rc, op2 = _stencil(L, dim=2, bc=0)
+    assert rc == 0
+    for bad in (2, 3, 30, 68, -4):
+        assert L.expi_op_set_pairs(op2, bad) == -1
+    for good in (4, 32, 64, 1, 0):
+        assert L.expi_op_set_pairs(op2, good) == 0
+        assert L.expi_op_get_pairs(op2, ctypes.byref(use)) == 0 and use.value == good
+    L.expi_op_destroy(op2)
+    for dim, bc in ((3, 0), (2, 2)):     # a 3D operator; 2D with only the interior rows (no 2D pair sweep)
+        rc, op = _stencil(L, dim=dim, bc=bc)
+        assert rc == 0
+        assert L.expi_op_set_pairs(op, 32) == -1
+        assert L.expi_op_set_pairs(op, 1) == 0
+        L.expi_op_destroy(op)
+
+
 def test_noalloc_size_limit_before_any_hip_call(L):
     """The allocation-free phi_action refuses an operator whose workspace is
     larger than the library's scratch array, and a bad dtype, before it
