@@ -58,9 +58,9 @@ __device__ __forceinline__ void bst2(__amdgpu_buffer_rsrc_t r, int voff, int sof
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, q), r, voff, soff, 0);
         } else if constexpr (sizeof(TW) == 4) {
             Pack2<TW, 2> q;
-            q.v[0] = o[0];
-            q.v[1] = o[1];
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, q), r, voff, soff, 0);
+            q.v[0] = o[2 * h];
+            q.v[1] = o[2 * h + 1];
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, q), r, voff + 8 * h, soff, 0);
         } else {
             Pack2<TW, 1> q;
             q.v[0] = o[h];
@@ -238,6 +238,13 @@ __global__ __launch_bounds__(kP2Waves * 64) void pair2d_sweep(PairArgs a, int ti
 
 template <class TW, int MODE>
 hipError_t go2(int vec, int grid, int tiles0, int ntiles, int march, const PairArgs& a, hipStream_t s) {
+    if constexpr (sizeof(TW) == 4) {
+        if (vec == 4) {
+            hipLaunchKernelGGL((pair2d_sweep<TW, 4, MODE>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0,
+                               ntiles, march);
+            return hipGetLastError();
+        }
+    }
     if (vec == 2)
         hipLaunchKernelGGL((pair2d_sweep<TW, 2, MODE>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0, ntiles,
                            march);
@@ -271,10 +278,12 @@ hipError_t launch_pair2d(const Op& op, int tw, PairArgs a, hipStream_t s, hipEve
         a.c0ih[d] = op.c0 * a.ih2[d];
     }
     a.bc = op.bc;
-    // two points per lane where rows start on 2-value boundaries
+    // four FP32 points per lane where rows start on 16-byte boundaries, else
+    // two points where they start on 2-value boundaries, else one
     const size_t al = 2 * (tw == 1 ? 4 : 8);
     const bool aligned = ((uintptr_t)a.x % al == 0) && ((uintptr_t)a.out % al == 0) && ((uintptr_t)a.p % al == 0);
-    const int vec = (op.n[0] % 2 == 0 && aligned) ? 2 : 1;
+    const bool al16 = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.out % 16 == 0) && ((uintptr_t)a.p % 16 == 0);
+    const int vec = (tw == 1 && op.n[0] % 4 == 0 && al16) ? 4 : ((op.n[0] % 2 == 0 && aligned) ? 2 : 1);
     const int tiles0 = (op.n[0] + 64 * vec - 1) / (64 * vec);
     // rows per tile: 16, or fewer (a multiple of 4) where the grid has too
     // few tiles of 16 rows for a wave on every SIMD

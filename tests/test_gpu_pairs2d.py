@@ -100,10 +100,11 @@ def test_pair2d_plain_workload(E):
     assert sp["timed_pairs"] >= 1
 
 
-@pytest.mark.parametrize("shape", [(128, 128), (129, 33), (300, 17)])
+@pytest.mark.parametrize("shape", [(128, 128), (129, 33), (300, 17), (130, 37), (1000, 9), (4, 7)])
 def test_pair2d_f32_storage(E, shape):
     """FP32 storage: pairs and singles both within the FP32 error of the
-    FP64 oracle."""
+    FP64 oracle (four points per lane where rows have a multiple of 4
+    points, else two or one)."""
     op, A = make(E, shape, "neumann0")
     n = int(np.prod(shape))
     v = synth.uniform_vector(n, 5)
@@ -137,12 +138,15 @@ def test_pair2d_stops_after_either_product(E):
     assert parities == {0, 1}
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("rows", [4, 8, 16, 32, 64])
-def test_pair2d_every_tile_height(E, rows):
+def test_pair2d_every_tile_height(E, rows, dtype):
     """The operator's pair setting fixes the tile height: every allowed
     height gives the oracle's result (tiles ragged against the grid's rows
-    and taller than it)."""
-    for shape, bc in (((300, 70), "dirichlet0"), ((129, 33), "neumann0"), ((64, 5), "dirichlet0")):
+    and taller than it; one, two and, in FP32, four points per lane)."""
+    tol, bound = (1e-10, TOL_F64) if dtype == "f64" else (1e-6, 2e-5)
+    for shape, bc in (((300, 70), "dirichlet0"), ((129, 33), "neumann0"), ((64, 5), "dirichlet0"),
+                      ((258, 9), "neumann0")):
         op, A = make(E, shape, bc)
         op.set_pairs(rows)
         assert op.pair_setting() == rows
@@ -150,10 +154,10 @@ def test_pair2d_every_tile_height(E, rows):
         v = synth.uniform_vector(n, 21)
         a, b = O.gershgorin_interval(A)
         tau = 8.0 / (b - a)
-        print(f"pair2d rows={rows} {shape} {bc}", flush=True)
-        yp, sp = E.phi_action(op, 1, tau, T(v), tol=1e-10, params=E.LejaParams(profile=True))
-        yo, _ = I.phi_action(A, 1, tau, v, 1e-10)
-        assert relerr(N(yp), yo) <= TOL_F64, relerr(N(yp), yo)
+        print(f"pair2d rows={rows} {dtype} {shape} {bc}", flush=True)
+        yp, sp = E.phi_action(op, 1, tau, T(v), tol=tol, dtype=dtype, params=E.LejaParams(profile=True))
+        yo, _ = I.phi_action(A, 1, tau, v, 1e-12)
+        assert relerr(N(yp), yo) <= bound, relerr(N(yp), yo)
         assert sp["timed_pairs"] >= 1
 
 
