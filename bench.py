@@ -533,11 +533,11 @@ def _time_launches(fn, reps: int) -> float:
     return start.elapsed_time(end) / reps
 
 
-def tuned_2d(E, op):
+def tuned_2d(E, op, dtype="f64"):
     """Autotune a 2D operator (single-product tiles, and the pair sweep's
     tile height against single products); returns what it chose."""
     from paper_1309_4616_amd import autotune
-    res = autotune.tune(op, "f64", reps=5, use_cache=False)
+    res = autotune.tune(op, dtype, reps=5, use_cache=False)
     return {"tiles": list(op.tiles()), "single_us": res["us"], "pair_setting": op.pair_setting(),
             "pair_us_by_rows": {str(c[1]): round(t, 2) for c, t in res["candidates"] if c[0] == 0}}
 
@@ -551,7 +551,7 @@ def run_plain_2d(args):
     with single products, and the average kernel time per launch from the
     library's profiling events; the operator is autotuned first (tiles, and
     the pair sweep's tile height).  Then the same at 8192^2, where the
-    sweeps are bound by HBM."""
+    sweeps are bound by HBM, in FP64 and with FP32 storage."""
     import torch
     import paper_1309_4616_amd as E
     import synth
@@ -599,35 +599,40 @@ def run_plain_2d(args):
     tau = 30.0 / (b - a)
     v = torch.as_tensor(synth.uniform_vector(n * n, 1), device="cuda:0")
     y = torch.empty_like(v)
-    ws = op.workspace("f64")
-    large = {"workload": f"phi_1(tau A) v, 2D 5-point Dirichlet Laplacian, {n}^2, tau (b - a) = 30, tol 1e-8, "
-                         "FP64",
-             "autotune": tuned_2d(E, op)}
-    for key, pairs in (("pairs", True), ("singles", False)):
-        params = E.LejaParams(pairs=pairs)
-        E.phi_action(op, 1, tau, v, y=y, tol=1e-8, ws=ws, params=params)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            _, st = E.phi_action(op, 1, tau, v, y=y, tol=1e-8, ws=ws, params=params)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / 3
-        _, sp = E.phi_action(op, 1, tau, v, y=y, tol=1e-8, ws=ws, params=E.LejaParams(pairs=pairs, profile=True))
-        rec = {"ms_per_call": ms, "degree": st["degree_last"], "pair_launches": st["pair_launches"],
-               "single_launches": st["single_launches"]}
-        if sp["timed_pairs"]:
-            us = 1e3 * sp["pair_ms"] / sp["timed_pairs"]
-            rec.update(pair_avg_us=us, pair_gbs=32.0 * n * n / (us * 1e3),
-                       pair_frac=32.0 * n * n / (us * 1e3) / HBM_PEAK_GBS)
-        else:
-            us = 1e3 * sp["newton_ms"] / sp["timed_products"]
-            rec.update(single_avg_us=us, single_gbs=32.0 * n * n / (us * 1e3),
-                       single_frac=32.0 * n * n / (us * 1e3) / HBM_PEAK_GBS)
-        large[key] = rec
-    large["speedup_pairs"] = large["singles"]["ms_per_call"] / large["pairs"]["ms_per_call"]
-    large["note"] = "32 B per point and launch for both: a pair sweep reads w_j, p and writes w_{j+2}, p"
-    out["large"] = large
-    del op, v, y, ws
+    for dt in ("f64", "f32"):
+        bpp = 32.0 if dt == "f64" else 16.0   # read w_j, p; write w_{j+2}, p (or w_{j+1}, p)
+        ws = op.workspace(dt)
+        large = {"workload": f"phi_1(tau A) v, 2D 5-point Dirichlet Laplacian, {n}^2, tau (b - a) = 30, "
+                             f"tol 1e-8, {'FP64' if dt == 'f64' else 'FP32 storage'}",
+                 "autotune": tuned_2d(E, op, dt)}
+        for key, pairs in (("pairs", True), ("singles", False)):
+            params = E.LejaParams(pairs=pairs)
+            E.phi_action(op, 1, tau, v, y=y, tol=1e-8, dtype=dt, ws=ws, params=params)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, st = E.phi_action(op, 1, tau, v, y=y, tol=1e-8, dtype=dt, ws=ws, params=params)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / 3
+            _, sp = E.phi_action(op, 1, tau, v, y=y, tol=1e-8, dtype=dt, ws=ws,
+                                 params=E.LejaParams(pairs=pairs, profile=True))
+            rec = {"ms_per_call": ms, "degree": st["degree_last"], "pair_launches": st["pair_launches"],
+                   "single_launches": st["single_launches"]}
+            if sp["timed_pairs"]:
+                us = 1e3 * sp["pair_ms"] / sp["timed_pairs"]
+                rec.update(pair_avg_us=us, pair_gbs=bpp * n * n / (us * 1e3),
+                           pair_frac=bpp * n * n / (us * 1e3) / HBM_PEAK_GBS)
+            else:
+                us = 1e3 * sp["newton_ms"] / sp["timed_products"]
+                rec.update(single_avg_us=us, single_gbs=bpp * n * n / (us * 1e3),
+                           single_frac=bpp * n * n / (us * 1e3) / HBM_PEAK_GBS)
+            large[key] = rec
+        large["speedup_pairs"] = large["singles"]["ms_per_call"] / large["pairs"]["ms_per_call"]
+        large["note"] = (f"{bpp:.0f} B per point and launch for both: a pair sweep reads w_j, p and writes "
+                         "w_{j+2}, p; a single product reads w_j, p and writes w_{j+1}, p")
+        out["large" if dt == "f64" else "large_f32"] = large
+        del ws
+    del op, v, y
     torch.cuda.empty_cache()
     return out
 
@@ -1016,7 +1021,9 @@ def main():
         plain2d = run_plain_2d(args)
         print(f"[bench] plain 2D done: {plain2d['pairs']['ms_per_call']:.3f} ms per call with pairs, "
               f"{plain2d['singles']['ms_per_call']:.3f} ms with singles; {args.plain_large_n}^2: "
-              f"{plain2d['large']['pairs']['ms_per_call']:.2f} / {plain2d['large']['singles']['ms_per_call']:.2f} ms",
+              f"{plain2d['large']['pairs']['ms_per_call']:.2f} / {plain2d['large']['singles']['ms_per_call']:.2f} ms "
+              f"(FP32 {plain2d['large_f32']['pairs']['ms_per_call']:.2f} / "
+              f"{plain2d['large_f32']['singles']['ms_per_call']:.2f} ms)",
               file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
