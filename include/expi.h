@@ -159,8 +159,8 @@ typedef struct {
     int32_t selector_hidden;
     /* 1: never fuse two Newton products into one sweep.  By default, on 3D
      * stencils with a constant or separable coefficient and rows of at most
-     * 512 points, and on 2D stencils with a constant coefficient and
-     * homogeneous Dirichlet or Neumann conditions, consecutive products run
+     * 512 points, and on 2D stencils with a constant coefficient (any
+     * boundary handling), consecutive products run
      * as pair sweeps that keep w_{j+1} on chip (same arithmetic, half the
      * vector traffic) and test the stop rule after each of the two (unless
      * the operator's pair setting, expi_op_set_pairs, is 0). */
@@ -251,8 +251,8 @@ int expi_op_get_tiles(const expi_op *op, int *vec, int *waves, int *march);
 /* Pair sweeps (two consecutive Newton products per pass, Sec. III-C's
  * Newton recurrence taken two steps at a time; on 3D stencils with a
  * constant or separable coefficient and rows of at most 512 points, and on
- * 2D stencils with a constant coefficient and homogeneous Dirichlet or
- * Neumann conditions): use = 1 (the default) takes them wherever they
+ * 2D stencils with a constant coefficient and any boundary handling):
+ * use = 1 (the default) takes them wherever they
  * apply, 0 runs single products.  On a 2D operator with pair sweeps,
  * use = 4..64 (a multiple of 4) takes them with tiles of that many grid
  * rows (with 1 the height follows the grid size: 16 rows, fewer where the

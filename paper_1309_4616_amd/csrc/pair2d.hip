@@ -74,10 +74,12 @@ __device__ __forceinline__ void bst2(__amdgpu_buffer_rsrc_t r, int voff, int sof
 // product is written as sum over faces of (alpha f) w_nb +
 // (beta - alpha sum f) w_c (face weights f = c0/h^2; 0 towards a neighbour
 // that does not exist, which under homogeneous Dirichlet conditions still
-// takes its share of the diagonal).  Adds the tile's sums to s:
+// takes its share of the diagonal).  IO (only the interior rows): the
+// operator's rows of the outermost layer of points are zero, so there the
+// product is beta w_c.  Adds the tile's sums to s:
 // PAIR_NEWTON ||w_{j+1}||^2, ||p_{j+1}||^2, ||w_{j+2}||^2, ||p_{j+2}||^2;
 // PAIR_FIRST ||r||^2 first, then the same four.
-template <class TW, int V, int MODE>
+template <class TW, int V, int MODE, bool IO>
 __device__ void pair2d_tile(const PairArgs& a, int t0, int t1, int march, double (&s)[5]) {
     using TC = TW;
     constexpr int sz = (int)sizeof(TW);
@@ -111,27 +113,33 @@ __device__ void pair2d_tile(const PairArgs& a, int t0, int t1, int march, double
     const TC d0 = (TC)a.d0, d1 = (TC)a.d1, d2 = (TC)a.d2;
     const TC fx = (TC)a.c0ih[0], fy = (TC)a.c0ih[1];
     TC axm[V + 1], axq[V + 1], adx[V + 1];
+    bool xb[V + 1];   // IO: a point of the outermost columns
 #pragma unroll
     for (int v = 0; v <= V; ++v) {
         const int x = (v < V) ? i + v : xe;
         const bool em = x > 0, eq = x < n0 - 1;
+        xb[v] = IO && !(em && eq);
         axm[v] = em ? alpha * fx : (TC)0;
         axq[v] = eq ? alpha * fx : (TC)0;
         adx[v] = alpha * (((em || dir) ? fx : (TC)0) + ((eq || dir) ? fx : (TC)0));
     }
-    auto yw = [&](int q, TC beta, TC& aym, TC& ayq, TC& cdy) {
+    auto yw = [&](int q, TC beta, TC& aym, TC& ayq, TC& cdy, bool& rb) {
         const bool em = q > 0, eq = q < n1 - 1;
+        rb = IO && !(em && eq);   // IO: a point of the outermost rows
         aym = em ? alpha * fy : (TC)0;
         ayq = eq ? alpha * fy : (TC)0;
         cdy = beta - alpha * (((em || dir) ? fy : (TC)0) + ((eq || dir) ? fy : (TC)0));
     };
-    auto prod = [&](int v, TC wl, TC wr, TC wm, TC wq, TC wc, TC aym, TC ayq, TC cdy) -> TC {
-        return axm[v] * wl + axq[v] * wr + aym * wm + ayq * wq + (cdy - adx[v]) * wc;
+    auto prod = [&](int v, TC wl, TC wr, TC wm, TC wq, TC wc, TC aym, TC ayq, TC cdy, TC beta, bool rb) -> TC {
+        const TC u = axm[v] * wl + axq[v] * wr + aym * wm + ayq * wq + (cdy - adx[v]) * wc;
+        if constexpr (IO) return (xb[v] || rb) ? beta * wc : u;
+        else return u;
     };
     auto form_u = [&](const TC (&wm)[V], const TC (&wc)[V], const TC (&wq)[V], TC gm, TC gc, TC gq, int q,
                       TC (&u)[V], TC& ue) {
         TC aym, ayq, cdy;
-        yw(q, beta1, aym, ayq, cdy);
+        bool rb;
+        yw(q, beta1, aym, ayq, cdy, rb);
         TC left = __shfl_up(wc[V - 1], 1, 64);
         TC right = __shfl_down(wc[0], 1, 64);
         const TC far = __shfl(gc, gsrc, 64);
@@ -141,11 +149,11 @@ __device__ void pair2d_tile(const PairArgs& a, int t0, int t1, int march, double
         for (int v = 0; v < V; ++v) {
             const TC wl = (v > 0) ? wc[v - 1] : left;
             const TC wr = (v < V - 1) ? wc[v + 1] : right;
-            u[v] = (TC)(TW)prod(v, wl, wr, wm[v], wq[v], wc[v], aym, ayq, cdy);
+            u[v] = (TC)(TW)prod(v, wl, wr, wm[v], wq[v], wc[v], aym, ayq, cdy, beta1, rb);
         }
         const TC el = (lane == 63) ? wc[V - 1] : far;
         const TC er = (lane == 63) ? far : wc[0];
-        ue = (TC)(TW)prod(V, el, er, gm, gq, gc, aym, ayq, cdy);
+        ue = (TC)(TW)prod(V, el, er, gm, gq, gc, aym, ayq, cdy, beta1, rb);
     };
     // register queues indexed by row modulo 4 (the march is unrolled four
     // rows per block, so the queues rotate by renaming)
@@ -186,7 +194,8 @@ __device__ void pair2d_tile(const PairArgs& a, int t0, int t1, int march, double
             const TC* uc = U[st & 3];
             const TC* uq = U[(st + 1) & 3];
             TC aym, ayq, cdy;
-            yw(k, beta2, aym, ayq, cdy);
+            bool rb;
+            yw(k, beta2, aym, ayq, cdy, rb);
             TC left = __shfl_up(uc[V - 1], 1, 64);
             TC right = __shfl_down(uc[0], 1, 64);
             if (lane == 0) left = Ue[st & 1];
@@ -196,7 +205,7 @@ __device__ void pair2d_tile(const PairArgs& a, int t0, int t1, int march, double
             for (int v = 0; v < V; ++v) {
                 const TC wl = (v > 0) ? uc[v - 1] : left;
                 const TC wr = (v < V - 1) ? uc[v + 1] : right;
-                const TC u2 = (TC)(TW)prod(v, wl, wr, um[v], uq[v], uc[v], aym, ayq, cdy);
+                const TC u2 = (TC)(TW)prod(v, wl, wr, um[v], uq[v], uc[v], aym, ayq, cdy, beta2, rb);
                 TC p1;
                 if constexpr (kFirst) p1 = (TC)(TW)(d0 * wk[v] + d1 * uc[v]);
                 else p1 = (TC)(TW)(P[st & 3][v] + d1 * uc[v]);
@@ -221,7 +230,7 @@ __device__ void pair2d_tile(const PairArgs& a, int t0, int t1, int march, double
     }
 }
 
-template <class TW, int V, int MODE>
+template <class TW, int V, int MODE, bool IO>
 __global__ __launch_bounds__(kP2Waves * 64) void pair2d_sweep(PairArgs a, int tiles0, int ntiles, int march) {
     if (a.guard && a.st->done != 0) return;
     constexpr int N = (MODE == PAIR_FIRST) ? 5 : 4;
@@ -229,28 +238,34 @@ __global__ __launch_bounds__(kP2Waves * 64) void pair2d_sweep(PairArgs a, int ti
     const int nw = blockDim.x >> 6;
     const int G = gridDim.x * nw;
     const int L = __builtin_amdgcn_readfirstlane(xcd_tile(gridDim.x / kXcd) * nw + (int)(threadIdx.x >> 6));
-    for (int t = L; t < ntiles; t += G) pair2d_tile<TW, V, MODE>(a, t % tiles0, t / tiles0, march, s);
+    for (int t = L; t < ntiles; t += G) pair2d_tile<TW, V, MODE, IO>(a, t % tiles0, t / tiles0, march, s);
     double v[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) v[q] = s[q];
     finish_sweep_n<N>(a.partials, N == 5 ? 8 : 4, v);
 }
 
+template <class TW, int V, int MODE>
+void go_io(bool io, int grid, int tiles0, int ntiles, int march, const PairArgs& a, hipStream_t s) {
+    if (io)
+        hipLaunchKernelGGL((pair2d_sweep<TW, V, MODE, true>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0,
+                           ntiles, march);
+    else
+        hipLaunchKernelGGL((pair2d_sweep<TW, V, MODE, false>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0,
+                           ntiles, march);
+}
+
 template <class TW, int MODE>
 hipError_t go2(int vec, int grid, int tiles0, int ntiles, int march, const PairArgs& a, hipStream_t s) {
+    const bool io = (a.bc == EXPI_INTERIOR_ONLY);
     if constexpr (sizeof(TW) == 4) {
         if (vec == 4) {
-            hipLaunchKernelGGL((pair2d_sweep<TW, 4, MODE>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0,
-                               ntiles, march);
+            go_io<TW, 4, MODE>(io, grid, tiles0, ntiles, march, a, s);
             return hipGetLastError();
         }
     }
-    if (vec == 2)
-        hipLaunchKernelGGL((pair2d_sweep<TW, 2, MODE>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0, ntiles,
-                           march);
-    else
-        hipLaunchKernelGGL((pair2d_sweep<TW, 1, MODE>), dim3(grid), dim3(64 * kP2Waves), 0, s, a, tiles0, ntiles,
-                           march);
+    if (vec == 2) go_io<TW, 2, MODE>(io, grid, tiles0, ntiles, march, a, s);
+    else go_io<TW, 1, MODE>(io, grid, tiles0, ntiles, march, a, s);
     return hipGetLastError();
 }
 
@@ -263,7 +278,8 @@ bool pair2d_supported(const Op& op, int tw) {
     (void)tw;
     // buffer offsets are 32-bit byte offsets: below 2^31 bytes in FP64
     return op.kind == 0 && op.dim == 2 && op.coef == EXPI_COEF_CONST &&
-           (op.bc == EXPI_DIRICHLET0 || op.bc == EXPI_NEUMANN0) && op.size * 8 < ((int64_t)1 << 31) - 64;
+           (op.bc == EXPI_DIRICHLET0 || op.bc == EXPI_NEUMANN0 || op.bc == EXPI_INTERIOR_ONLY) &&
+           op.size * 8 < ((int64_t)1 << 31) - 64;
 }
 
 // rows: rows per tile (pair2d_rows_valid), or 0 for 16, fewer where the

@@ -5,7 +5,7 @@ phi_1(tau A) v on 2D grids with the pair sweep on (the default where it
 applies) against the FP64 oracle and against the single-product path on
 the same inputs: the 128 x 128 Dirichlet Laplacian of the plain-method
 workload, strips ragged against the 64- and 128-point tile width, odd row
-lengths (one point per lane), single rows and columns, both boundary
+lengths (one point per lane), single rows and columns, the three boundary
 handlings, FP32 storage, and stops after either product of a pair.
 """
 import numpy as np
@@ -46,10 +46,11 @@ def make(E, shape, bc, coef=1.3):
     return E.StencilOp(shape, h, bc, coef=coef), O.stencil_matrix(shape, h, bc, coef=coef)
 
 
-def run_pair_and_single(E, op, v, tau, tol, dtype="f64"):
-    yp, sp = E.phi_action(op, 1, tau, T(v), tol=tol, dtype=dtype, params=E.LejaParams(profile=True))
+def run_pair_and_single(E, op, v, tau, tol, dtype="f64", interval=None):
+    yp, sp = E.phi_action(op, 1, tau, T(v), tol=tol, dtype=dtype,
+                          params=E.LejaParams(profile=True, interval=interval))
     ys, ss = E.phi_action(op, 1, tau, T(v), tol=tol, dtype=dtype,
-                          params=E.LejaParams(pairs=False, profile=True))
+                          params=E.LejaParams(pairs=False, profile=True, interval=interval))
     return N(yp), sp, N(ys), ss
 
 
@@ -67,16 +68,19 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("bc", ["dirichlet0", "neumann0"])
+@pytest.mark.parametrize("bc", ["dirichlet0", "neumann0", "interior_only"])
 def test_pair2d_phi1_matches_oracle(E, shape, bc):
     op, A = make(E, shape, bc)
     n = int(np.prod(shape))
     v = synth.uniform_vector(n, 11)
     a, b = O.gershgorin_interval(A)
-    tau = 8.0 / (b - a)    # tau (b - a) = 8: one substep of a few dozen products
+    # interior_only with a side of at most 2 points has no interior: A = 0
+    # and a = b, so both sides get the interval [-1, 0] instead
+    iv = None if b > a else (-1.0, 0.0)
+    tau = 8.0 / (b - a) if iv is None else 1e-3   # tau (b - a) = 8: one substep of a few dozen products
     print(f"pair2d phi1 {shape} {bc}", flush=True)
-    yp, sp, ys, ss = run_pair_and_single(E, op, v, tau, 1e-10)
-    yo, so = I.phi_action(A, 1, tau, v, 1e-10)
+    yp, sp, ys, ss = run_pair_and_single(E, op, v, tau, 1e-10, interval=iv)
+    yo, so = I.phi_action(A, 1, tau, v, 1e-10, interval=iv)
     assert relerr(yp, yo) <= TOL_F64, relerr(yp, yo)
     assert relerr(ys, yo) <= TOL_F64
     assert abs(sp["degree_last"] - so.degrees[-1]) <= 1
@@ -146,7 +150,7 @@ def test_pair2d_every_tile_height(E, rows, dtype):
     and taller than it; one, two and, in FP32, four points per lane)."""
     tol, bound = (1e-10, TOL_F64) if dtype == "f64" else (1e-6, 2e-5)
     for shape, bc in (((300, 70), "dirichlet0"), ((129, 33), "neumann0"), ((64, 5), "dirichlet0"),
-                      ((258, 9), "neumann0")):
+                      ((258, 9), "neumann0"), ((132, 21), "interior_only")):
         op, A = make(E, shape, bc)
         op.set_pairs(rows)
         assert op.pair_setting() == rows
