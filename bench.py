@@ -16,8 +16,11 @@ FP64; the same run is repeated with FP32 storage of the Newton vectors.
 `roofline` covers the dominant kernel (the pair sweep), whose launches are
 timed with HIP events on the library's stream during the timed region.
 `cpu_baseline` is the FP64 oracle on a bounded sample of the same workload.
-Further legs: the learned step selector against the plain loop, and the
-batched solve of 256 uneven 2D problems.
+Further legs: the learned step selector against the plain loop, the
+batched solve of 256 uneven 2D problems, the CSR product, the paper's Table
+I-IV kernels, the complex spin-bath case, and the plain method on 2D
+Dirichlet Laplacians (128^2, and 8192^2 in FP64 and FP32 storage) with 2D
+pair sweeps against single products.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
